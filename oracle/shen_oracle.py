@@ -1,0 +1,354 @@
+"""FP64 CPU oracle for the wall-normal Shen-Galerkin Helmholtz and biharmonic solves.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library and does not import the package that wraps it.
+
+What it computes is the plain definition of the problem: for every system w
+it assembles the real dense Galerkin matrix from closed-form entries and
+solves it with LAPACK ``gesv`` (partial pivoting), the real and imaginary
+parts of the right-hand side being two right-hand sides of the same
+factorisation, then applies two steps of classical iterative refinement with
+the residual f - H u accumulated in extended precision (long double), so
+that the result is u = H^{-1} f to a few ulps even where pivoted LU alone is
+not (the row-graded biharmonic matrices at small wavenumber).
+
+Conventions (arrays of length N = number of Chebyshev modes = number of
+quadrature points; Sec. 2):
+
+* Dirichlet basis  phi_k = T_k - T_{k+2},                       k = 0..N-3
+* biharmonic basis phi_k = T_k - 2(k+2)/(k+3) T_{k+2} + (k+1)/(k+3) T_{k+4},
+                                                                k = 0..N-5
+* Matrix entry (k, j): row k is the test function, column j the trial one.
+* c_0 = 2, c_k = 1 otherwise, except c_{N-1} = 2 for Gauss-Lobatto
+  quadrature (appendix, matrix table caption).
+
+Matrices (row k, column j):
+
+* Bbar = (phi_j, phi_k) Dirichlet mass          -- appendix matrix table
+* Sbar = -(phi_j'', phi_k) Dirichlet stiffness  -- not printed (Sec. 3 defers
+  it to Shen 1995); closed form derived from the Chebyshev second-derivative
+  coefficients and pinned by the tests against exact rational arithmetic
+  and quadrature.
+* Bchk = (phi_j, phi_k) biharmonic mass         -- appendix matrix table
+* Achk = (phi_j'', phi_k) biharmonic Laplacian  -- not printed; derived,
+  pinned likewise (sign: the Crank-Nicolson biharmonic matrix of Sec. 3 is
+  only consistent with this sign).
+* Qchk = (phi_j'''', phi_k)                     -- Sec. 4 (rank-2 tail
+  p_k q_j + r_k s_j); its printed diagonal is not what the definition gives
+  and the diagonal used here is the one the definition gives (pinned by the
+  clamped-plate solution and by exact arithmetic).
+
+Systems solved (Sec. 3, Crank-Nicolson matrices divided by +-nu*dt/2):
+
+* Helmholtz:  (Sbar + alpha_w Bbar) u = f
+* biharmonic: (Qchk + a_w Achk + b_w Bchk) u = f
+
+Inputs: N, per-system coefficients, complex f of shape [nsys, N] whose
+entries k >= n are ignored.  Output: complex u [nsys, N] with the tail zero.
+"""
+from __future__ import annotations
+
+import os
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+PI = np.pi
+GC = 0
+GL = 1
+
+
+# ----------------------------------------------------------------------------
+# Quadrature constants
+# ----------------------------------------------------------------------------
+
+def ck(m, N: int, quad: int = GC):
+    """c_m of the discrete weighted inner product (appendix matrix table caption)."""
+    m = np.asarray(m)
+    c = np.where(m == 0, 2.0, 1.0)
+    if quad == GL:
+        c = np.where(m == N - 1, 2.0, c)
+    return c
+
+
+# ----------------------------------------------------------------------------
+# Dirichlet (Helmholtz) matrices
+# ----------------------------------------------------------------------------
+
+def dirichlet_mass(N: int, quad: int = GC) -> np.ndarray:
+    """Bbar_kj = (phi_j, phi_k): pi/2 (c_k + c_{k+2}) on the diagonal, -pi/2 at |j-k| = 2."""
+    n = N - 2
+    k = np.arange(n)
+    B = np.zeros((n, n))
+    B[k, k] = 0.5 * PI * (ck(k, N, quad) + ck(k + 2, N, quad))
+    i = np.arange(n - 2)
+    B[i, i + 2] = -0.5 * PI
+    B[i + 2, i] = -0.5 * PI
+    return B
+
+
+def dirichlet_stiffness(N: int) -> np.ndarray:
+    """Sbar_kj = -(phi_j'', phi_k): 2pi(k+1)(k+2) on the diagonal, 4pi(k+1) for j = k+2, k+4, ..."""
+    n = N - 2
+    S = np.zeros((n, n))
+    for k in range(n):
+        S[k, k] = 2.0 * PI * (k + 1) * (k + 2)
+        S[k, k + 2::2] = 4.0 * PI * (k + 1)
+    return S
+
+
+# ----------------------------------------------------------------------------
+# Biharmonic matrices
+# ----------------------------------------------------------------------------
+
+def biharmonic_mass(N: int, quad: int = GC) -> np.ndarray:
+    """Bchk_kj = (phi_j, phi_k), five diagonals, symmetric (appendix matrix table)."""
+    n = N - 4
+    B = np.zeros((n, n))
+    for k in range(n):
+        B[k, k] = 0.5 * PI * (ck(k, N, quad) + 4.0 * ((k + 2) / (k + 3)) ** 2
+                              + ck(k + 4, N, quad) * ((k + 1) / (k + 3)) ** 2)
+        if k + 2 < n:
+            v = -PI * ((k + 2) / (k + 3) + (k + 4) * (k + 1) / ((k + 5) * (k + 3)))
+            B[k, k + 2] = v
+            B[k + 2, k] = v
+        if k + 4 < n:
+            v = 0.5 * PI * (k + 1) / (k + 3)
+            B[k, k + 4] = v
+            B[k + 4, k] = v
+    return B
+
+
+def biharmonic_laplacian(N: int) -> np.ndarray:
+    """Achk_kj = (phi_j'', phi_k): three diagonals j = k-2, k, k+2 (Sec. 4 states the band)."""
+    n = N - 4
+    A = np.zeros((n, n))
+    for k in range(n):
+        A[k, k] = -4.0 * PI * (k + 1) * (k + 2) ** 2 / (k + 3)
+        if k + 2 < n:
+            A[k, k + 2] = 2.0 * PI * (k + 1) * (k + 2)
+        if k - 2 >= 0:
+            A[k, k - 2] = 2.0 * PI * (k - 1) * (k + 2)
+    return A
+
+
+def q_gen(N: int):
+    """Generators of the Qchk tail (Sec. 4): p_k, q_j, r_k, s_j."""
+    k = np.arange(N - 4, dtype=np.float64)
+    p = 8.0 * PI * k * (k + 1) * (k + 2) * (k + 4)
+    q = 1.0 / (k + 3)
+    r = 24.0 * PI * (k + 1) * (k + 2)
+    s = (k + 2) ** 2 / (k + 3)
+    return p, q, r, s
+
+
+def biharmonic_bilaplacian(N: int) -> np.ndarray:
+    """Qchk_kj = (phi_j'''', phi_k): upper triangular, Q_kk = 8pi(k+1)^2(k+2)(k+4),
+    Q_kj = p_k q_j + r_k s_j for j = k+2, k+4, ... (Sec. 4)."""
+    n = N - 4
+    p, q, r, s = q_gen(N)
+    Q = np.zeros((n, n))
+    for k in range(n):
+        Q[k, k] = 8.0 * PI * (k + 1) ** 2 * (k + 2) * (k + 4)
+        j = np.arange(k + 2, n, 2)
+        Q[k, j] = p[k] * q[j] + r[k] * s[j]
+    return Q
+
+
+# ----------------------------------------------------------------------------
+# System matrices
+# ----------------------------------------------------------------------------
+
+class Operators:
+    """Dense closed-form matrices for one N and quadrature, cached."""
+
+    _cache = {}
+
+    def __init__(self, N: int, quad: int = GC):
+        self.N = N
+        self.quad = quad
+        self.Bd = dirichlet_mass(N, quad)
+        self.Sd = dirichlet_stiffness(N)
+        if N >= 5:
+            self.Bb = biharmonic_mass(N, quad)
+            self.Ab = biharmonic_laplacian(N)
+            self.Qb = biharmonic_bilaplacian(N)
+
+    @classmethod
+    def get(cls, N: int, quad: int = GC) -> "Operators":
+        key = (N, quad)
+        if key not in cls._cache:
+            cls._cache[key] = cls(N, quad)
+        return cls._cache[key]
+
+
+def helmholtz_matrix(N: int, alpha, quad: int = GC) -> np.ndarray:
+    """H = Sbar + alpha Bbar, batched over alpha (Sec. 3 Helmholtz matrix / (nu dt / 2))."""
+    op = Operators.get(N, quad)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    return op.Sd + alpha[..., None, None] * op.Bd
+
+
+def biharmonic_matrix(N: int, a, b, quad: int = GC) -> np.ndarray:
+    """H = Qchk + a Achk + b Bchk, batched (Sec. 3 biharmonic matrix / (-nu dt / 2))."""
+    op = Operators.get(N, quad)
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return op.Qb + a[..., None, None] * op.Ab + b[..., None, None] * op.Bb
+
+
+def system_matrix(family: str, N: int, coeffs, quad: int = GC) -> np.ndarray:
+    if family == "helmholtz":
+        return helmholtz_matrix(N, coeffs[0], quad)
+    return biharmonic_matrix(N, coeffs[0], coeffs[1], quad)
+
+
+def n_of(family: str, N: int) -> int:
+    return N - 2 if family == "helmholtz" else N - 4
+
+
+# ----------------------------------------------------------------------------
+# Solves (dense LU with partial pivoting, LAPACK gesv)
+# ----------------------------------------------------------------------------
+
+def _solve_chunk(family, N, coeffs, f, quad, transpose, refine):
+    n = n_of(family, N)
+    H = system_matrix(family, N, coeffs, quad)
+    if transpose:
+        H = np.swapaxes(H, -1, -2)
+    rhs = np.stack([f[:, :n].real, f[:, :n].imag], axis=-1)
+    x = np.linalg.solve(H, rhs)
+    if refine:
+        # Classical iterative refinement, residual in extended precision: partial
+        # pivoting on these row-graded matrices can leave gesv ~1e-12 from the exact
+        # solution; two corrections bring it to a few ulps of u = H^{-1} f.
+        Hl = H.astype(np.longdouble)
+        rl = rhs.astype(np.longdouble)
+        for _ in range(refine):
+            r = rl - np.matmul(Hl, x.astype(np.longdouble))
+            x = x + np.linalg.solve(H, r.astype(np.float64))
+    u = np.zeros(f.shape, dtype=np.complex128)
+    u[:, :n] = x[..., 0] + 1j * x[..., 1]
+    return u
+
+
+def solve(family: str, N: int, coeffs, f: np.ndarray, quad: int = GC, transpose: bool = False,
+          chunk: int = 0, threads: int = 1, refine: int = 2) -> np.ndarray:
+    """Solve H u = f (or H^T u = f) for every system; coeffs = (alpha,) or (a, b).
+
+    LAPACK gesv followed by ``refine`` steps of iterative refinement with an
+    extended-precision residual (refine=0: plain gesv)."""
+    f = np.asarray(f, dtype=np.complex128)
+    nsys = f.shape[0]
+    coeffs = tuple(np.asarray(c, dtype=np.float64).reshape(nsys) for c in coeffs)
+    if nsys == 0:
+        return np.zeros_like(f)
+    n = n_of(family, N)
+    if chunk <= 0:
+        chunk = max(1, min(nsys, int(2.0e7 // max(1, n * n))))
+    starts = list(range(0, nsys, chunk))
+
+    def work(s0):
+        s1 = min(nsys, s0 + chunk)
+        return s0, _solve_chunk(family, N, tuple(c[s0:s1] for c in coeffs), f[s0:s1], quad, transpose, refine)
+
+    u = np.zeros_like(f)
+    if threads <= 1 or len(starts) == 1:
+        for s0 in starts:
+            _, part = work(s0)
+            u[s0:s0 + part.shape[0]] = part
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            for s0, part in ex.map(work, starts):
+                u[s0:s0 + part.shape[0]] = part
+    return u
+
+
+def helmholtz_solve(N, alpha, f, quad=GC, transpose=False, threads=1):
+    return solve("helmholtz", N, (alpha,), f, quad, transpose, threads=threads)
+
+
+def biharmonic_solve(N, a, b, f, quad=GC, transpose=False, threads=1):
+    return solve("biharmonic", N, (a, b), f, quad, transpose, threads=threads)
+
+
+def matvec(family: str, N: int, coeffs, u: np.ndarray, quad: int = GC, transpose: bool = False,
+           extended: bool = False) -> np.ndarray:
+    """Hu (tail of the result zero).  extended=True accumulates in long double."""
+    u = np.asarray(u, dtype=np.complex128)
+    nsys = u.shape[0]
+    n = n_of(family, N)
+    coeffs = tuple(np.asarray(c, dtype=np.float64).reshape(nsys) for c in coeffs)
+    H = system_matrix(family, N, coeffs, quad)
+    if transpose:
+        H = np.swapaxes(H, -1, -2)
+    out = np.zeros_like(u)
+    if extended:
+        Hl = H.astype(np.longdouble)
+        re = np.einsum("wkj,wj->wk", Hl, u[:, :n].real.astype(np.longdouble))
+        im = np.einsum("wkj,wj->wk", Hl, u[:, :n].imag.astype(np.longdouble))
+        out[:, :n] = re.astype(np.float64) + 1j * im.astype(np.float64)
+    else:
+        out[:, :n] = np.einsum("wkj,wj->wk", H, u[:, :n])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Adjoint and coefficient gradients
+# ----------------------------------------------------------------------------
+
+def solve_grads(family: str, N: int, coeffs, f: np.ndarray, gu: np.ndarray, quad: int = GC):
+    """Gradients of a real loss through u = H^{-1} f, given gu = dL/dRe(u) + i dL/dIm(u).
+
+    lambda = H^{-T} gu (H is real) is the gradient with respect to f; the
+    gradient with respect to a coefficient c multiplying the matrix M_c is
+    -Re(lambda^H M_c u), because du/dc = -H^{-1} M_c u.
+    Returns (u, grad_f, [grad per coefficient]).
+    """
+    u = solve(family, N, coeffs, f, quad)
+    lam = solve(family, N, coeffs, gu, quad, transpose=True)
+    n = n_of(family, N)
+    op = Operators.get(N, quad)
+    mats = [op.Bd] if family == "helmholtz" else [op.Ab, op.Bb]
+    grads = []
+    for M in mats:
+        Mu = np.einsum("kj,wj->wk", M, u[:, :n])
+        grads.append(-np.real(np.sum(np.conj(lam[:, :n]) * Mu, axis=1)))
+    return u, lam, grads
+
+
+# ----------------------------------------------------------------------------
+# Error metrics
+# ----------------------------------------------------------------------------
+
+def rel_err_per_system(u: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """max_k |u_k - ref_k| / max_k |ref_k| per system (the roundoff measure of Sec. 5)."""
+    num = np.max(np.abs(u - ref), axis=1)
+    den = np.max(np.abs(ref), axis=1)
+    den = np.where(den == 0, 1.0, den)
+    return num / den
+
+
+# ----------------------------------------------------------------------------
+# Timing of the oracle on the host (a baseline, not the target)
+# ----------------------------------------------------------------------------
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def time_solve(family, N, coeffs, f, threads=None, quad=GC, refine=2):
+    """Wall time of the oracle over the given systems; returns (seconds, threads, u)."""
+    threads = threads or host_threads()
+    n = n_of(family, N)
+    nsys = f.shape[0]
+    chunk = max(1, min(64, (nsys + threads - 1) // threads, int(2.0e7 // max(1, n * n))))
+    t0 = time.perf_counter()
+    u = solve(family, N, coeffs, f, quad, chunk=chunk, threads=threads, refine=refine)
+    return time.perf_counter() - t0, threads, u
