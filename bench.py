@@ -1,0 +1,175 @@
+"""Benchmark: batched wall-normal Helmholtz + biharmonic solves on one MI355X.
+
+One step = the FP64 Helmholtz solve and the FP64 biharmonic solve over every
+(kx, kz) of the channel-scale workload (N = 512 wall-normal modes, 512 x 257
+rfft wavenumber grid, 131,584 systems per family), inputs resident in HBM.
+The FP32 + FP64-refinement form is timed beside it on the same inputs.
+
+Prints ONE JSON line (rank 0).  `value` = wall-normal systems x N solved per
+second over the whole step (both families).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "wall-normal solves·N/s + HBM GB/s, FP32+refine vs FP64 at 1e-12 rel err, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def alg_bytes(family: str, N: int, nsys: int) -> int:
+    """Algorithmic HBM bytes of one solve: read f[k<n], write u[0:N], read coefficients."""
+    if family == "helmholtz":
+        return nsys * (16 * (N - 2) + 16 * N + 8)
+    return nsys * (16 * (N - 4) + 16 * N + 16)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--variant", default="auto")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the systems are independent and would shard by wavenumber range, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1701_03787_amd import api
+    from paper_1701_03787_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    grid = wl.config_grids(args.config)[0]
+    N, nsys = grid.N, grid.nsys
+    fams = [f for f in ("helmholtz", "biharmonic") if f in grid.families]
+    print(f"# workload {grid.name}: N={N} nsys={nsys} per family, families={fams}", file=sys.stderr, flush=True)
+
+    host = {}
+    data = {}
+    for fam in fams:
+        f = grid.rhs(fam)
+        cs = grid.coefficients(fam)
+        host[fam] = (f, cs)
+        data[fam] = (torch.from_numpy(f).to(dev), [torch.from_numpy(c).to(dev) for c in cs],
+                     torch.empty((nsys, N), dtype=torch.complex128, device=dev))
+    torch.cuda.synchronize()
+
+    def launch(fam, precision="fp64"):
+        f, cs, u = data[fam]
+        if fam == "helmholtz":
+            api.helmholtz_solve(f, cs[0], out=u, precision=precision, variant=args.variant)
+        else:
+            api.biharmonic_solve(f, cs[0], cs[1], out=u, precision=precision, variant=args.variant)
+
+    def timed(precision):
+        for _ in range(args.warmup):
+            for fam in fams:
+                launch(fam, precision)
+        torch.cuda.synchronize()
+        ev = {fam: [] for fam in fams}
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for fam in fams:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                launch(fam, precision)
+                e1.record()
+                ev[fam].append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = {fam: float(np.mean([a.elapsed_time(b) for a, b in ev[fam]])) for fam in fams}
+        return wall, kms
+
+    wall, kms = timed("fp64")
+    ms_per_step = 1e3 * wall / args.steps
+    units = sum(nsys * N for _ in fams)
+    value = units / (ms_per_step / 1e3)
+    step_bytes = sum(alg_bytes(fam, N, nsys) for fam in fams)
+
+    # accuracy of the timed outputs on a sample of systems (oracle, CPU)
+    from oracle import shen_oracle as so
+    rng = np.random.default_rng([1701, 77])
+    rows = np.unique(np.concatenate([[0, nsys - 1, int(np.argmin(grid.K2)), int(np.argmax(grid.K2))],
+                                     rng.choice(nsys, 28, replace=False)]))
+    acc = {}
+    for fam in fams:
+        launch(fam, "fp64")
+        torch.cuda.synchronize()
+        u = data[fam][2][torch.from_numpy(rows).to(dev)].cpu().numpy()
+        f, cs = host[fam]
+        ref = so.solve(fam, N, tuple(c[rows] for c in cs), f[rows])
+        acc[fam] = float(so.rel_err_per_system(u, ref).max())
+
+    dom = max(fams, key=lambda fm: kms[fm])
+    achieved = alg_bytes(dom, N, nsys) / (kms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{dom}_solve fp64", "kernel_ms": round(kms[dom], 4),
+                "bytes_per_launch": alg_bytes(dom, N, nsys)}
+
+    mixed = None
+    if not args.no_mixed:
+        wall_m, kms_m = timed("fp32_refine")
+        acc_m = {}
+        for fam in fams:
+            launch(fam, "fp32_refine")
+            torch.cuda.synchronize()
+            u = data[fam][2][torch.from_numpy(rows).to(dev)].cpu().numpy()
+            f, cs = host[fam]
+            ref = so.solve(fam, N, tuple(c[rows] for c in cs), f[rows])
+            acc_m[fam] = float(so.rel_err_per_system(u, ref).max())
+        ms_m = 1e3 * wall_m / args.steps
+        mixed = {"value": units / (ms_m / 1e3), "ms_per_step": round(ms_m, 4),
+                 "kernel_ms": {k: round(v, 4) for k, v in kms_m.items()},
+                 "speedup_vs_fp64": round(ms_per_step / ms_m, 4), "max_rel_err": acc_m}
+
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+        threads = so.host_threads()
+        per_fam = min(nsys, max(64, 24 * threads))
+        sample = rng.choice(nsys, per_fam, replace=False)
+        t_cpu = 0.0
+        with threadpool_limits(limits=1):
+            for fam in fams:
+                f, cs = host[fam]
+                dt, used, _ = so.time_solve(fam, N, tuple(c[sample] for c in cs), f[sample], threads=threads)
+                t_cpu += dt
+        cpu = {"value": round(len(fams) * per_fam * N / t_cpu, 2), "unit": "system·N/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{per_fam} random systems per family of {grid.name} (same inputs), dense LU + refinement, "
+                         f"{t_cpu:.1f} s on {threads} threads"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "system·N/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": grid.name, "N": N, "nsys_per_family": nsys, "families": fams,
+                   "precision": "fp64", "quadrature": "GC"},
+        "hbm_gbps_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+        "kernel_ms": {k: round(v, 4) for k, v in kms.items()},
+        "max_rel_err": acc,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed_fp32_refine": mixed,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * shenhip -- batched direct solvers for the wall-normal Shen-Galerkin
+ * Helmholtz and biharmonic systems of a Fourier/Chebyshev channel solver
+ * (Mortensen, "A spectral-Galerkin turbulent channel flow solver for
+ * large-scale simulations", Sec. 3 and Sec. 4), on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Problem (one independent system per Fourier wavenumber pair (kx, kz)):
+ *
+ *   Helmholtz  (Shen Dirichlet basis  phi_k = T_k - T_{k+2}, k < n = N-2):
+ *       (S + alpha_w B) u_w = f_w,
+ *       S_kj = -(phi_j'', phi_k)_sigma,  B_kj = (phi_j, phi_k)_sigma
+ *   biharmonic (Shen biharmonic basis phi_k = T_k - 2(k+2)/(k+3) T_{k+2}
+ *                                       + (k+1)/(k+3) T_{k+4}, k < n = N-4):
+ *       (Q + a_w A + b_w B) u_w = f_w,
+ *       Q_kj = (phi_j'''', phi_k)_sigma, A_kj = (phi_j'', phi_k)_sigma,
+ *       B_kj = (phi_j, phi_k)_sigma
+ *
+ * These are the paper's Crank-Nicolson Helmholtz and biharmonic matrices
+ * (Sec. 3) divided by nu*dt/2 and -nu*dt/2: alpha = K2 + 2/(nu dt),
+ * a = -(2 K2 + 2/(nu dt)), b = K2 (K2 + 2/(nu dt)).  (.,.)_sigma is the
+ * N-point Chebyshev-Gauss (default) or Gauss-Lobatto weighted inner product
+ * (Sec. 2); the two differ only in the last diagonal entry of B.
+ *
+ * Data layout (all solve entry points):
+ *   f, u   complex128 [nsys][N], C-contiguous, wavenumber-major, 16-byte
+ *          aligned DEVICE pointers owned by the caller.  Entries k >= n of f
+ *          are not read; entries k >= n of u are written as 0.  u == f
+ *          (in place) is allowed; partial overlap is not.
+ *   alpha, a, b   float64 [nsys] DEVICE pointers.
+ *
+ * Execution: every call validates its arguments on the host, then enqueues
+ * kernels on opts->stream and returns without synchronising.  The library
+ * allocates no memory per call and keeps no state between calls except a
+ * per-device table of device properties filled on first use.
+ *
+ * Errors: argument errors return a negative SHEN_E* code before anything is
+ * enqueued.  Numerical failures never return an error code; when
+ * opts->info is non-NULL the kernels write one int32 per system: 0 = ok,
+ * k+1 = a zero or non-finite pivot first met at row k (the system is
+ * singular for the unpivoted LU, or its inputs are not finite; u is then
+ * unspecified), SHEN_INFO_REFINE_FALLBACK = the FP32 refinement did not
+ * converge and the system was re-solved in FP64.
+ */
+#ifndef SHENHIP_H
+#define SHENHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHENHIP_ABI_VERSION 1
+
+typedef struct {
+  double re, im;
+} shen_c128;
+
+/* return codes */
+#define SHEN_OK 0
+#define SHEN_EINVAL (-1)   /* bad argument: NULL, size, alignment, enum */
+#define SHEN_ELAUNCH (-2)  /* the HIP runtime refused a launch */
+#define SHEN_ENOTSUP (-3)  /* N beyond what the chosen kernel supports */
+#define SHEN_EDEVICE (-4)  /* no usable HIP device */
+
+/* per-system info codes besides 0 and k+1 */
+#define SHEN_INFO_REFINE_FALLBACK (-2)
+
+/* opts.precision */
+#define SHEN_FP64 0        /* factor and solve in FP64 */
+#define SHEN_FP32_REFINE 1 /* FP32 factor/solve, FP64 residual refinement */
+
+/* opts.quad */
+#define SHEN_QUAD_GC 0 /* Chebyshev-Gauss points (default) */
+#define SHEN_QUAD_GL 1 /* Chebyshev-Gauss-Lobatto points */
+
+/* families (batched descriptors) */
+#define SHEN_HELMHOLTZ 0
+#define SHEN_BIHARMONIC 1
+
+typedef struct {
+  void* stream;       /* hipStream_t to enqueue on; NULL = null stream       */
+  int32_t precision;  /* SHEN_FP64 (default) or SHEN_FP32_REFINE             */
+  int32_t transpose;  /* 0: H u = f; 1: H^T u = f (the adjoint system)       */
+  int32_t quad;       /* SHEN_QUAD_GC (default) or SHEN_QUAD_GL              */
+  int32_t refine_max; /* FP32_REFINE: max corrections, <= 0 means 8          */
+  double refine_tol;  /* FP32_REFINE: stop at max|du| <= tol max|u|; <= 0
+                         means 1e-14.  Refinement also stops once a
+                         correction fails to halve (rounding floor).         */
+  int32_t* info;      /* optional DEVICE int32[nsys] status per system       */
+  int32_t variant;    /* kernel choice: 0 = automatic (see shen_variant_*)   */
+  int32_t reserved;
+} shen_opts;
+
+/* kernel variants (opts.variant); 0 picks per N and mode */
+#define SHEN_VARIANT_AUTO 0
+#define SHEN_VARIANT_CHAIN 1 /* one lane per odd/even chain, LDS-resident     */
+#define SHEN_VARIANT_WAVE 2  /* one wavefront per system, register-resident  */
+
+/* Fill *opts with the defaults (null stream, FP64, no transpose, GC). */
+void shen_opts_default(shen_opts* opts);
+
+/* Version of this interface (SHENHIP_ABI_VERSION). */
+int shen_abi_version(void);
+
+/* Static string describing a SHEN_* return code. */
+const char* shen_status_string(int code);
+
+/* Largest N each entry point accepts on the current device for the given
+ * family and precision (depends on the device's LDS size). */
+int32_t shen_max_n(int32_t family, int32_t precision);
+
+/*
+ * Helmholtz solve (Sec. 4, the odd/even upper-Hessenberg LU with the
+ * constant tail of U):  (S + alpha_w B) u_w = f_w  for w < nsys,
+ * or the transposed system when opts->transpose.  N >= 3.
+ */
+int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c128* f, shen_c128* u,
+                    const shen_opts* opts);
+
+/*
+ * Biharmonic solve (Sec. 4, Alg. LUbiharmonic, ReduceAB and
+ * LUSolveBiharmonic, in a compact form that keeps two rows of U):
+ * (Q + a_w A + b_w B) u_w = f_w, or the transposed system.  N >= 5.
+ */
+int biharmonic_solve(int32_t N, int64_t nsys, const double* a, const double* b, const shen_c128* f,
+                     shen_c128* u, const shen_opts* opts);
+
+/*
+ * Adjoint of the Helmholtz solve u = H^{-1} f for a real loss L, given
+ * gbar = dL/dRe(u) + i dL/dIm(u) (complex128 [nsys][N]) and the forward
+ * solution u: writes lambda = H^{-T} gbar (= the gradient with respect to f,
+ * tail zero) and, when grad_alpha != NULL, grad_alpha[w] =
+ * -Re(lambda_w^H B u_w) (float64 [nsys]).  lambda may alias gbar.
+ */
+int helmholtz_adjoint(int32_t N, int64_t nsys, const double* alpha, const shen_c128* u,
+                      const shen_c128* gbar, shen_c128* lambda, double* grad_alpha,
+                      const shen_opts* opts);
+
+/*
+ * Adjoint of the biharmonic solve: lambda = H^{-T} gbar, and when non-NULL
+ * grad_a[w] = -Re(lambda_w^H A u_w), grad_b[w] = -Re(lambda_w^H B u_w).
+ */
+int biharmonic_adjoint(int32_t N, int64_t nsys, const double* a, const double* b, const shen_c128* u,
+                       const shen_c128* gbar, shen_c128* lambda, double* grad_a, double* grad_b,
+                       const shen_opts* opts);
+
+/*
+ * Matrix-vector products Hu (or H^T u) in O(N) per system, FP64: the banded
+ * part plus same-parity suffix sums for the rank-structured tail (Sec. 3
+ * right-hand sides; also the residual of the refinement).  Hu must not
+ * alias u.
+ */
+int helmholtz_matvec(int32_t N, int64_t nsys, const double* alpha, const shen_c128* u, shen_c128* Hu,
+                     const shen_opts* opts);
+int biharmonic_matvec(int32_t N, int64_t nsys, const double* a, const double* b, const shen_c128* u,
+                      shen_c128* Hu, const shen_opts* opts);
+
+/*
+ * One batch of independent problems (many grids of uneven N, both
+ * families) in a single persistent launch.
+ *
+ * desc: DEVICE array of ndesc descriptors (built once by the caller and
+ *   reused; the library never reads it on the host).  c0 = alpha (Helmholtz)
+ *   or a (biharmonic), c1 = b (biharmonic, else unused); info may be NULL.
+ * work: DEVICE scratch of shen_batched_work_bytes(ndesc) bytes, owned by the
+ *   caller; its contents on entry do not matter (the library clears it
+ *   with a kernel, so the call may be captured in a hipGraph and replayed).
+ * tiles_total: value returned by shen_batched_plan() for the same
+ *   descriptors (host copy), the total number of work items.
+ * maxN: the largest N among the descriptors.
+ * Concurrent calls must not share `work`.
+ */
+typedef struct {
+  int32_t family;  /* SHEN_HELMHOLTZ or SHEN_BIHARMONIC */
+  int32_t N;
+  int64_t nsys;
+  const double* c0;
+  const double* c1;
+  const shen_c128* f;
+  shen_c128* u;
+  int32_t* info;
+  int64_t tile_begin; /* filled by shen_batched_plan: first work item       */
+  int32_t sys_per_tile; /* filled by shen_batched_plan                      */
+  int32_t reserved;
+} shen_problem;
+
+/* Host-side planning: fills tile_begin / sys_per_tile of each HOST
+ * descriptor and returns the total number of work items (or a negative
+ * code).  Choose tiles per (family, N) for the current device. */
+int64_t shen_batched_plan(shen_problem* desc_host, int32_t ndesc, const shen_opts* opts);
+
+/* Bytes of the `work` scratch for batched_solve. */
+int64_t shen_batched_work_bytes(int32_t ndesc);
+
+int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work,
+                  const shen_opts* opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHENHIP_H */

@@ -1,0 +1,226 @@
+"""Python binding of libshenhip: argument marshalling only.
+
+Tensors are torch CUDA (HIP) tensors; every call enqueues on torch's current
+stream.  Shapes: right-hand sides and solutions are complex128 [..., N]
+(wall-normal index last, contiguous), coefficients float64 [...] with the
+same leading shape.  Every step of the solve runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp64": L.SHEN_FP64, "fp32_refine": L.SHEN_FP32_REFINE}
+_QUAD = {"gc": L.SHEN_QUAD_GC, "gl": L.SHEN_QUAD_GL}
+_VARIANT = {"auto": 0, "chain": 1, "wave": 2}
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8, refine_tol=1e-14,
+          variant="auto") -> L.ShenOpts:
+    o = L.default_opts()
+    o.stream = _stream_handle(device)
+    o.precision = _PREC[precision]
+    o.quad = _QUAD[quad]
+    o.transpose = int(bool(transpose))
+    o.refine_max = int(refine_max)
+    o.refine_tol = float(refine_tol)
+    o.info = info.data_ptr() if info is not None else None
+    o.variant = _VARIANT[variant] if isinstance(variant, str) else int(variant)
+    return o
+
+
+def _rows(x: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex128:
+        raise TypeError(f"{name} must be a complex128 tensor")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be on a HIP device (no CPU path)")
+    if x.dim() < 1:
+        raise ValueError(f"{name} must have the wall-normal axis last")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _coef(c: torch.Tensor, lead, device, name: str) -> torch.Tensor:
+    if not isinstance(c, torch.Tensor) or c.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor")
+    if c.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    if tuple(c.shape) != tuple(lead):
+        raise ValueError(f"{name} has shape {tuple(c.shape)}, expected {tuple(lead)}")
+    if not c.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return c
+
+
+def _info_tensor(want, lead, device):
+    if want is None or want is False:
+        return None
+    if isinstance(want, torch.Tensor):
+        if want.dtype != torch.int32 or tuple(want.shape) != tuple(lead) or not want.is_contiguous() or want.device != device:
+            raise ValueError("info must be a contiguous int32 tensor of the batch shape on the same device")
+        return want
+    return torch.empty(lead, dtype=torch.int32, device=device)
+
+
+def _nsys(lead) -> int:
+    n = 1
+    for s in lead:
+        n *= int(s)
+    return n
+
+
+def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
+                    refine_tol=1e-14, variant="auto"):
+    """u = (S + alpha B)^{-1} f per system (or the transposed system).
+
+    Returns u, or (u, info) when info is requested (True or an int32 tensor)."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    lead = f.shape[:-1]
+    alpha = _coef(alpha, lead, f.device, "alpha")
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    inf = _info_tensor(info, lead, f.device)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant)
+    L.check(L.lib().helmholtz_solve(N, _nsys(lead), alpha.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
+            "helmholtz_solve")
+    return (u, inf) if inf is not None else u
+
+
+def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
+                     refine_tol=1e-14, variant="auto"):
+    """u = (Q + a A + b B)^{-1} f per system (or the transposed system)."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    lead = f.shape[:-1]
+    a = _coef(a, lead, f.device, "a")
+    b = _coef(b, lead, f.device, "b")
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    inf = _info_tensor(info, lead, f.device)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant)
+    L.check(L.lib().biharmonic_solve(N, _nsys(lead), a.data_ptr(), b.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
+            "biharmonic_solve")
+    return (u, inf) if inf is not None else u
+
+
+def helmholtz_matvec(u, alpha, *, out=None, quad="gc", transpose=False):
+    u = _rows(u, "u")
+    N = u.shape[-1]
+    lead = u.shape[:-1]
+    alpha = _coef(alpha, lead, u.device, "alpha")
+    y = torch.empty_like(u) if out is None else _rows(out, "out")
+    o = _opts(u.device, quad=quad, transpose=transpose)
+    L.check(L.lib().helmholtz_matvec(N, _nsys(lead), alpha.data_ptr(), u.data_ptr(), y.data_ptr(), C.byref(o)),
+            "helmholtz_matvec")
+    return y
+
+
+def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
+    u = _rows(u, "u")
+    N = u.shape[-1]
+    lead = u.shape[:-1]
+    a = _coef(a, lead, u.device, "a")
+    b = _coef(b, lead, u.device, "b")
+    y = torch.empty_like(u) if out is None else _rows(out, "out")
+    o = _opts(u.device, quad=quad, transpose=transpose)
+    L.check(L.lib().biharmonic_matvec(N, _nsys(lead), a.data_ptr(), b.data_ptr(), u.data_ptr(), y.data_ptr(), C.byref(o)),
+            "biharmonic_matvec")
+    return y
+
+
+def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None):
+    """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None)."""
+    gbar = _rows(gbar, "gbar")
+    N = gbar.shape[-1]
+    lead = gbar.shape[:-1]
+    alpha = _coef(alpha, lead, gbar.device, "alpha")
+    lam = torch.empty_like(gbar)
+    ga = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
+    if coef_grad:
+        u = _rows(u, "u")
+    inf = _info_tensor(info, lead, gbar.device)
+    o = _opts(gbar.device, quad=quad, info=inf)
+    L.check(L.lib().helmholtz_adjoint(N, _nsys(lead), alpha.data_ptr(), u.data_ptr() if coef_grad else None,
+                                      gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
+                                      C.byref(o)), "helmholtz_adjoint")
+    return (lam, ga, inf) if inf is not None else (lam, ga)
+
+
+def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None):
+    """lambda = H^{-T} gbar, grad_a = -Re(lambda^H A u), grad_b = -Re(lambda^H B u)."""
+    gbar = _rows(gbar, "gbar")
+    N = gbar.shape[-1]
+    lead = gbar.shape[:-1]
+    a = _coef(a, lead, gbar.device, "a")
+    b = _coef(b, lead, gbar.device, "b")
+    lam = torch.empty_like(gbar)
+    ga = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
+    gb = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
+    if coef_grad:
+        u = _rows(u, "u")
+    inf = _info_tensor(info, lead, gbar.device)
+    o = _opts(gbar.device, quad=quad, info=inf)
+    L.check(L.lib().biharmonic_adjoint(N, _nsys(lead), a.data_ptr(), b.data_ptr(), u.data_ptr() if coef_grad else None,
+                                       gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
+                                       gb.data_ptr() if gb is not None else None, C.byref(o)), "biharmonic_adjoint")
+    return (lam, ga, gb, inf) if inf is not None else (lam, ga, gb)
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+class HelmholtzSolve(torch.autograd.Function):
+    """u = (S + alpha B)^{-1} f with a hand-written adjoint:
+    grad_f = H^{-T} grad_u, grad_alpha = -Re(grad_f^H B u)."""
+
+    @staticmethod
+    def forward(ctx, f, alpha, quad="gc"):
+        u = helmholtz_solve(f.contiguous(), alpha.contiguous(), quad=quad)
+        ctx.save_for_backward(u, alpha)
+        ctx.quad = quad
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        u, alpha = ctx.saved_tensors
+        need_c = ctx.needs_input_grad[1]
+        lam, ga = helmholtz_adjoint(u, gu.contiguous(), alpha, quad=ctx.quad, coef_grad=need_c)
+        return (lam if ctx.needs_input_grad[0] else None), (ga if need_c else None), None
+
+
+class BiharmonicSolve(torch.autograd.Function):
+    """u = (Q + a A + b B)^{-1} f with a hand-written adjoint:
+    grad_f = H^{-T} grad_u, grad_a = -Re(grad_f^H A u), grad_b = -Re(grad_f^H B u)."""
+
+    @staticmethod
+    def forward(ctx, f, a, b, quad="gc"):
+        u = biharmonic_solve(f.contiguous(), a.contiguous(), b.contiguous(), quad=quad)
+        ctx.save_for_backward(u, a, b)
+        ctx.quad = quad
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        u, a, b = ctx.saved_tensors
+        need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        lam, ga, gb = biharmonic_adjoint(u, gu.contiguous(), a, b, quad=ctx.quad, coef_grad=need_c)
+        return ((lam if ctx.needs_input_grad[0] else None), (ga if ctx.needs_input_grad[1] else None),
+                (gb if ctx.needs_input_grad[2] else None), None)
+
+
+def helmholtz(f, alpha, quad="gc"):
+    """Differentiable Helmholtz solve (torch.autograd)."""
+    return HelmholtzSolve.apply(f, alpha, quad)
+
+
+def biharmonic(f, a, b, quad="gc"):
+    """Differentiable biharmonic solve (torch.autograd)."""
+    return BiharmonicSolve.apply(f, a, b, quad)

@@ -1,0 +1,312 @@
+// C-ABI layer: argument validation, kernel selection, launch on the caller's
+// stream.  See include/shenhip.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+
+#include "shen_launch.hpp"
+#include "shenhip.h"
+
+namespace {
+
+using shen::ChainArgs;
+using shen::ChainKind;
+
+struct DevInfo {
+  size_t lds_max = 0;  // max dynamic LDS per workgroup
+  int ok = 0;
+};
+
+constexpr int kMaxDevices = 64;
+DevInfo g_dev[kMaxDevices];
+std::mutex g_dev_mu;
+
+// Fills the per-device table on first use.  Returns SHEN_OK or SHEN_EDEVICE.
+int device_info(DevInfo* out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SHEN_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  if (!g_dev[dev].ok) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return SHEN_EDEVICE;
+    g_dev[dev].lds_max = (size_t)v;
+    g_dev[dev].ok = 1;
+  }
+  *out = g_dev[dev];
+  return SHEN_OK;
+}
+
+inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+shen_opts resolve(const shen_opts* o) {
+  shen_opts r;
+  shen_opts_default(&r);
+  if (o) r = *o;
+  if (r.refine_max <= 0) r.refine_max = 8;
+  if (!(r.refine_tol > 0.0)) r.refine_tol = 1e-14;
+  return r;
+}
+
+int check_opts(const shen_opts& o) {
+  if (o.precision != SHEN_FP64 && o.precision != SHEN_FP32_REFINE) return SHEN_EINVAL;
+  if (o.quad != SHEN_QUAD_GC && o.quad != SHEN_QUAD_GL) return SHEN_EINVAL;
+  if (o.transpose != 0 && o.transpose != 1) return SHEN_EINVAL;
+  if (o.variant < 0 || o.variant > 2) return SHEN_EINVAL;
+  if (o.info && !aligned(o.info, 4)) return SHEN_EINVAL;
+  if (o.refine_max > 64) return SHEN_EINVAL;
+  return SHEN_OK;
+}
+
+bool rows_overlap_partially(const void* a, const void* b, int64_t nsys, int32_t N) {
+  if (a == b) return false;
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  const uintptr_t len = (uintptr_t)nsys * (uintptr_t)N * 16u;
+  return pa < pb + len && pb < pa + len;
+}
+
+int check_rows(const void* p) { return (p && aligned(p, 16)) ? SHEN_OK : SHEN_EINVAL; }
+int check_coef(const void* p) { return (p && aligned(p, 8)) ? SHEN_OK : SHEN_EINVAL; }
+
+int lds_budget_for(ChainKind kind, int N, const DevInfo& d, size_t* budget) {
+  const size_t per = shen::chain_bytes_per_system(kind, N) + 4;
+  if (per > d.lds_max) return SHEN_ENOTSUP;
+  size_t b = 65536;
+  if (b > d.lds_max) b = d.lds_max;
+  if (per > b) b = per;  // one system per block, up to the device limit
+  *budget = b;
+  return SHEN_OK;
+}
+
+int run(ChainArgs& a) {
+  DevInfo d;
+  int rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  rc = lds_budget_for(a.kind, a.N, d, &a.lds_budget);
+  if (rc != SHEN_OK) return rc;
+  return shen::launch_chain(a) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+}
+
+int32_t max_n_for(ChainKind kind, const DevInfo& d) {
+  int32_t lo = 5, hi = 1 << 20;
+  while (lo < hi) {  // largest N with one system fitting
+    const int32_t mid = lo + (hi - lo + 1) / 2;
+    if (shen::chain_bytes_per_system(kind, mid) + 4 <= d.lds_max)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+extern "C" {
+
+void shen_opts_default(shen_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = SHEN_FP64;
+  o->quad = SHEN_QUAD_GC;
+  o->refine_max = 8;
+  o->refine_tol = 1e-14;
+}
+
+int shen_abi_version(void) { return SHENHIP_ABI_VERSION; }
+
+const char* shen_status_string(int code) {
+  switch (code) {
+    case SHEN_OK: return "ok";
+    case SHEN_EINVAL: return "invalid argument";
+    case SHEN_ELAUNCH: return "kernel launch failed";
+    case SHEN_ENOTSUP: return "size not supported by this kernel on this device";
+    case SHEN_EDEVICE: return "no usable HIP device";
+    default: return "unknown status";
+  }
+}
+
+int32_t shen_max_n(int32_t family, int32_t precision) {
+  DevInfo d;
+  if (device_info(&d) != SHEN_OK) return SHEN_EDEVICE;
+  ChainKind k;
+  if (family == SHEN_HELMHOLTZ)
+    k = precision == SHEN_FP32_REFINE ? ChainKind::HelmMixed : ChainKind::HelmSolve;
+  else if (family == SHEN_BIHARMONIC)
+    k = precision == SHEN_FP32_REFINE ? ChainKind::BihMixed : ChainKind::BihSolve;
+  else
+    return SHEN_EINVAL;
+  return max_n_for(k, d);
+}
+
+int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
+  if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
+  if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  ChainArgs a;
+  a.kind = o.transpose ? ChainKind::HelmAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::HelmMixed : ChainKind::HelmSolve);
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = alpha;
+  a.f = f;
+  a.u = u;
+  a.info = o.info;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.it_max = o.refine_max;
+  a.tol = o.refine_tol;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb, const shen_c128* f, shen_c128* u,
+                     const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
+  if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
+  if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  ChainArgs a;
+  a.kind = o.transpose ? ChainKind::BihAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::BihMixed : ChainKind::BihSolve);
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = ca;
+  a.c1 = cb;
+  a.f = f;
+  a.u = u;
+  a.info = o.info;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.it_max = o.refine_max;
+  a.tol = o.refine_tol;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int helmholtz_adjoint(int32_t N, int64_t nsys, const double* alpha, const shen_c128* u, const shen_c128* gbar, shen_c128* lambda,
+                      double* grad_alpha, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(gbar) || check_rows(lambda) || check_coef(alpha)) return SHEN_EINVAL;
+  if (grad_alpha && (check_rows(u) || !aligned(grad_alpha, 8))) return SHEN_EINVAL;
+  if (rows_overlap_partially(gbar, lambda, nsys, N)) return SHEN_EINVAL;
+  if (u && (u == lambda || rows_overlap_partially(u, lambda, nsys, N))) return SHEN_EINVAL;
+  ChainArgs a;
+  a.kind = ChainKind::HelmAdjoint;
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = alpha;
+  a.f = gbar;
+  a.u = lambda;
+  a.ufwd = grad_alpha ? u : nullptr;
+  a.g0 = grad_alpha;
+  a.info = o.info;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int biharmonic_adjoint(int32_t N, int64_t nsys, const double* ca, const double* cb, const shen_c128* u, const shen_c128* gbar,
+                       shen_c128* lambda, double* grad_a, double* grad_b, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(gbar) || check_rows(lambda) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
+  const bool grads = grad_a || grad_b;
+  if (grads && check_rows(u)) return SHEN_EINVAL;
+  if ((grad_a && !aligned(grad_a, 8)) || (grad_b && !aligned(grad_b, 8))) return SHEN_EINVAL;
+  if (rows_overlap_partially(gbar, lambda, nsys, N)) return SHEN_EINVAL;
+  if (u && (u == lambda || rows_overlap_partially(u, lambda, nsys, N))) return SHEN_EINVAL;
+  ChainArgs a;
+  a.kind = ChainKind::BihAdjoint;
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = ca;
+  a.c1 = cb;
+  a.f = gbar;
+  a.u = lambda;
+  a.ufwd = grads ? u : nullptr;
+  a.g0 = grad_a;
+  a.g1 = grad_b;
+  a.info = o.info;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int helmholtz_matvec(int32_t N, int64_t nsys, const double* alpha, const shen_c128* u, shen_c128* Hu, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(u) || check_rows(Hu) || check_coef(alpha)) return SHEN_EINVAL;
+  if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
+  ChainArgs a;
+  a.kind = ChainKind::HelmMatvec;
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = alpha;
+  a.f = u;
+  a.u = Hu;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.trans = o.transpose;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* cb, const shen_c128* u, shen_c128* Hu,
+                      const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(u) || check_rows(Hu) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
+  if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
+  ChainArgs a;
+  a.kind = ChainKind::BihMatvec;
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = ca;
+  a.c1 = cb;
+  a.f = u;
+  a.u = Hu;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.trans = o.transpose;
+  a.stream = o.stream;
+  return run(a);
+}
+
+int64_t shen_batched_plan(shen_problem* desc_host, int32_t ndesc, const shen_opts* opts) {
+  (void)desc_host;
+  (void)ndesc;
+  (void)opts;
+  return SHEN_ENOTSUP;
+}
+
+int64_t shen_batched_work_bytes(int32_t ndesc) { return ndesc < 0 ? SHEN_EINVAL : 256; }
+
+int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work, const shen_opts* opts) {
+  (void)desc;
+  (void)ndesc;
+  (void)tiles_total;
+  (void)maxN;
+  (void)work;
+  (void)opts;
+  return SHEN_ENOTSUP;
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Host-side launch interface shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace shen {
+
+enum class ChainKind { HelmSolve, HelmAdjoint, HelmMatvec, HelmMixed, BihSolve, BihAdjoint, BihMatvec, BihMixed };
+
+struct ChainArgs {
+  ChainKind kind;
+  int N = 0;
+  int64_t nsys = 0;
+  const double* c0 = nullptr;  // alpha or a
+  const double* c1 = nullptr;  // b
+  const void* f = nullptr;     // input rows (f, gbar or u)
+  void* u = nullptr;           // output rows (u, lambda or Hu)
+  const void* ufwd = nullptr;  // adjoint: forward solution (for coefficient gradients)
+  double* g0 = nullptr;        // adjoint: grad alpha / grad a
+  double* g1 = nullptr;        // adjoint: grad b
+  int32_t* info = nullptr;
+  int gl = 0;
+  int trans = 0;
+  int it_max = 8;
+  double tol = 1e-14;
+  size_t lds_budget = 65536;
+  void* stream = nullptr;
+};
+
+size_t chain_bytes_per_system(ChainKind kind, int N);
+int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);
+hipError_t launch_chain(const ChainArgs& a);
+
+}  // namespace shen

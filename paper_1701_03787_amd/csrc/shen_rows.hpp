@@ -1,0 +1,173 @@
+// Row entries of the wall-normal Galerkin matrices, evaluated on the fly in
+// device code (nothing is tabulated in memory).
+//
+// Row k (test function phi_k), column j (trial function phi_j).
+//
+// Helmholtz, S + alpha B in the Dirichlet basis phi_k = T_k - T_{k+2}:
+//   B_kk = pi/2 (c_k + c_{k+2}), B_{k,k+-2} = -pi/2       (appendix matrix table)
+//   S_kk = 2 pi (k+1)(k+2), S_kj = 4 pi (k+1), j = k+2, k+4, ...
+//   (S = -(phi_j'', phi_k): the paper refers to Shen 1995 for it; the entries
+//   follow from the Chebyshev second-derivative coefficients.)
+// so row k has H_{k,k-2} = hm = -alpha pi/2, H_kk = h0, H_{k,k+2} = hpp + hm
+// and H_kj = hpp = 4 pi (k+1) for every j >= k+4 of the same parity.
+//
+// Biharmonic, Q + a A + b B in phi_k = T_k - 2(k+2)/(k+3) T_{k+2}
+// + (k+1)/(k+3) T_{k+4}:
+//   B: five diagonals (appendix matrix table), A = (phi_j'', phi_k): three
+//   diagonals (Sec. 4), Q = (phi_j'''', phi_k): upper triangular with
+//   Q_kj = p_k q_j + r_k s_j for j >= k+2 (Sec. 4, eqs. for p_k, q_j, r_k, s_j)
+//   and Q_kk = 8 pi (k+1)^2 (k+2)(k+4), the value the definition gives.
+//
+// c_0 = 2, c_k = 1 otherwise, c_{N-1} = 2 for Gauss-Lobatto quadrature.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shen {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+__device__ __forceinline__ double ck(int k, int N, int gl) { return (k == 0 || (gl && k == N - 1)) ? 2.0 : 1.0; }
+
+// ----------------------------------------------------------------- Helmholtz
+struct HelmRow {
+  double hm;   // H_{k,k-2}
+  double h0;   // H_{k,k}
+  double hpp;  // H_{k,j}, j >= k+4 ; H_{k,k+2} = hpp + hm
+};
+
+__device__ __forceinline__ HelmRow helm_row(int k, double alpha, int N, int gl) {
+  const double ha = 0.5 * kPi * alpha;
+  const double kk = (double)k;
+  HelmRow h;
+  h.hm = -ha;
+  h.h0 = 2.0 * kPi * ((kk + 1.0) * (kk + 2.0)) + ha * (ck(k, N, gl) + ck(k + 2, N, gl));
+  h.hpp = 4.0 * kPi * (kk + 1.0);
+  return h;
+}
+
+// Dirichlet mass row: (B u)_k = bd0 u_k + bdo (u_{k-2} + u_{k+2})
+__device__ __forceinline__ double helm_mass_diag(int k, int N, int gl) {
+  return 0.5 * kPi * (ck(k, N, gl) + ck(k + 2, N, gl));
+}
+
+// ---------------------------------------------------------------- biharmonic
+// Reciprocals 1/(k+m), m = -1, 1, 3, 5, 7.  A parity chain steps k by 2, so
+// advancing the window costs one new division per row.
+struct Recip {
+  double m1, p1, p3, p5, p7;
+  __device__ __forceinline__ void init(int k) {
+    const double kk = (double)k;
+    m1 = (k == 1) ? 0.0 : 1.0 / (kk - 1.0);  // only used for k >= 4
+    p1 = 1.0 / (kk + 1.0);
+    p3 = 1.0 / (kk + 3.0);
+    p5 = 1.0 / (kk + 5.0);
+    p7 = 1.0 / (kk + 7.0);
+  }
+  __device__ __forceinline__ void advance(int knew) {  // from k to knew = k + 2
+    m1 = p1;
+    p1 = p3;
+    p3 = p5;
+    p5 = p7;
+    p7 = 1.0 / ((double)knew + 7.0);
+  }
+  __device__ __forceinline__ void retreat(int knew) {  // from k to knew = k - 2
+    p7 = p5;
+    p5 = p3;
+    p3 = p1;
+    p1 = m1;
+    m1 = (knew == 1) ? 0.0 : 1.0 / ((double)knew - 1.0);
+  }
+};
+
+// Raw matrix entries of row k.
+struct BihMats {
+  double Bm4, Bm2, B0, B2, B4;  // B_{k,k-4}, B_{k,k-2}, B_kk, B_{k,k+2}, B_{k,k+4}
+  double Am2, A0, A2;           // A_{k,k-2}, A_kk, A_{k,k+2}
+  double Q0, Q2, Q4;            // Q_kk, Q_{k,k+2}, Q_{k,k+4}
+  double p, r;                  // tail generators of row k
+  double q2, s2, q4, s4;        // q_{k+2}, s_{k+2}, q_{k+4}, s_{k+4}
+};
+
+__device__ __forceinline__ BihMats bih_mats(int k, int N, int gl, const Recip& R) {
+  const double K = (double)k;
+  const double g1 = (K + 2.0) * R.p3;  // (k+2)/(k+3)
+  const double g2 = (K + 1.0) * R.p3;  // (k+1)/(k+3)
+  BihMats m;
+  m.B0 = 0.5 * kPi * (ck(k, N, gl) + 4.0 * g1 * g1 + ck(k + 4, N, gl) * g2 * g2);
+  m.B2 = -kPi * (g1 + (K + 4.0) * R.p5 * g2);
+  m.B4 = 0.5 * kPi * g2;
+  // B_{k,k-2} = B_{k-2,k}: -pi (k/(k+1) + (k+2)(k-1)/((k+3)(k+1)))
+  m.Bm2 = (k >= 2) ? -kPi * (K * R.p1 + (K + 2.0) * (K - 1.0) * R.p3 * R.p1) : 0.0;
+  // B_{k,k-4} = B_{k-4,k}: pi/2 (k-3)/(k-1)
+  m.Bm4 = (k >= 4) ? 0.5 * kPi * (K - 3.0) * R.m1 : 0.0;
+  m.A0 = -4.0 * kPi * (K + 1.0) * (K + 2.0) * g1;
+  m.A2 = 2.0 * kPi * (K + 1.0) * (K + 2.0);
+  m.Am2 = (k >= 2) ? 2.0 * kPi * (K - 1.0) * (K + 2.0) : 0.0;
+  m.p = 8.0 * kPi * K * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  m.r = 24.0 * kPi * (K + 1.0) * (K + 2.0);
+  m.q2 = R.p5;
+  m.s2 = (K + 4.0) * (K + 4.0) * R.p5;
+  m.q4 = R.p7;
+  m.s4 = (K + 6.0) * (K + 6.0) * R.p7;
+  m.Q0 = 8.0 * kPi * (K + 1.0) * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  m.Q2 = m.p * m.q2 + m.r * m.s2;
+  m.Q4 = m.p * m.q4 + m.r * m.s4;
+  return m;
+}
+
+struct BihRow {
+  double hm4, hm2, h0, hp2, hp4;  // H_{k,k-4} .. H_{k,k+4}
+  double p, r;                    // tail: H_kj = p q_j + r s_j, j >= k+6
+  double q2, s2, q4, s4;
+};
+
+__device__ __forceinline__ BihRow bih_row(int k, double a, double b, int N, int gl, const Recip& R) {
+  const BihMats m = bih_mats(k, N, gl, R);
+  BihRow h;
+  h.hm4 = b * m.Bm4;
+  h.hm2 = a * m.Am2 + b * m.Bm2;
+  h.h0 = m.Q0 + a * m.A0 + b * m.B0;
+  h.hp2 = m.Q2 + a * m.A2 + b * m.B2;
+  h.hp4 = m.Q4 + b * m.B4;
+  h.p = m.p;
+  h.r = m.r;
+  h.q2 = m.q2;
+  h.s2 = m.s2;
+  h.q4 = m.q4;
+  h.s4 = m.s4;
+  return h;
+}
+
+// q_j, s_j of the Q tail
+__device__ __forceinline__ double q_of(int j) { return 1.0 / ((double)j + 3.0); }
+__device__ __forceinline__ double s_of(int j) {
+  const double jj = (double)j;
+  return (jj + 2.0) * (jj + 2.0) / (jj + 3.0);
+}
+
+// ------------------------------------------------------------------ complex
+template <typename T2, typename R>
+__device__ __forceinline__ T2 c_fnms(R s, T2 b, T2 a) {  // a - s b
+  T2 o;
+  o.x = __builtin_fma(-s, b.x, a.x);
+  o.y = __builtin_fma(-s, b.y, a.y);
+  return o;
+}
+__device__ __forceinline__ float2 c_fnms(float s, float2 b, float2 a) {
+  return make_float2(__builtin_fmaf(-s, b.x, a.x), __builtin_fmaf(-s, b.y, a.y));
+}
+__device__ __forceinline__ double2 c_fma(double s, double2 b, double2 a) {  // a + s b
+  return make_double2(__builtin_fma(s, b.x, a.x), __builtin_fma(s, b.y, a.y));
+}
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_mul(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double c_abs1(double2 a) { return fmax(fabs(a.x), fabs(a.y)); }
+__device__ __forceinline__ double c_absf(float2 a) { return fmax(fabs((double)a.x), fabs((double)a.y)); }
+__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+
+__device__ __forceinline__ bool bad_pivot(double d) { return !(fabs(d) > 0.0) || !isfinite(d); }
+
+}  // namespace shen

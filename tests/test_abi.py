@@ -1,0 +1,96 @@
+"""Host-only checks of the C-ABI library: it loads, exports every declared entry
+point, and rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1701_03787_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "shenhip.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in {"if", "defined"}))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    declared = _declared()
+    assert len(declared) >= 13
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == {s[0] for s in L.SIGNATURES}
+
+
+def test_version_and_strings():
+    lib = L.lib()
+    assert lib.shen_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, 7):
+        assert isinstance(lib.shen_status_string(code), bytes)
+    o = L.default_opts()
+    assert o.precision == 0 and o.quad == 0 and o.transpose == 0 and o.refine_max == 8
+    assert o.refine_tol == pytest.approx(1e-14)
+    assert C.sizeof(L.ShenOpts) == 48
+    assert C.sizeof(L.ShenProblem) == 72
+
+
+ALIGNED = 1 << 20  # never dereferenced: validation fails first or there is no device
+
+
+@pytest.mark.parametrize("args,code", [
+    ((2, 4, ALIGNED, ALIGNED, ALIGNED), L.SHEN_EINVAL),           # N < 3
+    ((16, -1, ALIGNED, ALIGNED, ALIGNED), L.SHEN_EINVAL),         # nsys < 0
+    ((16, 4, None, ALIGNED, ALIGNED), L.SHEN_EINVAL),             # NULL alpha
+    ((16, 4, ALIGNED, None, ALIGNED), L.SHEN_EINVAL),             # NULL f
+    ((16, 4, ALIGNED, ALIGNED + 8, ALIGNED + 4096), L.SHEN_EINVAL),  # misaligned f
+    ((16, 4, ALIGNED + 4, ALIGNED, ALIGNED + 4096), L.SHEN_EINVAL),  # misaligned alpha
+    ((16, 4, ALIGNED, ALIGNED, ALIGNED + 16), L.SHEN_EINVAL),     # partial overlap f/u
+    ((16, 0, None, None, None), L.SHEN_OK),                       # empty batch: nothing to do
+])
+def test_helmholtz_argument_errors(args, code):
+    lib = L.lib()
+    o = L.default_opts()
+    assert lib.helmholtz_solve(*args, C.byref(o)) == code
+
+
+def test_bad_enums_and_sizes():
+    lib = L.lib()
+    for field, val in (("precision", 5), ("quad", 2), ("transpose", 3), ("variant", 9), ("refine_max", 1000)):
+        o = L.default_opts()
+        setattr(o, field, val)
+        assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL, field
+        assert lib.biharmonic_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL, field
+    o = L.default_opts()
+    assert lib.biharmonic_solve(4, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+    o.info = ALIGNED + 2
+    assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+    o = L.default_opts()
+    o.precision = L.SHEN_FP32_REFINE
+    o.transpose = 1
+    assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_ENOTSUP
+    # matvec output may not alias its input; adjoint lambda may not alias u
+    o = L.default_opts()
+    assert lib.helmholtz_matvec(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.biharmonic_matvec(16, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.helmholtz_adjoint(16, 4, ALIGNED, ALIGNED, ALIGNED + 4096, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+
+
+def test_valid_call_without_device_reports_device_error():
+    """With valid arguments and no GPU the library says so instead of crashing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    lib = L.lib()
+    o = L.default_opts()
+    rc = lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED + (1 << 16), C.byref(o))
+    assert rc == L.SHEN_EDEVICE
+
+
+def test_null_opts_uses_defaults():
+    lib = L.lib()
+    assert lib.helmholtz_solve(2, 4, ALIGNED, ALIGNED, ALIGNED, None) == L.SHEN_EINVAL

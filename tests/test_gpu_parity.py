@@ -1,0 +1,158 @@
+"""GPU parity: the HIP library (through the C-ABI) against the CPU oracle.
+
+Bar: per-system relative max-norm error <= 1e-12 (the accuracy target of the
+plain and refined paths); bit-exact for integer outputs (info codes) and for
+the zero tail.
+"""
+import numpy as np
+import pytest
+
+from oracle import shen_oracle as so
+from paper_1701_03787_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1701_03787_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def gpu_solve(family, N, coeffs, f, dev, **kw):
+    from paper_1701_03787_amd import api
+    ft = T(f, dev)
+    cs = [T(c, dev) for c in coeffs]
+    if family == "helmholtz":
+        out = api.helmholtz_solve(ft, cs[0], **kw)
+    else:
+        out = api.biharmonic_solve(ft, cs[0], cs[1], **kw)
+    torch.cuda.synchronize()
+    if isinstance(out, tuple):
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+def _print_case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+SMALL_N = {
+    "helmholtz": [3, 4, 5, 6, 7, 8, 9, 10, 17, 33, 64, 65, 128, 255, 256, 257, 512, 1024],
+    "biharmonic": [5, 6, 7, 8, 9, 10, 11, 12, 17, 33, 64, 65, 128, 255, 256, 257, 512, 1024],
+}
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("gl", [False, True])
+def test_parity_sizes(dev, family, gl):
+    """Every small and ragged N, tiles that do not divide nsys, GC and GL."""
+    for N in SMALL_N[family]:
+        for nsys in (1, 3, 37):
+            _print_case(test="sizes", family=family, N=N, nsys=nsys, gl=gl)
+            g = wl.small_grid(N, nsys, kmax=200, index=N)
+            coeffs = g.coefficients(family)
+            f = g.rhs(family)
+            quad = so.GL if gl else so.GC
+            ref = so.solve(family, N, coeffs, f, quad=quad)
+            u = gpu_solve(family, N, coeffs, f, dev, quad="gl" if gl else "gc")
+            n = wl.n_unknowns(family, N)
+            assert np.all(u[:, n:] == 0)
+            e = so.rel_err_per_system(u, ref)
+            assert e.max() <= TOL, (N, nsys, e.max())
+
+
+def test_config1_full(dev):
+    g = wl.config_grids(1)[0]
+    _print_case(test="config1", N=g.N, nsys=g.nsys)
+    f = g.rhs("helmholtz")
+    ref = so.helmholtz_solve(g.N, g.alpha(), f)
+    u = gpu_solve("helmholtz", g.N, (g.alpha(),), f, dev)
+    assert so.rel_err_per_system(u, ref).max() <= TOL
+
+
+@pytest.mark.parametrize("config", [2, 3, 5])
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_config_full_size_sampled(dev, config, family):
+    """Full-size launch; the oracle checks a sample of systems (first, last, K2 = 0,
+    the largest K2, and random rows)."""
+    g = wl.config_grids(config)[0]
+    _print_case(test="config", config=config, family=family, N=g.N, nsys=g.nsys)
+    coeffs = g.coefficients(family)
+    f = g.rhs(family)
+    u = gpu_solve(family, g.N, coeffs, f, dev)
+    rng = np.random.default_rng([1701, config, 3])
+    K2 = g.K2
+    rows = np.unique(np.concatenate([[0, g.nsys - 1, int(np.argmin(K2)), int(np.argmax(K2))],
+                                     rng.choice(g.nsys, 60, replace=False)]))
+    ref = so.solve(family, g.N, tuple(c[rows] for c in coeffs), f[rows])
+    e = so.rel_err_per_system(u[rows], ref)
+    assert e.max() <= TOL, e.max()
+    n = wl.n_unknowns(family, g.N)
+    assert np.all(u[:, n:] == 0)
+    assert np.all(np.isfinite(u))
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_in_place_tail_and_determinism(dev, family):
+    from paper_1701_03787_amd import api
+    N, nsys = 130, 45
+    g = wl.small_grid(N, nsys)
+    coeffs = g.coefficients(family)
+    f = g.rhs(family)
+    n = wl.n_unknowns(family, N)
+    fbad = f.copy()
+    fbad[:, n:] = np.nan  # entries k >= n must not be read
+    ref = so.solve(family, N, coeffs, f)
+    _print_case(test="inplace", family=family, N=N, nsys=nsys)
+    ft = T(fbad, dev)
+    cs = [T(c, dev) for c in coeffs]
+    if family == "helmholtz":
+        u1 = api.helmholtz_solve(ft, cs[0])
+        api.helmholtz_solve(ft, cs[0], out=ft)  # in place
+        u2 = api.helmholtz_solve(T(fbad, dev), cs[0])
+    else:
+        u1 = api.biharmonic_solve(ft, cs[0], cs[1])
+        api.biharmonic_solve(ft, cs[0], cs[1], out=ft)
+        u2 = api.biharmonic_solve(T(fbad, dev), cs[0], cs[1])
+    torch.cuda.synchronize()
+    u1, u2, u3 = u1.cpu().numpy(), u2.cpu().numpy(), ft.cpu().numpy()
+    assert np.all(u1[:, n:] == 0) and np.all(u3[:, n:] == 0)
+    assert so.rel_err_per_system(u1, ref).max() <= TOL
+    assert np.array_equal(u1.view(np.uint64), u2.view(np.uint64))  # bitwise rerun
+    assert np.array_equal(u1.view(np.uint64), u3.view(np.uint64))  # in place == out of place
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_info_codes(dev, family):
+    N, nsys = 40, 6
+    g = wl.small_grid(N, nsys)
+    coeffs = [c.copy() for c in g.coefficients(family)]
+    coeffs[0][2] = np.nan  # first pivot of system 2 is NaN
+    f = g.rhs(family)
+    _print_case(test="info", family=family)
+    u, info = gpu_solve(family, N, coeffs, f, dev, info=True)
+    expect = np.zeros(nsys, np.int32)
+    expect[2] = 1
+    assert np.array_equal(info, expect)
+    ok = np.arange(nsys) != 2
+    ref = so.solve(family, N, tuple(c[ok] for c in coeffs), f[ok])
+    assert so.rel_err_per_system(u[ok], ref).max() <= TOL
+
+
+def test_empty_batch(dev):
+    from paper_1701_03787_amd import api
+    f = torch.zeros((0, 32), dtype=torch.complex128, device=dev)
+    a = torch.zeros((0,), dtype=torch.float64, device=dev)
+    assert api.helmholtz_solve(f, a).shape == (0, 32)
+    assert api.biharmonic_solve(f, a, a).shape == (0, 32)
