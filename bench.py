@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--variant", default="auto")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -168,6 +170,13 @@ def main():
         "cpu_baseline": cpu,
         "mixed_fp32_refine": mixed,
     }
+    if args.probe_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = int(x.numel() * 8)
     print(json.dumps(out), flush=True)
 
 
