@@ -89,6 +89,22 @@ int run(ChainArgs& a) {
   return shen::launch_chain(a) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
 }
 
+// The wave path serves plain FP64 forward solves out of place (it parks the LU
+// restart states in u); everything else, and sizes it does not cover, goes to
+// the chain kernels.
+bool use_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
+  if (o.variant == SHEN_VARIANT_CHAIN) return false;
+  if (o.variant == SHEN_VARIANT_WAVE) return true;  // caller insists: unsupported -> ENOTSUP
+  return o.precision == SHEN_FP64 && !o.transpose && f != u && shen::wave_supported(family, N);
+}
+
+int run_wave(const shen::WaveArgs& w) {
+  DevInfo d;
+  const int rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  return shen::launch_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+}
+
 int32_t max_n_for(ChainKind kind, const DevInfo& d) {
   int32_t lo = 5, hi = 1 << 20;
   while (lo < hi) {  // largest N with one system fitting
@@ -149,6 +165,20 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_wave(o, 0, N, f, u)) {
+    if (!shen::wave_supported(0, N) || f == (const void*)u) return SHEN_ENOTSUP;
+    shen::WaveArgs w;
+    w.family = 0;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = alpha;
+    w.f = f;
+    w.u = u;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    return run_wave(w);
+  }
   ChainArgs a;
   a.kind = o.transpose ? ChainKind::HelmAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::HelmMixed : ChainKind::HelmSolve);
   a.N = N;
@@ -174,6 +204,21 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_wave(o, 1, N, f, u)) {
+    if (!shen::wave_supported(1, N) || f == (const void*)u) return SHEN_ENOTSUP;
+    shen::WaveArgs w;
+    w.family = 1;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = ca;
+    w.c1 = cb;
+    w.f = f;
+    w.u = u;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    return run_wave(w);
+  }
   ChainArgs a;
   a.kind = o.transpose ? ChainKind::BihAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::BihMixed : ChainKind::BihSolve);
   a.N = N;

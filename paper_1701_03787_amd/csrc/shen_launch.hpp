@@ -29,6 +29,22 @@ struct ChainArgs {
   void* stream = nullptr;
 };
 
+struct WaveArgs {
+  int family = 0;  // 0 Helmholtz, 1 biharmonic
+  int N = 0;
+  int64_t nsys = 0;
+  const double* c0 = nullptr;
+  const double* c1 = nullptr;
+  const void* f = nullptr;
+  void* u = nullptr;  // must not alias f (restart states are parked in it)
+  int32_t* info = nullptr;
+  int gl = 0;
+  void* stream = nullptr;
+};
+
+bool wave_supported(int family, int N);
+hipError_t launch_wave(const WaveArgs& a);
+
 size_t chain_bytes_per_system(ChainKind kind, int N);
 int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);
 hipError_t launch_chain(const ChainArgs& a);

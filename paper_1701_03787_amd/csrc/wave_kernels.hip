@@ -1,0 +1,605 @@
+// "Wave" kernels: one system spread over 2G lanes of a wavefront, held in
+// registers, in a single pass over HBM.
+//
+// Each odd/even chain of a system (Sec. 4) is cut into G chunks of C
+// consecutive chain elements; lane (p, m) owns chunk m of chain p.
+//
+//  1. A boundary kernel (one lane per chain, no data) runs the exact LU
+//     recurrence of the chain and writes, at the start of every chunk, the
+//     state the recurrence needs to restart there (Helmholtz: 1/d and g of
+//     the previous row; biharmonic: the two previous reduced rows of U).
+//     The states are parked in the output row u[w], which the solve
+//     overwrites afterwards (so this path needs u != f).
+//  2. The solve kernel restarts the factorisation at its chunk start (the
+//     same arithmetic as the boundary kernel, so the factors are the ones of
+//     the sequential LU), then solves L y = f and U u = y.  Both are affine
+//     recurrences; per chunk they are summarised as an affine map (forward:
+//     2x2 / scalar transfer, backward: 4x4 / 2x2) and the maps are combined
+//     across lanes by a Kogge-Stone scan; each lane then reruns its chunk
+//     from the scanned incoming state.
+//
+// Rows k >= n ("padding" at the end of a chain) get zero factors, which
+// makes their maps finite and their contribution exactly zero.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "shen_launch.hpp"
+#include "shen_rows.hpp"
+
+namespace shen {
+
+// ----------------------------------------------------------------- helpers
+template <typename T>
+__device__ __forceinline__ T shfl_up_w(T v, int d, int w) {
+  return __shfl_up(v, (unsigned)d, w);
+}
+template <typename T>
+__device__ __forceinline__ T shfl_down_w(T v, int d, int w) {
+  return __shfl_down(v, (unsigned)d, w);
+}
+__device__ __forceinline__ double2 shfl_up2(double2 v, int d, int w) {
+  return make_double2(__shfl_up(v.x, (unsigned)d, w), __shfl_up(v.y, (unsigned)d, w));
+}
+__device__ __forceinline__ double2 shfl_down2(double2 v, int d, int w) {
+  return make_double2(__shfl_down(v.x, (unsigned)d, w), __shfl_down(v.y, (unsigned)d, w));
+}
+
+// One Helmholtz LU row step (shared by boundary and solve kernels so that the
+// restarted factorisation reproduces the sequential one exactly).
+struct HelmPrev {
+  double rd, g;  // 1/d and g of row k-2 (ignored for k < 2)
+};
+__device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const HelmPrev& pv, double& l, double& g, double& rd,
+                                          double& d) {
+  const HelmRow h = helm_row(k, al, N, gl);
+  if (k < 2) {
+    l = 0.0;
+    d = h.h0;
+    g = h.hpp;
+  } else {
+    l = h.hm * pv.rd;
+    d = __builtin_fma(-l, pv.g + h.hm, h.h0);
+    g = __builtin_fma(-l, pv.g, h.hpp);
+  }
+  rd = 1.0 / d;
+}
+
+// One biharmonic LU row step: row k reduced by rows k-4 (m4) and k-2 (m2).
+struct BihRowState {
+  double rU0, U2, U4, P, R;
+};
+__device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
+                                         const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
+  const BihRow h = bih_row(k, a, b, N, gl, Rc);
+  double tm2 = h.hm2, t0 = h.h0, t2 = h.hp2, t4 = h.hp4, P = h.p, Rr = h.r;
+  l1 = 0.0;
+  l2 = 0.0;
+  if (k >= 4) {
+    l2 = h.hm4 * m4.rU0;
+    tm2 = __builtin_fma(-l2, m4.U2, tm2);
+    t0 = __builtin_fma(-l2, m4.U4, t0);
+    t2 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q2, m4.R * h.s2), t2);
+    t4 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q4, m4.R * h.s4), t4);
+    P = __builtin_fma(-l2, m4.P, P);
+    Rr = __builtin_fma(-l2, m4.R, Rr);
+  }
+  if (k >= 2) {
+    l1 = tm2 * m2.rU0;
+    t0 = __builtin_fma(-l1, m2.U2, t0);
+    t2 = __builtin_fma(-l1, m2.U4, t2);
+    t4 = __builtin_fma(-l1, __builtin_fma(m2.P, h.q4, m2.R * h.s4), t4);
+    P = __builtin_fma(-l1, m2.P, P);
+    Rr = __builtin_fma(-l1, m2.R, Rr);
+  }
+  o.rU0 = 1.0 / t0;
+  o.U2 = t2;
+  o.U4 = t4;
+  o.P = P;
+  o.R = Rr;
+  t0out = t0;
+}
+
+// =========================================================================
+// Boundary kernels: one thread per chain.
+// =========================================================================
+
+// States parked in u[w] (as doubles): Helmholtz [(p*G + m)*2 + {0,1}] = (1/d, g)
+// of row 2(mC)-2+p; biharmonic [(p*G + m)*10 + ...] = rows k-2 then k-4.
+__global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
+                                                     double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  const int p = (int)(t & 1);
+  const int n = N - 2;
+  const int nc = (n - p + 1) / 2;  // elements in this chain
+  const int nchunks = (nc + C - 1) / C;
+  if (nchunks <= 1) return;
+  const double al = alpha[w];
+  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  HelmPrev pv = {0.0, 0.0};
+  const int ilast = (nchunks - 1) * C;  // last chunk start
+  for (int i = 0; i < ilast; ++i) {
+    const int k = 2 * i + p;
+    double l, g, rd, d;
+    helm_step(k, al, N, gl, pv, l, g, rd, d);
+    pv.rd = rd;
+    pv.g = g;
+    if ((i + 1) % C == 0) {
+      const int m = (i + 1) / C;
+      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 2);
+      *s = make_double2(pv.rd, pv.g);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
+                                                    const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  const int p = (int)(t & 1);
+  const int n = N - 4;
+  const int nc = (n - p + 1) / 2;
+  const int nchunks = (nc + C - 1) / C;
+  if (nchunks <= 1) return;
+  const double a = ca[w], b = cb[w];
+  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  Recip Rc;
+  Rc.init(p);
+  const int ilast = (nchunks - 1) * C;
+  for (int i = 0; i < ilast; ++i) {
+    const int k = 2 * i + p;
+    if (i > 0) Rc.advance(k);
+    BihRowState o;
+    double l1, l2, t0;
+    bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
+    m4 = m2;
+    m2 = o;
+    if ((i + 1) % C == 0) {
+      const int m = (i + 1) / C;
+      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 10);
+      s[0] = make_double2(m2.rU0, m2.U2);
+      s[1] = make_double2(m2.U4, m2.P);
+      s[2] = make_double2(m2.R, m4.rU0);
+      s[3] = make_double2(m4.U2, m4.U4);
+      s[4] = make_double2(m4.P, m4.R);
+    }
+  }
+}
+
+// =========================================================================
+// Helmholtz wave solve
+// =========================================================================
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                      const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                      int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  const int lane = threadIdx.x;
+  const int sl = lane / (2 * G);
+  const int p = (lane / G) & 1;
+  const int m = lane % G;
+  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 2;
+  const int k0 = 2 * m * C + p;
+  const double al = wok ? alpha[w] : 0.0;
+  const double hm = -0.5 * kPi * al;
+  const double2* frow = f + (wok ? w : 0) * (int64_t)N;
+  double2* urow = u + (wok ? w : 0) * (int64_t)N;
+
+  // restart state of the LU at the chunk start
+  HelmPrev pv = {0.0, 0.0};
+  if (wok && m > 0 && k0 < n) {
+    const double2 s = *reinterpret_cast<const double2*>(reinterpret_cast<const double*>(urow) + (p * G + m) * 2);
+    pv.rd = s.x;
+    pv.g = s.y;
+  }
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (wok && k < n) ? frow[k] : zero2();
+  }
+  // factorisation restart + local forward elimination (zero incoming state)
+  double lj[C], rdj[C], gj[C];
+  int bad = INT_MAX;
+  double T = 1.0;
+  double2 yp = zero2();
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const bool ok = wok && k < n;
+    double l, g, rd, d;
+    helm_step(k, al, N, gl, pv, l, g, rd, d);
+    if (ok && bad_pivot(d) && bad == INT_MAX) bad = k;
+    pv.rd = rd;
+    pv.g = g;
+    l = ok ? l : 0.0;
+    lj[j] = l;
+    rdj[j] = ok ? rd : 0.0;
+    gj[j] = ok ? g : 0.0;
+    const double2 y = c_fnms(l, yp, x[j]);
+    x[j] = y;
+    yp = y;
+    T *= -l;
+  }
+  // forward scan over chunks: (T, b) with b = last y; compose(later, earlier)
+  double sT = T;
+  double2 sb = yp;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const double oT = shfl_up_w(sT, d, G);
+    const double2 ob = shfl_up2(sb, d, G);
+    if (m >= d) {
+      sb = c_fma(sT, ob, sb);
+      sT = sT * oT;
+    }
+  }
+  double2 h = shfl_up2(sb, 1, G);
+  if (m == 0) h = zero2();
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    h = c_mul(-lj[j], h);
+    x[j] = c_add(x[j], h);
+  }
+  // backward: state (a = u_{i+1}, S = S_{i+2});  u_i = yh - eh a - gh S
+  double eh[C], gh[C];
+  double A00 = 1.0, A01 = 0.0, A10 = 0.0, A11 = 1.0;
+  double2 c0 = zero2(), c1 = zero2();
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const double r = rdj[j];
+    x[j] = c_mul(r, x[j]);  // yh
+    eh[j] = (r == 0.0) ? 0.0 : r * (gj[j] + hm);
+    gh[j] = r * gj[j];
+    // M = [[-eh, -gh], [1, 1]];  A <- M A ; c <- M c + (yh, 0)
+    const double n00 = -eh[j] * A00 - gh[j] * A10, n01 = -eh[j] * A01 - gh[j] * A11;
+    const double n10 = A00 + A10, n11 = A01 + A11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    double2 nc0 = c_fma(-eh[j], c0, x[j]);
+    nc0 = c_fma(-gh[j], c1, nc0);
+    const double2 nc1 = c_add(c0, c1);
+    c0 = nc0;
+    c1 = nc1;
+  }
+  // suffix scan: compose(lower, higher) = (A_lo A_hi, A_lo c_hi + c_lo)
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const double o00 = shfl_down_w(A00, d, G), o01 = shfl_down_w(A01, d, G);
+    const double o10 = shfl_down_w(A10, d, G), o11 = shfl_down_w(A11, d, G);
+    const double2 oc0 = shfl_down2(c0, d, G), oc1 = shfl_down2(c1, d, G);
+    if (m + d < G) {
+      const double2 n0 = c_add(c_fma(A00, oc0, c_mul(A01, oc1)), c0);
+      const double2 n1 = c_add(c_fma(A10, oc0, c_mul(A11, oc1)), c1);
+      const double n00 = A00 * o00 + A01 * o10, n01 = A00 * o01 + A01 * o11;
+      const double n10 = A10 * o00 + A11 * o10, n11 = A10 * o01 + A11 * o11;
+      A00 = n00;
+      A01 = n01;
+      A10 = n10;
+      A11 = n11;
+      c0 = n0;
+      c1 = n1;
+    }
+  }
+  double2 sa = shfl_down2(c0, 1, G), sS = shfl_down2(c1, 1, G);
+  if (m == G - 1) {
+    sa = zero2();
+    sS = zero2();
+  }
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    double2 uj = c_fma(-eh[j], sa, x[j]);
+    uj = c_fma(-gh[j], sS, uj);
+    x[j] = uj;
+    sS = c_add(sS, sa);
+    sa = uj;
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    // min over the 2G lanes of the system
+    int b = bad;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) b = min(b, __shfl_xor(b, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = (b == INT_MAX) ? 0 : b + 1;
+  }
+}
+
+// =========================================================================
+// Biharmonic wave solve
+// =========================================================================
+template <int C, int G>
+__global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
+                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                     int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  const int lane = threadIdx.x;
+  const int sl = lane / (2 * G);
+  const int p = (lane / G) & 1;
+  const int m = lane % G;
+  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 4;
+  const int k0 = 2 * m * C + p;
+  const double a = wok ? ca[w] : 0.0, b = wok ? cb[w] : 0.0;
+  const double2* frow = f + (wok ? w : 0) * (int64_t)N;
+  double2* urow = u + (wok ? w : 0) * (int64_t)N;
+
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  if (wok && m > 0 && k0 < n) {
+    const double2* s = reinterpret_cast<const double2*>(reinterpret_cast<const double*>(urow) + (p * G + m) * 10);
+    const double2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3], s4 = s[4];
+    m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
+    m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
+  }
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (wok && k < n) ? frow[k] : zero2();
+  }
+  // factorisation restart + local forward elimination; keep normalised U rows
+  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
+  int bad = INT_MAX;
+  double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
+  double2 y1 = zero2(), y2 = zero2();  // y_{i-1}, y_{i-2}
+  Recip Rc;
+  Rc.init(k0);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    if (j > 0) Rc.advance(k);
+    const bool ok = wok && k < n;
+    BihRowState o;
+    double l1, l2, t0;
+    bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
+    if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
+    m4 = m2;
+    m2 = o;
+    l1 = ok ? l1 : 0.0;
+    l2 = ok ? l2 : 0.0;
+    l1j[j] = l1;
+    l2j[j] = l2;
+    r0j[j] = ok ? o.rU0 : 0.0;
+    u2j[j] = ok ? o.rU0 * o.U2 : 0.0;
+    u4j[j] = ok ? o.rU0 * o.U4 : 0.0;
+    pj[j] = ok ? o.rU0 * o.P : 0.0;
+    rj[j] = ok ? o.rU0 * o.R : 0.0;
+    double2 y = c_fnms(l1, y1, x[j]);
+    y = c_fnms(l2, y2, y);
+    x[j] = y;
+    y2 = y1;
+    y1 = y;
+    // T <- [[-l1, -l2],[1, 0]] T
+    const double n00 = -l1 * T00 - l2 * T10, n01 = -l1 * T01 - l2 * T11;
+    T10 = T00;
+    T11 = T01;
+    T00 = n00;
+    T01 = n01;
+  }
+  // forward scan: (T, b = (y_last, y_last-1)); compose(later, earlier) = (T_l T_e, T_l b_e + b_l)
+  double2 b0 = y1, b1 = y2;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
+    const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
+    const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
+    if (m >= d) {
+      const double2 n0 = c_add(c_fma(T00, ob0, c_mul(T01, ob1)), b0);
+      const double2 n1 = c_add(c_fma(T10, ob0, c_mul(T11, ob1)), b1);
+      const double n00 = T00 * o00 + T01 * o10, n01 = T00 * o01 + T01 * o11;
+      const double n10 = T10 * o00 + T11 * o10, n11 = T10 * o01 + T11 * o11;
+      T00 = n00;
+      T01 = n01;
+      T10 = n10;
+      T11 = n11;
+      b0 = n0;
+      b1 = n1;
+    }
+  }
+  double2 h1 = shfl_up2(b0, 1, G), h2 = shfl_up2(b1, 1, G);
+  if (m == 0) {
+    h1 = zero2();
+    h2 = zero2();
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    double2 hj = c_mul(-l1j[j], h1);
+    hj = c_fma(-l2j[j], h2, hj);
+    x[j] = c_add(x[j], hj);
+    h2 = h1;
+    h1 = hj;
+  }
+  // backward: state s = (a = u_{i+1}, bb = u_{i+2}, cq = sq_{i+3}, cs = ss_{i+3})
+  //   u_i = yh - u2h a - u4h bb - ph cq - rh cs ;  s' = (u_i, a, cq + q4 bb, cs + s4 bb)
+  double A[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A[r][c] = (r == c) ? 1.0 : 0.0;
+  double2 cv[4] = {zero2(), zero2(), zero2(), zero2()};
+  double q4j[C], s4j[C];
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const int k = k0 + 2 * j;
+    const double kk = (double)k;
+    q4j[j] = 1.0 / (kk + 7.0);
+    s4j[j] = (kk + 6.0) * (kk + 6.0) * q4j[j];
+    x[j] = c_mul(r0j[j], x[j]);  // yh
+    double nA0[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      nA0[c] = -(u2j[j] * A[0][c] + u4j[j] * A[1][c] + pj[j] * A[2][c] + rj[j] * A[3][c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double a1 = A[1][c];
+      A[2][c] = __builtin_fma(q4j[j], a1, A[2][c]);
+      A[3][c] = __builtin_fma(s4j[j], a1, A[3][c]);
+      A[1][c] = A[0][c];
+      A[0][c] = nA0[c];
+    }
+    double2 nc0 = c_fma(-u2j[j], cv[0], x[j]);
+    nc0 = c_fma(-u4j[j], cv[1], nc0);
+    nc0 = c_fma(-pj[j], cv[2], nc0);
+    nc0 = c_fma(-rj[j], cv[3], nc0);
+    cv[2] = c_fma(q4j[j], cv[1], cv[2]);
+    cv[3] = c_fma(s4j[j], cv[1], cv[3]);
+    cv[1] = cv[0];
+    cv[0] = nc0;
+  }
+  // suffix scan: compose(lower, higher) = (A_lo A_hi, A_lo c_hi + c_lo)
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    double oA[4][4];
+    double2 oc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) oA[r][c] = shfl_down_w(A[r][c], d, G);
+      oc[r] = shfl_down2(cv[r], d, G);
+    }
+    if (m + d < G) {
+      double nA[4][4];
+      double2 ncv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double2 acc = cv[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], oc[c], acc);
+        ncv[r] = acc;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) s = __builtin_fma(A[r][t], oA[t][c], s);
+          nA[r][c] = s;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cv[r] = ncv[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A[r][c] = nA[r][c];
+      }
+    }
+  }
+  double2 sa = shfl_down2(cv[0], 1, G), sb = shfl_down2(cv[1], 1, G);
+  double2 sq = shfl_down2(cv[2], 1, G), ss = shfl_down2(cv[3], 1, G);
+  if (m == G - 1) {
+    sa = zero2();
+    sb = zero2();
+    sq = zero2();
+    ss = zero2();
+  }
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    double2 uj = c_fma(-u2j[j], sa, x[j]);
+    uj = c_fma(-u4j[j], sb, uj);
+    uj = c_fma(-pj[j], sq, uj);
+    uj = c_fma(-rj[j], ss, uj);
+    x[j] = uj;
+    sq = c_fma(q4j[j], sb, sq);
+    ss = c_fma(s4j[j], sb, ss);
+    sb = sa;
+    sa = uj;
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    int bq = bad;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) bq = min(bq, __shfl_xor(bq, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = (bq == INT_MAX) ? 0 : bq + 1;
+  }
+}
+
+// =========================================================================
+// host side
+// =========================================================================
+
+namespace {
+struct WaveCfg {
+  int C, G;
+};
+// chunk length C and lanes per chain G for a chain of nc elements (0 if none fits)
+WaveCfg pick_cfg(int nc) {
+  if (nc <= 32) return {4, 8};
+  if (nc <= 64) return {8, 8};
+  if (nc <= 128) return {8, 16};
+  if (nc <= 256) return {16, 16};
+  if (nc <= 512) return {16, 32};
+  return {0, 0};
+}
+}  // namespace
+
+bool wave_supported(int family, int N) {
+  const int n = family == 0 ? N - 2 : N - 4;
+  if (n < 1) return false;
+  const int nc = (n + 1) / 2;
+  const WaveCfg c = pick_cfg(nc);
+  if (c.C == 0) return false;
+  const int per = family == 0 ? 2 : 10;  // doubles of restart state per chunk
+  if (per * 2 * c.G > 2 * N) return false;  // states must fit in the output row
+  return 2 * c.G * c.C >= N;
+}
+
+template <int C, int G>
+static hipError_t launch_helm_t(const WaveArgs& a) {
+  constexpr int SPW = 64 / (2 * G);
+  const int64_t blocks = (a.nsys + SPW - 1) / SPW;
+  hipStream_t st = (hipStream_t)a.stream;
+  const int64_t bthreads = 2 * a.nsys;
+  hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((bthreads + 255) / 256)), dim3(256), 0, st, a.N, a.nsys, C, G, a.c0,
+                     (double2*)a.u, a.gl);
+  hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, (const double2*)a.f,
+                     (double2*)a.u, a.gl, a.info);
+  return hipGetLastError();
+}
+
+template <int C, int G>
+static hipError_t launch_bih_t(const WaveArgs& a) {
+  constexpr int SPW = 64 / (2 * G);
+  const int64_t blocks = (a.nsys + SPW - 1) / SPW;
+  hipStream_t st = (hipStream_t)a.stream;
+  const int64_t bthreads = 2 * a.nsys;
+  hipLaunchKernelGGL(bih_boundary, dim3((unsigned)((bthreads + 255) / 256)), dim3(256), 0, st, a.N, a.nsys, C, G, a.c0, a.c1,
+                     (double2*)a.u, a.gl);
+  hipLaunchKernelGGL((bih_wave_solve<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, a.c1,
+                     (const double2*)a.f, (double2*)a.u, a.gl, a.info);
+  return hipGetLastError();
+}
+
+hipError_t launch_wave(const WaveArgs& a) {
+  const int n = a.family == 0 ? a.N - 2 : a.N - 4;
+  const WaveCfg c = pick_cfg((n + 1) / 2);
+  if (a.nsys <= 0) return hipSuccess;
+  if ((a.nsys + 1) > 0x7fffffffLL) return hipErrorInvalidValue;
+#define SHEN_DISPATCH(CC, GG)                                                         \
+  if (c.C == CC && c.G == GG) return a.family == 0 ? launch_helm_t<CC, GG>(a) : launch_bih_t<CC, GG>(a);
+  SHEN_DISPATCH(4, 8)
+  SHEN_DISPATCH(8, 8)
+  SHEN_DISPATCH(8, 16)
+  SHEN_DISPATCH(16, 16)
+  SHEN_DISPATCH(16, 32)
+#undef SHEN_DISPATCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace shen
