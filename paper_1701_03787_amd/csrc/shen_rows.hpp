@@ -30,6 +30,16 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 
 __device__ __forceinline__ double ck(int k, int N, int gl) { return (k == 0 || (gl && k == N - 1)) ? 2.0 : 1.0; }
 
+// 1/d from the hardware reciprocal estimate refined by two Newton steps
+// (each roughly squares the relative error), cheaper than the IEEE divide.
+__device__ __forceinline__ double fast_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // ----------------------------------------------------------------- Helmholtz
 struct HelmRow {
   double hm;   // H_{k,k-2}
@@ -59,25 +69,25 @@ struct Recip {
   double m1, p1, p3, p5, p7;
   __device__ __forceinline__ void init(int k) {
     const double kk = (double)k;
-    m1 = (k == 1) ? 0.0 : 1.0 / (kk - 1.0);  // only used for k >= 4
-    p1 = 1.0 / (kk + 1.0);
-    p3 = 1.0 / (kk + 3.0);
-    p5 = 1.0 / (kk + 5.0);
-    p7 = 1.0 / (kk + 7.0);
+    m1 = (k == 1) ? 0.0 : fast_rcp(kk - 1.0);  // only used for k >= 4
+    p1 = fast_rcp(kk + 1.0);
+    p3 = fast_rcp(kk + 3.0);
+    p5 = fast_rcp(kk + 5.0);
+    p7 = fast_rcp(kk + 7.0);
   }
   __device__ __forceinline__ void advance(int knew) {  // from k to knew = k + 2
     m1 = p1;
     p1 = p3;
     p3 = p5;
     p5 = p7;
-    p7 = 1.0 / ((double)knew + 7.0);
+    p7 = fast_rcp((double)knew + 7.0);
   }
   __device__ __forceinline__ void retreat(int knew) {  // from k to knew = k - 2
     p7 = p5;
     p5 = p3;
     p3 = p1;
     p1 = m1;
-    m1 = (knew == 1) ? 0.0 : 1.0 / ((double)knew - 1.0);
+    m1 = (knew == 1) ? 0.0 : fast_rcp((double)knew - 1.0);
   }
 };
 

@@ -45,6 +45,25 @@ __device__ __forceinline__ double2 shfl_down2(double2 v, int d, int w) {
   return make_double2(__shfl_down(v.x, (unsigned)d, w), __shfl_down(v.y, (unsigned)d, w));
 }
 
+// DPP row shifts inside a row of 16 lanes with zero fill past the row ends
+// (bound_ctrl).  row_shr:D gives lane i the value of lane i-D, row_shl:D the
+// value of lane i+D.  A scan partner that does not exist thus arrives as 0,
+// and composing with a zero map leaves the running offset unchanged, so the
+// Kogge-Stone steps need no lane-dependent selects.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int D>
+struct RowShift {
+  static __device__ __forceinline__ double from_lower(double v) { return dpp_d<0x110 + D>(v); }  // lane i-D
+  static __device__ __forceinline__ double from_upper(double v) { return dpp_d<0x100 + D>(v); }  // lane i+D
+  static __device__ __forceinline__ double2 from_lower(double2 v) { return make_double2(from_lower(v.x), from_lower(v.y)); }
+  static __device__ __forceinline__ double2 from_upper(double2 v) { return make_double2(from_upper(v.x), from_upper(v.y)); }
+};
+
 // One Helmholtz LU row step (shared by boundary and solve kernels so that the
 // restarted factorisation reproduces the sequential one exactly).
 struct HelmPrev {
@@ -62,7 +81,7 @@ __device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const
     d = __builtin_fma(-l, pv.g + h.hm, h.h0);
     g = __builtin_fma(-l, pv.g, h.hpp);
   }
-  rd = 1.0 / d;
+  rd = fast_rcp(d);
 }
 
 // One biharmonic LU row step: row k reduced by rows k-4 (m4) and k-2 (m2).
@@ -92,7 +111,7 @@ __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int g
     P = __builtin_fma(-l1, m2.P, P);
     Rr = __builtin_fma(-l1, m2.R, Rr);
   }
-  o.rU0 = 1.0 / t0;
+  o.rU0 = fast_rcp(t0);
   o.U2 = t2;
   o.U4 = t4;
   o.P = P;
@@ -230,17 +249,33 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
   // forward scan over chunks: (T, b) with b = last y; compose(later, earlier)
   double sT = T;
   double2 sb = yp;
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const double oT = shfl_up_w(sT, d, G);
-    const double2 ob = shfl_up2(sb, d, G);
-    if (m >= d) {
+  double2 h;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      const double oT = S::from_lower(sT);
+      const double2 ob = S::from_lower(sb);
       sb = c_fma(sT, ob, sb);
       sT = sT * oT;
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    h = RowShift<1>::from_lower(sb);
+  } else {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const double oT = shfl_up_w(sT, d, G);
+      const double2 ob = shfl_up2(sb, d, G);
+      if (m >= d) {
+        sb = c_fma(sT, ob, sb);
+        sT = sT * oT;
+      }
     }
+    h = shfl_up2(sb, 1, G);
+    if (m == 0) h = zero2();
   }
-  double2 h = shfl_up2(sb, 1, G);
-  if (m == 0) h = zero2();
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     h = c_mul(-lj[j], h);
@@ -270,28 +305,45 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
     c1 = nc1;
   }
   // suffix scan: compose(lower, higher) = (A_lo A_hi, A_lo c_hi + c_lo)
+  auto compose2 = [&](double o00, double o01, double o10, double o11, double2 oc0, double2 oc1) {
+    const double2 n0 = c_add(c_fma(A00, oc0, c_mul(A01, oc1)), c0);
+    const double2 n1 = c_add(c_fma(A10, oc0, c_mul(A11, oc1)), c1);
+    const double n00 = A00 * o00 + A01 * o10, n01 = A00 * o01 + A01 * o11;
+    const double n10 = A10 * o00 + A11 * o10, n11 = A10 * o01 + A11 * o11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    c0 = n0;
+    c1 = n1;
+  };
+  double2 sa, sS;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      compose2(S::from_upper(A00), S::from_upper(A01), S::from_upper(A10), S::from_upper(A11), S::from_upper(c0),
+               S::from_upper(c1));
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    sa = RowShift<1>::from_upper(c0);
+    sS = RowShift<1>::from_upper(c1);
+  } else {
 #pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const double o00 = shfl_down_w(A00, d, G), o01 = shfl_down_w(A01, d, G);
-    const double o10 = shfl_down_w(A10, d, G), o11 = shfl_down_w(A11, d, G);
-    const double2 oc0 = shfl_down2(c0, d, G), oc1 = shfl_down2(c1, d, G);
-    if (m + d < G) {
-      const double2 n0 = c_add(c_fma(A00, oc0, c_mul(A01, oc1)), c0);
-      const double2 n1 = c_add(c_fma(A10, oc0, c_mul(A11, oc1)), c1);
-      const double n00 = A00 * o00 + A01 * o10, n01 = A00 * o01 + A01 * o11;
-      const double n10 = A10 * o00 + A11 * o10, n11 = A10 * o01 + A11 * o11;
-      A00 = n00;
-      A01 = n01;
-      A10 = n10;
-      A11 = n11;
-      c0 = n0;
-      c1 = n1;
+    for (int d = 1; d < G; d <<= 1) {
+      const double o00 = shfl_down_w(A00, d, G), o01 = shfl_down_w(A01, d, G);
+      const double o10 = shfl_down_w(A10, d, G), o11 = shfl_down_w(A11, d, G);
+      const double2 oc0 = shfl_down2(c0, d, G), oc1 = shfl_down2(c1, d, G);
+      if (m + d < G) compose2(o00, o01, o10, o11, oc0, oc1);
     }
-  }
-  double2 sa = shfl_down2(c0, 1, G), sS = shfl_down2(c1, 1, G);
-  if (m == G - 1) {
-    sa = zero2();
-    sS = zero2();
+    sa = shfl_down2(c0, 1, G);
+    sS = shfl_down2(c1, 1, G);
+    if (m == G - 1) {
+      sa = zero2();
+      sS = zero2();
+    }
   }
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
@@ -351,7 +403,7 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
     x[j] = (wok && k < n) ? frow[k] : zero2();
   }
   // factorisation restart + local forward elimination; keep normalised U rows
-  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
+  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C], q4j[C];
   int bad = INT_MAX;
   double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
   double2 y1 = zero2(), y2 = zero2();  // y_{i-1}, y_{i-2}
@@ -372,6 +424,7 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
     l2 = ok ? l2 : 0.0;
     l1j[j] = l1;
     l2j[j] = l2;
+    q4j[j] = Rc.p7;  // q_{k+4} = 1/(k+7)
     r0j[j] = ok ? o.rU0 : 0.0;
     u2j[j] = ok ? o.rU0 * o.U2 : 0.0;
     u4j[j] = ok ? o.rU0 * o.U4 : 0.0;
@@ -391,28 +444,45 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
   }
   // forward scan: (T, b = (y_last, y_last-1)); compose(later, earlier) = (T_l T_e, T_l b_e + b_l)
   double2 b0 = y1, b1 = y2;
+  auto composeT = [&](double o00, double o01, double o10, double o11, double2 ob0, double2 ob1) {
+    const double2 n0 = c_add(c_fma(T00, ob0, c_mul(T01, ob1)), b0);
+    const double2 n1 = c_add(c_fma(T10, ob0, c_mul(T11, ob1)), b1);
+    const double n00 = T00 * o00 + T01 * o10, n01 = T00 * o01 + T01 * o11;
+    const double n10 = T10 * o00 + T11 * o10, n11 = T10 * o01 + T11 * o11;
+    T00 = n00;
+    T01 = n01;
+    T10 = n10;
+    T11 = n11;
+    b0 = n0;
+    b1 = n1;
+  };
+  double2 h1, h2;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      composeT(S::from_lower(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower(T11), S::from_lower(b0),
+               S::from_lower(b1));
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    h1 = RowShift<1>::from_lower(b0);
+    h2 = RowShift<1>::from_lower(b1);
+  } else {
 #pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
-    const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
-    const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
-    if (m >= d) {
-      const double2 n0 = c_add(c_fma(T00, ob0, c_mul(T01, ob1)), b0);
-      const double2 n1 = c_add(c_fma(T10, ob0, c_mul(T11, ob1)), b1);
-      const double n00 = T00 * o00 + T01 * o10, n01 = T00 * o01 + T01 * o11;
-      const double n10 = T10 * o00 + T11 * o10, n11 = T10 * o01 + T11 * o11;
-      T00 = n00;
-      T01 = n01;
-      T10 = n10;
-      T11 = n11;
-      b0 = n0;
-      b1 = n1;
+    for (int d = 1; d < G; d <<= 1) {
+      const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
+      const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
+      const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
+      if (m >= d) composeT(o00, o01, o10, o11, ob0, ob1);
     }
-  }
-  double2 h1 = shfl_up2(b0, 1, G), h2 = shfl_up2(b1, 1, G);
-  if (m == 0) {
-    h1 = zero2();
-    h2 = zero2();
+    h1 = shfl_up2(b0, 1, G);
+    h2 = shfl_up2(b1, 1, G);
+    if (m == 0) {
+      h1 = zero2();
+      h2 = zero2();
+    }
   }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
@@ -430,13 +500,10 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
 #pragma unroll
     for (int c = 0; c < 4; ++c) A[r][c] = (r == c) ? 1.0 : 0.0;
   double2 cv[4] = {zero2(), zero2(), zero2(), zero2()};
-  double q4j[C], s4j[C];
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
-    const int k = k0 + 2 * j;
-    const double kk = (double)k;
-    q4j[j] = 1.0 / (kk + 7.0);
-    s4j[j] = (kk + 6.0) * (kk + 6.0) * q4j[j];
+    const double k6 = (double)(k0 + 2 * j) + 6.0;
+    const double s4 = k6 * k6 * q4j[j];  // s_{k+4}
     x[j] = c_mul(r0j[j], x[j]);  // yh
     double nA0[4];
 #pragma unroll
@@ -446,7 +513,7 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
     for (int c = 0; c < 4; ++c) {
       const double a1 = A[1][c];
       A[2][c] = __builtin_fma(q4j[j], a1, A[2][c]);
-      A[3][c] = __builtin_fma(s4j[j], a1, A[3][c]);
+      A[3][c] = __builtin_fma(s4, a1, A[3][c]);
       A[1][c] = A[0][c];
       A[0][c] = nA0[c];
     }
@@ -455,53 +522,80 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
     nc0 = c_fma(-pj[j], cv[2], nc0);
     nc0 = c_fma(-rj[j], cv[3], nc0);
     cv[2] = c_fma(q4j[j], cv[1], cv[2]);
-    cv[3] = c_fma(s4j[j], cv[1], cv[3]);
+    cv[3] = c_fma(s4, cv[1], cv[3]);
     cv[1] = cv[0];
     cv[0] = nc0;
   }
   // suffix scan: compose(lower, higher) = (A_lo A_hi, A_lo c_hi + c_lo)
-#pragma unroll
-  for (int d = 1; d < G; d <<= 1) {
-    double oA[4][4];
-    double2 oc[4];
+  auto compose4 = [&](const double (&oA)[4][4], const double2 (&oc)[4]) {
+    double nA[4][4];
+    double2 ncv[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      double2 acc = cv[r];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) oA[r][c] = shfl_down_w(A[r][c], d, G);
-      oc[r] = shfl_down2(cv[r], d, G);
-    }
-    if (m + d < G) {
-      double nA[4][4];
-      double2 ncv[4];
+      for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], oc[c], acc);
+      ncv[r] = acc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double2 acc = cv[r];
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], oc[c], acc);
-        ncv[r] = acc;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double s = 0.0;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) s = __builtin_fma(A[r][t], oA[t][c], s);
-          nA[r][c] = s;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cv[r] = ncv[r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) A[r][c] = nA[r][c];
+        for (int t = 0; t < 4; ++t) s = __builtin_fma(A[r][t], oA[t][c], s);
+        nA[r][c] = s;
       }
     }
-  }
-  double2 sa = shfl_down2(cv[0], 1, G), sb = shfl_down2(cv[1], 1, G);
-  double2 sq = shfl_down2(cv[2], 1, G), ss = shfl_down2(cv[3], 1, G);
-  if (m == G - 1) {
-    sa = zero2();
-    sb = zero2();
-    sq = zero2();
-    ss = zero2();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cv[r] = ncv[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) A[r][c] = nA[r][c];
+    }
+  };
+  double2 sa, sb, sq, ss;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      double oA[4][4];
+      double2 oc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) oA[r][c] = S::from_upper(A[r][c]);
+        oc[r] = S::from_upper(cv[r]);
+      }
+      compose4(oA, oc);
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    sa = RowShift<1>::from_upper(cv[0]);
+    sb = RowShift<1>::from_upper(cv[1]);
+    sq = RowShift<1>::from_upper(cv[2]);
+    ss = RowShift<1>::from_upper(cv[3]);
+  } else {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      double oA[4][4];
+      double2 oc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) oA[r][c] = shfl_down_w(A[r][c], d, G);
+        oc[r] = shfl_down2(cv[r], d, G);
+      }
+      if (m + d < G) compose4(oA, oc);
+    }
+    sa = shfl_down2(cv[0], 1, G);
+    sb = shfl_down2(cv[1], 1, G);
+    sq = shfl_down2(cv[2], 1, G);
+    ss = shfl_down2(cv[3], 1, G);
+    if (m == G - 1) {
+      sa = zero2();
+      sb = zero2();
+      sq = zero2();
+      ss = zero2();
+    }
   }
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
@@ -510,8 +604,9 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
     uj = c_fma(-pj[j], sq, uj);
     uj = c_fma(-rj[j], ss, uj);
     x[j] = uj;
+    const double k6 = (double)(k0 + 2 * j) + 6.0;
     sq = c_fma(q4j[j], sb, sq);
-    ss = c_fma(s4j[j], sb, ss);
+    ss = c_fma(k6 * k6 * q4j[j], sb, ss);
     sb = sa;
     sa = uj;
   }
@@ -560,29 +655,43 @@ bool wave_supported(int family, int N) {
   return 2 * c.G * c.C >= N;
 }
 
+// Systems per boundary/solve launch pair.  Smaller slices keep the restart
+// states in the last-level cache, but starve the sequential boundary kernel
+// of waves; measured slower at the channel-scale sizes, so off.
+static constexpr int64_t kWaveSlice = (int64_t)1 << 40;  // no slicing: boundary kernels need the whole grid for occupancy
+
 template <int C, int G>
 static hipError_t launch_helm_t(const WaveArgs& a) {
   constexpr int SPW = 64 / (2 * G);
-  const int64_t blocks = (a.nsys + SPW - 1) / SPW;
   hipStream_t st = (hipStream_t)a.stream;
-  const int64_t bthreads = 2 * a.nsys;
-  hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((bthreads + 255) / 256)), dim3(256), 0, st, a.N, a.nsys, C, G, a.c0,
-                     (double2*)a.u, a.gl);
-  hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, (const double2*)a.f,
-                     (double2*)a.u, a.gl, a.info);
+  for (int64_t s0 = 0; s0 < a.nsys; s0 += kWaveSlice) {
+    const int64_t ns = (a.nsys - s0 < kWaveSlice) ? a.nsys - s0 : kWaveSlice;
+    const double* c0 = a.c0 + s0;
+    const double2* f = (const double2*)a.f + s0 * a.N;
+    double2* u = (double2*)a.u + s0 * a.N;
+    int32_t* info = a.info ? a.info + s0 : nullptr;
+    hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
+    hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)((ns + SPW - 1) / SPW)), dim3(64), 0, st, a.N, ns, c0, f, u,
+                       a.gl, info);
+  }
   return hipGetLastError();
 }
 
 template <int C, int G>
 static hipError_t launch_bih_t(const WaveArgs& a) {
   constexpr int SPW = 64 / (2 * G);
-  const int64_t blocks = (a.nsys + SPW - 1) / SPW;
   hipStream_t st = (hipStream_t)a.stream;
-  const int64_t bthreads = 2 * a.nsys;
-  hipLaunchKernelGGL(bih_boundary, dim3((unsigned)((bthreads + 255) / 256)), dim3(256), 0, st, a.N, a.nsys, C, G, a.c0, a.c1,
-                     (double2*)a.u, a.gl);
-  hipLaunchKernelGGL((bih_wave_solve<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, a.c1,
-                     (const double2*)a.f, (double2*)a.u, a.gl, a.info);
+  for (int64_t s0 = 0; s0 < a.nsys; s0 += kWaveSlice) {
+    const int64_t ns = (a.nsys - s0 < kWaveSlice) ? a.nsys - s0 : kWaveSlice;
+    const double* c0 = a.c0 + s0;
+    const double* c1 = a.c1 + s0;
+    const double2* f = (const double2*)a.f + s0 * a.N;
+    double2* u = (double2*)a.u + s0 * a.N;
+    int32_t* info = a.info ? a.info + s0 : nullptr;
+    hipLaunchKernelGGL(bih_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, c1, u, a.gl);
+    hipLaunchKernelGGL((bih_wave_solve<C, G>), dim3((unsigned)((ns + SPW - 1) / SPW)), dim3(64), 0, st, a.N, ns, c0, c1, f, u,
+                       a.gl, info);
+  }
   return hipGetLastError();
 }
 
