@@ -1,0 +1,198 @@
+"""Batched form: many independent grids (uneven N, both families) in one
+persistent launch, optionally captured once in a hipGraph and replayed.
+
+Tile sizes (systems per work item) are chosen per (family, N) by a small
+autotuner that times candidate tiles on the device and caches the winners in
+a JSON file (env SHENHIP_AUTOTUNE_CACHE, default ~/.cache/shenhip/autotune.json).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+import time
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+from .api import _QUAD
+
+TILE_CANDIDATES = (4, 8, 16, 32, 64)
+DEFAULT_TILE = 32
+
+
+@dataclass
+class BatchedProblem:
+    """One grid: family "helmholtz" (coeffs = (alpha,)) or "biharmonic" (coeffs = (a, b)).
+    f and u are complex128 [nsys, N] device tensors (u must not alias f)."""
+
+    family: str
+    f: torch.Tensor
+    coeffs: Sequence[torch.Tensor]
+    u: Optional[torch.Tensor] = None
+    info: Optional[torch.Tensor] = None
+    tile: int = 0
+
+    def __post_init__(self):
+        if self.family not in ("helmholtz", "biharmonic"):
+            raise ValueError(self.family)
+        if self.f.dtype != torch.complex128 or self.f.dim() != 2 or not self.f.is_contiguous() or not self.f.is_cuda:
+            raise ValueError("f must be a contiguous complex128 [nsys, N] device tensor")
+        need = 1 if self.family == "helmholtz" else 2
+        if len(self.coeffs) != need:
+            raise ValueError(f"{self.family} needs {need} coefficient arrays")
+        for c in self.coeffs:
+            if c.dtype != torch.float64 or tuple(c.shape) != (self.f.shape[0],) or not c.is_contiguous():
+                raise ValueError("coefficients must be contiguous float64 [nsys]")
+        if self.u is None:
+            self.u = torch.empty_like(self.f)
+
+    @property
+    def N(self) -> int:
+        return int(self.f.shape[1])
+
+    @property
+    def nsys(self) -> int:
+        return int(self.f.shape[0])
+
+
+def _cache_path() -> str:
+    return os.environ.get("SHENHIP_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "shenhip", "autotune.json"))
+
+
+def _arch(device) -> str:
+    p = torch.cuda.get_device_properties(device)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+class Autotuner:
+    """Per (arch, family, N) choice of the tile size of the persistent kernel."""
+
+    def __init__(self, path: Optional[str] = None):
+        self.path = path or _cache_path()
+        self.table = {}
+        if os.path.exists(self.path):
+            try:
+                with open(self.path) as fh:
+                    self.table = json.load(fh)
+            except (OSError, ValueError):
+                self.table = {}
+
+    def key(self, device, family, N) -> str:
+        return f"{_arch(device)}|{family}|{N}"
+
+    def get(self, device, family, N) -> Optional[int]:
+        v = self.table.get(self.key(device, family, N))
+        return int(v["tile"]) if v else None
+
+    def tune(self, device, family: str, N: int, nsys: int = 4096, reps: int = 3, quad="gc") -> int:
+        """Time every candidate tile on a synthetic grid of the given shape; store the best."""
+        g = torch.Generator(device="cpu").manual_seed(1701 + N)
+        f = torch.randn((nsys, N), dtype=torch.complex128, generator=g).to(device)
+        K2 = torch.arange(nsys, dtype=torch.float64) % 4096
+        inv = 8e7
+        if family == "helmholtz":
+            coeffs = [(K2 + inv).to(device)]
+        else:
+            coeffs = [(-(2 * K2 + inv)).to(device), (K2 * (K2 + inv)).to(device)]
+        best, best_t = DEFAULT_TILE, float("inf")
+        timings = {}
+        for tile in TILE_CANDIDATES:
+            solver = BatchedSolver([BatchedProblem(family, f, coeffs, tile=tile)], quad=quad, autotune=False)
+            solver.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                solver.run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            timings[tile] = dt
+            if dt < best_t:
+                best, best_t = tile, dt
+        self.table[self.key(device, family, N)] = {"tile": best, "seconds": timings}
+        self.save()
+        return best
+
+    def save(self):
+        try:
+            os.makedirs(os.path.dirname(self.path), exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+        except OSError:
+            pass
+
+
+class BatchedSolver:
+    """Plans a batch of problems once; run() enqueues the single persistent launch."""
+
+    def __init__(self, problems: List[BatchedProblem], quad: str = "gc", autotune: bool = False,
+                 tuner: Optional[Autotuner] = None):
+        if not problems:
+            raise ValueError("empty batch")
+        self.device = problems[0].f.device
+        # largest work first: better balance of the dynamic work queue
+        self.problems = sorted(problems, key=lambda p: -p.N)
+        self.quad = quad
+        tuner = tuner or (Autotuner() if autotune else None)
+        n = len(self.problems)
+        host = (L.ShenProblem * n)()
+        for i, p in enumerate(self.problems):
+            d = host[i]
+            d.family = L.SHEN_HELMHOLTZ if p.family == "helmholtz" else L.SHEN_BIHARMONIC
+            d.N = p.N
+            d.nsys = p.nsys
+            d.c0 = p.coeffs[0].data_ptr()
+            d.c1 = p.coeffs[1].data_ptr() if p.family == "biharmonic" else None
+            d.f = p.f.data_ptr()
+            d.u = p.u.data_ptr()
+            d.info = p.info.data_ptr() if p.info is not None else None
+            tile = p.tile
+            if tile <= 0 and tuner is not None:
+                tile = tuner.get(self.device, p.family, p.N) or tuner.tune(self.device, p.family, p.N, quad=quad)
+            d.sys_per_tile = tile if tile > 0 else DEFAULT_TILE
+        o = self._opts()
+        total = L.lib().shen_batched_plan(host, n, C.byref(o))
+        if total < 0:
+            raise L.ShenError(int(total), "shen_batched_plan")
+        self.tiles_total = int(total)
+        self.maxN = max(p.N for p in self.problems)
+        raw = bytes(C.string_at(C.addressof(host), C.sizeof(host)))
+        self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        nbytes = int(L.lib().shen_batched_work_bytes(n))
+        self.work = torch.zeros((nbytes + 7) // 8, dtype=torch.int64, device=self.device)
+        self.tiles = [host[i].sys_per_tile for i in range(n)]
+        self.graph = None
+
+    def _opts(self):
+        o = L.default_opts()
+        o.stream = torch.cuda.current_stream(self.device).cuda_stream
+        o.quad = _QUAD[self.quad]
+        return o
+
+    def run(self):
+        o = self._opts()
+        L.check(L.lib().batched_solve(self.desc.data_ptr(), len(self.problems), self.tiles_total, self.maxN,
+                                      self.work.data_ptr(), C.byref(o)), "batched_solve")
+
+    def capture(self):
+        """Capture run() in a hipGraph once (warm up first); replay() re-launches it."""
+        s = torch.cuda.Stream(self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()

@@ -335,23 +335,49 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* c
   return run(a);
 }
 
-int64_t shen_batched_plan(shen_problem* desc_host, int32_t ndesc, const shen_opts* opts) {
-  (void)desc_host;
-  (void)ndesc;
-  (void)opts;
-  return SHEN_ENOTSUP;
+int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  if (check_opts(o)) return SHEN_EINVAL;
+  if (!desc || ndesc <= 0) return SHEN_EINVAL;
+  int64_t total = 0;
+  for (int32_t i = 0; i < ndesc; ++i) {
+    shen_problem& d = desc[i];
+    if (d.family != SHEN_HELMHOLTZ && d.family != SHEN_BIHARMONIC) return SHEN_EINVAL;
+    if (d.nsys < 0 || d.N < (d.family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
+    if (d.nsys > 0) {
+      if (check_rows(d.f) || check_rows(d.u) || check_coef(d.c0)) return SHEN_EINVAL;
+      if (d.family == SHEN_BIHARMONIC && check_coef(d.c1)) return SHEN_EINVAL;
+      if (d.info && !aligned(d.info, 4)) return SHEN_EINVAL;
+      if ((const void*)d.f == (const void*)d.u || rows_overlap_partially(d.f, d.u, d.nsys, d.N)) return SHEN_EINVAL;
+    }
+    if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
+    if (d.sys_per_tile <= 0) d.sys_per_tile = 32;
+    if (d.sys_per_tile > 1024) return SHEN_EINVAL;
+    d.tile_begin = total;
+    total += (d.nsys + d.sys_per_tile - 1) / d.sys_per_tile;
+  }
+  return total;
 }
 
 int64_t shen_batched_work_bytes(int32_t ndesc) { return ndesc < 0 ? SHEN_EINVAL : 256; }
 
 int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work, const shen_opts* opts) {
-  (void)desc;
-  (void)ndesc;
-  (void)tiles_total;
-  (void)maxN;
-  (void)work;
-  (void)opts;
-  return SHEN_ENOTSUP;
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!desc || !aligned(desc, 8) || ndesc <= 0 || tiles_total < 0 || maxN < 3) return SHEN_EINVAL;
+  if (!work || !aligned(work, 8)) return SHEN_EINVAL;
+  DevInfo d;
+  rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return SHEN_EDEVICE;
+  int64_t blocks = (int64_t)cus * 4;
+  if (blocks > tiles_total) blocks = tiles_total > 0 ? tiles_total : 1;
+  return shen::launch_batched(desc, ndesc, tiles_total, work, o.quad == SHEN_QUAD_GL, (int)blocks, o.stream) == hipSuccess
+             ? SHEN_OK
+             : SHEN_ELAUNCH;
 }
 
 }  // extern "C"

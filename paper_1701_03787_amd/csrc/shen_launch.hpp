@@ -42,7 +42,12 @@ struct WaveArgs {
   void* stream = nullptr;
 };
 
+struct WaveCfg {
+  int C, G;
+};
+__host__ __device__ WaveCfg pick_cfg(int nc, int family);
 bool wave_supported(int family, int N);
+hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);
 
 size_t chain_bytes_per_system(ChainKind kind, int N);

@@ -26,6 +26,7 @@
 
 #include "shen_launch.hpp"
 #include "shen_rows.hpp"
+#include "shenhip.h"
 
 namespace shen {
 
@@ -125,18 +126,12 @@ __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int g
 
 // States parked in u[w] (as doubles): Helmholtz [(p*G + m)*2 + {0,1}] = (1/d, g)
 // of row 2(mC)-2+p; biharmonic [(p*G + m)*10 + ...] = rows k-2 then k-4.
-__global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
-                                                     double2* __restrict__ u, int gl) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
-  const int64_t w = t >> 1;
-  const int p = (int)(t & 1);
+__device__ __forceinline__ void helm_boundary_chain(int N, int C, int G, int p, double al, double2* __restrict__ urow, int gl) {
   const int n = N - 2;
   const int nc = (n - p + 1) / 2;  // elements in this chain
   const int nchunks = (nc + C - 1) / C;
   if (nchunks <= 1) return;
-  const double al = alpha[w];
-  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  double* st = reinterpret_cast<double*>(urow);
   HelmPrev pv = {0.0, 0.0};
   const int ilast = (nchunks - 1) * C;  // last chunk start
   for (int i = 0; i < ilast; ++i) {
@@ -153,18 +148,21 @@ __global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C,
   }
 }
 
-__global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
-                                                    const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+__global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
+                                                     double2* __restrict__ u, int gl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * nsys) return;
   const int64_t w = t >> 1;
-  const int p = (int)(t & 1);
+  helm_boundary_chain(N, C, G, (int)(t & 1), alpha[w], u + w * (int64_t)N, gl);
+}
+
+__device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
+                                                   int gl) {
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
   if (nchunks <= 1) return;
-  const double a = ca[w], b = cb[w];
-  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  double* st = reinterpret_cast<double*>(urow);
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   Recip Rc;
   Rc.init(p);
@@ -189,19 +187,27 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
   }
 }
 
+__global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
+                                                    const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  bih_boundary_chain(N, C, G, (int)(t & 1), ca[w], cb[w], u + w * (int64_t)N, gl);
+}
+
 // =========================================================================
 // Helmholtz wave solve
 // =========================================================================
+// Solves systems wbase + (lane / 2G) of the wavefront (those below nsys).
 template <int C, int G>
-__global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                      const double2* __restrict__ f, double2* __restrict__ u, int gl,
-                                                      int32_t* __restrict__ info) {
-  constexpr int SPW = 64 / (2 * G);
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
+                                               const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                               int32_t* __restrict__ info) {
+  const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
-  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const int64_t w = wbase + sl;
   const bool wok = w < nsys;
   const int n = N - 2;
   const int k0 = 2 * m * C + p;
@@ -373,15 +379,14 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
 // Biharmonic wave solve
 // =========================================================================
 template <int C, int G>
-__global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
-                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
-                                                     int32_t* __restrict__ info) {
-  constexpr int SPW = 64 / (2 * G);
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ ca,
+                                              const double* __restrict__ cb, const double2* __restrict__ f,
+                                              double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+  const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
-  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const int64_t w = wbase + sl;
   const bool wok = w < nsys;
   const int n = N - 4;
   const int k0 = 2 * m * C + p;
@@ -625,30 +630,41 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
   }
 }
 
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                      const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                      int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  helm_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, alpha, f, u, gl, info);
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
+                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                     int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, gl, info);
+}
+
 // =========================================================================
 // host side
 // =========================================================================
 
-namespace {
-struct WaveCfg {
-  int C, G;
-};
-// chunk length C and lanes per chain G for a chain of nc elements (0 if none fits)
-WaveCfg pick_cfg(int nc) {
-  if (nc <= 32) return {4, 8};
+// chunk length C and lanes per chain G such that each parity owns nc >= ceil(N/2)
+// slots (the lanes also write the zero tail), 0 if none fits
+__host__ __device__ WaveCfg pick_cfg(int nc, int family) {
+  if (nc <= 32) return family == 1 ? WaveCfg{8, 4} : WaveCfg{4, 8};
   if (nc <= 64) return {8, 8};
   if (nc <= 128) return {8, 16};
   if (nc <= 256) return {16, 16};
   if (nc <= 512) return {16, 32};
   return {0, 0};
 }
-}  // namespace
 
 bool wave_supported(int family, int N) {
   const int n = family == 0 ? N - 2 : N - 4;
   if (n < 1) return false;
-  const int nc = (n + 1) / 2;
-  const WaveCfg c = pick_cfg(nc);
+  const WaveCfg c = pick_cfg((N + 1) / 2, family);
   if (c.C == 0) return false;
   const int per = family == 0 ? 2 : 10;  // doubles of restart state per chunk
   if (per * 2 * c.G > 2 * N) return false;  // states must fit in the output row
@@ -697,18 +713,120 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
 
 hipError_t launch_wave(const WaveArgs& a) {
   const int n = a.family == 0 ? a.N - 2 : a.N - 4;
-  const WaveCfg c = pick_cfg((n + 1) / 2);
+  (void)n;
+  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family);
   if (a.nsys <= 0) return hipSuccess;
   if ((a.nsys + 1) > 0x7fffffffLL) return hipErrorInvalidValue;
 #define SHEN_DISPATCH(CC, GG)                                                         \
   if (c.C == CC && c.G == GG) return a.family == 0 ? launch_helm_t<CC, GG>(a) : launch_bih_t<CC, GG>(a);
   SHEN_DISPATCH(4, 8)
+  SHEN_DISPATCH(8, 4)
   SHEN_DISPATCH(8, 8)
   SHEN_DISPATCH(8, 16)
   SHEN_DISPATCH(16, 16)
   SHEN_DISPATCH(16, 32)
 #undef SHEN_DISPATCH
   return hipErrorInvalidValue;
+}
+
+
+// =========================================================================
+// Batched form: one persistent launch over many grids of uneven N and both
+// families.  Work item = a tile of consecutive systems of one descriptor;
+// workgroups (one wavefront each) pull tiles from an atomic counter until the
+// queue is empty (every wavefront reaches that exit).  A tile first runs the
+// boundary recurrences of its chains (one lane per chain), then the wave
+// solve of its systems, so the restart states are written and read back by
+// the same compute unit.
+// =========================================================================
+template <int C, int G>
+__device__ __forceinline__ void helm_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
+  const int N = d.N;
+  double2* u = reinterpret_cast<double2*>(d.u);
+  const int64_t nch = 2 * (wend - w0);
+  for (int64_t c = threadIdx.x; c < nch; c += 64) {
+    const int64_t w = w0 + (c >> 1);
+    helm_boundary_chain(N, C, G, (int)(c & 1), d.c0[w], u + w * (int64_t)N, gl);
+  }
+  __threadfence();
+  __syncthreads();
+  constexpr int SPW = 64 / (2 * G);
+  for (int64_t wb = w0; wb < wend; wb += SPW)
+    helm_wave_body<C, G>(N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), u, gl, d.info);
+}
+
+template <int C, int G>
+__device__ __forceinline__ void bih_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
+  const int N = d.N;
+  double2* u = reinterpret_cast<double2*>(d.u);
+  const int64_t nch = 2 * (wend - w0);
+  for (int64_t c = threadIdx.x; c < nch; c += 64) {
+    const int64_t w = w0 + (c >> 1);
+    bih_boundary_chain(N, C, G, (int)(c & 1), d.c0[w], d.c1[w], u + w * (int64_t)N, gl);
+  }
+  __threadfence();
+  __syncthreads();
+  constexpr int SPW = 64 / (2 * G);
+  for (int64_t wb = w0; wb < wend; wb += SPW)
+    bih_wave_body<C, G>(N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), u, gl, d.info);
+}
+
+__device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
+  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family);
+#define SHEN_TILE(CC, GG)                                          \
+  if (c.C == CC && c.G == GG) {                                    \
+    if (d.family == SHEN_HELMHOLTZ)                                \
+      helm_tile<CC, GG>(d, w0, wend, gl);                          \
+    else                                                           \
+      bih_tile<CC, GG>(d, w0, wend, gl);                           \
+    return;                                                        \
+  }
+  SHEN_TILE(4, 8)
+  SHEN_TILE(8, 4)
+  SHEN_TILE(8, 8)
+  SHEN_TILE(8, 16)
+  SHEN_TILE(16, 16)
+  SHEN_TILE(16, 32)
+#undef SHEN_TILE
+}
+
+__global__ void batched_clear(unsigned long long* __restrict__ counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counter[0] = 0ULL;
+}
+
+__global__ __launch_bounds__(64) void batched_persistent(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                                         unsigned long long* __restrict__ counter, int gl) {
+  __shared__ long long s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ULL);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= tiles_total) break;
+    int lo = 0, hi = ndesc - 1;  // last descriptor whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].tile_begin <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const shen_problem d = desc[lo];
+    const int64_t w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
+    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
+    run_tile(d, w0, wend, gl);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(work);
+  hipLaunchKernelGGL(batched_clear, dim3(1), dim3(64), 0, st, counter);
+  if (tiles_total > 0)
+    hipLaunchKernelGGL(batched_persistent, dim3((unsigned)blocks), dim3(64), 0, st, (const shen_problem*)desc, ndesc, tiles_total,
+                       counter, gl);
+  return hipGetLastError();
 }
 
 }  // namespace shen

@@ -1,0 +1,316 @@
+"""GPU parity of the batched, differentiable, mixed-precision and matvec forms."""
+import numpy as np
+import pytest
+
+from oracle import shen_oracle as so
+from paper_1701_03787_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1701_03787_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+# ----------------------------------------------------------------- batched
+
+def _problems(grids, dev, families=("helmholtz", "biharmonic"), tile=0, rows_per_grid=None):
+    from paper_1701_03787_amd.batched import BatchedProblem
+    probs, host = [], []
+    rng = np.random.default_rng([1701, 44])
+    for g in grids:
+        for fam in families:
+            f = g.rhs(fam)
+            cs = g.coefficients(fam)
+            p = BatchedProblem(fam, T(f, dev), [T(c, dev) for c in cs], tile=tile)
+            rows = np.arange(g.nsys) if rows_per_grid is None else np.unique(
+                np.concatenate([[0, g.nsys - 1], rng.choice(g.nsys, min(g.nsys, rows_per_grid), replace=False)]))
+            probs.append(p)
+            host.append((g, fam, f[rows], tuple(c[rows] for c in cs), rows))
+    return probs, host
+
+
+def _check(probs, host):
+    for p, (g, fam, f, cs, rows) in zip(probs, host):
+        u = p.u.cpu().numpy()[rows]
+        ref = so.solve(fam, g.N, cs, f)
+        e = so.rel_err_per_system(u, ref).max()
+        assert e <= TOL, (g.name, fam, e)
+        n = wl.n_unknowns(fam, g.N)
+        assert np.all(p.u.cpu().numpy()[:, n:] == 0)
+
+
+@pytest.mark.parametrize("tile", [0, 7, 32, 64])
+def test_batched_mixed_grids(dev, tile):
+    from paper_1701_03787_amd.batched import BatchedSolver
+    grids = [wl.small_grid(N, ns, index=i) for i, (N, ns) in enumerate([(64, 33), (128, 70), (256, 17), (512, 40), (1024, 9),
+                                                                         (96, 5), (130, 64)])]
+    case(test="batched_mixed", tile=tile)
+    probs, host = _problems(grids, dev, tile=tile)
+    s = BatchedSolver(probs)
+    s.run()
+    torch.cuda.synchronize()
+    _check(probs, host)
+
+
+def test_batched_config4_full_size(dev):
+    """All 48 grids of the batching workload, both families, one persistent launch."""
+    from paper_1701_03787_amd.batched import BatchedSolver
+    grids = wl.config_grids(4)
+    case(test="batched_config4", grids=len(grids))
+    probs, host = _problems(grids, dev, rows_per_grid=6)
+    s = BatchedSolver(probs)
+    s.run()
+    torch.cuda.synchronize()
+    _check(probs, host)
+
+
+def test_batched_graph_replays(dev):
+    """Capture once, replay several times with eager work in between; every replay
+    must reproduce the eager result bit for bit."""
+    from paper_1701_03787_amd.batched import BatchedSolver
+    grids = [wl.small_grid(N, ns, index=10 + i) for i, (N, ns) in enumerate([(512, 50), (128, 90), (1024, 12)])]
+    case(test="batched_graph")
+    probs, host = _problems(grids, dev)
+    s = BatchedSolver(probs)
+    s.run()
+    torch.cuda.synchronize()
+    eager = [p.u.clone() for p in probs]
+    s.capture()
+    for r in range(3):
+        for p in probs:
+            p.u.zero_()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device=dev).sum()  # unrelated eager work between replays
+        s.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for p, e in zip(probs, eager):
+            assert torch.equal(p.u, e), r
+    _check(probs, host)
+
+
+def test_autotuner_cache(dev, tmp_path):
+    from paper_1701_03787_amd.batched import Autotuner, TILE_CANDIDATES
+    case(test="autotune")
+    t = Autotuner(str(tmp_path / "tune.json"))
+    tile = t.tune(dev, "biharmonic", 256, nsys=2048, reps=2)
+    assert tile in TILE_CANDIDATES
+    t2 = Autotuner(str(tmp_path / "tune.json"))
+    assert t2.get(dev, "biharmonic", 256) == tile
+
+
+# -------------------------------------------------------- differentiation
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("N", [33, 128, 512])
+def test_adjoint_vs_oracle(dev, family, N):
+    from paper_1701_03787_amd import api
+    g = wl.small_grid(N, 21, index=N)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    gu = wl.random_vector((g.nsys, N), (N, 1))
+    n = wl.n_unknowns(family, N)
+    gu[:, n:] = 0
+    case(test="adjoint", family=family, N=N)
+    u_ref, lam_ref, grads_ref = so.solve_grads(family, N, cs, f, gu)
+    ut = T(u_ref, dev)
+    if family == "helmholtz":
+        lam, ga = api.helmholtz_adjoint(ut, T(gu, dev), T(cs[0], dev))
+        grads = [ga]
+    else:
+        lam, ga, gb = api.biharmonic_adjoint(ut, T(gu, dev), T(cs[0], dev), T(cs[1], dev))
+        grads = [ga, gb]
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(lam.cpu().numpy(), lam_ref).max() <= TOL
+    for gg, gr in zip(grads, grads_ref):
+        np.testing.assert_allclose(gg.cpu().numpy(), gr, rtol=1e-10, atol=1e-300)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_dot_product_identity(dev, family):
+    """<H^T lam, v> = <lam, H v> with the GPU matvec, and H^T(H^-T g) = g."""
+    from paper_1701_03787_amd import api
+    N = 200
+    g = wl.small_grid(N, 16, index=3)
+    cs = [T(c, dev) for c in g.coefficients(family)]
+    n = wl.n_unknowns(family, N)
+    gv = wl.random_vector((g.nsys, N), (5,))
+    v = wl.random_vector((g.nsys, N), (6,))
+    gv[:, n:] = 0
+    v[:, n:] = 0
+    case(test="dot", family=family)
+    if family == "helmholtz":
+        lam = api.helmholtz_solve(T(gv, dev), *cs, transpose=True)
+        HTl = api.helmholtz_matvec(lam, *cs, transpose=True)
+        Hv = api.helmholtz_matvec(T(v, dev), *cs)
+    else:
+        lam = api.biharmonic_solve(T(gv, dev), *cs, transpose=True)
+        HTl = api.biharmonic_matvec(lam, *cs, transpose=True)
+        Hv = api.biharmonic_matvec(T(v, dev), *cs)
+    torch.cuda.synchronize()
+    lam, HTl, Hv = lam.cpu().numpy(), HTl.cpu().numpy(), Hv.cpu().numpy()
+    lhs = np.sum(HTl * v, axis=1)
+    rhs = np.sum(lam * Hv, axis=1)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11)
+    assert so.rel_err_per_system(HTl, gv).max() <= 1e-10
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_matvec_vs_oracle(dev, family):
+    from paper_1701_03787_amd import api
+    for N in (9, 64, 257):
+        g = wl.small_grid(N, 11, index=N)
+        cs = g.coefficients(family)
+        u = g.rhs(family)
+        for tr in (False, True):
+            case(test="matvec", family=family, N=N, transpose=tr)
+            ref = so.matvec(family, N, cs, u, transpose=tr, extended=True)
+            fn = api.helmholtz_matvec if family == "helmholtz" else api.biharmonic_matvec
+            got = fn(T(u, dev), *[T(c, dev) for c in cs], transpose=tr).cpu().numpy()
+            scale = np.max(np.abs(ref), axis=1, keepdims=True)
+            assert np.max(np.abs(got - ref) / scale) <= 1e-13
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_autograd_finite_differences(dev, family):
+    """torch.autograd through the hand-written adjoint vs central differences of the
+    FP64 forward solve (relative step 1e-6 * max(1, |c|) on coefficients, 1e-6 on f)."""
+    from paper_1701_03787_amd import api
+    N = 64
+    g = wl.small_grid(N, 6, index=7)
+    cs = [T(c, dev).requires_grad_(True) for c in g.coefficients(family)]
+    f = T(g.rhs(family), dev).requires_grad_(True)
+    w = T(wl.random_vector((g.nsys, N), (7,)), dev)
+
+    def loss(ff, *cc):
+        u = api.helmholtz(ff, *cc) if family == "helmholtz" else api.biharmonic(ff, *cc)
+        return (torch.real(torch.sum(torch.conj(w) * u)) + 0.5 * torch.sum(torch.abs(u) ** 2))
+
+    case(test="autograd_fd", family=family)
+    Lv = loss(f, *cs)
+    Lv.backward()
+    with torch.no_grad():
+        for ci, c in enumerate(cs):
+            for idx in (0, 3):
+                h = 1e-6 * max(1.0, abs(float(c[idx])))
+                cp = [x.detach().clone() for x in cs]
+                cm = [x.detach().clone() for x in cs]
+                cp[ci][idx] += h
+                cm[ci][idx] -= h
+                fd = float(loss(f.detach(), *cp) - loss(f.detach(), *cm)) / (2 * h)
+                an = float(c.grad[idx])
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (ci, idx, fd, an)
+        n = wl.n_unknowns(family, N)
+        d = T(wl.random_vector((g.nsys, N), (8,)), dev)
+        d[:, n:] = 0
+        h = 1e-6
+        fd = float(loss(f.detach() + h * d, *[x.detach() for x in cs]) - loss(f.detach() - h * d, *[x.detach() for x in cs])) / (2 * h)
+        an = float(torch.real(torch.sum(torch.conj(f.grad) * d)))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+        assert torch.all(f.grad[:, n:] == 0)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_autograd_config5_vs_dense(dev, family):
+    """Full-size differentiation workload; gradients of 256 sampled systems against the
+    dense-LU oracle gradient (<= 1e-10 relative)."""
+    from paper_1701_03787_amd import api
+    g = wl.config_grids(5)[0]
+    N = g.N
+    csn = g.coefficients(family)
+    fn = g.rhs(family)
+    case(test="autograd_c5", family=family, nsys=g.nsys)
+    wv = wl.random_vector((g.nsys, N), (5, 1))
+    cs = [T(c, dev).requires_grad_(True) for c in csn]
+    f = T(fn, dev).requires_grad_(True)
+    w = T(wv, dev)
+    u = api.helmholtz(f, *cs) if family == "helmholtz" else api.biharmonic(f, *cs)
+    L = torch.real(torch.sum(torch.conj(w) * u)) + 0.5 * torch.sum(torch.abs(u) ** 2)
+    L.backward()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng([1701, 5, 9])
+    rows = np.unique(np.concatenate([[0, g.nsys - 1, int(np.argmin(g.K2))], rng.choice(g.nsys, 253, replace=False)]))
+    u_np = u.detach().cpu().numpy()[rows]
+    gu = wv[rows] + u_np
+    n = wl.n_unknowns(family, N)
+    gu[:, n:] = 0
+    u_ref, lam_ref, grads_ref = so.solve_grads(family, N, tuple(c[rows] for c in csn), fn[rows], gu)
+    assert so.rel_err_per_system(u_np, u_ref).max() <= TOL
+    assert so.rel_err_per_system(f.grad.cpu().numpy()[rows], lam_ref).max() <= 1e-10
+    for c, gr in zip(cs, grads_ref):
+        got = c.grad.cpu().numpy()[rows]
+        assert np.max(np.abs(got - gr) / np.maximum(np.abs(gr), 1e-300)) <= 1e-10
+
+
+# -------------------------------------------------------------- precision
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("N", [64, 256, 512])
+def test_mixed_precision(dev, family, N):
+    from paper_1701_03787_amd import api
+    g = wl.small_grid(N, 40, kmax=256, index=N)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    case(test="mixed", family=family, N=N)
+    ref = so.solve(family, N, cs, f)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True)
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
+    assert np.all(info.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_mixed_precision_fallback(dev, family):
+    """One correction is not enough for 1e-14: every system falls back to FP64 (info -2)
+    and the answer still meets the FP64 bar."""
+    from paper_1701_03787_amd import api
+    N = 256
+    g = wl.small_grid(N, 12, kmax=256, index=5)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    case(test="mixed_fallback", family=family)
+    ref = so.solve(family, N, cs, f)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, refine_max=1)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == -2)
+    assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
+
+
+# ------------------------------------------------------ roundoff protocol
+
+@pytest.mark.parametrize("family", ["biharmonic", "helmholtz"])
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+def test_roundoff_protocol_vs_paper(dev, family, variant):
+    """Sec. 5 protocol on the GPU kernels: within 4x of the paper's table."""
+    from paper_1701_03787_amd import api
+    from test_oracle_solutions import _roundoff_table, roundoff_protocol
+    table = _roundoff_table()
+
+    def solver(fam, N, c, f):
+        fn = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
+        u = fn(T(f, dev), *[T(x, dev) for x in c], variant=variant)
+        return u.cpu().numpy()
+
+    for N in (64, 256, 1024):
+        for z in (0, 200, 1800, 5400):
+            case(test="roundoff", family=family, N=N, z=z, variant=variant)
+            e = roundoff_protocol(solver, family, N, z, runs=16)
+            assert e <= 4 * table[(family, z)][N], (N, z, e)
