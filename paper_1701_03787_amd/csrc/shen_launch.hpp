@@ -45,7 +45,7 @@ struct WaveArgs {
 struct WaveCfg {
   int C, G;
 };
-__host__ __device__ WaveCfg pick_cfg(int nc, int family);
+__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N);
 bool wave_supported(int family, int N);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);

@@ -650,25 +650,27 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
 // host side
 // =========================================================================
 
-// chunk length C and lanes per chain G such that each parity owns nc >= ceil(N/2)
-// slots (the lanes also write the zero tail), 0 if none fits
-__host__ __device__ WaveCfg pick_cfg(int nc, int family) {
-  if (nc <= 32) return family == 1 ? WaveCfg{8, 4} : WaveCfg{4, 8};
-  if (nc <= 64) return {8, 8};
-  if (nc <= 128) return {8, 16};
-  if (nc <= 256) return {16, 16};
-  if (nc <= 512) return {16, 32};
-  return {0, 0};
+// Chunk length C and lanes per chain G: the first candidate whose 2G lanes
+// cover every slot k < N (G*C >= nc = ceil(N/2)) and whose restart states fit
+// in one output row (2G chunks x 2 or 10 doubles <= 2N doubles); {0,0} if none.
+__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N) {
+  const WaveCfg helm[] = {{4, 8}, {8, 8}, {8, 16}, {16, 16}, {16, 32}};
+  const WaveCfg bih[] = {{8, 4}, {16, 4}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {16, 32}};
+  const WaveCfg* list = family == 0 ? helm : bih;
+  const int cnt = family == 0 ? 5 : 7;
+  const int per = family == 0 ? 2 : 10;
+  for (int i = 0; i < cnt; ++i) {
+    const WaveCfg c = list[i];
+    if (c.G * c.C >= nc && per * 2 * c.G <= 2 * N) return c;
+  }
+  return WaveCfg{0, 0};
 }
 
 bool wave_supported(int family, int N) {
   const int n = family == 0 ? N - 2 : N - 4;
   if (n < 1) return false;
-  const WaveCfg c = pick_cfg((N + 1) / 2, family);
-  if (c.C == 0) return false;
-  const int per = family == 0 ? 2 : 10;  // doubles of restart state per chunk
-  if (per * 2 * c.G > 2 * N) return false;  // states must fit in the output row
-  return 2 * c.G * c.C >= N;
+  const WaveCfg c = pick_cfg((N + 1) / 2, family, N);
+  return c.C != 0;
 }
 
 // Systems per boundary/solve launch pair.  Smaller slices keep the restart
@@ -714,15 +716,17 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
 hipError_t launch_wave(const WaveArgs& a) {
   const int n = a.family == 0 ? a.N - 2 : a.N - 4;
   (void)n;
-  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family);
+  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N);
   if (a.nsys <= 0) return hipSuccess;
   if ((a.nsys + 1) > 0x7fffffffLL) return hipErrorInvalidValue;
 #define SHEN_DISPATCH(CC, GG)                                                         \
   if (c.C == CC && c.G == GG) return a.family == 0 ? launch_helm_t<CC, GG>(a) : launch_bih_t<CC, GG>(a);
   SHEN_DISPATCH(4, 8)
   SHEN_DISPATCH(8, 4)
+  SHEN_DISPATCH(16, 4)
   SHEN_DISPATCH(8, 8)
   SHEN_DISPATCH(8, 16)
+  SHEN_DISPATCH(16, 8)
   SHEN_DISPATCH(16, 16)
   SHEN_DISPATCH(16, 32)
 #undef SHEN_DISPATCH
@@ -772,7 +776,7 @@ __device__ __forceinline__ void bih_tile(const shen_problem& d, int64_t w0, int6
 }
 
 __device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
-  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family);
+  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N);
 #define SHEN_TILE(CC, GG)                                          \
   if (c.C == CC && c.G == GG) {                                    \
     if (d.family == SHEN_HELMHOLTZ)                                \
@@ -783,8 +787,10 @@ __device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t
   }
   SHEN_TILE(4, 8)
   SHEN_TILE(8, 4)
+  SHEN_TILE(16, 4)
   SHEN_TILE(8, 8)
   SHEN_TILE(8, 16)
+  SHEN_TILE(16, 8)
   SHEN_TILE(16, 16)
   SHEN_TILE(16, 32)
 #undef SHEN_TILE
