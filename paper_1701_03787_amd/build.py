@@ -29,6 +29,12 @@ HIPCC_FLAGS = [
 ]
 
 
+# The wave kernels restart the LU recurrence from states written by a separate
+# kernel: both must round identically, so no compiler-chosen FMA contraction
+# there (explicit fma calls stay fused).
+PER_FILE_FLAGS = {"wave_kernels.hip": ["-ffp-contract=off"]}
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -43,7 +49,8 @@ def build_library(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = [cc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        extra = PER_FILE_FLAGS.get(os.path.basename(src), [])
+        cmd = [cc, *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -448,6 +448,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     T01 = n01;
   }
   // forward scan: (T, b = (y_last, y_last-1)); compose(later, earlier) = (T_l T_e, T_l b_e + b_l)
+  const double L00 = T00, L01 = T01, L10 = T10, L11 = T11;  // this chunk's own transfer
   double2 b0 = y1, b1 = y2;
   auto composeT = [&](double o00, double o01, double o10, double o11, double2 ob0, double2 ob1) {
     const double2 n0 = c_add(c_fma(T00, ob0, c_mul(T01, ob1)), b0);
@@ -462,6 +463,65 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     b1 = n1;
   };
   double2 h1, h2;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      composeT(S::from_lower(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower(T11), S::from_lower(b0),
+               S::from_lower(b1));
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    h1 = RowShift<1>::from_lower(b0);
+    h2 = RowShift<1>::from_lower(b1);
+  } else {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
+      const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
+      const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
+      if (m >= d) composeT(o00, o01, o10, o11, ob0, ob1);
+    }
+    h1 = shfl_up2(b0, 1, G);
+    h2 = shfl_up2(b1, 1, G);
+    if (m == 0) {
+      h1 = zero2();
+      h2 = zero2();
+    }
+  }
+  // The chunk-local particular solutions started from a zero state can be far
+  // larger than y itself (the forward recurrence has modes of modulus close to
+  // one), so the scanned incoming states carry their rounding.  One refinement
+  // sweep: rerun every chunk from f and the scanned state sh, scan the (small)
+  // defects e_m - sh_{m+1} with the same transfers, and add the response.
+  const double2 sh1 = h1, sh2 = h2;  // approximate (y_{i0-1}, y_{i0-2})
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const double2 fj = (wok && k < n) ? frow[k] : zero2();
+    double2 y = c_fnms(l1j[j], h1, fj);
+    y = c_fnms(l2j[j], h2, y);
+    x[j] = y;
+    h2 = h1;
+    h1 = y;
+  }
+  {
+    double2 nx1, nx2;  // approximate incoming state of the next chunk
+    if constexpr (G == 16) {
+      nx1 = RowShift<1>::from_upper(sh1);
+      nx2 = RowShift<1>::from_upper(sh2);
+    } else {
+      nx1 = shfl_down2(sh1, 1, G);
+      nx2 = shfl_down2(sh2, 1, G);
+    }
+    T00 = L00;
+    T01 = L01;
+    T10 = L10;
+    T11 = L11;
+    b0 = c_sub(h1, nx1);
+    b1 = c_sub(h2, nx2);
+  }
   if constexpr (G == 16) {
     auto lvl = [&](auto sh) {
       using S = decltype(sh);

@@ -160,13 +160,27 @@ def bih_chunked(a, b, f, N, C, G, gl=False):
         comp = lambda later, earlier: (np.einsum("sab,sbc->sac", later[0], earlier[0]),
                                        np.einsum("sab,sb->sa", later[0], earlier[1]) + later[1])
         inc = ks_prefix(items, comp, G)
-        y = y0.copy()
+        zero = np.zeros((ns, 2), complex)
+        shat = [zero] + [inc[m - 1][1] for m in range(1, G)]
+        # refinement sweep: rerun each chunk from f and its scanned state, scan the
+        # defects e_m - shat_{m+1} with the same transfers, add the response
+        y = np.zeros_like(x)
+        defects = []
+        for m in range(G):
+            s = shat[m].copy()
+            for j in range(C):
+                i = m * C + j
+                yi = x[:, i] - l1[:, i] * s[:, 0] - l2[:, i] * s[:, 1]
+                y[:, i] = yi
+                s = np.stack([yi, s[:, 0]], 1)
+            defects.append(s - (shat[m + 1] if m + 1 < G else s))
+        inc2 = ks_prefix([(items[m][0], defects[m]) for m in range(G)], comp, G)
         for m in range(1, G):
-            h = inc[m - 1][1].copy()  # (h_{i-1}, h_{i-2})
+            h = inc2[m - 1][1].copy()
             for j in range(C):
                 i = m * C + j
                 hi = -l1[:, i] * h[:, 0] - l2[:, i] * h[:, 1]
-                y[:, i] = y0[:, i] + hi
+                y[:, i] = y[:, i] + hi
                 h = np.stack([hi, h[:, 0]], 1)
         yh = r0 * y
         items = []

@@ -29,8 +29,8 @@ def test_chunked_roundoff_protocol():
     """Sec. 5 protocol at z = 0 and 5400 (the extremes), N = 512."""
     from test_oracle_solutions import _roundoff_table, roundoff_protocol
     table = _roundoff_table()
-    for z in (0, 5400):
+    for z in (0, 1800, 5400):
         e = roundoff_protocol(lambda fam, N, c, f: ca.bih_chunked(c[0], c[1], f, N, 16, 16), "biharmonic", 512, z, 4)
-        assert e <= 4 * table[("biharmonic", z)][512], (z, e)
+        assert e <= 1.5 * table[("biharmonic", z)][512], (z, e)
         e = roundoff_protocol(lambda fam, N, c, f: ca.helm_chunked(c[0], f, N, 16, 16), "helmholtz", 512, z, 4)
         assert e <= 4 * table[("helmholtz", z)][512], (z, e)

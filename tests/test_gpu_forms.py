@@ -253,9 +253,15 @@ def test_autograd_config5_vs_dense(dev, family):
     u_ref, lam_ref, grads_ref = so.solve_grads(family, N, tuple(c[rows] for c in csn), fn[rows], gu)
     assert so.rel_err_per_system(u_np, u_ref).max() <= TOL
     assert so.rel_err_per_system(f.grad.cpu().numpy()[rows], lam_ref).max() <= 1e-10
-    for c, gr in zip(cs, grads_ref):
+    # A coefficient gradient is a sum -Re sum_k conj(lam_k) (M u)_k whose terms can cancel:
+    # its attainable accuracy is relative to sum_k |lam_k| |(M u)_k|, the scale used here.
+    op = so.Operators.get(N)
+    mats = [op.Bd] if family == "helmholtz" else [op.Ab, op.Bb]
+    for c, gr, M in zip(cs, grads_ref, mats):
         got = c.grad.cpu().numpy()[rows]
-        assert np.max(np.abs(got - gr) / np.maximum(np.abs(gr), 1e-300)) <= 1e-10
+        scale = np.sum(np.abs(lam_ref[:, :n]) * np.abs(np.einsum("kj,wj->wk", M, u_ref[:, :n])), axis=1)
+        assert np.max(np.abs(got - gr) / scale) <= 1e-12
+        assert np.max(np.abs(got - gr) / np.abs(gr)) <= 1e-8
 
 
 # -------------------------------------------------------------- precision
@@ -309,8 +315,14 @@ def test_roundoff_protocol_vs_paper(dev, family, variant):
         u = fn(T(f, dev), *[T(x, dev) for x in c], variant=variant)
         return u.cpu().numpy()
 
+    # Both kernel families stay within 4x of the paper's table; the wave kernels need
+    # the refinement sweep of their forward-elimination scan for that.
+    bound = 4.0
+    worst = []
     for N in (64, 256, 1024):
         for z in (0, 200, 1800, 5400):
             case(test="roundoff", family=family, N=N, z=z, variant=variant)
             e = roundoff_protocol(solver, family, N, z, runs=16)
-            assert e <= 4 * table[(family, z)][N], (N, z, e)
+            worst.append((e / table[(family, z)][N], N, z, e))
+    print("roundoff ratios to the paper:", sorted(worst)[-4:], flush=True)
+    assert max(w[0] for w in worst) <= bound, sorted(worst)[-3:]
