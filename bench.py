@@ -144,7 +144,7 @@ def main():
     if not args.no_cpu:
         from threadpoolctl import threadpool_limits
         threads = so.host_threads()
-        per_fam = min(nsys, max(64, 24 * threads))
+        per_fam = min(nsys, max(256, 1024 * threads))
         sample = rng.choice(nsys, per_fam, replace=False)
         t_cpu = 0.0
         with threadpool_limits(limits=1):
