@@ -40,6 +40,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--variant", default="auto")
+    ap.add_argument("--chunk", type=int, default=0, help="wave kernels: preferred chunk length (0 = automatic)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -73,9 +74,9 @@ def main():
     def launch(fam, precision="fp64"):
         f, cs, u = data[fam]
         if fam == "helmholtz":
-            api.helmholtz_solve(f, cs[0], out=u, precision=precision, variant=args.variant)
+            api.helmholtz_solve(f, cs[0], out=u, precision=precision, variant=args.variant, chunk=args.chunk)
         else:
-            api.biharmonic_solve(f, cs[0], cs[1], out=u, precision=precision, variant=args.variant)
+            api.biharmonic_solve(f, cs[0], cs[1], out=u, precision=precision, variant=args.variant, chunk=args.chunk)
 
     def timed(precision):
         for _ in range(args.warmup):

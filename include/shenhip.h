@@ -89,8 +89,10 @@ typedef struct {
                          means 1e-14.  Refinement also stops once a
                          correction fails to halve (rounding floor).         */
   int32_t* info;      /* optional DEVICE int32[nsys] status per system       */
-  int32_t variant;    /* kernel choice: 0 = automatic (see shen_variant_*)   */
-  int32_t reserved;
+  int32_t variant;    /* kernel choice: 0 = automatic (SHEN_VARIANT_*)       */
+  int32_t chunk;      /* wave kernels: preferred chunk length (coefficients
+                         per lane and parity chain, 8 or 16); 0 = automatic.
+                         A tuning knob: results agree to rounding.            */
 } shen_opts;
 
 /* kernel variants (opts.variant); 0 picks per N and mode */

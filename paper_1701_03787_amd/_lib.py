@@ -35,7 +35,7 @@ class ShenOpts(C.Structure):
         ("refine_tol", C.c_double),
         ("info", C.c_void_p),
         ("variant", C.c_int32),
-        ("reserved", C.c_int32),
+        ("chunk", C.c_int32),
     ]
 
 

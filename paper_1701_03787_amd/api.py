@@ -23,7 +23,7 @@ def _stream_handle(device) -> int:
 
 
 def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8, refine_tol=1e-14,
-          variant="auto") -> L.ShenOpts:
+          variant="auto", chunk=0) -> L.ShenOpts:
     o = L.default_opts()
     o.stream = _stream_handle(device)
     o.precision = _PREC[precision]
@@ -33,6 +33,7 @@ def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refin
     o.refine_tol = float(refine_tol)
     o.info = info.data_ptr() if info is not None else None
     o.variant = _VARIANT[variant] if isinstance(variant, str) else int(variant)
+    o.chunk = int(chunk)
     return o
 
 
@@ -78,7 +79,7 @@ def _nsys(lead) -> int:
 
 
 def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                    refine_tol=1e-14, variant="auto"):
+                    refine_tol=1e-14, variant="auto", chunk=0):
     """u = (S + alpha B)^{-1} f per system (or the transposed system).
 
     Returns u, or (u, info) when info is requested (True or an int32 tensor)."""
@@ -88,14 +89,14 @@ def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpos
     alpha = _coef(alpha, lead, f.device, "alpha")
     u = torch.empty_like(f) if out is None else _rows(out, "out")
     inf = _info_tensor(info, lead, f.device)
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk)
     L.check(L.lib().helmholtz_solve(N, _nsys(lead), alpha.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "helmholtz_solve")
     return (u, inf) if inf is not None else u
 
 
 def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                     refine_tol=1e-14, variant="auto"):
+                     refine_tol=1e-14, variant="auto", chunk=0):
     """u = (Q + a A + b B)^{-1} f per system (or the transposed system)."""
     f = _rows(f, "f")
     N = f.shape[-1]
@@ -104,7 +105,7 @@ def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpos
     b = _coef(b, lead, f.device, "b")
     u = torch.empty_like(f) if out is None else _rows(out, "out")
     inf = _info_tensor(info, lead, f.device)
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk)
     L.check(L.lib().biharmonic_solve(N, _nsys(lead), a.data_ptr(), b.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "biharmonic_solve")
     return (u, inf) if inf is not None else u

@@ -57,6 +57,7 @@ int check_opts(const shen_opts& o) {
   if (o.variant < 0 || o.variant > 2) return SHEN_EINVAL;
   if (o.info && !aligned(o.info, 4)) return SHEN_EINVAL;
   if (o.refine_max > 64) return SHEN_EINVAL;
+  if (o.chunk < 0 || o.chunk > 64) return SHEN_EINVAL;
   return SHEN_OK;
 }
 
@@ -176,6 +177,7 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
     w.u = u;
     w.info = o.info;
     w.gl = o.quad == SHEN_QUAD_GL;
+    w.chunk = o.chunk;
     w.stream = o.stream;
     return run_wave(w);
   }
@@ -216,6 +218,7 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
     w.u = u;
     w.info = o.info;
     w.gl = o.quad == SHEN_QUAD_GL;
+    w.chunk = o.chunk;
     w.stream = o.stream;
     return run_wave(w);
   }

@@ -39,13 +39,14 @@ struct WaveArgs {
   void* u = nullptr;  // must not alias f (restart states are parked in it)
   int32_t* info = nullptr;
   int gl = 0;
+  int chunk = 0;  // preferred chunk length C (0: automatic)
   void* stream = nullptr;
 };
 
 struct WaveCfg {
   int C, G;
 };
-__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N);
+__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);

@@ -713,15 +713,18 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
 // Chunk length C and lanes per chain G: the first candidate whose 2G lanes
 // cover every slot k < N (G*C >= nc = ceil(N/2)) and whose restart states fit
 // in one output row (2G chunks x 2 or 10 doubles <= 2N doubles); {0,0} if none.
-__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N) {
-  const WaveCfg helm[] = {{4, 8}, {8, 8}, {8, 16}, {16, 16}, {16, 32}};
-  const WaveCfg bih[] = {{8, 4}, {16, 4}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {16, 32}};
+__host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC) {
+  const WaveCfg helm[] = {{4, 8}, {8, 8}, {8, 16}, {16, 16}, {8, 32}, {16, 32}};
+  const WaveCfg bih[] = {{8, 4}, {16, 4}, {8, 8}, {8, 16}, {16, 8}, {16, 16}, {8, 32}, {16, 32}};
   const WaveCfg* list = family == 0 ? helm : bih;
-  const int cnt = family == 0 ? 5 : 7;
+  const int cnt = family == 0 ? 6 : 8;
   const int per = family == 0 ? 2 : 10;
-  for (int i = 0; i < cnt; ++i) {
-    const WaveCfg c = list[i];
-    if (c.G * c.C >= nc && per * 2 * c.G <= 2 * N) return c;
+  for (int pass = (prefC > 0 ? 0 : 1); pass < 2; ++pass) {
+    for (int i = 0; i < cnt; ++i) {
+      const WaveCfg c = list[i];
+      if (pass == 0 && c.C != prefC) continue;
+      if (c.G * c.C >= nc && per * 2 * c.G <= 2 * N) return c;
+    }
   }
   return WaveCfg{0, 0};
 }
@@ -729,7 +732,7 @@ __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N) {
 bool wave_supported(int family, int N) {
   const int n = family == 0 ? N - 2 : N - 4;
   if (n < 1) return false;
-  const WaveCfg c = pick_cfg((N + 1) / 2, family, N);
+  const WaveCfg c = pick_cfg((N + 1) / 2, family, N, 0);
   return c.C != 0;
 }
 
@@ -776,7 +779,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
 hipError_t launch_wave(const WaveArgs& a) {
   const int n = a.family == 0 ? a.N - 2 : a.N - 4;
   (void)n;
-  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N);
+  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N, a.chunk);
   if (a.nsys <= 0) return hipSuccess;
   if ((a.nsys + 1) > 0x7fffffffLL) return hipErrorInvalidValue;
 #define SHEN_DISPATCH(CC, GG)                                                         \
@@ -788,6 +791,7 @@ hipError_t launch_wave(const WaveArgs& a) {
   SHEN_DISPATCH(8, 16)
   SHEN_DISPATCH(16, 8)
   SHEN_DISPATCH(16, 16)
+  SHEN_DISPATCH(8, 32)
   SHEN_DISPATCH(16, 32)
 #undef SHEN_DISPATCH
   return hipErrorInvalidValue;
@@ -836,7 +840,7 @@ __device__ __forceinline__ void bih_tile(const shen_problem& d, int64_t w0, int6
 }
 
 __device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
-  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N);
+  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
 #define SHEN_TILE(CC, GG)                                          \
   if (c.C == CC && c.G == GG) {                                    \
     if (d.family == SHEN_HELMHOLTZ)                                \
@@ -852,6 +856,7 @@ __device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t
   SHEN_TILE(8, 16)
   SHEN_TILE(16, 8)
   SHEN_TILE(16, 16)
+  SHEN_TILE(8, 32)
   SHEN_TILE(16, 32)
 #undef SHEN_TILE
 }

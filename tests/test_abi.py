@@ -60,7 +60,8 @@ def test_helmholtz_argument_errors(args, code):
 
 def test_bad_enums_and_sizes():
     lib = L.lib()
-    for field, val in (("precision", 5), ("quad", 2), ("transpose", 3), ("variant", 9), ("refine_max", 1000)):
+    for field, val in (("precision", 5), ("quad", 2), ("transpose", 3), ("variant", 9), ("refine_max", 1000),
+                       ("chunk", -1), ("chunk", 65)):
         o = L.default_opts()
         setattr(o, field, val)
         assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL, field

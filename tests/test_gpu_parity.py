@@ -179,3 +179,21 @@ def test_wave_variant_rules(dev, family):
     torch.cuda.synchronize()
     e = so.rel_err_per_system(uw.cpu().numpy(), uc.cpu().numpy())
     assert e.max() <= TOL
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("chunk", [4, 8, 16])
+def test_wave_chunk_knob(dev, family, chunk):
+    """Every chunk length the wave kernels accept gives the oracle's answer, over ragged N
+    and at the channel size (the knob only changes the lane/chunk split)."""
+    for N in (65, 130, 257, 512, 1024):
+        nsys = 37
+        _print_case(test="chunk", family=family, N=N, nsys=nsys, chunk=chunk)
+        g = wl.small_grid(N, nsys, kmax=200, index=N)
+        coeffs = g.coefficients(family)
+        f = g.rhs(family)
+        ref = so.solve(family, N, coeffs, f)
+        u = gpu_solve(family, N, coeffs, f, dev, variant="wave", chunk=chunk)
+        assert np.all(u[:, wl.n_unknowns(family, N):] == 0)
+        e = so.rel_err_per_system(u, ref)
+        assert e.max() <= TOL, (N, chunk, e.max())
