@@ -24,6 +24,37 @@ METRIC = "wall-normal solves·N/s + HBM GB/s, FP32+refine vs FP64 at 1e-12 rel e
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ("wave_kernels.hip", "shen_rows.hpp", "shen_launch.hpp", "host.hip")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources of the FP64 solve kernels (identifies the code the counters were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_03787_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, family: str):
+    """HBM bytes per solve call from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of this workload,
+    or None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith(("kernel_source_sha256", "traffic_bytes_")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_{family}")
+    return int(v) if v else None
+
+
 def alg_bytes(family: str, N: int, nsys: int) -> int:
     """Algorithmic HBM bytes of one solve: read f[k<n], write u[0:N], read coefficients."""
     if family == "helmholtz":
@@ -121,7 +152,7 @@ def main():
     dom = max(fams, key=lambda fm: kms[fm])
     achieved = alg_bytes(dom, N, nsys) / (kms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(grid.name, dom),
                 "kernel": f"{dom}_solve fp64", "kernel_ms": round(kms[dom], 4),
                 "bytes_per_launch": alg_bytes(dom, N, nsys)}
 
@@ -178,6 +209,7 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = int(x.numel() * 8)
+    out["kernel_source_sha256"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
 
 
