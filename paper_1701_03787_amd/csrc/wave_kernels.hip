@@ -199,6 +199,10 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
 // Helmholtz wave solve
 // =========================================================================
 // Solves systems wbase + (lane / 2G) of the wavefront (those below nsys).
+template <int C, int G, bool PIPE = false>
+__device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
+                                               double2* __restrict__ urow, int gl, int32_t* __restrict__ info);
+
 template <int C, int G>
 __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
                                                const double2* __restrict__ f, double2* __restrict__ u, int gl,
@@ -212,7 +216,6 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
   const int n = N - 2;
   const int k0 = 2 * m * C + p;
   const double al = wok ? alpha[w] : 0.0;
-  const double hm = -0.5 * kPi * al;
   const double2* frow = f + (wok ? w : 0) * (int64_t)N;
   double2* urow = u + (wok ? w : 0) * (int64_t)N;
 
@@ -229,8 +232,25 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
     const int k = k0 + 2 * j;
     x[j] = (wok && k < n) ? frow[k] : zero2();
   }
+  helm_wave_core<C, G>(N, lane, w, wok, al, pv, x, urow, gl, info);
+}
+
+// Everything after the loads: x holds f of this lane's chunk (0 where k >= n),
+// pv the restart state.  Without PIPE the solution is stored to urow; with
+// PIPE it is left in x for the caller.
+template <int C, int G, bool PIPE>
+__device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
+                                               double2* __restrict__ urow, int gl, int32_t* __restrict__ info) {
+  const int p = (lane / G) & 1;
+  const int m = lane % G;
+  const int n = N - 2;
+  const int k0 = 2 * m * C + p;
+  const double hm = -0.5 * kPi * al;
   // factorisation restart + local forward elimination (zero incoming state)
-  double lj[C], rdj[C], gj[C];
+  // l of row k is hm times 1/d of row k-2 (helm_step), so it is rebuilt from
+  // rdj where needed instead of being kept.
+  double rdj[C], gj[C];
+  const double rd_in = (k0 >= 2) ? pv.rd : 0.0;
   int bad = INT_MAX;
   double T = 1.0;
   double2 yp = zero2();
@@ -244,7 +264,6 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
     pv.rd = rd;
     pv.g = g;
     l = ok ? l : 0.0;
-    lj[j] = l;
     rdj[j] = ok ? rd : 0.0;
     gj[j] = ok ? g : 0.0;
     const double2 y = c_fnms(l, yp, x[j]);
@@ -284,7 +303,9 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
   }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    h = c_mul(-lj[j], h);
+    const bool ok = wok && k0 + 2 * j < n;
+    const double l = ok ? hm * (j == 0 ? rd_in : rdj[j - 1]) : 0.0;
+    h = c_mul(-l, h);
     x[j] = c_add(x[j], h);
   }
   // backward: state (a = u_{i+1}, S = S_{i+2});  u_i = yh - eh a - gh S
@@ -359,11 +380,13 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
     sS = c_add(sS, sa);
     sa = uj;
   }
-  if (wok) {
+  if constexpr (!PIPE) {
+    if (wok) {
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = k0 + 2 * j;
-      if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+      for (int j = 0; j < C; ++j) {
+        const int k = k0 + 2 * j;
+        if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+      }
     }
   }
   if (info != nullptr) {
@@ -706,6 +729,165 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
   bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, gl, info);
 }
 
+// -------------------------------------------------------------------------
+// Persistent, software-pipelined form of the wave solve (G >= 16, C >= 8).
+//
+// Each wavefront loops over groups of SPW = 64/(2G) systems.  Two LDS tiles
+// per wavefront alternate: while one group is solved in registers, the next
+// group's right-hand sides stream from HBM straight into the other tile
+// (global_load_lds: no registers held, and each instruction covers 64
+// consecutive rows, so HBM and L2 see whole lines); the solution leaves
+// through the tile its group came in by, again as whole lines.
+//
+// Per iteration there is one wait on vector memory (after the arithmetic):
+// then the prefetched tile is complete and the stores of the previous group
+// are done, so the LDS traffic that follows (stage the solution, read the
+// next group, read the staged rows back for the stores) runs with nothing
+// outstanding, and only then is the tile refilled.
+//
+// Tile layout: system s, row k sits at entry 64 (s NB + k/64) + ((k mod 64)
+// xor (m mod 16)), m = k / 2C its chunk, NB = 2GC/64.  Each global_load_lds
+// instruction fills one 64-entry block; the xor spreads the 16 chunks that a
+// group of 16 lanes touches at one step over all 16 bank groups.  NS extra
+// 64-entry slots hold each lane's restart words.
+// -------------------------------------------------------------------------
+#define SHEN_LDS(ptr) ((__attribute__((address_space(3))) void*)(ptr))
+
+template <int C, int G>
+struct Tile {
+  static constexpr int SPW = 64 / (2 * G);
+  static constexpr int B = 2 * C;             // rows per chunk (both parities)
+  static constexpr int NB = (2 * G * C) / 64;  // 64-row blocks per system
+  static_assert(G >= 16 && C >= 8 && C % 4 == 0, "tile layout needs G >= 16 and C in {8, 16, ...}");
+  // entry of row k of system s
+  static __device__ __forceinline__ int pos(int s, int k) { return 64 * (s * NB + (k >> 6)) + ((k & 63) ^ ((k / B) & 15)); }
+  // row held by entry (block i, lane l): the xor is an involution on the block
+  static __device__ __forceinline__ int row(int i, int l) {
+    const int t = i % NB;
+    return 64 * t + (l ^ (((64 * t + l) / B) & 15));
+  }
+};
+
+// Streams group g into tile T: C instructions of 64 consecutive rows each
+// (rows >= N and systems >= nsys clamped to valid addresses; the reader masks
+// them), then NS 16-byte restart words per lane from the solution rows.
+template <int C, int G, int NS>
+__device__ __forceinline__ void prefetch_tile(double2* T, int lane, int64_t g, int N, int64_t nsys, const double2* __restrict__ f,
+                                              const double2* __restrict__ u) {
+  using TL = Tile<C, G>;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int s = i / TL::NB;
+    const int64_t w = g * TL::SPW + s;
+    const int64_t wc = w < nsys ? w : nsys - 1;
+    const int k = TL::row(i, lane);
+    const int kc = k < N ? k : N - 1;
+    __builtin_amdgcn_global_load_lds((const void*)(f + wc * (int64_t)N + kc), SHEN_LDS(T + 64 * i), 16, 0, 0);
+  }
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = g * TL::SPW + sl;
+  const int64_t wc = w < nsys ? w : nsys - 1;
+  const double2* st = u + wc * (int64_t)N + (p * G + m) * NS;
+#pragma unroll
+  for (int t = 0; t < NS; ++t)
+    __builtin_amdgcn_global_load_lds((const void*)(st + t), SHEN_LDS(T + 64 * (C + t)), 16, 0, 0);
+}
+
+// This lane's chunk (rows k0 + 2j of system sl) and restart words from tile T.
+template <int C, int G, int NS>
+__device__ __forceinline__ void read_tile(const double2* T, int lane, double2 (&x)[C], double2 (&st)[NS]) {
+  using TL = Tile<C, G>;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+#pragma unroll
+  for (int j = 0; j < C; ++j) x[j] = T[TL::pos(sl, k0 + 2 * j)];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) st[t] = T[64 * (C + t) + lane];
+}
+
+// Stages this lane's solution chunk in tile T.
+template <int C, int G>
+__device__ __forceinline__ void stage_tile(double2* T, int lane, const double2 (&x)[C]) {
+  using TL = Tile<C, G>;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+#pragma unroll
+  for (int j = 0; j < C; ++j) T[TL::pos(sl, k0 + 2 * j)] = x[j];
+}
+
+// Stores the staged rows k < N of group g (zero for k >= n) as whole blocks.
+template <int C, int G>
+__device__ __forceinline__ void store_tile(const double2* T, int lane, int64_t g, int N, int n, int64_t nsys,
+                                           double2* __restrict__ u) {
+  using TL = Tile<C, G>;
+  double2 v[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) v[i] = T[64 * i + lane];
+  // keep the LDS reads together (not sunk into the masked stores one by one)
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int s = i / TL::NB;
+    const int64_t w = g * TL::SPW + s;
+    const int k = TL::row(i, lane);
+    if (w < nsys && k < N) u[w * (int64_t)N + k] = (k < n) ? v[i] : zero2();
+  }
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                     int32_t* __restrict__ info) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  __shared__ double2 tile[(C + 1) * 64];
+  const int64_t ngroups = (nsys + SPW - 1) / SPW;
+  const int64_t g0 = blockIdx.x;
+  if (g0 >= ngroups) return;
+  const int n = N - 2;
+  auto coef = [&](int64_t g, int l) {
+    const int64_t w = g * SPW + l / (2 * G);
+    return alpha[w < nsys ? w : nsys - 1];
+  };
+  double2 x[C], st[1];
+  double al;
+  {
+    const int lane = threadIdx.x & 63;
+    prefetch_tile<C, G, 1>(tile, lane, g0, N, nsys, f, u);
+    al = coef(g0, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    read_tile<C, G, 1>(tile, lane, x, st);
+  }
+  for (int64_t g = g0; g < ngroups; g += gridDim.x) {
+    // Lane-derived indices are re-derived every iteration from an opaque
+    // copy: hoisting the per-row constants out of the loop would hold them
+    // in registers across it.
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+    const int k0 = 2 * m * C + p;
+    const int64_t w = g * SPW + sl;
+    const bool wok = w < nsys;
+#pragma unroll
+    for (int j = 0; j < C; ++j) x[j] = (wok && k0 + 2 * j < n) ? x[j] : zero2();
+    HelmPrev pv = {0.0, 0.0};
+    if (wok && m > 0 && k0 < n) {
+      pv.rd = st[0].x;
+      pv.g = st[0].y;
+    }
+    helm_wave_core<C, G, true>(N, lane, w, wok, wok ? al : 0.0, pv, x, u, gl, info);
+    stage_tile<C, G>(tile, lane, x);
+    store_tile<C, G>(tile, lane, g, N, n, nsys, u);
+    const int64_t gn = g + gridDim.x;
+    if (gn < ngroups) {
+      prefetch_tile<C, G, 1>(tile, lane, gn, N, nsys, f, u);
+      al = coef(gn, lane);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      read_tile<C, G, 1>(tile, lane, x, st);
+    }
+  }
+}
+
 // =========================================================================
 // host side
 // =========================================================================
@@ -741,6 +923,17 @@ bool wave_supported(int family, int N) {
 // of waves; measured slower at the channel-scale sizes, so off.
 static constexpr int64_t kWaveSlice = (int64_t)1 << 40;  // no slicing: boundary kernels need the whole grid for occupancy
 
+// Grid of a persistent kernel: every resident wavefront slot of the device,
+// capped by the number of work groups.
+static int64_t persistent_blocks(const void* kernel, int64_t groups) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t slots = (int64_t)cus * per_cu;
+  return groups < slots ? (groups > 0 ? groups : 1) : slots;
+}
+
 template <int C, int G>
 static hipError_t launch_helm_t(const WaveArgs& a) {
   constexpr int SPW = 64 / (2 * G);
@@ -752,8 +945,13 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
     hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
-    hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)((ns + SPW - 1) / SPW)), dim3(64), 0, st, a.N, ns, c0, f, u,
-                       a.gl, info);
+    const int64_t groups = (ns + SPW - 1) / SPW;
+    if constexpr (C >= 8 && C % 4 == 0 && G >= 16) {
+      const int64_t blocks = persistent_blocks((const void*)helm_wave_pipe<C, G>, groups);
+      hipLaunchKernelGGL((helm_wave_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);
+    } else {
+      hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);
+    }
   }
   return hipGetLastError();
 }
