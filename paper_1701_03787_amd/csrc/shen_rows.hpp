@@ -150,6 +150,59 @@ __device__ __forceinline__ BihRow bih_row(int k, double a, double b, int N, int 
   return h;
 }
 
+// Coefficient-free constants of biharmonic row k, from which BihRow is
+// assembled together with a few constants of rows k-2 and k-4 (the entries
+// below the diagonal are those of the symmetric B above it, and q_{k+2},
+// s_{k+2} are q4, s4 of row k-2).  Tabulated once per work group; every
+// kernel that restarts a factorisation from another kernel's state must
+// assemble its rows from the same values.  Valid for k >= -4 (only q4, s4
+// are meaningful for k < 0).
+struct BihConst {
+  double Am2, Q0, A0, B0, A2, B2, B4, p, r, q4, s4;
+};
+static constexpr int kBihConstN = 11;
+
+__device__ __forceinline__ BihConst bih_const(int k, int N, int gl) {
+  const double K = (double)k;
+  const double p3 = fast_rcp(K + 3.0), p5 = fast_rcp(K + 5.0), p7 = fast_rcp(K + 7.0);
+  const double g1 = (K + 2.0) * p3;  // (k+2)/(k+3)
+  const double g2 = (K + 1.0) * p3;  // (k+1)/(k+3)
+  BihConst c;
+  c.B0 = 0.5 * kPi * (ck(k, N, gl) + 4.0 * g1 * g1 + ck(k + 4, N, gl) * g2 * g2);
+  c.B2 = -kPi * (g1 + (K + 4.0) * p5 * g2);
+  c.B4 = 0.5 * kPi * g2;
+  c.A0 = -4.0 * kPi * (K + 1.0) * (K + 2.0) * g1;
+  c.A2 = 2.0 * kPi * (K + 1.0) * (K + 2.0);
+  c.Am2 = (k >= 2) ? 2.0 * kPi * (K - 1.0) * (K + 2.0) : 0.0;
+  c.p = 8.0 * kPi * K * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  c.r = 24.0 * kPi * (K + 1.0) * (K + 2.0);
+  c.q4 = p7;
+  c.s4 = (K + 6.0) * (K + 6.0) * p7;
+  c.Q0 = 8.0 * kPi * (K + 1.0) * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  return c;
+}
+
+// Row k from its constants c and the needed constants of rows k-2 (B2, q4,
+// s4) and k-4 (B4).
+__device__ __forceinline__ BihRow bih_row_tab(int k, double a, double b, const BihConst& c, double B2m2, double q4m2,
+                                              double s4m2, double B4m4) {
+  BihRow h;
+  h.hm4 = (k >= 4) ? b * B4m4 : 0.0;
+  h.hm2 = (k >= 2) ? a * c.Am2 + b * B2m2 : 0.0;
+  h.h0 = c.Q0 + a * c.A0 + b * c.B0;
+  h.q2 = q4m2;
+  h.s2 = s4m2;
+  h.q4 = c.q4;
+  h.s4 = c.s4;
+  const double Q2 = c.p * h.q2 + c.r * h.s2;
+  const double Q4 = c.p * h.q4 + c.r * h.s4;
+  h.hp2 = Q2 + a * c.A2 + b * c.B2;
+  h.hp4 = Q4 + b * c.B4;
+  h.p = c.p;
+  h.r = c.r;
+  return h;
+}
+
 // q_j, s_j of the Q tail
 __device__ __forceinline__ double q_of(int j) { return 1.0 / ((double)j + 3.0); }
 __device__ __forceinline__ double s_of(int j) {

@@ -89,9 +89,8 @@ __device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const
 struct BihRowState {
   double rU0, U2, U4, P, R;
 };
-__device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
-                                         const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
-  const BihRow h = bih_row(k, a, b, N, gl, Rc);
+__device__ __forceinline__ void bih_step_row(int k, const BihRow& h, const BihRowState& m2, const BihRowState& m4,
+                                             BihRowState& o, double& l1, double& l2, double& t0out) {
   double tm2 = h.hm2, t0 = h.h0, t2 = h.hp2, t4 = h.hp4, P = h.p, Rr = h.r;
   l1 = 0.0;
   l2 = 0.0;
@@ -118,6 +117,65 @@ __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int g
   o.P = P;
   o.R = Rr;
   t0out = t0;
+}
+__device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
+                                         const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
+  bih_step_row(k, bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out);
+}
+
+// ------------------------------------------------------------------------
+// LDS table of BihConst for rows 0 .. RT-1 (RT = 2GC): six 16-byte pairs per
+// row, [pair][row'] with row' = k xor ((k / 2C) mod min(2C, 16)).  The rows
+// that the lanes of one parity read at one step (one per chunk) then fall in
+// distinct 16-byte bank groups, and a row never leaves its chunk's block.
+// Pair 0 holds (q4, s4), which the back substitution reads on its own.
+// ------------------------------------------------------------------------
+static constexpr int kBihTabPairs = 6;
+__device__ __forceinline__ int bih_tab_row(int k, int C) {
+  const int sh = 31 - __builtin_clz(2 * C);  // log2(2C)
+  const int mask = (2 * C - 1) < 15 ? (2 * C - 1) : 15;
+  return k ^ ((k >> sh) & mask);
+}
+__device__ __forceinline__ void bih_tab_fill(double* tab, int RT, int C, int N, int gl, int tid, int nthreads) {
+  double2* t2 = reinterpret_cast<double2*>(tab);
+  for (int k = tid; k < RT; k += nthreads) {
+    const BihConst c = bih_const(k, N, gl);
+    const int r = bih_tab_row(k, C);
+    t2[0 * RT + r] = make_double2(c.q4, c.s4);
+    t2[1 * RT + r] = make_double2(c.Am2, c.Q0);
+    t2[2 * RT + r] = make_double2(c.A0, c.B0);
+    t2[3 * RT + r] = make_double2(c.A2, c.B2);
+    t2[4 * RT + r] = make_double2(c.B4, c.p);
+    t2[5 * RT + r] = make_double2(c.r, 0.0);
+  }
+}
+__device__ __forceinline__ BihConst bih_tab_get(const double* tab, int RT, int C, int k) {
+  const double2* t2 = reinterpret_cast<const double2*>(tab);
+  const int r = bih_tab_row(k, C);
+  const double2 v0 = t2[0 * RT + r], v1 = t2[1 * RT + r], v2 = t2[2 * RT + r], v3 = t2[3 * RT + r], v4 = t2[4 * RT + r],
+                v5 = t2[5 * RT + r];
+  BihConst c;
+  c.q4 = v0.x;
+  c.s4 = v0.y;
+  c.Am2 = v1.x;
+  c.Q0 = v1.y;
+  c.A0 = v2.x;
+  c.B0 = v2.y;
+  c.A2 = v3.x;
+  c.B2 = v3.y;
+  c.B4 = v4.x;
+  c.p = v4.y;
+  c.r = v5.x;
+  return c;
+}
+// (q_{k+4}, s_{k+4}) of row k
+__device__ __forceinline__ double2 bih_tab_qs(const double* tab, int C, int k) {
+  return reinterpret_cast<const double2*>(tab)[bih_tab_row(k, C)];
+}
+// constants of a row k >= -4: from the table for k >= 0, computed below
+__device__ __forceinline__ BihConst bih_const_at(const double* tab, int RT, int C, int k, int N, int gl) {
+  if (k >= 0) return bih_tab_get(tab, RT, C, k);
+  return bih_const(k, N, gl);
 }
 
 // =========================================================================
@@ -193,6 +251,55 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
   if (t >= 2 * nsys) return;
   const int64_t w = t >> 1;
   bih_boundary_chain(N, C, G, (int)(t & 1), ca[w], cb[w], u + w * (int64_t)N, gl);
+}
+
+// Table-driven form of the biharmonic boundary walk: the rows are assembled
+// from the LDS table (bih_row_tab), exactly as the table-driven wave solve
+// assembles them, so the restart states continue the same factorisation.
+// The four wavefronts of a 256-thread block walk chains of one parity each,
+// so every step reads one table row for the whole wavefront (broadcast).
+__device__ __forceinline__ void bih_boundary_chain_tab(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
+                                                       int gl, const double* tab) {
+  const int RT = 2 * G * C;
+  const int n = N - 4;
+  const int nc = (n - p + 1) / 2;
+  const int nchunks = (nc + C - 1) / C;
+  if (nchunks <= 1) return;
+  double* st = reinterpret_cast<double*>(urow);
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  BihConst cm2 = bih_const_at(tab, RT, C, p - 2, N, gl), cm4 = bih_const_at(tab, RT, C, p - 4, N, gl);
+  const int ilast = (nchunks - 1) * C;
+  for (int i = 0; i < ilast; ++i) {
+    const int k = 2 * i + p;
+    const BihConst c = bih_tab_get(tab, RT, C, k);
+    BihRowState o;
+    double l1, l2, t0;
+    bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+    m4 = m2;
+    m2 = o;
+    cm4 = cm2;
+    cm2 = c;
+    if ((i + 1) % C == 0) {
+      const int m = (i + 1) / C;
+      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 10);
+      s[0] = make_double2(m2.rU0, m2.U2);
+      s[1] = make_double2(m2.U4, m2.P);
+      s[2] = make_double2(m2.R, m4.rU0);
+      s[3] = make_double2(m4.U2, m4.U4);
+      s[4] = make_double2(m4.P, m4.R);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void bih_boundary_tab(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
+                                                        const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+  extern __shared__ double tab[];
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 128 + (wv >> 1) * 64 + lane;
+  if (w >= nsys) return;
+  bih_boundary_chain_tab(N, C, G, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
 }
 
 // =========================================================================
@@ -401,10 +508,19 @@ __device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool 
 // =========================================================================
 // Biharmonic wave solve
 // =========================================================================
-template <int C, int G>
+struct NoHook {
+  __device__ void operator()() const {}
+};
+template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook>
+__device__ __forceinline__ void bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
+                                              BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
+                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook());
+
+template <int C, int G, bool TAB = false>
 __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ ca,
                                               const double* __restrict__ cb, const double2* __restrict__ f,
-                                              double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+                                              double2* __restrict__ u, int gl, int32_t* __restrict__ info,
+                                              const double* tab = nullptr) {
   const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
@@ -430,21 +546,62 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     const int k = k0 + 2 * j;
     x[j] = (wok && k < n) ? frow[k] : zero2();
   }
+  auto fetch = [&](int j) {
+    const int k = k0 + 2 * j;
+    return (wok && k < n) ? frow[k] : zero2();
+  };
+  bih_wave_core<C, G, false, TAB>(N, lane, w, wok, a, b, m2, m4, x, fetch, urow, gl, info, tab);
+}
+
+// Everything after the loads: x holds f of this lane's chunk (0 where k >= n),
+// m2/m4 the restart state, fetch_f(j) gives f of chunk element j again (the
+// forward refinement sweep).  Without PIPE the solution is stored to urow;
+// with PIPE it is left in x for the caller.
+template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook>
+__device__ __forceinline__ void bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
+                                              BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
+                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f) {
+  const int p = (lane / G) & 1;
+  const int m = lane % G;
+  const int n = N - 4;
+  const int k0 = 2 * m * C + p;
   // factorisation restart + local forward elimination; keep normalised U rows
-  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C], q4j[C];
+  constexpr int RT = 2 * G * C;
+  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
+  double q4j[TAB ? 1 : C];
+  // q_{k+4}, s_{k+4} of chunk element j (backward passes)
+  auto qs_of = [&](int j) {
+    if constexpr (TAB) return bih_tab_qs(tab, C, k0 + 2 * j);
+    const double k6 = (double)(k0 + 2 * j) + 6.0;
+    return make_double2(q4j[TAB ? 0 : j], k6 * k6 * q4j[TAB ? 0 : j]);
+  };
   int bad = INT_MAX;
   double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
   double2 y1 = zero2(), y2 = zero2();  // y_{i-1}, y_{i-2}
   Recip Rc;
-  Rc.init(k0);
+  BihConst cm2, cm4;
+  if constexpr (TAB) {
+    cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl);
+    cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+  } else {
+    Rc.init(k0);
+  }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int k = k0 + 2 * j;
-    if (j > 0) Rc.advance(k);
     const bool ok = wok && k < n;
     BihRowState o;
     double l1, l2, t0;
-    bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
+    if constexpr (TAB) {
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      cm4 = cm2;
+      cm2 = c;
+    } else {
+      if (j > 0) Rc.advance(k);
+      bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
+      q4j[TAB ? 0 : j] = Rc.p7;  // q_{k+4} = 1/(k+7)
+    }
     if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
     m4 = m2;
     m2 = o;
@@ -452,7 +609,6 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     l2 = ok ? l2 : 0.0;
     l1j[j] = l1;
     l2j[j] = l2;
-    q4j[j] = Rc.p7;  // q_{k+4} = 1/(k+7)
     r0j[j] = ok ? o.rU0 : 0.0;
     u2j[j] = ok ? o.rU0 * o.U2 : 0.0;
     u4j[j] = ok ? o.rU0 * o.U4 : 0.0;
@@ -521,14 +677,14 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
   const double2 sh1 = h1, sh2 = h2;  // approximate (y_{i0-1}, y_{i0-2})
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    const int k = k0 + 2 * j;
-    const double2 fj = (wok && k < n) ? frow[k] : zero2();
+    const double2 fj = fetch_f(j);
     double2 y = c_fnms(l1j[j], h1, fj);
     y = c_fnms(l2j[j], h2, y);
     x[j] = y;
     h2 = h1;
     h1 = y;
   }
+  after_f();  // f is not read again
   {
     double2 nx1, nx2;  // approximate incoming state of the next chunk
     if constexpr (G == 16) {
@@ -590,8 +746,8 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
   double2 cv[4] = {zero2(), zero2(), zero2(), zero2()};
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
-    const double k6 = (double)(k0 + 2 * j) + 6.0;
-    const double s4 = k6 * k6 * q4j[j];  // s_{k+4}
+    const double2 qs = qs_of(j);
+    const double q4 = qs.x, s4 = qs.y;  // q_{k+4}, s_{k+4}
     x[j] = c_mul(r0j[j], x[j]);  // yh
     double nA0[4];
 #pragma unroll
@@ -600,7 +756,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double a1 = A[1][c];
-      A[2][c] = __builtin_fma(q4j[j], a1, A[2][c]);
+      A[2][c] = __builtin_fma(q4, a1, A[2][c]);
       A[3][c] = __builtin_fma(s4, a1, A[3][c]);
       A[1][c] = A[0][c];
       A[0][c] = nA0[c];
@@ -609,7 +765,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     nc0 = c_fma(-u4j[j], cv[1], nc0);
     nc0 = c_fma(-pj[j], cv[2], nc0);
     nc0 = c_fma(-rj[j], cv[3], nc0);
-    cv[2] = c_fma(q4j[j], cv[1], cv[2]);
+    cv[2] = c_fma(q4, cv[1], cv[2]);
     cv[3] = c_fma(s4, cv[1], cv[3]);
     cv[1] = cv[0];
     cv[0] = nc0;
@@ -692,17 +848,19 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     uj = c_fma(-pj[j], sq, uj);
     uj = c_fma(-rj[j], ss, uj);
     x[j] = uj;
-    const double k6 = (double)(k0 + 2 * j) + 6.0;
-    sq = c_fma(q4j[j], sb, sq);
-    ss = c_fma(k6 * k6 * q4j[j], sb, ss);
+    const double2 qs = qs_of(j);
+    sq = c_fma(qs.x, sb, sq);
+    ss = c_fma(qs.y, sb, ss);
     sb = sa;
     sa = uj;
   }
-  if (wok) {
+  if constexpr (!PIPE) {
+    if (wok) {
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = k0 + 2 * j;
-      if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+      for (int j = 0; j < C; ++j) {
+        const int k = k0 + 2 * j;
+        if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+      }
     }
   }
   if (info != nullptr) {
@@ -719,6 +877,18 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
                                                       int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
   helm_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, alpha, f, u, gl, info);
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(256) void bih_wave_tab(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
+                                                    const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                    int32_t* __restrict__ info) {
+  extern __shared__ double tab[];
+  constexpr int SPW = 64 / (2 * G);
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW;
+  bih_wave_body<C, G, true>(N, nsys, wbase, ca, cb, f, u, gl, info, tab);
 }
 
 template <int C, int G>
@@ -805,6 +975,51 @@ __device__ __forceinline__ void read_tile(const double2* T, int lane, double2 (&
   for (int t = 0; t < NS; ++t) st[t] = T[64 * (C + t) + lane];
 }
 
+// As read_tile, with the LDS reads in asm that waits for them itself: used
+// where stores of the previous group may still be in flight, which the
+// compiler would otherwise wait for before touching a tile that an LDS-DMA
+// wrote.
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void lds_read4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, v2d& x0, v2d& x1, v2d& x2,
+                                          v2d& x3) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+}
+template <int C, int G, int NS>
+__device__ __forceinline__ void read_tile_asm(const double2* T, int lane, double2 (&x)[C], double2 (&st)[NS]) {
+  using TL = Tile<C, G>;
+  static_assert(C % 4 == 0, "chunk length must be a multiple of 4");
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  const uint32_t base = (uint32_t)(uintptr_t)SHEN_LDS(T);
+  double2 tmp[C + ((NS + 3) / 4) * 4];
+  uint32_t ad[C + ((NS + 3) / 4) * 4];
+#pragma unroll
+  for (int j = 0; j < C; ++j) ad[j] = base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * j);
+#pragma unroll
+  for (int t = 0; t < ((NS + 3) / 4) * 4; ++t) ad[C + t] = base + 16u * (uint32_t)(64 * (C + (t < NS ? t : 0)) + lane);
+#pragma unroll
+  for (int j = 0; j < C + ((NS + 3) / 4) * 4; j += 4) {
+    v2d r0, r1, r2, r3;
+    lds_read4(ad[j], ad[j + 1], ad[j + 2], ad[j + 3], r0, r1, r2, r3);
+    tmp[j] = make_double2(r0.x, r0.y);
+    tmp[j + 1] = make_double2(r1.x, r1.y);
+    tmp[j + 2] = make_double2(r2.x, r2.y);
+    tmp[j + 3] = make_double2(r3.x, r3.y);
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) x[j] = tmp[j];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) st[t] = tmp[C + t];
+}
+
 // Stages this lane's solution chunk in tile T.
 template <int C, int G>
 __device__ __forceinline__ void stage_tile(double2* T, int lane, const double2 (&x)[C]) {
@@ -888,6 +1103,85 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
   }
 }
 
+// Persistent table-driven biharmonic wave solve: one 256-thread block per
+// compute unit fills the row table once; each of its wavefronts then loops
+// over groups of systems on its own, streaming the next group's right-hand
+// sides and restart states into its LDS tile (whole 64-row blocks) once the
+// refinement sweep has read the current group's f from it.
+template <int C, int G>
+__global__ __launch_bounds__(256) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
+                                                     const double* __restrict__ cb, const double2* __restrict__ f,
+                                                     double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  constexpr int RT = 2 * G * C;
+  extern __shared__ double smem[];
+  double* tab = smem;
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + (threadIdx.x >> 6) * ((C + 5) * 64);
+  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int n = N - 4;
+  const int64_t ngroups = (nsys + SPW - 1) / SPW;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= ngroups) return;
+  auto sysc = [&](int64_t gg, int l) {
+    const int64_t w = gg * SPW + l / (2 * G);
+    return w < nsys ? w : nsys - 1;
+  };
+  double ca_, cb_, ca_n = 0.0, cb_n = 0.0;
+  {
+    const int lane = threadIdx.x & 63;
+    prefetch_tile<C, G, 5>(tile, lane, g, N, nsys, f, u);
+    ca_ = ca[sysc(g, lane)];
+    cb_ = cb[sysc(g, lane)];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  for (; g < ngroups; g += stride) {
+    // Lane-derived indices are re-derived every iteration from an opaque
+    // copy: hoisting the per-row constants out of the loop would hold them
+    // in registers across it.
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+    const int k0 = 2 * m * C + p;
+    const int64_t w = g * SPW + sl;
+    const bool wok = w < nsys;
+    double2 x[C], st[5];
+    read_tile_asm<C, G, 5>(tile, lane, x, st);
+#pragma unroll
+    for (int j = 0; j < C; ++j) x[j] = (wok && k0 + 2 * j < n) ? x[j] : zero2();
+    BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+    if (wok && m > 0 && k0 < n) {
+      m2 = BihRowState{st[0].x, st[0].y, st[1].x, st[1].y, st[2].x};
+      m4 = BihRowState{st[2].y, st[3].x, st[3].y, st[4].x, st[4].y};
+    }
+    auto fetch = [&](int j) {
+      const int k = k0 + 2 * j;
+      uint32_t ad = (uint32_t)(uintptr_t)SHEN_LDS(tile) + 16u * (uint32_t)TL::pos(sl, k);
+      v2d r0;
+      asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(r0) : "v"(ad) : "memory");
+      return (wok && k < n) ? make_double2(r0.x, r0.y) : zero2();
+    };
+    const int64_t gn = g + stride;
+    auto prefetch_next = [&]() {
+      if (gn < ngroups) {
+        prefetch_tile<C, G, 5>(tile, lane, gn, N, nsys, f, u);
+        ca_n = ca[sysc(gn, lane)];
+        cb_n = cb[sysc(gn, lane)];
+      }
+    };
+    double2* urow = u + (wok ? w : 0) * (int64_t)N;
+    bih_wave_core<C, G, false, true>(N, lane, w, wok, wok ? ca_ : 0.0, wok ? cb_ : 0.0, m2, m4, x, fetch, urow, gl, info, tab,
+                                     prefetch_next);
+    // the next group has landed (and the stores above are issued)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    ca_ = ca_n;
+    cb_ = cb_n;
+  }
+}
+
+
 // =========================================================================
 // host side
 // =========================================================================
@@ -923,13 +1217,18 @@ bool wave_supported(int family, int N) {
 // of waves; measured slower at the channel-scale sizes, so off.
 static constexpr int64_t kWaveSlice = (int64_t)1 << 40;  // no slicing: boundary kernels need the whole grid for occupancy
 
+// Allows a kernel dynamic LDS beyond the default 64 KiB.
+static bool set_dynamic_lds(const void* kernel, size_t bytes) {
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
 // Grid of a persistent kernel: every resident wavefront slot of the device,
 // capped by the number of work groups.
-static int64_t persistent_blocks(const void* kernel, int64_t groups) {
+static int64_t persistent_blocks(const void* kernel, int64_t groups, int threads = 64, size_t lds = 0) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t slots = (int64_t)cus * per_cu;
   return groups < slots ? (groups > 0 ? groups : 1) : slots;
 }
@@ -967,9 +1266,24 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     const double2* f = (const double2*)a.f + s0 * a.N;
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
-    hipLaunchKernelGGL(bih_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, c1, u, a.gl);
-    hipLaunchKernelGGL((bih_wave_solve<C, G>), dim3((unsigned)((ns + SPW - 1) / SPW)), dim3(64), 0, st, a.N, ns, c0, c1, f, u,
-                       a.gl, info);
+    const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    static const bool attr = set_dynamic_lds((const void*)bih_wave_tab<C, G>, lds) &&
+                             set_dynamic_lds((const void*)bih_boundary_tab, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+    (void)attr;
+    hipLaunchKernelGGL(bih_boundary_tab, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u, a.gl);
+    // gfx950: 160 KiB of LDS per work group
+    constexpr size_t kPtabLds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 5) * 64 * sizeof(double2);
+    if constexpr (C >= 8 && C % 4 == 0 && G >= 16 && kPtabLds <= 160 * 1024) {
+      const size_t lds2 = kPtabLds;
+      static const bool attr2 = set_dynamic_lds((const void*)bih_wave_ptab<C, G>, lds2);
+      (void)attr2;
+      const int64_t groups = (ns + SPW - 1) / SPW;
+      const int64_t blocks = persistent_blocks((const void*)bih_wave_ptab<C, G>, (groups + 3) / 4, 256, lds2);
+      hipLaunchKernelGGL((bih_wave_ptab<C, G>), dim3((unsigned)blocks), dim3(256), lds2, st, a.N, ns, c0, c1, f, u, a.gl, info);
+    } else {
+      hipLaunchKernelGGL((bih_wave_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns, c0,
+                         c1, f, u, a.gl, info);
+    }
   }
   return hipGetLastError();
 }
@@ -1037,26 +1351,50 @@ __device__ __forceinline__ void bih_tile(const shen_problem& d, int64_t w0, int6
     bih_wave_body<C, G>(N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), u, gl, d.info);
 }
 
-__device__ __noinline__ void run_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
-  const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
-#define SHEN_TILE(CC, GG)                                          \
-  if (c.C == CC && c.G == GG) {                                    \
-    if (d.family == SHEN_HELMHOLTZ)                                \
-      helm_tile<CC, GG>(d, w0, wend, gl);                          \
-    else                                                           \
-      bih_tile<CC, GG>(d, w0, wend, gl);                           \
-    return;                                                        \
+// Descriptor of work item t: the last one whose first tile is <= t.
+__device__ __forceinline__ int find_desc(const shen_problem* __restrict__ desc, int ndesc, int64_t t) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile_begin <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-  SHEN_TILE(4, 8)
-  SHEN_TILE(8, 4)
-  SHEN_TILE(16, 4)
-  SHEN_TILE(8, 8)
-  SHEN_TILE(8, 16)
-  SHEN_TILE(16, 8)
-  SHEN_TILE(16, 16)
-  SHEN_TILE(8, 32)
-  SHEN_TILE(16, 32)
-#undef SHEN_TILE
+  return lo;
+}
+
+__device__ __forceinline__ long long next_item(unsigned long long* __restrict__ counter, long long* s_tile) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_tile = (long long)atomicAdd(counter, 1ULL);
+  __syncthreads();
+  const long long t = *s_tile;
+  __syncthreads();
+  return t;
+}
+
+// Runs work item t and then keeps pulling items for as long as they need the
+// same kernel configuration (family, C, G); returns the first item that does
+// not (or one >= tiles_total).  Each configuration is its own non-inlined
+// function, so a wavefront pays for the call only when the configuration
+// changes, not per item.
+template <int C, int G, int FAM>
+__device__ __noinline__ int64_t run_tiles(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                          unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
+  for (;;) {
+    const shen_problem d = desc[find_desc(desc, ndesc, t)];
+    const int64_t w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
+    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
+    if constexpr (FAM == SHEN_HELMHOLTZ)
+      helm_tile<C, G>(d, w0, wend, gl);
+    else
+      bih_tile<C, G>(d, w0, wend, gl);
+    t = next_item(counter, s_tile);
+    if (t >= tiles_total) return t;
+    const shen_problem& e = desc[find_desc(desc, ndesc, t)];
+    const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
+    if (!(e.family == FAM && c.C == C && c.G == G)) return t;
+  }
 }
 
 __global__ void batched_clear(unsigned long long* __restrict__ counter) {
@@ -1066,25 +1404,26 @@ __global__ void batched_clear(unsigned long long* __restrict__ counter) {
 __global__ __launch_bounds__(64) void batched_persistent(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
                                                          unsigned long long* __restrict__ counter, int gl) {
   __shared__ long long s_tile;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (long long)atomicAdd(counter, 1ULL);
-    __syncthreads();
-    const int64_t t = s_tile;
-    __syncthreads();
-    if (t >= tiles_total) break;
-    int lo = 0, hi = ndesc - 1;  // last descriptor whose first tile is <= t
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (desc[mid].tile_begin <= t)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const shen_problem d = desc[lo];
-    const int64_t w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
-    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
-    run_tile(d, w0, wend, gl);
-    __syncthreads();
+  int64_t t = next_item(counter, &s_tile);
+  while (t < tiles_total) {
+    const shen_problem& d = desc[find_desc(desc, ndesc, t)];
+    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
+    const int64_t t0 = t;
+#define SHEN_TILE(CC, GG)                                                                               \
+  if (c.C == CC && c.G == GG)                                                                           \
+    t = (d.family == SHEN_HELMHOLTZ) ? run_tiles<CC, GG, SHEN_HELMHOLTZ>(desc, ndesc, tiles_total, counter, gl, t, &s_tile) \
+                                     : run_tiles<CC, GG, SHEN_BIHARMONIC>(desc, ndesc, tiles_total, counter, gl, t, &s_tile);
+    SHEN_TILE(4, 8)
+    else SHEN_TILE(8, 4)
+    else SHEN_TILE(16, 4)
+    else SHEN_TILE(8, 8)
+    else SHEN_TILE(8, 16)
+    else SHEN_TILE(16, 8)
+    else SHEN_TILE(16, 16)
+    else SHEN_TILE(8, 32)
+    else SHEN_TILE(16, 32)
+#undef SHEN_TILE
+    if (t == t0) t = next_item(counter, &s_tile);  // no kernel for this item (excluded by the planner)
   }
 }
 
