@@ -62,6 +62,111 @@ def alg_bytes(family: str, N: int, nsys: int) -> int:
     return nsys * (16 * (N - 4) + 16 * N + 16)
 
 
+def _sampled_err(fam, N, cs_host, f_host, u_dev, rows, transpose=False):
+    """max per-system relative error of the device result on the given rows (oracle on the CPU)."""
+    import numpy as np
+    import torch
+    from oracle import shen_oracle as so
+    u = u_dev[torch.from_numpy(rows).to(u_dev.device)].cpu().numpy()
+    ref = so.solve(fam, N, tuple(c[rows] for c in cs_host), f_host[rows], transpose=transpose)
+    return float(so.rel_err_per_system(u, ref).max())
+
+
+def measure_batched(dev, args):
+    """Batching form: the 48 grids of uneven N (both families) in one persistent launch,
+    captured in a hipGraph; replays are timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1701_03787_amd import workloads as wl
+    from paper_1701_03787_amd.batched import BatchedProblem, BatchedSolver
+    grids = wl.config_grids(4)
+    probs, checks, units, nbytes = [], [], 0, 0
+    rng = np.random.default_rng([1701, 4, 4])
+    for g in grids:
+        for fam in ("helmholtz", "biharmonic"):
+            f = g.rhs(fam)
+            cs = g.coefficients(fam)
+            p = BatchedProblem(fam, torch.from_numpy(f).to(dev), [torch.from_numpy(c).to(dev) for c in cs])
+            probs.append(p)
+            rows = np.unique(np.concatenate([[0, g.nsys - 1], rng.choice(g.nsys, 2, replace=False)]))
+            checks.append((fam, g.N, tuple(c[rows] for c in cs), f[rows], rows))
+            units += g.nsys * g.N
+            nbytes += alg_bytes(fam, g.N, g.nsys)
+            del f
+    solver = BatchedSolver(probs)
+    solver.capture()
+    for _ in range(max(1, args.warmup)):
+        solver.replay()
+    torch.cuda.synchronize()
+    reps = max(3, min(args.steps, 10))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        solver.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    err = 0.0
+    for p, (fam, N, cs, f, rows) in zip(probs, checks):
+        u = p.u[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        from oracle import shen_oracle as so
+        err = max(err, float(so.rel_err_per_system(u, so.solve(fam, N, cs, f)).max()))
+    out = {"workload": "48 grids, N in {64..1024}, both families", "problems": len(probs), "ms_per_launch": round(ms, 4),
+           "value": round(units / (ms * 1e-3), 2), "unit": "system·N/s",
+           "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err, "graph_replays": reps}
+    del solver, probs
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_adjoint(dev, args):
+    """Differentiation form: forward solve + hand-written adjoint (torch.autograd) on the
+    N=512, 256x129 workload, per family; the gradient w.r.t. f is checked on sampled rows."""
+    import numpy as np
+    import torch
+    from paper_1701_03787_amd import api
+    from paper_1701_03787_amd import workloads as wl
+    g = wl.config_grids(5)[0]
+    out = {"workload": g.name}
+    rng = np.random.default_rng([1701, 5, 5])
+    rows = np.unique(np.concatenate([[0, g.nsys - 1], rng.choice(g.nsys, 14, replace=False)]))
+    for fam in ("helmholtz", "biharmonic"):
+        fh = g.rhs(fam)
+        csh = g.coefficients(fam)
+        f = torch.from_numpy(fh).to(dev).requires_grad_(True)
+        cs = [torch.from_numpy(c).to(dev).requires_grad_(True) for c in csh]
+        gbar = torch.from_numpy(wl.random_vector((g.nsys, g.N), (5, 2))).to(dev)
+
+        def step():
+            f.grad = None
+            for c in cs:
+                c.grad = None
+            u = api.helmholtz(f, *cs) if fam == "helmholtz" else api.biharmonic(f, *cs)
+            u.backward(gbar)
+            return u
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gb = gbar.cpu().numpy()
+        n = wl.n_unknowns(fam, g.N)
+        gb[:, n:] = 0
+        err = _sampled_err(fam, g.N, csh, gb, f.grad, rows, transpose=True)
+        out[fam] = {"ms_forward_backward": round(ms, 4), "value": round(g.nsys * g.N / (ms * 1e-3), 2),
+                    "unit": "system·N/s", "max_rel_err_grad_f_sampled": err}
+        del f, cs, gbar
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +175,7 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched (48 grids) and adjoint measurements")
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--chunk", type=int, default=0, help="wave kernels: preferred chunk length (0 = automatic)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -172,6 +278,10 @@ def main():
                  "kernel_ms": {k: round(v, 4) for k, v in kms_m.items()},
                  "speedup_vs_fp64": round(ms_per_step / ms_m, 4), "max_rel_err": acc_m}
 
+    forms = None
+    if not args.no_forms:
+        forms = {"batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
+
     cpu = None
     if not args.no_cpu:
         from threadpoolctl import threadpool_limits
@@ -201,6 +311,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed_fp32_refine": mixed,
+        "forms": forms,
     }
     if args.probe_copy:
         x = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
