@@ -1311,46 +1311,20 @@ hipError_t launch_wave(const WaveArgs& a) {
 
 
 // =========================================================================
-// Batched form: one persistent launch over many grids of uneven N and both
-// families.  Work item = a tile of consecutive systems of one descriptor;
-// workgroups (one wavefront each) pull tiles from an atomic counter until the
-// queue is empty (every wavefront reaches that exit).  A tile first runs the
-// boundary recurrences of its chains (one lane per chain), then the wave
-// solve of its systems, so the restart states are written and read back by
-// the same compute unit.
+// Batched form: many grids of uneven N and both families, one descriptor
+// table, four persistent kernels enqueued back to back (one graph launch):
+//
+//  1. batched_boundary<family>: work item = a tile of consecutive systems of
+//     one descriptor; its lanes walk the LU recurrences of the tile's chains
+//     and park the restart states (small kernels, so many wavefronts per SIMD
+//     hide the latency of the sequential walk);
+//  2. batched_wave<family>: the wave solves of the tiles of that family, each
+//     kernel compiled for its own family only (its register budget is that
+//     family's).
+//
+// Every kernel pulls items from its own atomic counter until the queue is
+// empty; every wavefront reaches that exit.
 // =========================================================================
-template <int C, int G>
-__device__ __forceinline__ void helm_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
-  const int N = d.N;
-  double2* u = reinterpret_cast<double2*>(d.u);
-  const int64_t nch = 2 * (wend - w0);
-  for (int64_t c = threadIdx.x; c < nch; c += 64) {
-    const int64_t w = w0 + (c >> 1);
-    helm_boundary_chain(N, C, G, (int)(c & 1), d.c0[w], u + w * (int64_t)N, gl);
-  }
-  __threadfence();
-  __syncthreads();
-  constexpr int SPW = 64 / (2 * G);
-  for (int64_t wb = w0; wb < wend; wb += SPW)
-    helm_wave_body<C, G>(N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), u, gl, d.info);
-}
-
-template <int C, int G>
-__device__ __forceinline__ void bih_tile(const shen_problem& d, int64_t w0, int64_t wend, int gl) {
-  const int N = d.N;
-  double2* u = reinterpret_cast<double2*>(d.u);
-  const int64_t nch = 2 * (wend - w0);
-  for (int64_t c = threadIdx.x; c < nch; c += 64) {
-    const int64_t w = w0 + (c >> 1);
-    bih_boundary_chain(N, C, G, (int)(c & 1), d.c0[w], d.c1[w], u + w * (int64_t)N, gl);
-  }
-  __threadfence();
-  __syncthreads();
-  constexpr int SPW = 64 / (2 * G);
-  for (int64_t wb = w0; wb < wend; wb += SPW)
-    bih_wave_body<C, G>(N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), u, gl, d.info);
-}
-
 // Descriptor of work item t: the last one whose first tile is <= t.
 __device__ __forceinline__ int find_desc(const shen_problem* __restrict__ desc, int ndesc, int64_t t) {
   int lo = 0, hi = ndesc - 1;
@@ -1373,46 +1347,93 @@ __device__ __forceinline__ long long next_item(unsigned long long* __restrict__ 
   return t;
 }
 
-// Runs work item t and then keeps pulling items for as long as they need the
-// same kernel configuration (family, C, G); returns the first item that does
-// not (or one >= tiles_total).  Each configuration is its own non-inlined
-// function, so a wavefront pays for the call only when the configuration
-// changes, not per item.
-template <int C, int G, int FAM>
-__device__ __noinline__ int64_t run_tiles(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                          unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
-  for (;;) {
-    const shen_problem d = desc[find_desc(desc, ndesc, t)];
-    const int64_t w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
-    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
-    if constexpr (FAM == SHEN_HELMHOLTZ)
-      helm_tile<C, G>(d, w0, wend, gl);
-    else
-      bih_tile<C, G>(d, w0, wend, gl);
-    t = next_item(counter, s_tile);
-    if (t >= tiles_total) return t;
-    const shen_problem& e = desc[find_desc(desc, ndesc, t)];
-    const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
-    if (!(e.family == FAM && c.C == C && c.G == G)) return t;
-  }
+__device__ __forceinline__ void tile_range(const shen_problem& d, int64_t t, int64_t& w0, int64_t& wend) {
+  w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
+  wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
 }
 
 __global__ void batched_clear(unsigned long long* __restrict__ counter) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) counter[0] = 0ULL;
+  if (blockIdx.x == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0ULL;
 }
 
-__global__ __launch_bounds__(64) void batched_persistent(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                                         unsigned long long* __restrict__ counter, int gl) {
+// Next item of family FAM (items of the other family are skipped).
+template <int FAM>
+__device__ __forceinline__ int64_t next_own(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                            unsigned long long* __restrict__ counter, long long* s_tile) {
+  for (;;) {
+    const int64_t t = next_item(counter, s_tile);
+    if (t >= tiles_total || desc[find_desc(desc, ndesc, t)].family == FAM) return t;
+  }
+}
+
+template <int FAM>
+__global__ __launch_bounds__(64) void batched_boundary(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                                       unsigned long long* __restrict__ counter, int gl) {
   __shared__ long long s_tile;
-  int64_t t = next_item(counter, &s_tile);
+  for (int64_t t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile); t < tiles_total;
+       t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile)) {
+    const shen_problem d = desc[find_desc(desc, ndesc, t)];
+    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
+    if (c.C == 0) continue;
+    int64_t w0, wend;
+    tile_range(d, t, w0, wend);
+    double2* u = reinterpret_cast<double2*>(d.u);
+    for (int64_t ch = w0 * 2 + threadIdx.x; ch < wend * 2; ch += 64) {
+      const int64_t w = ch >> 1;
+      if constexpr (FAM == SHEN_HELMHOLTZ)
+        helm_boundary_chain(d.N, c.C, c.G, (int)(ch & 1), d.c0[w], u + w * (int64_t)d.N, gl);
+      else
+        bih_boundary_chain(d.N, c.C, c.G, (int)(ch & 1), d.c0[w], d.c1[w], u + w * (int64_t)d.N, gl);
+    }
+  }
+}
+
+// Solves item t and then keeps pulling items of the same family for as long
+// as they use the same (C, G); returns the first one that does not (or one
+// >= tiles_total).  One non-inlined function per configuration, so the call
+// is paid once per configuration change, not per item.
+template <int C, int G, int FAM>
+__device__ __forceinline__ int64_t tiles_loop(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                              unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
+  constexpr int SPW = 64 / (2 * G);
+  for (;;) {
+    const shen_problem d = desc[find_desc(desc, ndesc, t)];
+    int64_t w0, wend;
+    tile_range(d, t, w0, wend);
+    for (int64_t wb = w0; wb < wend; wb += SPW) {
+      if constexpr (FAM == SHEN_HELMHOLTZ)
+        helm_wave_body<C, G>(d.N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u), gl,
+                             d.info);
+      else
+        bih_wave_body<C, G>(d.N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
+                            gl, d.info);
+    }
+    t = next_own<FAM>(desc, ndesc, tiles_total, counter, s_tile);
+    if (t >= tiles_total) return t;
+    const shen_problem& e = desc[find_desc(desc, ndesc, t)];
+    const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
+    if (!(c.C == C && c.G == G)) return t;
+  }
+}
+// Each configuration is a function of its own: inlining all of them into one
+// kernel makes the register allocation of their union spill.
+template <int C, int G, int FAM>
+__device__ __noinline__ int64_t run_tiles(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                          unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
+  return tiles_loop<C, G, FAM>(desc, ndesc, tiles_total, counter, gl, t, s_tile);
+}
+
+template <int FAM>
+__global__ __launch_bounds__(64) void batched_wave(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
+                                                   unsigned long long* __restrict__ counter, int gl) {
+  __shared__ long long s_tile;
+  int64_t t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile);
   while (t < tiles_total) {
     const shen_problem& d = desc[find_desc(desc, ndesc, t)];
     const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
     const int64_t t0 = t;
-#define SHEN_TILE(CC, GG)                                                                               \
-  if (c.C == CC && c.G == GG)                                                                           \
-    t = (d.family == SHEN_HELMHOLTZ) ? run_tiles<CC, GG, SHEN_HELMHOLTZ>(desc, ndesc, tiles_total, counter, gl, t, &s_tile) \
-                                     : run_tiles<CC, GG, SHEN_BIHARMONIC>(desc, ndesc, tiles_total, counter, gl, t, &s_tile);
+#define SHEN_TILE(CC, GG) \
+  if (c.C == CC && c.G == GG) t = run_tiles<CC, GG, FAM>(desc, ndesc, tiles_total, counter, gl, t, &s_tile);
     SHEN_TILE(4, 8)
     else SHEN_TILE(8, 4)
     else SHEN_TILE(16, 4)
@@ -1423,17 +1444,30 @@ __global__ __launch_bounds__(64) void batched_persistent(const shen_problem* __r
     else SHEN_TILE(8, 32)
     else SHEN_TILE(16, 32)
 #undef SHEN_TILE
-    if (t == t0) t = next_item(counter, &s_tile);  // no kernel for this item (excluded by the planner)
+    if (t == t0) t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile);  // not a wave configuration
   }
 }
 
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   unsigned long long* counter = reinterpret_cast<unsigned long long*>(work);
+  (void)blocks;
   hipLaunchKernelGGL(batched_clear, dim3(1), dim3(64), 0, st, counter);
-  if (tiles_total > 0)
-    hipLaunchKernelGGL(batched_persistent, dim3((unsigned)blocks), dim3(64), 0, st, (const shen_problem*)desc, ndesc, tiles_total,
-                       counter, gl);
+  if (tiles_total > 0) {
+    const shen_problem* d = (const shen_problem*)desc;
+    hipLaunchKernelGGL(batched_boundary<SHEN_HELMHOLTZ>,
+                       dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_HELMHOLTZ>, tiles_total)), dim3(64),
+                       0, st, d, ndesc, tiles_total, counter + 3, gl);
+    hipLaunchKernelGGL(batched_boundary<SHEN_BIHARMONIC>,
+                       dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_BIHARMONIC>, tiles_total)), dim3(64),
+                       0, st, d, ndesc, tiles_total, counter, gl);
+    hipLaunchKernelGGL(batched_wave<SHEN_HELMHOLTZ>,
+                       dim3((unsigned)persistent_blocks((const void*)batched_wave<SHEN_HELMHOLTZ>, tiles_total)), dim3(64), 0,
+                       st, d, ndesc, tiles_total, counter + 1, gl);
+    hipLaunchKernelGGL(batched_wave<SHEN_BIHARMONIC>,
+                       dim3((unsigned)persistent_blocks((const void*)batched_wave<SHEN_BIHARMONIC>, tiles_total)), dim3(64), 0,
+                       st, d, ndesc, tiles_total, counter + 2, gl);
+  }
   return hipGetLastError();
 }
 
