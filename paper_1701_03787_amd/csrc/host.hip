@@ -93,10 +93,15 @@ int run(ChainArgs& a) {
 // The wave path serves plain FP64 forward solves out of place (it parks the LU
 // restart states in u); everything else, and sizes it does not cover, goes to
 // the chain kernels.
+// The wave kernels cover the plain FP64 solve of both families and the
+// FP32 + refinement solve of the Helmholtz family, not the transposed solve.
+bool wave_mode_ok(const shen_opts& o, int family) {
+  return !o.transpose && (o.precision == SHEN_FP64 || family == SHEN_HELMHOLTZ);
+}
 bool use_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
   if (o.variant == SHEN_VARIANT_CHAIN) return false;
   if (o.variant == SHEN_VARIANT_WAVE) return true;  // caller insists: unsupported -> ENOTSUP
-  return o.precision == SHEN_FP64 && !o.transpose && f != u && shen::wave_supported(family, N);
+  return wave_mode_ok(o, family) && f != u && shen::wave_supported(family, N);
 }
 
 int run_wave(const shen::WaveArgs& w) {
@@ -167,9 +172,12 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
   if (use_wave(o, 0, N, f, u)) {
-    if (!shen::wave_supported(0, N) || f == (const void*)u) return SHEN_ENOTSUP;
+    if (!wave_mode_ok(o, 0) || !shen::wave_supported(0, N) || f == (const void*)u) return SHEN_ENOTSUP;
     shen::WaveArgs w;
     w.family = 0;
+    w.mixed = o.precision == SHEN_FP32_REFINE;
+    w.it_max = o.refine_max;
+    w.tol = o.refine_tol;
     w.N = N;
     w.nsys = nsys;
     w.c0 = alpha;
@@ -207,7 +215,7 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
   if (use_wave(o, 1, N, f, u)) {
-    if (!shen::wave_supported(1, N) || f == (const void*)u) return SHEN_ENOTSUP;
+    if (!wave_mode_ok(o, 1) || !shen::wave_supported(1, N) || f == (const void*)u) return SHEN_ENOTSUP;
     shen::WaveArgs w;
     w.family = 1;
     w.N = N;

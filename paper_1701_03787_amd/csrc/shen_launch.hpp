@@ -39,7 +39,10 @@ struct WaveArgs {
   void* u = nullptr;  // must not alias f (restart states are parked in it)
   int32_t* info = nullptr;
   int gl = 0;
-  int chunk = 0;  // preferred chunk length C (0: automatic)
+  int chunk = 0;   // preferred chunk length C (0: automatic)
+  int mixed = 0;   // FP32 factor/solve + FP64 refinement (Helmholtz)
+  int it_max = 8;  // refinement steps at most
+  double tol = 1e-14;
   void* stream = nullptr;
 };
 

@@ -57,13 +57,35 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 template <int D>
 struct RowShift {
   static __device__ __forceinline__ double from_lower(double v) { return dpp_d<0x110 + D>(v); }  // lane i-D
   static __device__ __forceinline__ double from_upper(double v) { return dpp_d<0x100 + D>(v); }  // lane i+D
   static __device__ __forceinline__ double2 from_lower(double2 v) { return make_double2(from_lower(v.x), from_lower(v.y)); }
   static __device__ __forceinline__ double2 from_upper(double2 v) { return make_double2(from_upper(v.x), from_upper(v.y)); }
+  static __device__ __forceinline__ float from_lower(float v) { return dpp_f<0x110 + D>(v); }
+  static __device__ __forceinline__ float from_upper(float v) { return dpp_f<0x100 + D>(v); }
+  static __device__ __forceinline__ float2 from_lower(float2 v) { return make_float2(from_lower(v.x), from_lower(v.y)); }
+  static __device__ __forceinline__ float2 from_upper(float2 v) { return make_float2(from_upper(v.x), from_upper(v.y)); }
 };
+
+// FP32 helpers of the mixed-precision form
+__device__ __forceinline__ float rcp32(float d) {  // hardware estimate + one Newton step
+  const float r = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
+}
+__device__ __forceinline__ float2 cf_fma(float s, float2 b, float2 a) {
+  return make_float2(__builtin_fmaf(s, b.x, a.x), __builtin_fmaf(s, b.y, a.y));
+}
+__device__ __forceinline__ float2 cf_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cf_mul(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+__device__ __forceinline__ float2 to_f2(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
+__device__ __forceinline__ double cabs1(double2 a) { return fmax(fabs(a.x), fabs(a.y)); }
 
 // One Helmholtz LU row step (shared by boundary and solve kernels so that the
 // restarted factorisation reproduces the sequential one exactly).
@@ -83,6 +105,27 @@ __device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const
     g = __builtin_fma(-l, pv.g, h.hpp);
   }
   rd = fast_rcp(d);
+}
+
+// The same step in FP32 (mixed-precision form): entries formed in FP64,
+// rounded once, factorisation arithmetic in FP32.
+struct HelmPrev32 {
+  float rd, g;
+};
+__device__ __forceinline__ void helm_step32(int k, double al, int N, int gl, const HelmPrev32& pv, float& l, float& g, float& rd,
+                                            float& d) {
+  const HelmRow h = helm_row(k, al, N, gl);
+  const float hm = (float)h.hm, h0 = (float)h.h0, hpp = (float)h.hpp;
+  if (k < 2) {
+    l = 0.0f;
+    d = h0;
+    g = hpp;
+  } else {
+    l = hm * pv.rd;
+    d = __builtin_fmaf(-l, pv.g + hm, h0);
+    g = __builtin_fmaf(-l, pv.g, hpp);
+  }
+  rd = rcp32(d);
 }
 
 // One biharmonic LU row step: row k reduced by rows k-4 (m4) and k-2 (m2).
@@ -206,6 +249,30 @@ __device__ __forceinline__ void helm_boundary_chain(int N, int C, int G, int p, 
   }
 }
 
+// FP32 restart states (float2 (1/d, g) at float2 slot p*G + m of u[w]).
+__global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
+                                                       double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  const int p = (int)(t & 1);
+  const int n = N - 2;
+  const int nc = (n - p + 1) / 2;
+  const int nchunks = (nc + C - 1) / C;
+  if (nchunks <= 1) return;
+  const double al = alpha[w];
+  float2* st = reinterpret_cast<float2*>(u + w * (int64_t)N);
+  HelmPrev32 pv = {0.0f, 0.0f};
+  const int ilast = (nchunks - 1) * C;
+  for (int i = 0; i < ilast; ++i) {
+    float l, g, rd, d;
+    helm_step32(2 * i + p, al, N, gl, pv, l, g, rd, d);
+    pv.rd = rd;
+    pv.g = g;
+    if ((i + 1) % C == 0) st[p * G + (i + 1) / C] = make_float2(pv.rd, pv.g);
+  }
+}
+
 __global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
                                                      double2* __restrict__ u, int gl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,8 +374,8 @@ __global__ __launch_bounds__(256) void bih_boundary_tab(int N, int64_t nsys, int
 // =========================================================================
 // Solves systems wbase + (lane / 2G) of the wavefront (those below nsys).
 template <int C, int G, bool PIPE = false>
-__device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
-                                               double2* __restrict__ urow, int gl, int32_t* __restrict__ info);
+__device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
+                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info);
 
 template <int C, int G>
 __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
@@ -346,8 +413,8 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
 // pv the restart state.  Without PIPE the solution is stored to urow; with
 // PIPE it is left in x for the caller.
 template <int C, int G, bool PIPE>
-__device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
-                                               double2* __restrict__ urow, int gl, int32_t* __restrict__ info) {
+__device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
+                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info) {
   const int p = (lane / G) & 1;
   const int m = lane % G;
   const int n = N - 2;
@@ -502,6 +569,333 @@ __device__ __forceinline__ void helm_wave_core(int N, int lane, int64_t w, bool 
 #pragma unroll
     for (int d = 1; d < 2 * G; d <<= 1) b = min(b, __shfl_xor(b, d, 2 * G));
     if (wok && (lane % (2 * G)) == 0) info[w] = (b == INT_MAX) ? 0 : b + 1;
+  }
+  return bad;
+}
+
+// =========================================================================
+// Helmholtz, FP32 factor/solve + FP64 iterative refinement (wave layout)
+// =========================================================================
+// The FP32 factors (1/d, g) stay in registers; every refinement step solves
+// the current FP64 residual in FP32 with the same scans as the FP64 solve,
+// adds the correction to u in FP64 and forms the next residual f - H u in
+// FP64 in the wave layout (neighbours by row shifts, the same-parity suffix
+// sum by a suffix scan of chunk totals).  f is read once and u written once.
+
+// Solves (in place) L U x = x in FP32 with stored factors: rd[j], gg[j] of
+// chunk element j (0 on padding rows), rd_in = 1/d of the row before the chunk.
+template <int C, int G>
+__device__ __forceinline__ void helm_solve32(int lane, bool wok, int n, float hm, float rd_in, const float (&rd)[C],
+                                             const float (&gg)[C], float2 (&x)[C]) {
+  const int p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  auto lof = [&](int j) {
+    const bool ok = wok && k0 + 2 * j < n;
+    return ok ? hm * (j == 0 ? rd_in : rd[j == 0 ? 0 : j - 1]) : 0.0f;
+  };
+  float T = 1.0f;
+  float2 yp = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const float l = lof(j);
+    const float2 y = cf_fma(-l, yp, x[j]);
+    x[j] = y;
+    yp = y;
+    T *= -l;
+  }
+  float sT = T;
+  float2 sb = yp, h;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      const float oT = S::from_lower(sT);
+      const float2 ob = S::from_lower(sb);
+      sb = cf_fma(sT, ob, sb);
+      sT = sT * oT;
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    h = RowShift<1>::from_lower(sb);
+  } else {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const float oT = __shfl_up(sT, (unsigned)d, G);
+      const float2 ob = make_float2(__shfl_up(sb.x, (unsigned)d, G), __shfl_up(sb.y, (unsigned)d, G));
+      if (m >= d) {
+        sb = cf_fma(sT, ob, sb);
+        sT = sT * oT;
+      }
+    }
+    h = make_float2(__shfl_up(sb.x, 1u, G), __shfl_up(sb.y, 1u, G));
+    if (m == 0) h = make_float2(0.0f, 0.0f);
+  }
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    h = cf_mul(-lof(j), h);
+    x[j] = cf_add(x[j], h);
+  }
+  float A00 = 1.0f, A01 = 0.0f, A10 = 0.0f, A11 = 1.0f;
+  float2 c0 = make_float2(0.0f, 0.0f), c1 = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const float r = rd[j];
+    x[j] = cf_mul(r, x[j]);
+    const float eh = r * (gg[j] + hm), gh = r * gg[j];
+    const float n00 = -eh * A00 - gh * A10, n01 = -eh * A01 - gh * A11;
+    const float n10 = A00 + A10, n11 = A01 + A11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    float2 nc0 = cf_fma(-eh, c0, x[j]);
+    nc0 = cf_fma(-gh, c1, nc0);
+    const float2 nc1 = cf_add(c0, c1);
+    c0 = nc0;
+    c1 = nc1;
+  }
+  auto compose2 = [&](float o00, float o01, float o10, float o11, float2 oc0, float2 oc1) {
+    const float2 n0 = cf_add(cf_fma(A00, oc0, cf_mul(A01, oc1)), c0);
+    const float2 n1 = cf_add(cf_fma(A10, oc0, cf_mul(A11, oc1)), c1);
+    const float n00 = A00 * o00 + A01 * o10, n01 = A00 * o01 + A01 * o11;
+    const float n10 = A10 * o00 + A11 * o10, n11 = A10 * o01 + A11 * o11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    c0 = n0;
+    c1 = n1;
+  };
+  float2 sa, sS;
+  if constexpr (G == 16) {
+    auto lvl = [&](auto sh) {
+      using S = decltype(sh);
+      compose2(S::from_upper(A00), S::from_upper(A01), S::from_upper(A10), S::from_upper(A11), S::from_upper(c0),
+               S::from_upper(c1));
+    };
+    lvl(RowShift<1>{});
+    lvl(RowShift<2>{});
+    lvl(RowShift<4>{});
+    lvl(RowShift<8>{});
+    sa = RowShift<1>::from_upper(c0);
+    sS = RowShift<1>::from_upper(c1);
+  } else {
+    auto dn = [&](float v, int d) { return __shfl_down(v, (unsigned)d, G); };
+    auto dn2 = [&](float2 v, int d) { return make_float2(dn(v.x, d), dn(v.y, d)); };
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const float o00 = dn(A00, d), o01 = dn(A01, d), o10 = dn(A10, d), o11 = dn(A11, d);
+      const float2 oc0 = dn2(c0, d), oc1 = dn2(c1, d);
+      if (m + d < G) compose2(o00, o01, o10, o11, oc0, oc1);
+    }
+    sa = dn2(c0, 1);
+    sS = dn2(c1, 1);
+    if (m == G - 1) {
+      sa = make_float2(0.0f, 0.0f);
+      sS = make_float2(0.0f, 0.0f);
+    }
+  }
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const float r = rd[j];
+    const float eh = r * (gg[j] + hm), gh = r * gg[j];
+    float2 uj = cf_fma(-eh, sa, x[j]);
+    uj = cf_fma(-gh, sS, uj);
+    x[j] = uj;
+    sS = cf_add(sS, sa);
+    sa = uj;
+  }
+}
+
+// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows.
+template <int C, int G>
+__device__ __forceinline__ void helm_residual(int N, int lane, bool wok, double al, int gl, const double2 (&f)[C],
+                                              const double2 (&u)[C], float2 (&x)[C]) {
+  const int p = (lane / G) & 1, m = lane % G;
+  const int n = N - 2;
+  const int k0 = 2 * m * C + p;
+  double2 tot = zero2();
+#pragma unroll
+  for (int j = 0; j < C; ++j) tot = c_add(tot, u[j]);
+  double2 u_prev, u_next, E;
+  if constexpr (G == 16) {
+    u_prev = RowShift<1>::from_lower(u[C - 1]);
+    u_next = RowShift<1>::from_upper(u[0]);
+    double2 inc = tot;  // inclusive suffix sum of chunk totals over lanes >= m
+    inc = c_add(inc, RowShift<1>::from_upper(inc));
+    inc = c_add(inc, RowShift<2>::from_upper(inc));
+    inc = c_add(inc, RowShift<4>::from_upper(inc));
+    inc = c_add(inc, RowShift<8>::from_upper(inc));
+    E = RowShift<1>::from_upper(inc);
+  } else {
+    u_prev = shfl_up2(u[C - 1], 1, G);
+    if (m == 0) u_prev = zero2();
+    u_next = shfl_down2(u[0], 1, G);
+    if (m == G - 1) u_next = zero2();
+    double2 inc = tot;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const double2 o = shfl_down2(inc, d, G);
+      if (m + d < G) inc = c_add(inc, o);
+    }
+    E = shfl_down2(inc, 1, G);
+    if (m == G - 1) E = zero2();
+  }
+  // R = suffix sum from element j+2 (rows >= k+4 of the chain, all lanes)
+  double2 R2 = c_sub(E, u_next);  // from element C+1
+  double2 R1 = E;                 // from element C
+  const double hm = -0.5 * kPi * al;
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const int k = k0 + 2 * j;
+    const HelmRow h = helm_row(k, al, N, gl);
+    const double2 um = (j == 0) ? u_prev : u[j == 0 ? 0 : j - 1];
+    const double2 up = (j == C - 1) ? u_next : u[j == C - 1 ? 0 : j + 1];
+    double2 hu = c_mul(h.h0, u[j]);
+    hu = c_fma(hm, um, hu);
+    hu = c_fma(h.hpp + hm, up, hu);
+    hu = c_fma(h.hpp, R2, hu);
+    const bool ok = wok && k < n;
+    x[j] = ok ? to_f2(c_sub(f[j], hu)) : make_float2(0.0f, 0.0f);
+    R2 = R1;
+    R1 = c_add(R1, u[j]);
+  }
+}
+
+// Reduction over the 2G lanes of a system.
+template <int G>
+__device__ __forceinline__ double sys_max(double v) {
+#pragma unroll
+  for (int d = 1; d < 2 * G; d <<= 1) v = fmax(v, __shfl_xor(v, d, 2 * G));
+  return v;
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                      const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                      int32_t* __restrict__ info, int it_max, double tol) {
+  constexpr int SPW = 64 / (2 * G);
+  __shared__ double2 st64[64];
+  const int lane = threadIdx.x & 63;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 2;
+  const int k0 = 2 * m * C + p;
+  const double al = wok ? alpha[w] : 0.0;
+  const double2* frow = f + (wok ? w : 0) * (int64_t)N;
+  double2* urow = u + (wok ? w : 0) * (int64_t)N;
+  HelmPrev32 pv = {0.0f, 0.0f};
+  if (wok && m > 0 && k0 < n) {
+    const float2 s2 = reinterpret_cast<const float2*>(urow)[p * G + m];
+    pv.rd = s2.x;
+    pv.g = s2.y;
+  }
+  double2 fx[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    fx[j] = (wok && k < n) ? frow[k] : zero2();
+  }
+  // FP32 factorisation
+  const float hm32 = (float)(-0.5 * kPi * al);
+  const float rd_in = (k0 >= 2) ? pv.rd : 0.0f;
+  float rd[C], gg[C];
+  bool finite32 = true;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const bool ok = wok && k < n;
+    float l, g, r, d;
+    helm_step32(k, al, N, gl, pv, l, g, r, d);
+    pv.rd = r;
+    pv.g = g;
+    rd[j] = ok ? r : 0.0f;
+    gg[j] = ok ? g : 0.0f;
+    if (ok && !(fabsf(d) > 0.0f && fabsf(d) < 3.0e38f && fabsf(r) < 3.0e38f)) finite32 = false;
+  }
+  // refinement
+  double2 ux[C];
+  float2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    ux[j] = zero2();
+    x[j] = to_f2(fx[j]);
+  }
+  bool running = wok && (sys_max<G>(finite32 ? 0.0 : 1.0) == 0.0);
+  bool conv = false;
+  double prev = 1e300;
+  for (int it = 0; it <= it_max; ++it) {  // the first solve, then it_max corrections at most
+    helm_solve32<C, G>(lane, wok, n, hm32, rd_in, rd, gg, x);
+    double dmax = 0.0, umax = 0.0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      if (running) ux[j] = c_add(ux[j], to_d2(x[j]));
+      dmax = fmax(dmax, cabs1(to_d2(x[j])));
+      umax = fmax(umax, cabs1(ux[j]));
+    }
+    dmax = sys_max<G>(dmax);
+    umax = sys_max<G>(umax);
+    if (running) {
+      if (!(dmax <= 1e300)) {
+        running = false;  // non-finite: FP64 below
+      } else if (dmax <= tol * umax) {
+        running = false;
+        conv = true;
+      } else if (dmax > 0.5 * prev) {  // rounding floor reached
+        running = false;
+        conv = dmax <= 1e-11 * umax;
+      }
+      prev = dmax;
+    }
+    if (!__any(running)) break;
+    helm_residual<C, G>(N, lane, wok, al, gl, fx, ux, x);
+  }
+  const bool failed = wok && !conv;
+  int bad = INT_MAX;
+  if (__any(failed)) {
+    // FP64 re-solve of this wavefront's systems: restart states by one
+    // sequential walk per chain (lane m = 0), then the FP64 wave solve
+    if (m == 0 && wok) {
+      const int nc = (n - p + 1) / 2;
+      const int nchunks = (nc + C - 1) / C;
+      HelmPrev q = {0.0, 0.0};
+      for (int i = 0; i < (nchunks - 1) * C; ++i) {
+        double l, g, r, d;
+        helm_step(2 * i + p, al, N, gl, q, l, g, r, d);
+        q.rd = r;
+        q.g = g;
+        if ((i + 1) % C == 0) st64[sl * 2 * G + p * G + (i + 1) / C] = make_double2(q.rd, q.g);
+      }
+    }
+    __syncthreads();
+    HelmPrev q = {0.0, 0.0};
+    if (wok && m > 0 && k0 < n) {
+      q.rd = st64[lane].x;
+      q.g = st64[lane].y;
+    }
+    double2 x64[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) x64[j] = fx[j];
+    bad = helm_wave_core<C, G, true>(N, lane, w, wok, al, q, x64, urow, gl, nullptr);
+    if (failed) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) ux[j] = x64[j];
+    }
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) urow[k] = (k < n) ? ux[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    int b = failed ? bad : INT_MAX;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) b = min(b, __shfl_xor(b, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = failed ? (b == INT_MAX ? SHEN_INFO_REFINE_FALLBACK : b + 1) : 0;
   }
 }
 
@@ -1243,8 +1637,14 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     const double2* f = (const double2*)a.f + s0 * a.N;
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
-    hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
     const int64_t groups = (ns + SPW - 1) / SPW;
+    if (a.mixed) {
+      hipLaunchKernelGGL(helm_boundary32, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
+      hipLaunchKernelGGL((helm_mixed_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info, a.it_max,
+                         a.tol);
+      continue;
+    }
+    hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16) {
       const int64_t blocks = persistent_blocks((const void*)helm_wave_pipe<C, G>, groups);
       hipLaunchKernelGGL((helm_wave_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);

@@ -268,22 +268,24 @@ def test_autograd_config5_vs_dense(dev, family):
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
 @pytest.mark.parametrize("N", [64, 256, 512])
-def test_mixed_precision(dev, family, N):
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+def test_mixed_precision(dev, family, N, variant):
     from paper_1701_03787_amd import api
     g = wl.small_grid(N, 40, kmax=256, index=N)
     cs = g.coefficients(family)
     f = g.rhs(family)
-    case(test="mixed", family=family, N=N)
+    case(test="mixed", family=family, N=N, variant=variant)
     ref = so.solve(family, N, cs, f)
     fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
-    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True)
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, variant=variant)
     torch.cuda.synchronize()
     assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
     assert np.all(info.cpu().numpy() == 0)
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-def test_mixed_precision_fallback(dev, family):
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+def test_mixed_precision_fallback(dev, family, variant):
     """One correction is not enough for 1e-14: every system falls back to FP64 (info -2)
     and the answer still meets the FP64 bar."""
     from paper_1701_03787_amd import api
@@ -291,10 +293,10 @@ def test_mixed_precision_fallback(dev, family):
     g = wl.small_grid(N, 12, kmax=256, index=5)
     cs = g.coefficients(family)
     f = g.rhs(family)
-    case(test="mixed_fallback", family=family)
+    case(test="mixed_fallback", family=family, variant=variant)
     ref = so.solve(family, N, cs, f)
     fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
-    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, refine_max=1)
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, refine_max=1, variant=variant)
     torch.cuda.synchronize()
     assert np.all(info.cpu().numpy() == -2)
     assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
@@ -326,3 +328,29 @@ def test_roundoff_protocol_vs_paper(dev, family, variant):
             worst.append((e / table[(family, z)][N], N, z, e))
     print("roundoff ratios to the paper:", sorted(worst)[-4:], flush=True)
     assert max(w[0] for w in worst) <= bound, sorted(worst)[-3:]
+
+
+@pytest.mark.parametrize("N", [130, 512, 1024])
+def test_mixed_precision_wave_sizes(dev, N):
+    """The register-resident FP32 + refinement Helmholtz path over ragged and large N,
+    at the bench's coefficients (config 3 law), against the oracle."""
+    from paper_1701_03787_amd import api
+    g = wl.small_grid(N, 37, kmax=362, index=N, nu=5e-5, dt=5e-4)
+    cs = g.coefficients("helmholtz")
+    f = g.rhs("helmholtz")
+    case(test="mixed_wave", N=N)
+    ref = so.solve("helmholtz", N, cs, f)
+    u, info = api.helmholtz_solve(T(f, dev), T(cs[0], dev), precision="fp32_refine", info=True, variant="wave")
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
+    assert np.all(info.cpu().numpy() == 0)
+    assert np.all(u.cpu().numpy()[:, N - 2:] == 0)
+
+
+def test_wave_variant_refuses_transpose(dev):
+    from paper_1701_03787_amd import api, _lib
+    g = wl.small_grid(64, 3)
+    f = T(g.rhs("helmholtz"), dev)
+    a = T(g.coefficients("helmholtz")[0], dev)
+    with pytest.raises(_lib.ShenError):
+        api.helmholtz_solve(f, a, transpose=True, variant="wave")
