@@ -93,10 +93,11 @@ int run(ChainArgs& a) {
 // The wave path serves plain FP64 forward solves out of place (it parks the LU
 // restart states in u); everything else, and sizes it does not cover, goes to
 // the chain kernels.
-// The wave kernels cover the plain FP64 solve of both families and the
-// FP32 + refinement solve of the Helmholtz family, not the transposed solve.
+// The wave kernels cover the plain FP64 and the FP32 + refinement solves of
+// both families, not the transposed solve.
 bool wave_mode_ok(const shen_opts& o, int family) {
-  return !o.transpose && (o.precision == SHEN_FP64 || family == SHEN_HELMHOLTZ);
+  (void)family;
+  return !o.transpose;
 }
 bool use_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
   if (o.variant == SHEN_VARIANT_CHAIN) return false;
@@ -218,6 +219,9 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
     if (!wave_mode_ok(o, 1) || !shen::wave_supported(1, N) || f == (const void*)u) return SHEN_ENOTSUP;
     shen::WaveArgs w;
     w.family = 1;
+    w.mixed = o.precision == SHEN_FP32_REFINE;
+    w.it_max = o.refine_max;
+    w.tol = o.refine_tol;
     w.N = N;
     w.nsys = nsys;
     w.c0 = ca;

@@ -24,6 +24,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "shen_launch.hpp"
 #include "shen_rows.hpp"
 #include "shenhip.h"
@@ -164,6 +166,43 @@ __device__ __forceinline__ void bih_step_row(int k, const BihRow& h, const BihRo
 __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
                                          const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
   bih_step_row(k, bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out);
+}
+
+// The same step in FP32 (mixed-precision form): row entries formed in FP64
+// and rounded once, factorisation arithmetic in FP32.
+struct BihRowState32 {
+  float rU0, U2, U4, P, R;
+};
+__device__ __forceinline__ void bih_step_row32(int k, const BihRow& hd, const BihRowState32& m2, const BihRowState32& m4,
+                                               BihRowState32& o, float& l1, float& l2, float& t0out) {
+  const float hm4 = (float)hd.hm4, hm2 = (float)hd.hm2, h0 = (float)hd.h0, hp2 = (float)hd.hp2, hp4 = (float)hd.hp4;
+  const float q2 = (float)hd.q2, s2 = (float)hd.s2, q4 = (float)hd.q4, s4 = (float)hd.s4;
+  float tm2 = hm2, t0 = h0, t2 = hp2, t4 = hp4, P = (float)hd.p, Rr = (float)hd.r;
+  l1 = 0.0f;
+  l2 = 0.0f;
+  if (k >= 4) {
+    l2 = hm4 * m4.rU0;
+    tm2 = __builtin_fmaf(-l2, m4.U2, tm2);
+    t0 = __builtin_fmaf(-l2, m4.U4, t0);
+    t2 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q2, m4.R * s2), t2);
+    t4 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q4, m4.R * s4), t4);
+    P = __builtin_fmaf(-l2, m4.P, P);
+    Rr = __builtin_fmaf(-l2, m4.R, Rr);
+  }
+  if (k >= 2) {
+    l1 = tm2 * m2.rU0;
+    t0 = __builtin_fmaf(-l1, m2.U2, t0);
+    t2 = __builtin_fmaf(-l1, m2.U4, t2);
+    t4 = __builtin_fmaf(-l1, __builtin_fmaf(m2.P, q4, m2.R * s4), t4);
+    P = __builtin_fmaf(-l1, m2.P, P);
+    Rr = __builtin_fmaf(-l1, m2.R, Rr);
+  }
+  o.rU0 = rcp32(t0);
+  o.U2 = t2;
+  o.U4 = t4;
+  o.P = P;
+  o.R = Rr;
+  t0out = t0;
 }
 
 // ------------------------------------------------------------------------
@@ -321,43 +360,66 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
 }
 
 // Table-driven form of the biharmonic boundary walk: the rows are assembled
-// from the LDS table (bih_row_tab), exactly as the table-driven wave solve
-// assembles them, so the restart states continue the same factorisation.
+// from the LDS table (bih_row_tab), exactly as the table-driven wave solves
+// assemble them, so the restart states continue the same factorisation.
+// States of chunk m go to st[(p G + m) 10 + 0..9] (FP64, or FP32 with F32).
 // The four wavefronts of a 256-thread block walk chains of one parity each,
 // so every step reads one table row for the whole wavefront (broadcast).
-__device__ __forceinline__ void bih_boundary_chain_tab(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
-                                                       int gl, const double* tab) {
+template <bool F32>
+__device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double a, double b, void* st, int gl, const double* tab) {
   const int RT = 2 * G * C;
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
   if (nchunks <= 1) return;
-  double* st = reinterpret_cast<double*>(urow);
-  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   BihConst cm2 = bih_const_at(tab, RT, C, p - 2, N, gl), cm4 = bih_const_at(tab, RT, C, p - 4, N, gl);
   const int ilast = (nchunks - 1) * C;
-  for (int i = 0; i < ilast; ++i) {
-    const int k = 2 * i + p;
-    const BihConst c = bih_tab_get(tab, RT, C, k);
-    BihRowState o;
-    double l1, l2, t0;
-    bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
-    m4 = m2;
-    m2 = o;
-    cm4 = cm2;
-    cm2 = c;
-    if ((i + 1) % C == 0) {
-      const int m = (i + 1) / C;
-      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 10);
-      s[0] = make_double2(m2.rU0, m2.U2);
-      s[1] = make_double2(m2.U4, m2.P);
-      s[2] = make_double2(m2.R, m4.rU0);
-      s[3] = make_double2(m4.U2, m4.U4);
-      s[4] = make_double2(m4.P, m4.R);
+  if constexpr (F32) {
+    BihRowState32 m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+    for (int i = 0; i < ilast; ++i) {
+      const int k = 2 * i + p;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      BihRowState32 o;
+      float l1, l2, t0;
+      bih_step_row32(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      m4 = m2;
+      m2 = o;
+      cm4 = cm2;
+      cm2 = c;
+      if ((i + 1) % C == 0) {
+        float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + (i + 1) / C) * 10);
+        sv[0] = make_float2(m2.rU0, m2.U2);
+        sv[1] = make_float2(m2.U4, m2.P);
+        sv[2] = make_float2(m2.R, m4.rU0);
+        sv[3] = make_float2(m4.U2, m4.U4);
+        sv[4] = make_float2(m4.P, m4.R);
+      }
+    }
+  } else {
+    BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+    for (int i = 0; i < ilast; ++i) {
+      const int k = 2 * i + p;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      BihRowState o;
+      double l1, l2, t0;
+      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      m4 = m2;
+      m2 = o;
+      cm4 = cm2;
+      cm2 = c;
+      if ((i + 1) % C == 0) {
+        double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G + (i + 1) / C) * 10);
+        sv[0] = make_double2(m2.rU0, m2.U2);
+        sv[1] = make_double2(m2.U4, m2.P);
+        sv[2] = make_double2(m2.R, m4.rU0);
+        sv[3] = make_double2(m4.U2, m4.U4);
+        sv[4] = make_double2(m4.P, m4.R);
+      }
     }
   }
 }
 
+template <bool F32>
 __global__ __launch_bounds__(256) void bih_boundary_tab(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
                                                         const double* __restrict__ cb, double2* __restrict__ u, int gl) {
   extern __shared__ double tab[];
@@ -366,7 +428,7 @@ __global__ __launch_bounds__(256) void bih_boundary_tab(int N, int64_t nsys, int
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 128 + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
-  bih_boundary_chain_tab(N, C, G, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
+  bih_walk_tab<F32>(N, C, G, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
 }
 
 // =========================================================================
@@ -906,7 +968,7 @@ struct NoHook {
   __device__ void operator()() const {}
 };
 template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook>
-__device__ __forceinline__ void bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
+__device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook());
 
@@ -952,7 +1014,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
 // forward refinement sweep).  Without PIPE the solution is stored to urow;
 // with PIPE it is left in x for the caller.
 template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook>
-__device__ __forceinline__ void bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
+__device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f) {
   const int p = (lane / G) & 1;
@@ -1263,6 +1325,7 @@ __device__ __forceinline__ void bih_wave_core(int N, int lane, int64_t w, bool w
     for (int d = 1; d < 2 * G; d <<= 1) bq = min(bq, __shfl_xor(bq, d, 2 * G));
     if (wok && (lane % (2 * G)) == 0) info[w] = (bq == INT_MAX) ? 0 : bq + 1;
   }
+  return bad;
 }
 
 template <int C, int G>
@@ -1271,6 +1334,404 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
                                                       int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
   helm_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, alpha, f, u, gl, info);
+}
+
+// =========================================================================
+// Biharmonic, FP32 factor/solve + FP64 iterative refinement (wave layout)
+// =========================================================================
+// Shifts across the G lanes of a chain: value of lane m - D (lo) or m + D
+// (hi), zero where that lane does not exist.
+template <int G, int D, typename V>
+__device__ __forceinline__ V chain_lo(V v, int m) {
+  if constexpr (G == 16) {
+    return RowShift<D>::from_lower(v);
+  } else {
+    V o;
+    if constexpr (std::is_same_v<V, double2>) {
+      o = shfl_up2(v, D, G);
+    } else if constexpr (std::is_same_v<V, float2>) {
+      o = make_float2(__shfl_up(v.x, (unsigned)D, G), __shfl_up(v.y, (unsigned)D, G));
+    } else {
+      o = __shfl_up(v, (unsigned)D, G);
+    }
+    return (m >= D) ? o : V{};
+  }
+}
+template <int G, int D, typename V>
+__device__ __forceinline__ V chain_hi(V v, int m) {
+  if constexpr (G == 16) {
+    return RowShift<D>::from_upper(v);
+  } else {
+    V o;
+    if constexpr (std::is_same_v<V, double2>) {
+      o = shfl_down2(v, D, G);
+    } else if constexpr (std::is_same_v<V, float2>) {
+      o = make_float2(__shfl_down(v.x, (unsigned)D, G), __shfl_down(v.y, (unsigned)D, G));
+    } else {
+      o = __shfl_down(v, (unsigned)D, G);
+    }
+    return (m + D < G) ? o : V{};
+  }
+}
+
+// Factors of the FP32 solve, per chunk element (0 on padding rows).
+template <int C>
+struct BihFac32 {
+  float l1[C], l2[C], r0[C], u2[C], u4[C], p[C], r[C];
+};
+
+// In place: x <- H^{-1} x in FP32 with stored factors (the FP64 wave solve's
+// scans, without the forward refinement sweep).
+template <int C, int G>
+__device__ __forceinline__ void bih_solve32(int lane, const BihFac32<C>& F, const double* tab, float2 (&x)[C]) {
+  const int p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  float T00 = 1.0f, T01 = 0.0f, T10 = 0.0f, T11 = 1.0f;
+  float2 y1 = make_float2(0.0f, 0.0f), y2 = y1;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    float2 y = cf_fma(-F.l1[j], y1, x[j]);
+    y = cf_fma(-F.l2[j], y2, y);
+    x[j] = y;
+    y2 = y1;
+    y1 = y;
+    const float n00 = -F.l1[j] * T00 - F.l2[j] * T10, n01 = -F.l1[j] * T01 - F.l2[j] * T11;
+    T10 = T00;
+    T11 = T01;
+    T00 = n00;
+    T01 = n01;
+  }
+  float2 b0 = y1, b1 = y2;
+  auto composeT = [&](float o00, float o01, float o10, float o11, float2 ob0, float2 ob1) {
+    const float2 n0 = cf_add(cf_fma(T00, ob0, cf_mul(T01, ob1)), b0);
+    const float2 n1 = cf_add(cf_fma(T10, ob0, cf_mul(T11, ob1)), b1);
+    const float n00 = T00 * o00 + T01 * o10, n01 = T00 * o01 + T01 * o11;
+    const float n10 = T10 * o00 + T11 * o10, n11 = T10 * o01 + T11 * o11;
+    T00 = n00;
+    T01 = n01;
+    T10 = n10;
+    T11 = n11;
+    b0 = n0;
+    b1 = n1;
+  };
+  auto lvlT = [&](auto dd) {
+    constexpr int D = decltype(dd)::value;
+    const float o00 = chain_lo<G, D>(T00, m), o01 = chain_lo<G, D>(T01, m), o10 = chain_lo<G, D>(T10, m),
+                o11 = chain_lo<G, D>(T11, m);
+    const float2 ob0 = chain_lo<G, D>(b0, m), ob1 = chain_lo<G, D>(b1, m);
+    composeT(o00, o01, o10, o11, ob0, ob1);
+  };
+  lvlT(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvlT(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvlT(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvlT(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvlT(std::integral_constant<int, 16>{});
+  float2 h1 = chain_lo<G, 1>(b0, m), h2 = chain_lo<G, 1>(b1, m);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    float2 hj = cf_mul(-F.l1[j], h1);
+    hj = cf_fma(-F.l2[j], h2, hj);
+    x[j] = cf_add(x[j], hj);
+    h2 = h1;
+    h1 = hj;
+  }
+  float A[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A[r][c] = (r == c) ? 1.0f : 0.0f;
+  float2 cv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cv[r] = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const double2 qs = bih_tab_qs(tab, C, k0 + 2 * j);
+    const float q4 = (float)qs.x, s4 = (float)qs.y;
+    x[j] = cf_mul(F.r0[j], x[j]);
+    float nA0[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nA0[c] = -(F.u2[j] * A[0][c] + F.u4[j] * A[1][c] + F.p[j] * A[2][c] + F.r[j] * A[3][c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float a1 = A[1][c];
+      A[2][c] = __builtin_fmaf(q4, a1, A[2][c]);
+      A[3][c] = __builtin_fmaf(s4, a1, A[3][c]);
+      A[1][c] = A[0][c];
+      A[0][c] = nA0[c];
+    }
+    float2 nc0 = cf_fma(-F.u2[j], cv[0], x[j]);
+    nc0 = cf_fma(-F.u4[j], cv[1], nc0);
+    nc0 = cf_fma(-F.p[j], cv[2], nc0);
+    nc0 = cf_fma(-F.r[j], cv[3], nc0);
+    cv[2] = cf_fma(q4, cv[1], cv[2]);
+    cv[3] = cf_fma(s4, cv[1], cv[3]);
+    cv[1] = cv[0];
+    cv[0] = nc0;
+  }
+  auto lvlA = [&](auto dd) {
+    constexpr int D = decltype(dd)::value;
+    float oA[4][4];
+    float2 oc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) oA[r][c] = chain_hi<G, D>(A[r][c], m);
+      oc[r] = chain_hi<G, D>(cv[r], m);
+    }
+    float nA[4][4];
+    float2 ncv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float2 acc = cv[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc = cf_fma(A[r][c], oc[c], acc);
+      ncv[r] = acc;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float t = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t = __builtin_fmaf(A[r][q], oA[q][c], t);
+        nA[r][c] = t;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cv[r] = ncv[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) A[r][c] = nA[r][c];
+    }
+  };
+  lvlA(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvlA(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvlA(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvlA(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvlA(std::integral_constant<int, 16>{});
+  float2 sa = chain_hi<G, 1>(cv[0], m), sb = chain_hi<G, 1>(cv[1], m), sq = chain_hi<G, 1>(cv[2], m),
+         ss = chain_hi<G, 1>(cv[3], m);
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const double2 qs = bih_tab_qs(tab, C, k0 + 2 * j);
+    float2 uj = cf_fma(-F.u2[j], sa, x[j]);
+    uj = cf_fma(-F.u4[j], sb, uj);
+    uj = cf_fma(-F.p[j], sq, uj);
+    uj = cf_fma(-F.r[j], ss, uj);
+    x[j] = uj;
+    sq = cf_fma((float)qs.x, sb, sq);
+    ss = cf_fma((float)qs.y, sb, ss);
+    sb = sa;
+    sa = uj;
+  }
+}
+
+// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows; rows
+// from the table as in the factorisation.
+template <int C, int G>
+__device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a, double b, int gl, const double* tab,
+                                             const double2 (&f)[C], const double2 (&u)[C], float2 (&x)[C]) {
+  constexpr int RT = 2 * G * C;
+  const int p = (lane / G) & 1, m = lane % G;
+  const int n = N - 4;
+  const int k0 = 2 * m * C + p;
+  auto qw = [](int k) { return fast_rcp((double)k + 3.0); };  // q_k = 1/(k+3)
+  auto sw = [](int k, double q) {                            // s_k = (k+2)^2/(k+3)
+    const double t = (double)k + 2.0;
+    return t * t * q;
+  };
+  double2 TQ = zero2(), TS = zero2();
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const double q = qw(k);
+    TQ = c_fma(q, u[j], TQ);
+    TS = c_fma(sw(k, q), u[j], TS);
+  }
+  const double2 pl1 = chain_lo<G, 1>(u[C - 1], m), pl2 = chain_lo<G, 1>(u[C - 2], m);  // rows k0-2, k0-4
+  const double2 nx1 = chain_hi<G, 1>(u[0], m), nx2 = chain_hi<G, 1>(u[1], m);          // rows k0+2C, k0+2C+2
+  double2 iq = TQ, is = TS;  // inclusive suffix sums over lanes >= m
+  auto lvl = [&](auto dd) {
+    constexpr int D = decltype(dd)::value;
+    iq = c_add(iq, chain_hi<G, D>(iq, m));
+    is = c_add(is, chain_hi<G, D>(is, m));
+  };
+  lvl(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvl(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvl(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvl(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvl(std::integral_constant<int, 16>{});
+  const double2 EQ = chain_hi<G, 1>(iq, m), ES = chain_hi<G, 1>(is, m);
+  const int kn1 = k0 + 2 * C, kn2 = kn1 + 2;
+  const double qn1 = qw(kn1), qn2 = qw(kn2);
+  // sliding suffix sums from elements j+3, j+2, j+1 (rows >= k+6, k+4, k+2)
+  double2 Q1 = EQ, S1 = ES;                                        // from element C
+  double2 Q2 = c_fnms(qn1, nx1, EQ), S2 = c_fnms(sw(kn1, qn1), nx1, ES);  // from element C+1
+  double2 Q3 = c_fnms(qn2, nx2, Q2), S3 = c_fnms(sw(kn2, qn2), nx2, S2);  // from element C+2
+  // rows k-2, k-4 of the chunk's last element: carried downwards
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const int k = k0 + 2 * j;
+    const BihConst c = bih_tab_get(tab, RT, C, k);
+    const BihConst c2 = bih_const_at(tab, RT, C, k - 2, N, gl), c4 = bih_const_at(tab, RT, C, k - 4, N, gl);
+    const BihRow h = bih_row_tab(k, a, b, c, c2.B2, c2.q4, c2.s4, c4.B4);
+    const double2 um4 = (j >= 2) ? u[j >= 2 ? j - 2 : 0] : (j == 1 ? pl1 : pl2);
+    const double2 um2 = (j >= 1) ? u[j >= 1 ? j - 1 : 0] : pl1;
+    const double2 up2 = (j <= C - 2) ? u[j <= C - 2 ? j + 1 : 0] : nx1;
+    const double2 up4 = (j <= C - 3) ? u[j <= C - 3 ? j + 2 : 0] : (j == C - 2 ? nx1 : nx2);
+    double2 hu = c_mul(h.h0, u[j]);
+    hu = c_fma(h.hm4, um4, hu);
+    hu = c_fma(h.hm2, um2, hu);
+    hu = c_fma(h.hp2, up2, hu);
+    hu = c_fma(h.hp4, up4, hu);
+    hu = c_fma(h.p, Q3, hu);
+    hu = c_fma(h.r, S3, hu);
+    const bool ok = wok && k < n;
+    x[j] = ok ? to_f2(c_sub(f[j], hu)) : make_float2(0.0f, 0.0f);
+    const double q = qw(k);
+    Q3 = Q2;
+    S3 = S2;
+    Q2 = Q1;
+    S2 = S1;
+    Q1 = c_fma(q, u[j], Q1);
+    S1 = c_fma(sw(k, q), u[j], S1);
+  }
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const double* __restrict__ ca,
+                                                     const double* __restrict__ cb, const double2* __restrict__ f,
+                                                     double2* __restrict__ u, int gl, int32_t* __restrict__ info, int it_max,
+                                                     double tol) {
+  constexpr int SPW = 64 / (2 * G);
+  constexpr int RT = 2 * G * C;
+  extern __shared__ double smem[];
+  const double* tab = smem;
+  bih_tab_fill(smem, RT, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  double* st64 = smem + 2 * kBihTabPairs * RT + (threadIdx.x >> 6) * 64 * 10;  // FP64 restart states (fallback)
+  const int lane = threadIdx.x & 63;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 4;
+  const int k0 = 2 * m * C + p;
+  const double a = wok ? ca[w] : 0.0, b = wok ? cb[w] : 0.0;
+  const double2* frow = f + (wok ? w : 0) * (int64_t)N;
+  double2* urow = u + (wok ? w : 0) * (int64_t)N;
+  BihRowState32 m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  if (wok && m > 0 && k0 < n) {
+    const float2* s = reinterpret_cast<const float2*>(urow) + (p * G + m) * 5;
+    const float2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3], s4 = s[4];
+    m2 = BihRowState32{s0.x, s0.y, s1.x, s1.y, s2.x};
+    m4 = BihRowState32{s2.y, s3.x, s3.y, s4.x, s4.y};
+  }
+  double2 fx[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    fx[j] = (wok && k < n) ? frow[k] : zero2();
+  }
+  // FP32 factorisation
+  BihFac32<C> F;
+  bool finite32 = true;
+  {
+    BihConst cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      const bool ok = wok && k < n;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      BihRowState32 o;
+      float l1, l2, t0;
+      bih_step_row32(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      cm4 = cm2;
+      cm2 = c;
+      m4 = m2;
+      m2 = o;
+      if (ok && !(fabsf(t0) > 0.0f && fabsf(t0) < 3.0e38f && fabsf(o.rU0) < 3.0e38f)) finite32 = false;
+      F.l1[j] = ok ? l1 : 0.0f;
+      F.l2[j] = ok ? l2 : 0.0f;
+      F.r0[j] = ok ? o.rU0 : 0.0f;
+      F.u2[j] = ok ? o.rU0 * o.U2 : 0.0f;
+      F.u4[j] = ok ? o.rU0 * o.U4 : 0.0f;
+      F.p[j] = ok ? o.rU0 * o.P : 0.0f;
+      F.r[j] = ok ? o.rU0 * o.R : 0.0f;
+    }
+  }
+  // refinement
+  double2 ux[C];
+  float2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    ux[j] = zero2();
+    x[j] = to_f2(fx[j]);
+  }
+  bool running = wok && (sys_max<G>(finite32 ? 0.0 : 1.0) == 0.0);
+  bool conv = false;
+  double prev = 1e300;
+  for (int it = 0; it <= it_max; ++it) {  // the first solve, then it_max corrections at most
+    bih_solve32<C, G>(lane, F, tab, x);
+    double dmax = 0.0, umax = 0.0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      if (running) ux[j] = c_add(ux[j], to_d2(x[j]));
+      dmax = fmax(dmax, cabs1(to_d2(x[j])));
+      umax = fmax(umax, cabs1(ux[j]));
+    }
+    dmax = sys_max<G>(dmax);
+    umax = sys_max<G>(umax);
+    if (running) {
+      if (!(dmax <= 1e300)) {
+        running = false;
+      } else if (dmax <= tol * umax) {
+        running = false;
+        conv = true;
+      } else if (dmax > 0.5 * prev) {
+        running = false;
+        conv = dmax <= 1e-11 * umax;
+      }
+      prev = dmax;
+    }
+    if (!__any(running)) break;
+    bih_residual<C, G>(N, lane, wok, a, b, gl, tab, fx, ux, x);
+  }
+  const bool failed = wok && !conv;
+  int bad = INT_MAX;
+  if (__any(failed)) {
+    // FP64 re-solve of this wavefront's systems: restart states by one
+    // sequential walk per chain (lane m = 0) with the table rows, then the
+    // FP64 wave solve with the same rows
+    double* sts = st64 + sl * 2 * G * 10;
+    if (m == 0 && wok) bih_walk_tab<false>(N, C, G, p, a, b, sts, gl, tab);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    BihRowState q2 = {0, 0, 0, 0, 0}, q4 = {0, 0, 0, 0, 0};
+    if (wok && m > 0 && k0 < n) {
+      const double* sv = sts + (p * G + m) * 10;
+      q2 = BihRowState{sv[0], sv[1], sv[2], sv[3], sv[4]};
+      q4 = BihRowState{sv[5], sv[6], sv[7], sv[8], sv[9]};
+    }
+    double2 x64[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) x64[j] = fx[j];
+    auto fetch = [&](int j) { return fx[j]; };
+    bad = bih_wave_core<C, G, true, true>(N, lane, w, wok, a, b, q2, q4, x64, fetch, urow, gl, nullptr, tab);
+    if (failed) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) ux[j] = x64[j];
+    }
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) urow[k] = (k < n) ? ux[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    int bq = failed ? bad : INT_MAX;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) bq = min(bq, __shfl_xor(bq, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = failed ? (bq == INT_MAX ? SHEN_INFO_REFINE_FALLBACK : bq + 1) : 0;
+  }
 }
 
 template <int C, int G>
@@ -1667,10 +2128,23 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    if (a.mixed) {
+      const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double);
+      static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
+                                set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+      (void)attrm;
+      hipLaunchKernelGGL(bih_boundary_tab<true>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+                         a.gl);
+      hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
+                         c1, f, u, a.gl, info, a.it_max, a.tol);
+      continue;
+    }
     static const bool attr = set_dynamic_lds((const void*)bih_wave_tab<C, G>, lds) &&
-                             set_dynamic_lds((const void*)bih_boundary_tab, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+                             set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2)) &&
+                             set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
     (void)attr;
-    hipLaunchKernelGGL(bih_boundary_tab, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u, a.gl);
+    hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+                       a.gl);
     // gfx950: 160 KiB of LDS per work group
     constexpr size_t kPtabLds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 5) * 64 * sizeof(double2);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16 && kPtabLds <= 160 * 1024) {

@@ -330,21 +330,24 @@ def test_roundoff_protocol_vs_paper(dev, family, variant):
     assert max(w[0] for w in worst) <= bound, sorted(worst)[-3:]
 
 
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
 @pytest.mark.parametrize("N", [130, 512, 1024])
-def test_mixed_precision_wave_sizes(dev, N):
-    """The register-resident FP32 + refinement Helmholtz path over ragged and large N,
-    at the bench's coefficients (config 3 law), against the oracle."""
+def test_mixed_precision_wave_sizes(dev, family, N):
+    """The register-resident FP32 + refinement path over ragged and large N, at the
+    bench's coefficient law, against the oracle; every system converges in FP32+FP64."""
     from paper_1701_03787_amd import api
     g = wl.small_grid(N, 37, kmax=362, index=N, nu=5e-5, dt=5e-4)
-    cs = g.coefficients("helmholtz")
-    f = g.rhs("helmholtz")
-    case(test="mixed_wave", N=N)
-    ref = so.solve("helmholtz", N, cs, f)
-    u, info = api.helmholtz_solve(T(f, dev), T(cs[0], dev), precision="fp32_refine", info=True, variant="wave")
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    case(test="mixed_wave", family=family, N=N)
+    ref = so.solve(family, N, cs, f)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, variant="wave")
     torch.cuda.synchronize()
     assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
+    print("info", np.unique(info.cpu().numpy(), return_counts=True), flush=True)
     assert np.all(info.cpu().numpy() == 0)
-    assert np.all(u.cpu().numpy()[:, N - 2:] == 0)
+    assert np.all(u.cpu().numpy()[:, wl.n_unknowns(family, N):] == 0)
 
 
 def test_wave_variant_refuses_transpose(dev):
