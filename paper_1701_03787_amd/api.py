@@ -136,7 +136,7 @@ def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
     return y
 
 
-def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None):
+def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, variant="auto"):
     """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None)."""
     gbar = _rows(gbar, "gbar")
     N = gbar.shape[-1]
@@ -147,14 +147,14 @@ def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None):
     if coef_grad:
         u = _rows(u, "u")
     inf = _info_tensor(info, lead, gbar.device)
-    o = _opts(gbar.device, quad=quad, info=inf)
+    o = _opts(gbar.device, quad=quad, info=inf, variant=variant)
     L.check(L.lib().helmholtz_adjoint(N, _nsys(lead), alpha.data_ptr(), u.data_ptr() if coef_grad else None,
                                       gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
                                       C.byref(o)), "helmholtz_adjoint")
     return (lam, ga, inf) if inf is not None else (lam, ga)
 
 
-def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None):
+def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, variant="auto"):
     """lambda = H^{-T} gbar, grad_a = -Re(lambda^H A u), grad_b = -Re(lambda^H B u)."""
     gbar = _rows(gbar, "gbar")
     N = gbar.shape[-1]
@@ -167,7 +167,7 @@ def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None):
     if coef_grad:
         u = _rows(u, "u")
     inf = _info_tensor(info, lead, gbar.device)
-    o = _opts(gbar.device, quad=quad, info=inf)
+    o = _opts(gbar.device, quad=quad, info=inf, variant=variant)
     L.check(L.lib().biharmonic_adjoint(N, _nsys(lead), a.data_ptr(), b.data_ptr(), u.data_ptr() if coef_grad else None,
                                        gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
                                        gb.data_ptr() if gb is not None else None, C.byref(o)), "biharmonic_adjoint")

@@ -261,6 +261,24 @@ int helmholtz_adjoint(int32_t N, int64_t nsys, const double* alpha, const shen_c
   if (grad_alpha && (check_rows(u) || !aligned(grad_alpha, 8))) return SHEN_EINVAL;
   if (rows_overlap_partially(gbar, lambda, nsys, N)) return SHEN_EINVAL;
   if (u && (u == lambda || rows_overlap_partially(u, lambda, nsys, N))) return SHEN_EINVAL;
+  if (o.variant != SHEN_VARIANT_CHAIN && (const void*)gbar != (const void*)lambda && shen::wave_supported(0, N)) {
+    shen::WaveArgs w;
+    w.family = 0;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = alpha;
+    w.f = gbar;
+    w.u = lambda;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.chunk = o.chunk;
+    w.adjoint = 1;
+    w.ufwd = grad_alpha ? u : nullptr;
+    w.g0 = grad_alpha;
+    w.stream = o.stream;
+    return run_wave(w);
+  }
+  if (o.variant == SHEN_VARIANT_WAVE) return SHEN_ENOTSUP;
   ChainArgs a;
   a.kind = ChainKind::HelmAdjoint;
   a.N = N;

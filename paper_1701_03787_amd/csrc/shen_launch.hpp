@@ -40,9 +40,15 @@ struct WaveArgs {
   int32_t* info = nullptr;
   int gl = 0;
   int chunk = 0;   // preferred chunk length C (0: automatic)
-  int mixed = 0;   // FP32 factor/solve + FP64 refinement (Helmholtz)
+  int mixed = 0;   // FP32 factor/solve + FP64 refinement
   int it_max = 8;  // refinement steps at most
   double tol = 1e-14;
+  // adjoint: f = gbar, u = lambda (must not alias gbar); ufwd = forward
+  // solution and g0/g1 = coefficient gradients (optional)
+  int adjoint = 0;
+  const void* ufwd = nullptr;
+  double* g0 = nullptr;
+  double* g1 = nullptr;
   void* stream = nullptr;
 };
 

@@ -89,6 +89,43 @@ __device__ __forceinline__ float2 to_f2(double2 a) { return make_float2((float)a
 __device__ __forceinline__ double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
 __device__ __forceinline__ double cabs1(double2 a) { return fmax(fabs(a.x), fabs(a.y)); }
 
+// Shifts across the G lanes of a chain: value of lane m - D (lo) or m + D
+// (hi), zero where that lane does not exist.
+template <int G, int D, typename V>
+__device__ __forceinline__ V chain_lo(V v, int m) {
+  if constexpr (G == 16) {
+    return RowShift<D>::from_lower(v);
+  } else {
+    V o;
+    if constexpr (std::is_same_v<V, double2>) {
+      o = shfl_up2(v, D, G);
+    } else if constexpr (std::is_same_v<V, float2>) {
+      o = make_float2(__shfl_up(v.x, (unsigned)D, G), __shfl_up(v.y, (unsigned)D, G));
+    } else {
+      o = __shfl_up(v, (unsigned)D, G);
+    }
+    return (m >= D) ? o : V{};
+  }
+}
+template <int G, int D, typename V>
+__device__ __forceinline__ V chain_hi(V v, int m) {
+  if constexpr (G == 16) {
+    return RowShift<D>::from_upper(v);
+  } else {
+    V o;
+    if constexpr (std::is_same_v<V, double2>) {
+      o = shfl_down2(v, D, G);
+    } else if constexpr (std::is_same_v<V, float2>) {
+      o = make_float2(__shfl_down(v.x, (unsigned)D, G), __shfl_down(v.y, (unsigned)D, G));
+    } else {
+      o = __shfl_down(v, (unsigned)D, G);
+    }
+    return (m + D < G) ? o : V{};
+  }
+}
+
+
+
 // One Helmholtz LU row step (shared by boundary and solve kernels so that the
 // restarted factorisation reproduces the sequential one exactly).
 struct HelmPrev {
@@ -633,6 +670,195 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
     if (wok && (lane % (2 * G)) == 0) info[w] = (b == INT_MAX) ? 0 : b + 1;
   }
   return bad;
+}
+
+// =========================================================================
+// Helmholtz adjoint (wave layout): lambda = H^{-T} gbar and, when asked,
+// grad_alpha = -Re(lambda^H B u).  H^T = U^T L^T: U^T z = gbar runs forward
+// with the state (z of row k-2, sum of g_i z_i over rows <= k-4), an affine
+// 2x2 recurrence scanned like the forward solve's; L^T lambda = z runs
+// backward, scalar.  Restart states come from the same boundary walk as the
+// solve (parked in the lambda row, so lambda must not alias gbar).
+// =========================================================================
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                        const double2* __restrict__ ufwd, const double2* __restrict__ gbar,
+                                                        double2* __restrict__ lam, double* __restrict__ grad, int gl,
+                                                        int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  const int lane = threadIdx.x & 63;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = (int64_t)blockIdx.x * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 2;
+  const int k0 = 2 * m * C + p;
+  const double al = wok ? alpha[w] : 0.0;
+  const double hm = -0.5 * kPi * al;
+  const double2* grow = gbar + (wok ? w : 0) * (int64_t)N;
+  double2* lrow = lam + (wok ? w : 0) * (int64_t)N;
+  HelmPrev pv = {0.0, 0.0};
+  if (wok && m > 0 && k0 < n) {
+    const double2 s2 = *reinterpret_cast<const double2*>(reinterpret_cast<const double*>(lrow) + (p * G + m) * 2);
+    pv.rd = s2.x;
+    pv.g = s2.y;
+  }
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (wok && k < n) ? grow[k] : zero2();
+  }
+  // factorisation restart (as the solve)
+  const bool has_prev = k0 >= 2;
+  const double rd_in = has_prev ? pv.rd : 0.0, g_in = has_prev ? pv.g : 0.0;
+  double rdj[C], gj[C];
+  int bad = INT_MAX;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const bool ok = wok && k < n;
+    double l, g, r, d;
+    helm_step(k, al, N, gl, pv, l, g, r, d);
+    if (ok && bad_pivot(d) && bad == INT_MAX) bad = k;
+    pv.rd = r;
+    pv.g = g;
+    rdj[j] = ok ? r : 0.0;
+    gj[j] = ok ? g : 0.0;
+  }
+  // U^T z = gbar: local pass from a zero state, composing the chunk's map
+  // state (zp, P) -> (z_j, P + g_{j-1} zp);  z_j = rd_j (gbar_j - e_{j-1} zp - P)
+  auto gprev = [&](int j) { return j == 0 ? g_in : gj[j == 0 ? 0 : j - 1]; };
+  auto eprev = [&](int j) {
+    const double g = gprev(j);
+    return (j == 0 && !has_prev) ? 0.0 : g + hm;
+  };
+  double A00 = 1.0, A01 = 0.0, A10 = 0.0, A11 = 1.0;
+  double2 c0 = zero2(), c1 = zero2();
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const double r = rdj[j], e = eprev(j), g = gprev(j);
+    // M = [[-r e, -r], [g, 1]]
+    const double m00 = -r * e, m01 = -r;
+    const double n00 = m00 * A00 + m01 * A10, n01 = m00 * A01 + m01 * A11;
+    const double n10 = g * A00 + A10, n11 = g * A01 + A11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    double2 z = c_mul(r, x[j]);
+    z = c_fma(m00, c0, z);
+    z = c_fma(m01, c1, z);
+    const double2 nP = c_fma(g, c0, c1);
+    c0 = z;
+    c1 = nP;
+  }
+  auto compose = [&](double o00, double o01, double o10, double o11, double2 oc0, double2 oc1) {
+    // (this after other): (A A_o, A c_o + c)
+    const double2 n0 = c_add(c_fma(A00, oc0, c_mul(A01, oc1)), c0);
+    const double2 n1 = c_add(c_fma(A10, oc0, c_mul(A11, oc1)), c1);
+    const double n00 = A00 * o00 + A01 * o10, n01 = A00 * o01 + A01 * o11;
+    const double n10 = A10 * o00 + A11 * o10, n11 = A10 * o01 + A11 * o11;
+    A00 = n00;
+    A01 = n01;
+    A10 = n10;
+    A11 = n11;
+    c0 = n0;
+    c1 = n1;
+  };
+  auto lvl = [&](auto dd) {
+    constexpr int D = decltype(dd)::value;
+    compose(chain_lo<G, D>(A00, m), chain_lo<G, D>(A01, m), chain_lo<G, D>(A10, m), chain_lo<G, D>(A11, m),
+            chain_lo<G, D>(c0, m), chain_lo<G, D>(c1, m));
+  };
+  lvl(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvl(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvl(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvl(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvl(std::integral_constant<int, 16>{});
+  double2 zp = chain_lo<G, 1>(c0, m), P = chain_lo<G, 1>(c1, m);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const double r = rdj[j], e = eprev(j), g = gprev(j);
+    double2 z = c_mul(r, x[j]);
+    z = c_fma(-r * e, zp, z);
+    z = c_fma(-r, P, z);
+    P = c_fma(g, zp, P);
+    zp = z;
+    x[j] = z;
+  }
+  // L^T lambda = z: lambda_j = z_j - l_{j+1} lambda_{j+1}, l_{j+1} = hm rd_j on rows < n
+  auto lnext = [&](int j) {
+    const bool ok = wok && k0 + 2 * (j + 1) < n;
+    return ok ? hm * rdj[j] : 0.0;
+  };
+  double T = 1.0;
+  double2 lp = zero2();
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const double l = lnext(j);
+    const double2 v = c_fnms(l, lp, x[j]);
+    x[j] = v;
+    lp = v;
+    T *= -l;
+  }
+  double sT = T;
+  double2 sb = lp;
+  auto lvlb = [&](auto dd) {
+    constexpr int D = decltype(dd)::value;
+    const double oT = chain_hi<G, D>(sT, m);
+    const double2 ob = chain_hi<G, D>(sb, m);
+    sb = c_fma(sT, ob, sb);
+    sT = sT * oT;
+  };
+  lvlb(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvlb(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvlb(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvlb(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvlb(std::integral_constant<int, 16>{});
+  double2 h = chain_hi<G, 1>(sb, m);
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    h = c_mul(-lnext(j), h);
+    x[j] = c_add(x[j], h);
+  }
+  if (grad != nullptr) {
+    // -Re(lambda^H B u), (B u)_k = bd0 u_k - pi/2 (u_{k-2} + u_{k+2})
+    const double2* urow = ufwd + (wok ? w : 0) * (int64_t)N;
+    double2 uu[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      uu[j] = (wok && k < n) ? urow[k] : zero2();
+    }
+    const double2 up = chain_lo<G, 1>(uu[C - 1], m), un = chain_hi<G, 1>(uu[0], m);
+    double gs = 0.0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      const double2 um = (j == 0) ? up : uu[j == 0 ? 0 : j - 1];
+      const double2 upn = (j == C - 1) ? un : uu[j == C - 1 ? 0 : j + 1];
+      double2 bu = c_mul(helm_mass_diag(k, N, gl), uu[j]);
+      bu = c_fnms(0.5 * kPi, c_add(um, upn), bu);
+      const bool ok = wok && k < n;
+      if (ok) gs -= x[j].x * bu.x + x[j].y * bu.y;
+    }
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) gs += __shfl_xor(gs, d, 2 * G);
+    if (wok && (lane % (2 * G)) == 0) grad[w] = gs;
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) lrow[k] = (k < n) ? x[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    int b = bad;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) b = min(b, __shfl_xor(b, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = (b == INT_MAX) ? 0 : b + 1;
+  }
 }
 
 // =========================================================================
@@ -1339,41 +1565,6 @@ __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const
 // =========================================================================
 // Biharmonic, FP32 factor/solve + FP64 iterative refinement (wave layout)
 // =========================================================================
-// Shifts across the G lanes of a chain: value of lane m - D (lo) or m + D
-// (hi), zero where that lane does not exist.
-template <int G, int D, typename V>
-__device__ __forceinline__ V chain_lo(V v, int m) {
-  if constexpr (G == 16) {
-    return RowShift<D>::from_lower(v);
-  } else {
-    V o;
-    if constexpr (std::is_same_v<V, double2>) {
-      o = shfl_up2(v, D, G);
-    } else if constexpr (std::is_same_v<V, float2>) {
-      o = make_float2(__shfl_up(v.x, (unsigned)D, G), __shfl_up(v.y, (unsigned)D, G));
-    } else {
-      o = __shfl_up(v, (unsigned)D, G);
-    }
-    return (m >= D) ? o : V{};
-  }
-}
-template <int G, int D, typename V>
-__device__ __forceinline__ V chain_hi(V v, int m) {
-  if constexpr (G == 16) {
-    return RowShift<D>::from_upper(v);
-  } else {
-    V o;
-    if constexpr (std::is_same_v<V, double2>) {
-      o = shfl_down2(v, D, G);
-    } else if constexpr (std::is_same_v<V, float2>) {
-      o = make_float2(__shfl_down(v.x, (unsigned)D, G), __shfl_down(v.y, (unsigned)D, G));
-    } else {
-      o = __shfl_down(v, (unsigned)D, G);
-    }
-    return (m + D < G) ? o : V{};
-  }
-}
-
 // Factors of the FP32 solve, per chunk element (0 on padding rows).
 template <int C>
 struct BihFac32 {
@@ -2099,6 +2290,12 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const int64_t groups = (ns + SPW - 1) / SPW;
+    if (a.adjoint) {
+      hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
+      hipLaunchKernelGGL((helm_adjoint_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0,
+                         a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr, a.gl, info);
+      continue;
+    }
     if (a.mixed) {
       hipLaunchKernelGGL(helm_boundary32, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
       hipLaunchKernelGGL((helm_mixed_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info, a.it_max,

@@ -118,8 +118,9 @@ def test_autotuner_cache(dev, tmp_path):
 # -------------------------------------------------------- differentiation
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-@pytest.mark.parametrize("N", [33, 128, 512])
-def test_adjoint_vs_oracle(dev, family, N):
+@pytest.mark.parametrize("N", [33, 128, 257, 512, 1024])
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+def test_adjoint_vs_oracle(dev, family, N, variant):
     from paper_1701_03787_amd import api
     g = wl.small_grid(N, 21, index=N)
     cs = g.coefficients(family)
@@ -127,14 +128,14 @@ def test_adjoint_vs_oracle(dev, family, N):
     gu = wl.random_vector((g.nsys, N), (N, 1))
     n = wl.n_unknowns(family, N)
     gu[:, n:] = 0
-    case(test="adjoint", family=family, N=N)
+    case(test="adjoint", family=family, N=N, variant=variant)
     u_ref, lam_ref, grads_ref = so.solve_grads(family, N, cs, f, gu)
     ut = T(u_ref, dev)
     if family == "helmholtz":
-        lam, ga = api.helmholtz_adjoint(ut, T(gu, dev), T(cs[0], dev))
+        lam, ga = api.helmholtz_adjoint(ut, T(gu, dev), T(cs[0], dev), variant=variant)
         grads = [ga]
     else:
-        lam, ga, gb = api.biharmonic_adjoint(ut, T(gu, dev), T(cs[0], dev), T(cs[1], dev))
+        lam, ga, gb = api.biharmonic_adjoint(ut, T(gu, dev), T(cs[0], dev), T(cs[1], dev), variant=variant)
         grads = [ga, gb]
     torch.cuda.synchronize()
     assert so.rel_err_per_system(lam.cpu().numpy(), lam_ref).max() <= TOL
