@@ -307,6 +307,26 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* ca, const double* 
   if ((grad_a && !aligned(grad_a, 8)) || (grad_b && !aligned(grad_b, 8))) return SHEN_EINVAL;
   if (rows_overlap_partially(gbar, lambda, nsys, N)) return SHEN_EINVAL;
   if (u && (u == lambda || rows_overlap_partially(u, lambda, nsys, N))) return SHEN_EINVAL;
+  if (o.variant != SHEN_VARIANT_CHAIN && (const void*)gbar != (const void*)lambda && shen::wave_supported(1, N)) {
+    shen::WaveArgs w;
+    w.family = 1;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = ca;
+    w.c1 = cb;
+    w.f = gbar;
+    w.u = lambda;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.chunk = o.chunk;
+    w.adjoint = 1;
+    w.ufwd = grads ? u : nullptr;
+    w.g0 = grad_a;
+    w.g1 = grad_b;
+    w.stream = o.stream;
+    return run_wave(w);
+  }
+  if (o.variant == SHEN_VARIANT_WAVE) return SHEN_ENOTSUP;
   ChainArgs a;
   a.kind = ChainKind::BihAdjoint;
   a.N = N;

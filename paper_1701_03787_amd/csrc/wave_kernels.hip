@@ -1925,6 +1925,288 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
   }
 }
 
+// =========================================================================
+// Biharmonic adjoint (wave layout): lambda = H^{-T} gbar and, when asked,
+// grad_a = -Re(lambda^H A u), grad_b = -Re(lambda^H B u).  U^T z = gbar runs
+// forward with the state (z_{j-1}, z_{j-2}, sum P_i z_i, sum R_i z_i over
+// rows <= k-6), an affine 4x4 recurrence; L^T lambda = z runs backward with
+// the state (lambda_{j+1}, lambda_{j+2}).  Rows from the LDS table, restart
+// states from the table-driven boundary walk (parked in the lambda row).
+// =========================================================================
+template <int C, int G>
+__global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, const double* __restrict__ ca,
+                                                       const double* __restrict__ cb, const double2* __restrict__ ufwd,
+                                                       const double2* __restrict__ gbar, double2* __restrict__ lam,
+                                                       double* __restrict__ grad_a, double* __restrict__ grad_b, int gl,
+                                                       int32_t* __restrict__ info) {
+  constexpr int SPW = 64 / (2 * G);
+  constexpr int RT = 2 * G * C;
+  extern __shared__ double tab[];
+  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + sl;
+  const bool wok = w < nsys;
+  const int n = N - 4;
+  const int k0 = 2 * m * C + p;
+  const double a = wok ? ca[w] : 0.0, b = wok ? cb[w] : 0.0;
+  const double2* grow = gbar + (wok ? w : 0) * (int64_t)N;
+  double2* lrow = lam + (wok ? w : 0) * (int64_t)N;
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  if (wok && m > 0 && k0 < n) {
+    const double2* sv = reinterpret_cast<const double2*>(reinterpret_cast<const double*>(lrow) + (p * G + m) * 10);
+    const double2 s0 = sv[0], s1 = sv[1], s2 = sv[2], s3 = sv[3], s4 = sv[4];
+    m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
+    m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
+  }
+  const BihRowState in2 = m2, in4 = m4;
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (wok && k < n) ? grow[k] : zero2();
+  }
+  // factorisation restart (as the table-driven solve); raw U rows kept
+  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
+  int bad = INT_MAX;
+  {
+    BihConst cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      const bool ok = wok && k < n;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      BihRowState o;
+      double l1, l2, t0;
+      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
+      cm4 = cm2;
+      cm2 = c;
+      m4 = m2;
+      m2 = o;
+      l1j[j] = ok ? l1 : 0.0;
+      l2j[j] = ok ? l2 : 0.0;
+      r0j[j] = ok ? o.rU0 : 0.0;
+      u2j[j] = ok ? o.U2 : 0.0;
+      u4j[j] = ok ? o.U4 : 0.0;
+      pj[j] = ok ? o.P : 0.0;
+      rj[j] = ok ? o.R : 0.0;
+    }
+  }
+  // coefficients of element j's forward step: U2 of row j-1, U4/P/R of row j-2
+  auto U2p = [&](int j) { return j >= 1 ? u2j[j >= 1 ? j - 1 : 0] : in2.U2; };
+  auto U4pp = [&](int j) { return j >= 2 ? u4j[j >= 2 ? j - 2 : 0] : (j == 1 ? in2.U4 : in4.U4); };
+  auto Ppp = [&](int j) { return j >= 2 ? pj[j >= 2 ? j - 2 : 0] : (j == 1 ? in2.P : in4.P); };
+  auto Rpp = [&](int j) { return j >= 2 ? rj[j >= 2 ? j - 2 : 0] : (j == 1 ? in2.R : in4.R); };
+  auto qsj = [&](int j) {  // (q, s) of row k_j: q4, s4 of row k_j - 4
+    const int k = k0 + 2 * j;
+    if (k >= 4) return bih_tab_qs(tab, C, k - 4);
+    const BihConst c = bih_const(k - 4, N, gl);
+    return make_double2(c.q4, c.s4);
+  };
+  // U^T z = gbar, local pass from a zero state with the chunk's 4x4 map
+  double A[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A[r][c] = (r == c) ? 1.0 : 0.0;
+  double2 cv[4] = {zero2(), zero2(), zero2(), zero2()};
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const double r0 = r0j[j];
+    const double2 qs = qsj(j);
+    const double e1 = -r0 * U2p(j), e2 = -r0 * U4pp(j), e3 = -r0 * qs.x, e4 = -r0 * qs.y;
+    const double pp = Ppp(j), rr = Rpp(j);
+    double nA0[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nA0[c] = e1 * A[0][c] + e2 * A[1][c] + e3 * A[2][c] + e4 * A[3][c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double a1 = A[1][c];
+      A[2][c] = __builtin_fma(pp, a1, A[2][c]);
+      A[3][c] = __builtin_fma(rr, a1, A[3][c]);
+      A[1][c] = A[0][c];
+      A[0][c] = nA0[c];
+    }
+    double2 nc0 = c_mul(r0, x[j]);
+    nc0 = c_fma(e1, cv[0], nc0);
+    nc0 = c_fma(e2, cv[1], nc0);
+    nc0 = c_fma(e3, cv[2], nc0);
+    nc0 = c_fma(e4, cv[3], nc0);
+    cv[2] = c_fma(pp, cv[1], cv[2]);
+    cv[3] = c_fma(rr, cv[1], cv[3]);
+    cv[1] = cv[0];
+    cv[0] = nc0;
+  }
+  auto lvlA = [&](auto dd) {  // this chunk after the lower ones
+    constexpr int D = decltype(dd)::value;
+    double oA[4][4];
+    double2 oc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) oA[r][c] = chain_lo<G, D>(A[r][c], m);
+      oc[r] = chain_lo<G, D>(cv[r], m);
+    }
+    double nA[4][4];
+    double2 ncv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double2 acc = cv[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], oc[c], acc);
+      ncv[r] = acc;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t = __builtin_fma(A[r][q], oA[q][c], t);
+        nA[r][c] = t;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cv[r] = ncv[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) A[r][c] = nA[r][c];
+    }
+  };
+  lvlA(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvlA(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvlA(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvlA(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvlA(std::integral_constant<int, 16>{});
+  // incoming state from the lane below, then the exact rerun
+  double2 z1 = chain_lo<G, 1>(cv[0], m), z2 = chain_lo<G, 1>(cv[1], m), SP = chain_lo<G, 1>(cv[2], m),
+          SR = chain_lo<G, 1>(cv[3], m);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const double r0 = r0j[j];
+    const double2 qs = qsj(j);
+    double2 z = c_mul(r0, x[j]);
+    z = c_fma(-r0 * U2p(j), z1, z);
+    z = c_fma(-r0 * U4pp(j), z2, z);
+    z = c_fma(-r0 * qs.x, SP, z);
+    z = c_fma(-r0 * qs.y, SR, z);
+    SP = c_fma(Ppp(j), z2, SP);
+    SR = c_fma(Rpp(j), z2, SR);
+    z2 = z1;
+    z1 = z;
+    x[j] = z;
+  }
+  // L^T lambda = z: lambda_j = z_j - l1_{j+1} lambda_{j+1} - l2_{j+2} lambda_{j+2}
+  const double nl1_0 = chain_hi<G, 1>(l1j[0], m), nl2_0 = chain_hi<G, 1>(l2j[0], m), nl2_1 = chain_hi<G, 1>(l2j[1], m);
+  auto L1n = [&](int j) { return j + 1 < C ? l1j[j + 1 < C ? j + 1 : 0] : nl1_0; };
+  auto L2nn = [&](int j) { return j + 2 < C ? l2j[j + 2 < C ? j + 2 : 0] : (j + 2 == C ? nl2_0 : nl2_1); };
+  double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
+  double2 a1v = zero2(), a2v = zero2();  // lambda_{j+1}, lambda_{j+2}
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    const double l1 = L1n(j), l2 = L2nn(j);
+    double2 v = c_fnms(l1, a1v, x[j]);
+    v = c_fnms(l2, a2v, v);
+    x[j] = v;
+    a2v = a1v;
+    a1v = v;
+    const double n00 = -l1 * T00 - l2 * T10, n01 = -l1 * T01 - l2 * T11;
+    T10 = T00;
+    T11 = T01;
+    T00 = n00;
+    T01 = n01;
+  }
+  double2 b0 = a1v, b1 = a2v;
+  auto lvlT = [&](auto dd) {  // this chunk after the upper ones
+    constexpr int D = decltype(dd)::value;
+    const double o00 = chain_hi<G, D>(T00, m), o01 = chain_hi<G, D>(T01, m), o10 = chain_hi<G, D>(T10, m),
+                 o11 = chain_hi<G, D>(T11, m);
+    const double2 ob0 = chain_hi<G, D>(b0, m), ob1 = chain_hi<G, D>(b1, m);
+    const double2 n0 = c_add(c_fma(T00, ob0, c_mul(T01, ob1)), b0);
+    const double2 n1 = c_add(c_fma(T10, ob0, c_mul(T11, ob1)), b1);
+    const double n00 = T00 * o00 + T01 * o10, n01 = T00 * o01 + T01 * o11;
+    const double n10 = T10 * o00 + T11 * o10, n11 = T10 * o01 + T11 * o11;
+    T00 = n00;
+    T01 = n01;
+    T10 = n10;
+    T11 = n11;
+    b0 = n0;
+    b1 = n1;
+  };
+  lvlT(std::integral_constant<int, 1>{});
+  if constexpr (G > 2) lvlT(std::integral_constant<int, 2>{});
+  if constexpr (G > 4) lvlT(std::integral_constant<int, 4>{});
+  if constexpr (G > 8) lvlT(std::integral_constant<int, 8>{});
+  if constexpr (G > 16) lvlT(std::integral_constant<int, 16>{});
+  double2 h1 = chain_hi<G, 1>(b0, m), h2 = chain_hi<G, 1>(b1, m);  // (lambda_C, lambda_{C+1})
+#pragma unroll
+  for (int j = C - 1; j >= 0; --j) {
+    double2 hj = c_mul(-L1n(j), h1);
+    hj = c_fma(-L2nn(j), h2, hj);
+    x[j] = c_add(x[j], hj);
+    h2 = h1;
+    h1 = hj;
+  }
+  if (grad_a != nullptr || grad_b != nullptr) {
+    const double2* urow = ufwd + (wok ? w : 0) * (int64_t)N;
+    double2 uu[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      uu[j] = (wok && k < n) ? urow[k] : zero2();
+    }
+    const double2 pl1 = chain_lo<G, 1>(uu[C - 1], m), pl2 = chain_lo<G, 1>(uu[C - 2], m);
+    const double2 nx1 = chain_hi<G, 1>(uu[0], m), nx2 = chain_hi<G, 1>(uu[1], m);
+    double ga = 0.0, gb = 0.0;
+    BihConst cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      const double2 um4 = (j >= 2) ? uu[j >= 2 ? j - 2 : 0] : (j == 1 ? pl1 : pl2);
+      const double2 um2 = (j >= 1) ? uu[j >= 1 ? j - 1 : 0] : pl1;
+      const double2 up2 = (j <= C - 2) ? uu[j <= C - 2 ? j + 1 : 0] : nx1;
+      const double2 up4 = (j <= C - 3) ? uu[j <= C - 3 ? j + 2 : 0] : (j == C - 2 ? nx1 : nx2);
+      double2 au = c_mul(c.A0, uu[j]);
+      au = c_fma(k >= 2 ? c.Am2 : 0.0, um2, au);
+      au = c_fma(c.A2, up2, au);
+      double2 bu = c_mul(c.B0, uu[j]);
+      bu = c_fma(k >= 4 ? cm4.B4 : 0.0, um4, bu);
+      bu = c_fma(k >= 2 ? cm2.B2 : 0.0, um2, bu);
+      bu = c_fma(c.B2, up2, bu);
+      bu = c_fma(c.B4, up4, bu);
+      const bool ok = wok && k < n;
+      if (ok) {
+        ga -= x[j].x * au.x + x[j].y * au.y;
+        gb -= x[j].x * bu.x + x[j].y * bu.y;
+      }
+      cm4 = cm2;
+      cm2 = c;
+    }
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) {
+      ga += __shfl_xor(ga, d, 2 * G);
+      gb += __shfl_xor(gb, d, 2 * G);
+    }
+    if (wok && (lane % (2 * G)) == 0) {
+      if (grad_a) grad_a[w] = ga;
+      if (grad_b) grad_b[w] = gb;
+    }
+  }
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) lrow[k] = (k < n) ? x[j] : zero2();
+    }
+  }
+  if (info != nullptr) {
+    int bq = bad;
+#pragma unroll
+    for (int d = 1; d < 2 * G; d <<= 1) bq = min(bq, __shfl_xor(bq, d, 2 * G));
+    if (wok && (lane % (2 * G)) == 0) info[w] = (bq == INT_MAX) ? 0 : bq + 1;
+  }
+}
+
 template <int C, int G>
 __global__ __launch_bounds__(256) void bih_wave_tab(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
@@ -2325,6 +2607,17 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    if (a.adjoint) {
+      static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
+                                set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+      (void)attra;
+      hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+                         a.gl);
+      hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
+                         c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
+                         a.g1 ? a.g1 + s0 : nullptr, a.gl, info);
+      continue;
+    }
     if (a.mixed) {
       const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double);
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
