@@ -480,7 +480,10 @@ template <int C, int G>
 __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
                                                const double2* __restrict__ f, double2* __restrict__ u, int gl,
                                                int32_t* __restrict__ info) {
-  const int lane = threadIdx.x & 63;
+  // opaque lane index: when this body sits in a loop (batched kernels), the
+  // per-row constants derived from it are not hoisted out and held across it
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
@@ -1203,7 +1206,8 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
                                               const double* __restrict__ cb, const double2* __restrict__ f,
                                               double2* __restrict__ u, int gl, int32_t* __restrict__ info,
                                               const double* tab = nullptr) {
-  const int lane = threadIdx.x & 63;
+  int lane = threadIdx.x & 63;  // opaque, as in helm_wave_body
+  asm volatile("" : "+v"(lane));
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
@@ -2676,15 +2680,14 @@ hipError_t launch_wave(const WaveArgs& a) {
 
 // =========================================================================
 // Batched form: many grids of uneven N and both families, one descriptor
-// table, four persistent kernels enqueued back to back (one graph launch):
+// table, persistent kernels enqueued back to back (one graph launch):
 //
 //  1. batched_boundary<family>: work item = a tile of consecutive systems of
 //     one descriptor; its lanes walk the LU recurrences of the tile's chains
 //     and park the restart states (small kernels, so many wavefronts per SIMD
 //     hide the latency of the sequential walk);
-//  2. batched_wave<family>: the wave solves of the tiles of that family, each
-//     kernel compiled for its own family only (its register budget is that
-//     family's).
+//  2. batched_wave_cfg<C, G, family>: the wave solves of the tiles of one
+//     configuration, one kernel per configuration (its own register budget).
 //
 // Every kernel pulls items from its own atomic counter until the queue is
 // empty; every wavefront reaches that exit.
@@ -2717,7 +2720,7 @@ __device__ __forceinline__ void tile_range(const shen_problem& d, int64_t t, int
 }
 
 __global__ void batched_clear(unsigned long long* __restrict__ counter) {
-  if (blockIdx.x == 0 && threadIdx.x < 4) counter[threadIdx.x] = 0ULL;
+  if (blockIdx.x == 0 && threadIdx.x < 32) counter[threadIdx.x] = 0ULL;
 }
 
 // Next item of family FAM (items of the other family are skipped).
@@ -2752,18 +2755,37 @@ __global__ __launch_bounds__(64) void batched_boundary(const shen_problem* __res
   }
 }
 
-// Solves item t and then keeps pulling items of the same family for as long
-// as they use the same (C, G); returns the first one that does not (or one
-// >= tiles_total).  One non-inlined function per configuration, so the call
-// is paid once per configuration change, not per item.
+// Wave solves of one configuration (family FAM, chunk C, G lanes per chain):
+// its work items are the tiles of the descriptors that use this
+// configuration, numbered consecutively in descriptor order; a wavefront maps
+// an item to (descriptor, tile) by one pass over the descriptor table.  Every
+// configuration is a kernel of its own, compiled with that configuration's
+// register budget.
 template <int C, int G, int FAM>
-__device__ __forceinline__ int64_t tiles_loop(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                              unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
+__global__ __launch_bounds__(64) void batched_wave_cfg(const shen_problem* __restrict__ desc, int ndesc,
+                                                       unsigned long long* __restrict__ counter, int gl) {
+  __shared__ long long s_tile;
   constexpr int SPW = 64 / (2 * G);
   for (;;) {
-    const shen_problem d = desc[find_desc(desc, ndesc, t)];
-    int64_t w0, wend;
-    tile_range(d, t, w0, wend);
+    const int64_t t = next_item(counter, &s_tile);
+    int64_t base = 0;
+    int di = -1;
+    for (int i = 0; i < ndesc; ++i) {
+      const shen_problem& e = desc[i];
+      if (e.family != FAM || e.nsys <= 0) continue;
+      const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
+      if (!(c.C == C && c.G == G)) continue;
+      const int64_t nt = (e.nsys + e.sys_per_tile - 1) / e.sys_per_tile;
+      if (t < base + nt) {
+        di = i;
+        break;
+      }
+      base += nt;
+    }
+    if (di < 0) return;  // past the last item of this configuration
+    const shen_problem d = desc[di];
+    const int64_t w0 = (t - base) * (int64_t)d.sys_per_tile;
+    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
     for (int64_t wb = w0; wb < wend; wb += SPW) {
       if constexpr (FAM == SHEN_HELMHOLTZ)
         helm_wave_body<C, G>(d.N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u), gl,
@@ -2772,43 +2794,6 @@ __device__ __forceinline__ int64_t tiles_loop(const shen_problem* __restrict__ d
         bih_wave_body<C, G>(d.N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
                             gl, d.info);
     }
-    t = next_own<FAM>(desc, ndesc, tiles_total, counter, s_tile);
-    if (t >= tiles_total) return t;
-    const shen_problem& e = desc[find_desc(desc, ndesc, t)];
-    const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
-    if (!(c.C == C && c.G == G)) return t;
-  }
-}
-// Each configuration is a function of its own: inlining all of them into one
-// kernel makes the register allocation of their union spill.
-template <int C, int G, int FAM>
-__device__ __noinline__ int64_t run_tiles(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                          unsigned long long* __restrict__ counter, int gl, int64_t t, long long* s_tile) {
-  return tiles_loop<C, G, FAM>(desc, ndesc, tiles_total, counter, gl, t, s_tile);
-}
-
-template <int FAM>
-__global__ __launch_bounds__(64) void batched_wave(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                                   unsigned long long* __restrict__ counter, int gl) {
-  __shared__ long long s_tile;
-  int64_t t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile);
-  while (t < tiles_total) {
-    const shen_problem& d = desc[find_desc(desc, ndesc, t)];
-    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
-    const int64_t t0 = t;
-#define SHEN_TILE(CC, GG) \
-  if (c.C == CC && c.G == GG) t = run_tiles<CC, GG, FAM>(desc, ndesc, tiles_total, counter, gl, t, &s_tile);
-    SHEN_TILE(4, 8)
-    else SHEN_TILE(8, 4)
-    else SHEN_TILE(16, 4)
-    else SHEN_TILE(8, 8)
-    else SHEN_TILE(8, 16)
-    else SHEN_TILE(16, 8)
-    else SHEN_TILE(16, 16)
-    else SHEN_TILE(8, 32)
-    else SHEN_TILE(16, 32)
-#undef SHEN_TILE
-    if (t == t0) t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile);  // not a wave configuration
   }
 }
 
@@ -2821,16 +2806,30 @@ hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void
     const shen_problem* d = (const shen_problem*)desc;
     hipLaunchKernelGGL(batched_boundary<SHEN_HELMHOLTZ>,
                        dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_HELMHOLTZ>, tiles_total)), dim3(64),
-                       0, st, d, ndesc, tiles_total, counter + 3, gl);
+                       0, st, d, ndesc, tiles_total, counter + 1, gl);
     hipLaunchKernelGGL(batched_boundary<SHEN_BIHARMONIC>,
                        dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_BIHARMONIC>, tiles_total)), dim3(64),
                        0, st, d, ndesc, tiles_total, counter, gl);
-    hipLaunchKernelGGL(batched_wave<SHEN_HELMHOLTZ>,
-                       dim3((unsigned)persistent_blocks((const void*)batched_wave<SHEN_HELMHOLTZ>, tiles_total)), dim3(64), 0,
-                       st, d, ndesc, tiles_total, counter + 1, gl);
-    hipLaunchKernelGGL(batched_wave<SHEN_BIHARMONIC>,
-                       dim3((unsigned)persistent_blocks((const void*)batched_wave<SHEN_BIHARMONIC>, tiles_total)), dim3(64), 0,
-                       st, d, ndesc, tiles_total, counter + 2, gl);
+    int slot = 2;
+#define SHEN_CFG(CC, GG)                                                                                                      \
+  hipLaunchKernelGGL((batched_wave_cfg<CC, GG, SHEN_HELMHOLTZ>),                                                             \
+                     dim3((unsigned)persistent_blocks((const void*)batched_wave_cfg<CC, GG, SHEN_HELMHOLTZ>, tiles_total)),   \
+                     dim3(64), 0, st, d, ndesc, counter + slot, gl);                                                         \
+  ++slot;                                                                                                                   \
+  hipLaunchKernelGGL((batched_wave_cfg<CC, GG, SHEN_BIHARMONIC>),                                                            \
+                     dim3((unsigned)persistent_blocks((const void*)batched_wave_cfg<CC, GG, SHEN_BIHARMONIC>, tiles_total)),  \
+                     dim3(64), 0, st, d, ndesc, counter + slot, gl);                                                         \
+  ++slot;
+    SHEN_CFG(4, 8)
+    SHEN_CFG(8, 4)
+    SHEN_CFG(16, 4)
+    SHEN_CFG(8, 8)
+    SHEN_CFG(8, 16)
+    SHEN_CFG(16, 8)
+    SHEN_CFG(16, 16)
+    SHEN_CFG(8, 32)
+    SHEN_CFG(16, 32)
+#undef SHEN_CFG
   }
   return hipGetLastError();
 }
