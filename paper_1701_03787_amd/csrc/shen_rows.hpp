@@ -52,7 +52,7 @@ __device__ __forceinline__ HelmRow helm_row(int k, double alpha, int N, int gl) 
   const double kk = (double)k;
   HelmRow h;
   h.hm = -ha;
-  h.h0 = 2.0 * kPi * ((kk + 1.0) * (kk + 2.0)) + ha * (ck(k, N, gl) + ck(k + 2, N, gl));
+  h.h0 = __builtin_fma(ha, ck(k, N, gl) + ck(k + 2, N, gl), 2.0 * kPi * ((kk + 1.0) * (kk + 2.0)));
   h.hpp = 4.0 * kPi * (kk + 1.0);
   return h;
 }
@@ -186,18 +186,19 @@ __device__ __forceinline__ BihConst bih_const(int k, int N, int gl) {
 // s4) and k-4 (B4).
 __device__ __forceinline__ BihRow bih_row_tab(int k, double a, double b, const BihConst& c, double B2m2, double q4m2,
                                               double s4m2, double B4m4) {
+  // explicit fused multiply-adds: the same rounding wherever a row is built
   BihRow h;
   h.hm4 = (k >= 4) ? b * B4m4 : 0.0;
-  h.hm2 = (k >= 2) ? a * c.Am2 + b * B2m2 : 0.0;
-  h.h0 = c.Q0 + a * c.A0 + b * c.B0;
+  h.hm2 = (k >= 2) ? __builtin_fma(a, c.Am2, b * B2m2) : 0.0;
+  h.h0 = __builtin_fma(b, c.B0, __builtin_fma(a, c.A0, c.Q0));
   h.q2 = q4m2;
   h.s2 = s4m2;
   h.q4 = c.q4;
   h.s4 = c.s4;
-  const double Q2 = c.p * h.q2 + c.r * h.s2;
-  const double Q4 = c.p * h.q4 + c.r * h.s4;
-  h.hp2 = Q2 + a * c.A2 + b * c.B2;
-  h.hp4 = Q4 + b * c.B4;
+  const double Q2 = __builtin_fma(c.p, h.q2, c.r * h.s2);
+  const double Q4 = __builtin_fma(c.p, h.q4, c.r * h.s4);
+  h.hp2 = __builtin_fma(b, c.B2, __builtin_fma(a, c.A2, Q2));
+  h.hp4 = __builtin_fma(b, c.B4, Q4);
   h.p = c.p;
   h.r = c.r;
   return h;

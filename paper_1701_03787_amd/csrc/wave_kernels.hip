@@ -349,6 +349,41 @@ __global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int 
   }
 }
 
+// The same walk with the chunk geometry fixed at compile time: the restart
+// states are kept in registers and written at the end, one lane's states
+// back to back, so that the cache combines them into whole lines.
+template <int C, int G>
+__global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                       double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  const int p = (int)(t & 1);
+  const int n = N - 2;
+  const int nc = (n - p + 1) / 2;
+  const int nchunks = (nc + C - 1) / C;
+  const double al = alpha[w];
+  double2 st[G];
+  HelmPrev pv = {0.0, 0.0};
+#pragma unroll
+  for (int mm = 1; mm < G; ++mm) {
+    if (mm < nchunks) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        double l, g, rd, d;
+        helm_step(2 * ((mm - 1) * C + j) + p, al, N, gl, pv, l, g, rd, d);
+        pv.rd = rd;
+        pv.g = g;
+      }
+      st[mm] = make_double2(pv.rd, pv.g);
+    }
+  }
+  double2* dst = u + w * (int64_t)N + p * G;  // states at (p G + m) of the row, 16 bytes each
+#pragma unroll
+  for (int mm = 1; mm < G; ++mm)
+    if (mm < nchunks) dst[mm] = st[mm];
+}
+
 __global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
                                                      double2* __restrict__ u, int gl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -400,8 +435,8 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
 // from the LDS table (bih_row_tab), exactly as the table-driven wave solves
 // assemble them, so the restart states continue the same factorisation.
 // States of chunk m go to st[(p G + m) 10 + 0..9] (FP64, or FP32 with F32).
-// The four wavefronts of a 256-thread block walk chains of one parity each,
-// so every step reads one table row for the whole wavefront (broadcast).
+// Each wavefront of a block walks chains of one parity, so every step reads
+// one table row for the whole wavefront (broadcast).
 template <bool F32>
 __device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double a, double b, void* st, int gl, const double* tab) {
   const int RT = 2 * G * C;
@@ -409,43 +444,42 @@ __device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double 
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
   if (nchunks <= 1) return;
-  BihConst cm2 = bih_const_at(tab, RT, C, p - 2, N, gl), cm4 = bih_const_at(tab, RT, C, p - 4, N, gl);
+  // only the constants of rows k-2 (B2, q4, s4) and k-4 (B4) are carried
+  const BihConst c2 = bih_const_at(tab, RT, C, p - 2, N, gl), c4 = bih_const_at(tab, RT, C, p - 4, N, gl);
+  double B2m2 = c2.B2, q4m2 = c2.q4, s4m2 = c2.s4, B4m2 = c2.B4, B4m4 = c4.B4;
   const int ilast = (nchunks - 1) * C;
-  if constexpr (F32) {
-    BihRowState32 m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-    for (int i = 0; i < ilast; ++i) {
-      const int k = 2 * i + p;
-      const BihConst c = bih_tab_get(tab, RT, C, k);
-      BihRowState32 o;
+  using State = typename std::conditional<F32, BihRowState32, BihRowState>::type;
+  State m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  for (int i = 0; i < ilast; ++i) {
+    const int k = 2 * i + p;
+    const BihConst c = bih_tab_get(tab, RT, C, k);
+    const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
+    State o;
+    if constexpr (F32) {
       float l1, l2, t0;
-      bih_step_row32(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
-      m4 = m2;
-      m2 = o;
-      cm4 = cm2;
-      cm2 = c;
-      if ((i + 1) % C == 0) {
-        float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + (i + 1) / C) * 10);
+      bih_step_row32(k, h, m2, m4, o, l1, l2, t0);
+    } else {
+      double l1, l2, t0;
+      bih_step_row(k, h, m2, m4, o, l1, l2, t0);
+    }
+    m4 = m2;
+    m2 = o;
+    B4m4 = B4m2;
+    B4m2 = c.B4;
+    B2m2 = c.B2;
+    q4m2 = c.q4;
+    s4m2 = c.s4;
+    if ((i + 1) % C == 0) {
+      const int mm = (i + 1) / C;
+      if constexpr (F32) {
+        float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + mm) * 10);
         sv[0] = make_float2(m2.rU0, m2.U2);
         sv[1] = make_float2(m2.U4, m2.P);
         sv[2] = make_float2(m2.R, m4.rU0);
         sv[3] = make_float2(m4.U2, m4.U4);
         sv[4] = make_float2(m4.P, m4.R);
-      }
-    }
-  } else {
-    BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-    for (int i = 0; i < ilast; ++i) {
-      const int k = 2 * i + p;
-      const BihConst c = bih_tab_get(tab, RT, C, k);
-      BihRowState o;
-      double l1, l2, t0;
-      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
-      m4 = m2;
-      m2 = o;
-      cm4 = cm2;
-      cm2 = c;
-      if ((i + 1) % C == 0) {
-        double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G + (i + 1) / C) * 10);
+      } else {
+        double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G + mm) * 10);
         sv[0] = make_double2(m2.rU0, m2.U2);
         sv[1] = make_double2(m2.U4, m2.P);
         sv[2] = make_double2(m2.R, m4.rU0);
@@ -456,14 +490,16 @@ __device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double 
   }
 }
 
+// 512 threads: eight wavefronts (four pairs of parities, 256 systems) share
+// one table, so that every block of the launch is resident at once.
 template <bool F32>
-__global__ __launch_bounds__(256) void bih_boundary_tab(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
+__global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
                                                         const double* __restrict__ cb, double2* __restrict__ u, int gl) {
   extern __shared__ double tab[];
-  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 256);
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 512);
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 128 + (wv >> 1) * 64 + lane;
+  const int64_t w = (int64_t)blockIdx.x * 256 + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
   bih_walk_tab<F32>(N, C, G, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
 }
@@ -2577,7 +2613,7 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const int64_t groups = (ns + SPW - 1) / SPW;
     if (a.adjoint) {
-      hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
+      hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u, a.gl);
       hipLaunchKernelGGL((helm_adjoint_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0,
                          a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr, a.gl, info);
       continue;
@@ -2588,7 +2624,7 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
                          a.tol);
       continue;
     }
-    hipLaunchKernelGGL(helm_boundary, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
+    hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u, a.gl);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16) {
       const int64_t blocks = persistent_blocks((const void*)helm_wave_pipe<C, G>, groups);
       hipLaunchKernelGGL((helm_wave_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);
@@ -2615,7 +2651,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
       (void)attra;
-      hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+      hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
                          a.gl);
       hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
                          c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
@@ -2627,7 +2663,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
       (void)attrm;
-      hipLaunchKernelGGL(bih_boundary_tab<true>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+      hipLaunchKernelGGL(bih_boundary_tab<true>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
                          a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
                          c1, f, u, a.gl, info, a.it_max, a.tol);
@@ -2637,7 +2673,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                              set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2)) &&
                              set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
     (void)attr;
-    hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 127) / 128)), dim3(256), lds, st, a.N, ns, C, G, c0, c1, u,
+    hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
                        a.gl);
     // gfx950: 160 KiB of LDS per work group
     constexpr size_t kPtabLds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 5) * 64 * sizeof(double2);
