@@ -358,3 +358,37 @@ def test_wave_variant_refuses_transpose(dev):
     a = T(g.coefficients("helmholtz")[0], dev)
     with pytest.raises(_lib.ShenError):
         api.helmholtz_solve(f, a, transpose=True, variant="wave")
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("N", [97, 512])
+def test_gauss_lobatto_mixed_and_adjoint(dev, family, N):
+    """Gauss-Lobatto mass matrices (different last diagonal entry of B) through the
+    FP32 + refinement solve and the adjoint, on the wave kernels, against the oracle."""
+    from paper_1701_03787_amd import api
+    g = wl.small_grid(N, 23, kmax=362, index=N + 1, nu=5e-5, dt=5e-4)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    n = wl.n_unknowns(family, N)
+    gu = wl.random_vector((g.nsys, N), (N, 2))
+    gu[:, n:] = 0
+    case(test="gl_forms", family=family, N=N)
+    u_ref, lam_ref, grads_ref = so.solve_grads(family, N, cs, f, gu, quad=so.GL)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", quad="gl", info=True,
+                 variant="wave")
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(u.cpu().numpy(), u_ref).max() <= TOL
+    assert np.all(info.cpu().numpy() == 0)
+    ut = T(u_ref, dev)
+    if family == "helmholtz":
+        lam, ga = api.helmholtz_adjoint(ut, T(gu, dev), T(cs[0], dev), quad="gl", variant="wave")
+        grads = [ga]
+    else:
+        lam, ga, gb = api.biharmonic_adjoint(ut, T(gu, dev), T(cs[0], dev), T(cs[1], dev), quad="gl",
+                                             variant="wave")
+        grads = [ga, gb]
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(lam.cpu().numpy(), lam_ref).max() <= TOL
+    for gg, gr in zip(grads, grads_ref):
+        np.testing.assert_allclose(gg.cpu().numpy(), gr, rtol=1e-10, atol=1e-300)
