@@ -255,10 +255,21 @@ __device__ __forceinline__ int bih_tab_row(int k, int C) {
   const int mask = (2 * C - 1) < 15 ? (2 * C - 1) : 15;
   return k ^ ((k >> sh) & mask);
 }
+// Rows k >= n = N-4 lie outside the system; they are tabulated as identity
+// rows (unit diagonal, nothing else), and the couplings of the last rows to
+// columns >= n (B2 of rows n-2, n-1 and B4 of rows n-4 .. n-1) are dropped.
+// Those entries only ever reach columns >= n, so the factors of the rows
+// k < n are unchanged, and a factorisation run on past n yields l = 0 and
+// unit pivots there: with a zero right-hand side on those rows the solve
+// leaves them exactly zero without any masking.
 __device__ __forceinline__ void bih_tab_fill(double* tab, int RT, int C, int N, int gl, int tid, int nthreads) {
   double2* t2 = reinterpret_cast<double2*>(tab);
+  const int n = N - 4;
   for (int k = tid; k < RT; k += nthreads) {
-    const BihConst c = bih_const(k, N, gl);
+    BihConst c = bih_const(k, N, gl);
+    if (k >= n) c = BihConst{0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k >= n - 2) c.B2 = 0.0;
+    if (k >= n - 4) c.B4 = 0.0;
     const int r = bih_tab_row(k, C);
     t2[0 * RT + r] = make_double2(c.q4, c.s4);
     t2[1 * RT + r] = make_double2(c.Am2, c.Q0);
@@ -520,6 +531,7 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
   // per-row constants derived from it are not hoisted out and held across it
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
+  lane &= 63;  // opaque, but known to be a lane index
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
@@ -1244,6 +1256,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
                                               const double* tab = nullptr) {
   int lane = threadIdx.x & 63;  // opaque, as in helm_wave_body
   asm volatile("" : "+v"(lane));
+  lane &= 63;  // opaque, but known to be a lane index
   const int sl = lane / (2 * G);
   const int p = (lane / G) & 1;
   const int m = lane % G;
@@ -1327,15 +1340,21 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
     m4 = m2;
     m2 = o;
-    l1 = ok ? l1 : 0.0;
-    l2 = ok ? l2 : 0.0;
+    // Table rows past the system are identity rows (zero l, unit pivot, no
+    // coupling), so only the computed-row path masks them.
+    auto keep = [&](double v) {
+      if constexpr (TAB) return v;
+      return ok ? v : 0.0;
+    };
+    l1 = keep(l1);
+    l2 = keep(l2);
     l1j[j] = l1;
     l2j[j] = l2;
-    r0j[j] = ok ? o.rU0 : 0.0;
-    u2j[j] = ok ? o.rU0 * o.U2 : 0.0;
-    u4j[j] = ok ? o.rU0 * o.U4 : 0.0;
-    pj[j] = ok ? o.rU0 * o.P : 0.0;
-    rj[j] = ok ? o.rU0 * o.R : 0.0;
+    r0j[j] = keep(o.rU0);
+    u2j[j] = keep(o.rU0 * o.U2);
+    u4j[j] = keep(o.rU0 * o.U4);
+    pj[j] = keep(o.rU0 * o.P);
+    rj[j] = keep(o.rU0 * o.R);
     double2 y = c_fnms(l1, y1, x[j]);
     y = c_fnms(l2, y2, y);
     x[j] = y;
@@ -2447,6 +2466,7 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
     // in registers across it.
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
+  lane &= 63;  // opaque, but known to be a lane index
     const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
     const int k0 = 2 * m * C + p;
     const int64_t w = g * SPW + sl;
@@ -2511,6 +2531,7 @@ __global__ __launch_bounds__(256) void bih_wave_ptab(int N, int64_t nsys, const 
     // in registers across it.
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
+    lane &= 63;  // opaque, but known to be a lane index
     const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
     const int k0 = 2 * m * C + p;
     const int64_t w = g * SPW + sl;
