@@ -188,8 +188,10 @@ __device__ __forceinline__ BihRow bih_row_tab(int k, double a, double b, const B
                                               double s4m2, double B4m4) {
   // explicit fused multiply-adds: the same rounding wherever a row is built
   BihRow h;
-  h.hm4 = (k >= 4) ? b * B4m4 : 0.0;
-  h.hm2 = (k >= 2) ? __builtin_fma(a, c.Am2, b * B2m2) : 0.0;
+  // rows 0 .. 3: B4m4 (k < 4), B2m2 and Am2 (k < 2) are +0 (no such rows
+  // or entries), so hm4, hm2 come out zero without masking
+  h.hm4 = b * B4m4;
+  h.hm2 = __builtin_fma(a, c.Am2, b * B2m2);
   h.h0 = __builtin_fma(b, c.B0, __builtin_fma(a, c.A0, c.Q0));
   h.q2 = q4m2;
   h.s2 = s4m2;

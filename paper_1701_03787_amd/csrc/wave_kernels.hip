@@ -168,31 +168,28 @@ __device__ __forceinline__ void helm_step32(int k, double al, int N, int gl, con
 }
 
 // One biharmonic LU row step: row k reduced by rows k-4 (m4) and k-2 (m2).
+// Branch-free: for k < 4 (k < 2) the entry hm4 (hm2) is +0 and the state m4
+// (m2) is the all-zero state, so the reduction by it adds exact zeros and
+// every result is bitwise that of skipping it.
 struct BihRowState {
   double rU0, U2, U4, P, R;
 };
-__device__ __forceinline__ void bih_step_row(int k, const BihRow& h, const BihRowState& m2, const BihRowState& m4,
-                                             BihRowState& o, double& l1, double& l2, double& t0out) {
+__device__ __forceinline__ void bih_step_row(const BihRow& h, const BihRowState& m2, const BihRowState& m4, BihRowState& o,
+                                             double& l1, double& l2, double& t0out) {
   double tm2 = h.hm2, t0 = h.h0, t2 = h.hp2, t4 = h.hp4, P = h.p, Rr = h.r;
-  l1 = 0.0;
-  l2 = 0.0;
-  if (k >= 4) {
-    l2 = h.hm4 * m4.rU0;
-    tm2 = __builtin_fma(-l2, m4.U2, tm2);
-    t0 = __builtin_fma(-l2, m4.U4, t0);
-    t2 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q2, m4.R * h.s2), t2);
-    t4 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q4, m4.R * h.s4), t4);
-    P = __builtin_fma(-l2, m4.P, P);
-    Rr = __builtin_fma(-l2, m4.R, Rr);
-  }
-  if (k >= 2) {
-    l1 = tm2 * m2.rU0;
-    t0 = __builtin_fma(-l1, m2.U2, t0);
-    t2 = __builtin_fma(-l1, m2.U4, t2);
-    t4 = __builtin_fma(-l1, __builtin_fma(m2.P, h.q4, m2.R * h.s4), t4);
-    P = __builtin_fma(-l1, m2.P, P);
-    Rr = __builtin_fma(-l1, m2.R, Rr);
-  }
+  l2 = h.hm4 * m4.rU0;
+  tm2 = __builtin_fma(-l2, m4.U2, tm2);
+  t0 = __builtin_fma(-l2, m4.U4, t0);
+  t2 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q2, m4.R * h.s2), t2);
+  t4 = __builtin_fma(-l2, __builtin_fma(m4.P, h.q4, m4.R * h.s4), t4);
+  P = __builtin_fma(-l2, m4.P, P);
+  Rr = __builtin_fma(-l2, m4.R, Rr);
+  l1 = tm2 * m2.rU0;
+  t0 = __builtin_fma(-l1, m2.U2, t0);
+  t2 = __builtin_fma(-l1, m2.U4, t2);
+  t4 = __builtin_fma(-l1, __builtin_fma(m2.P, h.q4, m2.R * h.s4), t4);
+  P = __builtin_fma(-l1, m2.P, P);
+  Rr = __builtin_fma(-l1, m2.R, Rr);
   o.rU0 = fast_rcp(t0);
   o.U2 = t2;
   o.U4 = t4;
@@ -202,7 +199,7 @@ __device__ __forceinline__ void bih_step_row(int k, const BihRow& h, const BihRo
 }
 __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
                                          const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
-  bih_step_row(k, bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out);
+  bih_step_row(bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out);
 }
 
 // The same step in FP32 (mixed-precision form): row entries formed in FP64
@@ -210,30 +207,25 @@ __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int g
 struct BihRowState32 {
   float rU0, U2, U4, P, R;
 };
-__device__ __forceinline__ void bih_step_row32(int k, const BihRow& hd, const BihRowState32& m2, const BihRowState32& m4,
+__device__ __forceinline__ void bih_step_row32(const BihRow& hd, const BihRowState32& m2, const BihRowState32& m4,
                                                BihRowState32& o, float& l1, float& l2, float& t0out) {
   const float hm4 = (float)hd.hm4, hm2 = (float)hd.hm2, h0 = (float)hd.h0, hp2 = (float)hd.hp2, hp4 = (float)hd.hp4;
   const float q2 = (float)hd.q2, s2 = (float)hd.s2, q4 = (float)hd.q4, s4 = (float)hd.s4;
   float tm2 = hm2, t0 = h0, t2 = hp2, t4 = hp4, P = (float)hd.p, Rr = (float)hd.r;
-  l1 = 0.0f;
-  l2 = 0.0f;
-  if (k >= 4) {
-    l2 = hm4 * m4.rU0;
-    tm2 = __builtin_fmaf(-l2, m4.U2, tm2);
-    t0 = __builtin_fmaf(-l2, m4.U4, t0);
-    t2 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q2, m4.R * s2), t2);
-    t4 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q4, m4.R * s4), t4);
-    P = __builtin_fmaf(-l2, m4.P, P);
-    Rr = __builtin_fmaf(-l2, m4.R, Rr);
-  }
-  if (k >= 2) {
-    l1 = tm2 * m2.rU0;
-    t0 = __builtin_fmaf(-l1, m2.U2, t0);
-    t2 = __builtin_fmaf(-l1, m2.U4, t2);
-    t4 = __builtin_fmaf(-l1, __builtin_fmaf(m2.P, q4, m2.R * s4), t4);
-    P = __builtin_fmaf(-l1, m2.P, P);
-    Rr = __builtin_fmaf(-l1, m2.R, Rr);
-  }
+  // branch-free as bih_step_row
+  l2 = hm4 * m4.rU0;
+  tm2 = __builtin_fmaf(-l2, m4.U2, tm2);
+  t0 = __builtin_fmaf(-l2, m4.U4, t0);
+  t2 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q2, m4.R * s2), t2);
+  t4 = __builtin_fmaf(-l2, __builtin_fmaf(m4.P, q4, m4.R * s4), t4);
+  P = __builtin_fmaf(-l2, m4.P, P);
+  Rr = __builtin_fmaf(-l2, m4.R, Rr);
+  l1 = tm2 * m2.rU0;
+  t0 = __builtin_fmaf(-l1, m2.U2, t0);
+  t2 = __builtin_fmaf(-l1, m2.U4, t2);
+  t4 = __builtin_fmaf(-l1, __builtin_fmaf(m2.P, q4, m2.R * s4), t4);
+  P = __builtin_fmaf(-l1, m2.P, P);
+  Rr = __builtin_fmaf(-l1, m2.R, Rr);
   o.rU0 = rcp32(t0);
   o.U2 = t2;
   o.U4 = t4;
@@ -302,10 +294,31 @@ __device__ __forceinline__ BihConst bih_tab_get(const double* tab, int RT, int C
 __device__ __forceinline__ double2 bih_tab_qs(const double* tab, int C, int k) {
   return reinterpret_cast<const double2*>(tab)[bih_tab_row(k, C)];
 }
-// constants of a row k >= -4: from the table for k >= 0, computed below
+// constants of a row k >= -4: from the table for k >= 0; for k < 0 only
+// q4, s4 (= q_{k+4}, s_{k+4}) exist, everything else is +0, so that the
+// entries below the diagonal of rows 0 .. 3 assemble to +0 unmasked
+// (field-wise selects rather than a branch: a branch between two whole
+// structs is kept in scratch memory)
 __device__ __forceinline__ BihConst bih_const_at(const double* tab, int RT, int C, int k, int N, int gl) {
-  if (k >= 0) return bih_tab_get(tab, RT, C, k);
-  return bih_const(k, N, gl);
+  const bool neg = k < 0;
+  BihConst c = bih_tab_get(tab, RT, C, neg ? 0 : k);
+  const double K = (double)k;
+  const double p7 = fast_rcp(K + 7.0);
+  const double q4n = p7, s4n = (K + 6.0) * (K + 6.0) * p7;  // as bih_const
+  c.Am2 = neg ? 0.0 : c.Am2;
+  c.Q0 = neg ? 0.0 : c.Q0;
+  c.A0 = neg ? 0.0 : c.A0;
+  c.B0 = neg ? 0.0 : c.B0;
+  c.A2 = neg ? 0.0 : c.A2;
+  c.B2 = neg ? 0.0 : c.B2;
+  c.B4 = neg ? 0.0 : c.B4;
+  c.p = neg ? 0.0 : c.p;
+  c.r = neg ? 0.0 : c.r;
+  c.q4 = neg ? q4n : c.q4;
+  c.s4 = neg ? s4n : c.s4;
+  (void)N;
+  (void)gl;
+  return c;
 }
 
 // =========================================================================
@@ -448,9 +461,9 @@ __global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, 
 // States of chunk m go to st[(p G + m) 10 + 0..9] (FP64, or FP32 with F32).
 // Each wavefront of a block walks chains of one parity, so every step reads
 // one table row for the whole wavefront (broadcast).
-template <bool F32>
-__device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double a, double b, void* st, int gl, const double* tab) {
-  const int RT = 2 * G * C;
+template <int C, int G, bool F32>
+__device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, void* st, int gl, const double* tab) {
+  constexpr int RT = 2 * G * C;
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
@@ -458,53 +471,54 @@ __device__ __forceinline__ void bih_walk_tab(int N, int C, int G, int p, double 
   // only the constants of rows k-2 (B2, q4, s4) and k-4 (B4) are carried
   const BihConst c2 = bih_const_at(tab, RT, C, p - 2, N, gl), c4 = bih_const_at(tab, RT, C, p - 4, N, gl);
   double B2m2 = c2.B2, q4m2 = c2.q4, s4m2 = c2.s4, B4m2 = c2.B4, B4m4 = c4.B4;
-  const int ilast = (nchunks - 1) * C;
   using State = typename std::conditional<F32, BihRowState32, BihRowState>::type;
   State m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-  for (int i = 0; i < ilast; ++i) {
-    const int k = 2 * i + p;
-    const BihConst c = bih_tab_get(tab, RT, C, k);
-    const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
-    State o;
-    if constexpr (F32) {
-      float l1, l2, t0;
-      bih_step_row32(k, h, m2, m4, o, l1, l2, t0);
-    } else {
-      double l1, l2, t0;
-      bih_step_row(k, h, m2, m4, o, l1, l2, t0);
-    }
-    m4 = m2;
-    m2 = o;
-    B4m4 = B4m2;
-    B4m2 = c.B4;
-    B2m2 = c.B2;
-    q4m2 = c.q4;
-    s4m2 = c.s4;
-    if ((i + 1) % C == 0) {
-      const int mm = (i + 1) / C;
+  // one chunk of rows per iteration (unrolled, so the carried state is
+  // renamed rather than copied), then the restart state of the next chunk
+  for (int mm = 1; mm < nchunks; ++mm) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = 2 * ((mm - 1) * C + j) + p;
+      const BihConst c = bih_tab_get(tab, RT, C, k);
+      const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
+      State o;
       if constexpr (F32) {
-        float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + mm) * 10);
-        sv[0] = make_float2(m2.rU0, m2.U2);
-        sv[1] = make_float2(m2.U4, m2.P);
-        sv[2] = make_float2(m2.R, m4.rU0);
-        sv[3] = make_float2(m4.U2, m4.U4);
-        sv[4] = make_float2(m4.P, m4.R);
+        float l1, l2, t0;
+        bih_step_row32(h, m2, m4, o, l1, l2, t0);
       } else {
-        double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G + mm) * 10);
-        sv[0] = make_double2(m2.rU0, m2.U2);
-        sv[1] = make_double2(m2.U4, m2.P);
-        sv[2] = make_double2(m2.R, m4.rU0);
-        sv[3] = make_double2(m4.U2, m4.U4);
-        sv[4] = make_double2(m4.P, m4.R);
+        double l1, l2, t0;
+        bih_step_row(h, m2, m4, o, l1, l2, t0);
       }
+      m4 = m2;
+      m2 = o;
+      B4m4 = B4m2;
+      B4m2 = c.B4;
+      B2m2 = c.B2;
+      q4m2 = c.q4;
+      s4m2 = c.s4;
+    }
+    if constexpr (F32) {
+      float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + mm) * 10);
+      sv[0] = make_float2(m2.rU0, m2.U2);
+      sv[1] = make_float2(m2.U4, m2.P);
+      sv[2] = make_float2(m2.R, m4.rU0);
+      sv[3] = make_float2(m4.U2, m4.U4);
+      sv[4] = make_float2(m4.P, m4.R);
+    } else {
+      double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G + mm) * 10);
+      sv[0] = make_double2(m2.rU0, m2.U2);
+      sv[1] = make_double2(m2.U4, m2.P);
+      sv[2] = make_double2(m2.R, m4.rU0);
+      sv[3] = make_double2(m4.U2, m4.U4);
+      sv[4] = make_double2(m4.P, m4.R);
     }
   }
 }
 
 // 512 threads: eight wavefronts (four pairs of parities, 256 systems) share
 // one table, so that every block of the launch is resident at once.
-template <bool F32>
-__global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
+template <int C, int G, bool F32>
+__global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, const double* __restrict__ ca,
                                                         const double* __restrict__ cb, double2* __restrict__ u, int gl) {
   extern __shared__ double tab[];
   bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 512);
@@ -512,7 +526,7 @@ __global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, int
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 256 + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
-  bih_walk_tab<F32>(N, C, G, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
+  bih_walk_tab<C, G, F32>(N, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
 }
 
 // =========================================================================
@@ -1329,7 +1343,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     double l1, l2, t0;
     if constexpr (TAB) {
       const BihConst c = bih_tab_get(tab, RT, C, k);
-      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
       cm4 = cm2;
       cm2 = c;
     } else {
@@ -1469,11 +1483,13 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       h2 = zero2();
     }
   }
+  // ... and scale by the pivot reciprocal here, so that r0j dies with the
+  // forward pass
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     double2 hj = c_mul(-l1j[j], h1);
     hj = c_fma(-l2j[j], h2, hj);
-    x[j] = c_add(x[j], hj);
+    x[j] = c_mul(r0j[j], c_add(x[j], hj));  // yh
     h2 = h1;
     h1 = hj;
   }
@@ -1489,7 +1505,6 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
   for (int j = C - 1; j >= 0; --j) {
     const double2 qs = qs_of(j);
     const double q4 = qs.x, s4 = qs.y;  // q_{k+4}, s_{k+4}
-    x[j] = c_mul(r0j[j], x[j]);  // yh
     double nA0[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -1891,7 +1906,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
       const BihConst c = bih_tab_get(tab, RT, C, k);
       BihRowState32 o;
       float l1, l2, t0;
-      bih_step_row32(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      bih_step_row32(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
       cm4 = cm2;
       cm2 = c;
       m4 = m2;
@@ -1950,7 +1965,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     // sequential walk per chain (lane m = 0) with the table rows, then the
     // FP64 wave solve with the same rows
     double* sts = st64 + sl * 2 * G * 10;
-    if (m == 0 && wok) bih_walk_tab<false>(N, C, G, p, a, b, sts, gl, tab);
+    if (m == 0 && wok) bih_walk_tab<C, G, false>(N, p, a, b, sts, gl, tab);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     BihRowState q2 = {0, 0, 0, 0, 0}, q4 = {0, 0, 0, 0, 0};
@@ -2038,7 +2053,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
       const BihConst c = bih_tab_get(tab, RT, C, k);
       BihRowState o;
       double l1, l2, t0;
-      bih_step_row(k, bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
       if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
       cm4 = cm2;
       cm2 = c;
@@ -2505,13 +2520,16 @@ __global__ __launch_bounds__(256) void bih_wave_ptab(int N, int64_t nsys, const 
   constexpr int RT = 2 * G * C;
   extern __shared__ double smem[];
   double* tab = smem;
-  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + (threadIdx.x >> 6) * ((C + 5) * 64);
+  // wavefront index as a scalar: the tile base (and with it the LDS-DMA
+  // destinations) and the group loop stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 5) * 64);
   bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
   __syncthreads();
   const int n = N - 4;
   const int64_t ngroups = (nsys + SPW - 1) / SPW;
   const int64_t stride = (int64_t)gridDim.x * 4;
-  int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int64_t g = (int64_t)blockIdx.x * 4 + wv;
   if (g >= ngroups) return;
   auto sysc = [&](int64_t gg, int l) {
     const int64_t w = gg * SPW + l / (2 * G);
@@ -2670,9 +2688,9 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
     if (a.adjoint) {
       static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
-                                set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+                                set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds);
       (void)attra;
-      hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
                          a.gl);
       hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
                          c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
@@ -2682,19 +2700,19 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     if (a.mixed) {
       const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double);
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
-                                set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+                                set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
       (void)attrm;
-      hipLaunchKernelGGL(bih_boundary_tab<true>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, true>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
                          a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
                          c1, f, u, a.gl, info, a.it_max, a.tol);
       continue;
     }
     static const bool attr = set_dynamic_lds((const void*)bih_wave_tab<C, G>, lds) &&
-                             set_dynamic_lds((const void*)bih_boundary_tab<false>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2)) &&
-                             set_dynamic_lds((const void*)bih_boundary_tab<true>, kBihTabPairs * 2 * 32 * 16 * sizeof(double2));
+                             set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds) &&
+                             set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
     (void)attr;
-    hipLaunchKernelGGL(bih_boundary_tab<false>, dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, C, G, c0, c1, u,
+    hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
                        a.gl);
     // gfx950: 160 KiB of LDS per work group
     constexpr size_t kPtabLds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 5) * 64 * sizeof(double2);
