@@ -63,10 +63,22 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
+// The same shift with 1.0 where the source lane does not exist: for the
+// diagonal of a map, so that a missing partner composes as the identity
+// (G = 32, where a row's own prefix must stay intact for the step that
+// joins the two rows of a chain).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d_one(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0x3FF00000, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
 template <int D>
 struct RowShift {
   static __device__ __forceinline__ double from_lower(double v) { return dpp_d<0x110 + D>(v); }  // lane i-D
   static __device__ __forceinline__ double from_upper(double v) { return dpp_d<0x100 + D>(v); }  // lane i+D
+  static __device__ __forceinline__ double from_lower_one(double v) { return dpp_d_one<0x110 + D>(v); }
+  static __device__ __forceinline__ double from_upper_one(double v) { return dpp_d_one<0x100 + D>(v); }
   static __device__ __forceinline__ double2 from_lower(double2 v) { return make_double2(from_lower(v.x), from_lower(v.y)); }
   static __device__ __forceinline__ double2 from_upper(double2 v) { return make_double2(from_upper(v.x), from_upper(v.y)); }
   static __device__ __forceinline__ float from_lower(float v) { return dpp_f<0x110 + D>(v); }
@@ -74,6 +86,21 @@ struct RowShift {
   static __device__ __forceinline__ float2 from_lower(float2 v) { return make_float2(from_lower(v.x), from_lower(v.y)); }
   static __device__ __forceinline__ float2 from_upper(float2 v) { return make_float2(from_upper(v.x), from_upper(v.y)); }
 };
+
+// Chains of G = 32 lanes span two DPP rows; the steps that cross from one
+// row to the other read single lanes.  Value of lane L of this lane's chain
+// (lanes 32p .. 32p + 31 hold the chain of parity p).
+template <int L>
+__device__ __forceinline__ double chain_lane32(double v, int p) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo0 = __builtin_amdgcn_readlane(lo, L), hi0 = __builtin_amdgcn_readlane(hi, L);
+  const int lo1 = __builtin_amdgcn_readlane(lo, L + 32), hi1 = __builtin_amdgcn_readlane(hi, L + 32);
+  return __hiloint2double(p ? hi1 : hi0, p ? lo1 : lo0);
+}
+template <int L>
+__device__ __forceinline__ double2 chain_lane32(double2 v, int p) {
+  return make_double2(chain_lane32<L>(v.x, p), chain_lane32<L>(v.y, p));
+}
 
 // FP32 helpers of the mixed-precision form
 __device__ __forceinline__ float rcp32(float d) {  // hardware estimate + one Newton step
@@ -1397,33 +1424,58 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     b1 = n1;
   };
   double2 h1, h2;
-  if constexpr (G == 16) {
-    auto lvl = [&](auto sh) {
-      using S = decltype(sh);
-      composeT(S::from_lower(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower(T11), S::from_lower(b0),
-               S::from_lower(b1));
-    };
-    lvl(RowShift<1>{});
-    lvl(RowShift<2>{});
-    lvl(RowShift<4>{});
-    lvl(RowShift<8>{});
-    h1 = RowShift<1>::from_lower(b0);
-    h2 = RowShift<1>::from_lower(b1);
-  } else {
+  // Prefix scan of the chunk maps across the chain; afterwards (h1, h2) is
+  // the state entering this chunk.  G = 16: one DPP row per chain.  G = 32:
+  // the same within each row, then the upper row completes its prefixes with
+  // the lower row's total (lane 15), which is also the state entering lane 16.
+  auto fscan = [&]() {
+    if constexpr (G == 16 || G == 32) {
+      auto lvl = [&](auto sh) {
+        using S = decltype(sh);
+        if constexpr (G == 32) {
+          composeT(S::from_lower_one(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower_one(T11),
+                   S::from_lower(b0), S::from_lower(b1));
+        } else {
+          composeT(S::from_lower(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower(T11), S::from_lower(b0),
+                   S::from_lower(b1));
+        }
+      };
+      lvl(RowShift<1>{});
+      lvl(RowShift<2>{});
+      lvl(RowShift<4>{});
+      lvl(RowShift<8>{});
+      if constexpr (G == 32) {
+        // (T is now this lane's prefix within its row: missing partners
+        // composed as the identity)
+        const double2 t0 = chain_lane32<15>(b0, p), t1 = chain_lane32<15>(b1, p);
+        const double2 n0 = c_add(c_fma(T00, t0, c_mul(T01, t1)), b0);
+        const double2 n1 = c_add(c_fma(T10, t0, c_mul(T11, t1)), b1);
+        b0 = (m >= 16) ? n0 : b0;
+        b1 = (m >= 16) ? n1 : b1;
+        const double2 s0 = RowShift<1>::from_lower(b0), s1 = RowShift<1>::from_lower(b1);
+        h1 = (m == 16) ? t0 : s0;
+        h2 = (m == 16) ? t1 : s1;
+      } else {
+        h1 = RowShift<1>::from_lower(b0);
+        h2 = RowShift<1>::from_lower(b1);
+      }
+    } else {
 #pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
-      const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
-      const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
-      if (m >= d) composeT(o00, o01, o10, o11, ob0, ob1);
+      for (int d = 1; d < G; d <<= 1) {
+        const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
+        const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
+        const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
+        if (m >= d) composeT(o00, o01, o10, o11, ob0, ob1);
+      }
+      h1 = shfl_up2(b0, 1, G);
+      h2 = shfl_up2(b1, 1, G);
+      if (m == 0) {
+        h1 = zero2();
+        h2 = zero2();
+      }
     }
-    h1 = shfl_up2(b0, 1, G);
-    h2 = shfl_up2(b1, 1, G);
-    if (m == 0) {
-      h1 = zero2();
-      h2 = zero2();
-    }
-  }
+  };
+  fscan();
   // The chunk-local particular solutions started from a zero state can be far
   // larger than y itself (the forward recurrence has modes of modulus close to
   // one), so the scanned incoming states carry their rounding.  One refinement
@@ -1445,6 +1497,11 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     if constexpr (G == 16) {
       nx1 = RowShift<1>::from_upper(sh1);
       nx2 = RowShift<1>::from_upper(sh2);
+    } else if constexpr (G == 32) {
+      const double2 u1 = RowShift<1>::from_upper(sh1), u2 = RowShift<1>::from_upper(sh2);
+      const double2 c1 = chain_lane32<16>(sh1, p), c2 = chain_lane32<16>(sh2, p);
+      nx1 = (m == 15) ? c1 : u1;
+      nx2 = (m == 15) ? c2 : u2;
     } else {
       nx1 = shfl_down2(sh1, 1, G);
       nx2 = shfl_down2(sh2, 1, G);
@@ -1456,35 +1513,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     b0 = c_sub(h1, nx1);
     b1 = c_sub(h2, nx2);
   }
-  if constexpr (G == 16) {
-    auto lvl = [&](auto sh) {
-      using S = decltype(sh);
-      composeT(S::from_lower(T00), S::from_lower(T01), S::from_lower(T10), S::from_lower(T11), S::from_lower(b0),
-               S::from_lower(b1));
-    };
-    lvl(RowShift<1>{});
-    lvl(RowShift<2>{});
-    lvl(RowShift<4>{});
-    lvl(RowShift<8>{});
-    h1 = RowShift<1>::from_lower(b0);
-    h2 = RowShift<1>::from_lower(b1);
-  } else {
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const double o00 = shfl_up_w(T00, d, G), o01 = shfl_up_w(T01, d, G);
-      const double o10 = shfl_up_w(T10, d, G), o11 = shfl_up_w(T11, d, G);
-      const double2 ob0 = shfl_up2(b0, d, G), ob1 = shfl_up2(b1, d, G);
-      if (m >= d) composeT(o00, o01, o10, o11, ob0, ob1);
-    }
-    h1 = shfl_up2(b0, 1, G);
-    h2 = shfl_up2(b1, 1, G);
-    if (m == 0) {
-      h1 = zero2();
-      h2 = zero2();
-    }
-  }
-  // ... and scale by the pivot reciprocal here, so that r0j dies with the
-  // forward pass
+  fscan();
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     double2 hj = c_mul(-l1j[j], h1);
@@ -1552,7 +1581,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     }
   };
   double2 sa, sb, sq, ss;
-  if constexpr (G == 16) {
+  if constexpr (G == 16 || G == 32) {
     auto lvl = [&](auto sh) {
       using S = decltype(sh);
       double oA[4][4];
@@ -1560,7 +1589,13 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) oA[r][c] = S::from_upper(A[r][c]);
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (G == 32) {
+            oA[r][c] = (r == c) ? S::from_upper_one(A[r][c]) : S::from_upper(A[r][c]);
+          } else {
+            oA[r][c] = S::from_upper(A[r][c]);
+          }
+        }
         oc[r] = S::from_upper(cv[r]);
       }
       compose4(oA, oc);
@@ -1569,10 +1604,32 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     lvl(RowShift<2>{});
     lvl(RowShift<4>{});
     lvl(RowShift<8>{});
-    sa = RowShift<1>::from_upper(cv[0]);
-    sb = RowShift<1>::from_upper(cv[1]);
-    sq = RowShift<1>::from_upper(cv[2]);
-    ss = RowShift<1>::from_upper(cv[3]);
+    if constexpr (G == 32) {
+      // the lower row completes its suffixes with the upper row's total
+      // (lane 16, whose own suffix reaches the top of the chain), which is
+      // also the state entering lane 15
+      double2 t[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t[r] = chain_lane32<16>(cv[r], p);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double2 acc = cv[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], t[c], acc);
+        cv[r] = (m < 16) ? acc : cv[r];
+      }
+      const double2 s0 = RowShift<1>::from_upper(cv[0]), s1 = RowShift<1>::from_upper(cv[1]);
+      const double2 s2 = RowShift<1>::from_upper(cv[2]), s3 = RowShift<1>::from_upper(cv[3]);
+      sa = (m == 15) ? t[0] : s0;
+      sb = (m == 15) ? t[1] : s1;
+      sq = (m == 15) ? t[2] : s2;
+      ss = (m == 15) ? t[3] : s3;
+    } else {
+      sa = RowShift<1>::from_upper(cv[0]);
+      sb = RowShift<1>::from_upper(cv[1]);
+      sq = RowShift<1>::from_upper(cv[2]);
+      ss = RowShift<1>::from_upper(cv[3]);
+    }
   } else {
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) {
@@ -2511,8 +2568,17 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
 // over groups of systems on its own, streaming the next group's right-hand
 // sides and restart states into its LDS tile (whole 64-row blocks) once the
 // refinement sweep has read the current group's f from it.
+// Wavefronts per block of the pipelined biharmonic kernel: four for G = 16
+// (two systems per wavefront, about 500 registers each: one wavefront per
+// SIMD); eight for G = 32 (one system per wavefront, at most 256 registers:
+// two per SIMD), all sharing one row table.
+template <int G>
+struct PtabWaves {
+  static constexpr int value = (G == 32) ? 8 : 4;
+};
+
 template <int C, int G>
-__global__ __launch_bounds__(256) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
+__global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
                                                      const double* __restrict__ cb, const double2* __restrict__ f,
                                                      double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
   using TL = Tile<C, G>;
@@ -2524,12 +2590,13 @@ __global__ __launch_bounds__(256) void bih_wave_ptab(int N, int64_t nsys, const 
   // destinations) and the group loop stay in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 5) * 64);
-  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
+  constexpr int WPB = PtabWaves<G>::value;
+  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 64 * WPB);
   __syncthreads();
   const int n = N - 4;
   const int64_t ngroups = (nsys + SPW - 1) / SPW;
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  int64_t g = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t stride = (int64_t)gridDim.x * WPB;
+  int64_t g = (int64_t)blockIdx.x * WPB + wv;
   if (g >= ngroups) return;
   auto sysc = [&](int64_t gg, int l) {
     const int64_t w = gg * SPW + l / (2 * G);
@@ -2715,14 +2782,18 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
                        a.gl);
     // gfx950: 160 KiB of LDS per work group
-    constexpr size_t kPtabLds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 5) * 64 * sizeof(double2);
+    constexpr int kWpb = PtabWaves<G>::value;
+    constexpr size_t kPtabLds =
+        (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)kWpb * (C + 5) * 64 * sizeof(double2);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16 && kPtabLds <= 160 * 1024) {
       const size_t lds2 = kPtabLds;
       static const bool attr2 = set_dynamic_lds((const void*)bih_wave_ptab<C, G>, lds2);
       (void)attr2;
       const int64_t groups = (ns + SPW - 1) / SPW;
-      const int64_t blocks = persistent_blocks((const void*)bih_wave_ptab<C, G>, (groups + 3) / 4, 256, lds2);
-      hipLaunchKernelGGL((bih_wave_ptab<C, G>), dim3((unsigned)blocks), dim3(256), lds2, st, a.N, ns, c0, c1, f, u, a.gl, info);
+      const int64_t blocks =
+          persistent_blocks((const void*)bih_wave_ptab<C, G>, (groups + kWpb - 1) / kWpb, 64 * kWpb, lds2);
+      hipLaunchKernelGGL((bih_wave_ptab<C, G>), dim3((unsigned)blocks), dim3(64 * kWpb), lds2, st, a.N, ns, c0, c1, f, u, a.gl,
+                         info);
     } else {
       hipLaunchKernelGGL((bih_wave_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns, c0,
                          c1, f, u, a.gl, info);
