@@ -167,6 +167,63 @@ def measure_adjoint(dev, args):
     return out
 
 
+def measure_factored(dev, args, grid, data, host, rows):
+    """Factor-once / solve-many form on the bench workload: the restart states are computed
+    once per family (timed on its own), then a step is the two factored solves; the state
+    slots read by each solve are reported beside the algorithmic bytes."""
+    import numpy as np
+    import torch
+    from paper_1701_03787_amd import api
+    N, nsys = grid.N, grid.nsys
+    out = {"workload": grid.name}
+    facs, fac_ms = {}, {}
+    for fam, (f, cs, u) in data.items():
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            facs[fam] = (api.helmholtz_factor(cs[0], N, chunk=args.chunk) if fam == "helmholtz"
+                         else api.biharmonic_factor(cs[0], cs[1], N, chunk=args.chunk))
+            e1.record()
+            torch.cuda.synchronize()
+            fac_ms[fam] = e0.elapsed_time(e1)
+
+    def launch(fam):
+        f, cs, u = data[fam]
+        if fam == "helmholtz":
+            api.helmholtz_solve_factored(f, cs[0], facs[fam], out=u, chunk=args.chunk)
+        else:
+            api.biharmonic_solve_factored(f, cs[0], cs[1], facs[fam], out=u, chunk=args.chunk)
+
+    for _ in range(max(1, args.warmup)):
+        for fam in data:
+            launch(fam)
+    torch.cuda.synchronize()
+    ev = {fam: [] for fam in data}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for fam in data:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            launch(fam)
+            e1.record()
+            ev[fam].append((e0, e1))
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kms = {fam: float(np.mean([a.elapsed_time(b) for a, b in ev[fam]])) for fam in data}
+    out.update({"ms_per_step": round(ms, 4), "value": round(len(data) * nsys * N / (ms * 1e-3), 2),
+                "unit": "system·N/s", "kernel_ms": {k: round(v, 4) for k, v in kms.items()},
+                "factor_ms": {k: round(v, 4) for k, v in fac_ms.items()}})
+    for fam in data:
+        state = facs[fam].numel() * 8
+        out[fam] = {"hbm_gbps_algorithmic": round(alg_bytes(fam, N, nsys) / (kms[fam] * 1e-3) / 1e9, 2),
+                    "state_bytes": int(state),
+                    "hbm_gbps_with_states": round((alg_bytes(fam, N, nsys) + state) / (kms[fam] * 1e-3) / 1e9, 2),
+                    "max_rel_err_sampled": _sampled_err(fam, N, host[fam][1], host[fam][0], data[fam][2], rows)}
+    del facs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,7 +232,7 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched (48 grids) and adjoint measurements")
+    ap.add_argument("--no-forms", action="store_true", help="skip the factored, batched (48 grids) and adjoint measurements")
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--chunk", type=int, default=0, help="wave kernels: preferred chunk length (0 = automatic)")
     ap.add_argument("--probe-copy", action="store_true",
@@ -280,7 +337,8 @@ def main():
 
     forms = None
     if not args.no_forms:
-        forms = {"batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
+        forms = {"factored": measure_factored(dev, args, grid, data, host, rows),
+                 "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
 
     cpu = None
     if not args.no_cpu:

@@ -149,6 +149,34 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* a, const double* b
                        const shen_opts* opts);
 
 /*
+ * Factor-once / solve-many (the time-stepping use: Alg. NS factors every
+ * wavenumber pair's matrix once and reuses the factors at every step, Sec. 3
+ * and Sec. 4).  Here the factor is compact: the LU restart state at each
+ * chunk start of both parity chains, computed by the sequential recurrence
+ * once; every later solve recomputes the factors inside each chunk from
+ * these states and reads only f, u and the states.
+ *
+ * fac: caller-owned DEVICE buffer, 16-byte aligned, of nsys *
+ *   shen_factor_bytes(family, N, opts) bytes, layout [nsys][bytes/16]
+ *   double2, opaque.  It is valid for the coefficients, N, opts->quad and
+ *   opts->chunk of the factor call; the solve must pass the same.
+ * The factor call writes fac and nothing else (opts->info is not touched);
+ * the solve writes u and, when opts->info is non-NULL, the per-system status
+ * as helmholtz_solve does.  u == f (in place) is allowed; fac must not
+ * overlap u.  FP64 only, no transpose, wave kernels only: SHEN_ENOTSUP for
+ * opts->precision != SHEN_FP64, opts->transpose, opts->variant ==
+ * SHEN_VARIANT_CHAIN, or an N without a wave configuration.  Results are
+ * bitwise those of helmholtz_solve / biharmonic_solve with the same opts.
+ */
+int64_t shen_factor_bytes(int32_t family, int32_t N, const shen_opts* opts); /* per system, or < 0 */
+int helmholtz_factor(int32_t N, int64_t nsys, const double* alpha, void* fac, const shen_opts* opts);
+int biharmonic_factor(int32_t N, int64_t nsys, const double* a, const double* b, void* fac, const shen_opts* opts);
+int helmholtz_solve_factored(int32_t N, int64_t nsys, const double* alpha, const void* fac, const shen_c128* f, shen_c128* u,
+                             const shen_opts* opts);
+int biharmonic_solve_factored(int32_t N, int64_t nsys, const double* a, const double* b, const void* fac, const shen_c128* f,
+                              shen_c128* u, const shen_opts* opts);
+
+/*
  * Matrix-vector products Hu (or H^T u) in O(N) per system, FP64: the banded
  * part plus same-parity suffix sums for the rank-structured tail (Sec. 3
  * right-hand sides; also the residual of the refinement).  Hu must not

@@ -111,6 +111,87 @@ def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpos
     return (u, inf) if inf is not None else u
 
 
+def factor_bytes(family, N, *, chunk=0):
+    """Bytes per system of the factor-once state (shen_factor_bytes)."""
+    o = L.default_opts()
+    o.chunk = int(chunk)
+    fam = {"helmholtz": L.SHEN_HELMHOLTZ, "biharmonic": L.SHEN_BIHARMONIC}[family]
+    nb = L.lib().shen_factor_bytes(fam, int(N), C.byref(o))
+    if nb < 0:
+        raise L.ShenError(int(nb), "shen_factor_bytes")
+    return int(nb)
+
+
+def _fac_tensor(family, N, lead, device, chunk):
+    nb = factor_bytes(family, N, chunk=chunk)
+    return torch.empty(tuple(lead) + (nb // 8,), dtype=torch.float64, device=device)
+
+
+def _check_fac(fac, family, N, lead, device, chunk):
+    nb = factor_bytes(family, N, chunk=chunk)
+    if (not isinstance(fac, torch.Tensor) or fac.dtype != torch.float64 or fac.device != device
+            or tuple(fac.shape) != tuple(lead) + (nb // 8,) or not fac.is_contiguous()):
+        raise ValueError(f"fac must be a contiguous float64 tensor of shape {tuple(lead) + (nb // 8,)} on {device}")
+    return fac
+
+
+def helmholtz_factor(alpha, N, *, quad="gc", chunk=0):
+    """Factor-once: the LU restart states of (S + alpha B) for every system."""
+    if not isinstance(alpha, torch.Tensor) or not alpha.is_cuda:
+        raise ValueError("alpha must be a float64 tensor on a HIP device (no CPU path)")
+    lead = alpha.shape
+    alpha = _coef(alpha, lead, alpha.device, "alpha")
+    fac = _fac_tensor("helmholtz", N, lead, alpha.device, chunk)
+    o = _opts(alpha.device, quad=quad, chunk=chunk)
+    L.check(L.lib().helmholtz_factor(int(N), _nsys(lead), alpha.data_ptr(), fac.data_ptr(), C.byref(o)), "helmholtz_factor")
+    return fac
+
+
+def biharmonic_factor(a, b, N, *, quad="gc", chunk=0):
+    """Factor-once: the LU restart states of (Q + a A + b B) for every system."""
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise ValueError("a must be a float64 tensor on a HIP device (no CPU path)")
+    lead = a.shape
+    a = _coef(a, lead, a.device, "a")
+    b = _coef(b, lead, a.device, "b")
+    fac = _fac_tensor("biharmonic", N, lead, a.device, chunk)
+    o = _opts(a.device, quad=quad, chunk=chunk)
+    L.check(L.lib().biharmonic_factor(int(N), _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), C.byref(o)),
+            "biharmonic_factor")
+    return fac
+
+
+def helmholtz_solve_factored(f, alpha, fac, *, out=None, quad="gc", info=None, chunk=0):
+    """u = (S + alpha B)^{-1} f from the states of helmholtz_factor (same alpha, quad, chunk)."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    lead = f.shape[:-1]
+    alpha = _coef(alpha, lead, f.device, "alpha")
+    fac = _check_fac(fac, "helmholtz", N, lead, f.device, chunk)
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    inf = _info_tensor(info, lead, f.device)
+    o = _opts(f.device, quad=quad, info=inf, chunk=chunk)
+    L.check(L.lib().helmholtz_solve_factored(N, _nsys(lead), alpha.data_ptr(), fac.data_ptr(), f.data_ptr(), u.data_ptr(),
+                                             C.byref(o)), "helmholtz_solve_factored")
+    return (u, inf) if inf is not None else u
+
+
+def biharmonic_solve_factored(f, a, b, fac, *, out=None, quad="gc", info=None, chunk=0):
+    """u = (Q + a A + b B)^{-1} f from the states of biharmonic_factor (same a, b, quad, chunk)."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    lead = f.shape[:-1]
+    a = _coef(a, lead, f.device, "a")
+    b = _coef(b, lead, f.device, "b")
+    fac = _check_fac(fac, "biharmonic", N, lead, f.device, chunk)
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    inf = _info_tensor(info, lead, f.device)
+    o = _opts(f.device, quad=quad, info=inf, chunk=chunk)
+    L.check(L.lib().biharmonic_solve_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), f.data_ptr(),
+                                              u.data_ptr(), C.byref(o)), "biharmonic_solve_factored")
+    return (u, inf) if inf is not None else u
+
+
 def helmholtz_matvec(u, alpha, *, out=None, quad="gc", transpose=False):
     u = _rows(u, "u")
     N = u.shape[-1]

@@ -124,6 +124,43 @@ int32_t max_n_for(ChainKind kind, const DevInfo& d) {
   return lo;
 }
 
+// Factor-once mode (mode 1: boundary walk into fac; 2: wave solve from fac).
+int factored(int family, int32_t N, int64_t nsys, const double* c0, const double* c1, void* fac, const shen_c128* f, shen_c128* u,
+             const shen_opts* opts, int mode) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (!fac || !aligned(fac, 16) || check_coef(c0) || (family == SHEN_BIHARMONIC && check_coef(c1))) return SHEN_EINVAL;
+  const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
+  if (mode == 2) {
+    if (check_rows(f) || check_rows(u)) return SHEN_EINVAL;
+    if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
+    // the state slots must not share memory with the solution rows
+    const uintptr_t pa = (uintptr_t)fac, pb = (uintptr_t)u;
+    const uintptr_t la = (uintptr_t)nsys * (uintptr_t)(slot > 0 ? slot : 1) * 16u, lb = (uintptr_t)nsys * (uintptr_t)N * 16u;
+    if (pa < pb + lb && pb < pa + la) return SHEN_EINVAL;
+  }
+  if (o.precision != SHEN_FP64 || o.transpose || o.variant == SHEN_VARIANT_CHAIN) return SHEN_ENOTSUP;
+  if (slot == 0) return SHEN_ENOTSUP;
+  shen::WaveArgs w;
+  w.family = family;
+  w.N = N;
+  w.nsys = nsys;
+  w.c0 = c0;
+  w.c1 = c1;
+  w.f = f;
+  w.u = u;
+  w.info = mode == 2 ? o.info : nullptr;
+  w.gl = o.quad == SHEN_QUAD_GL;
+  w.chunk = o.chunk;
+  w.stream = o.stream;
+  w.fac = fac;
+  w.fac_mode = mode;
+  return run_wave(w);
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,6 +379,30 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* ca, const double* 
   a.gl = o.quad == SHEN_QUAD_GL;
   a.stream = o.stream;
   return run(a);
+}
+
+int64_t shen_factor_bytes(int32_t family, int32_t N, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  if (check_opts(o)) return SHEN_EINVAL;
+  if (family != SHEN_HELMHOLTZ && family != SHEN_BIHARMONIC) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
+  const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
+  return slot > 0 ? slot * 16 : SHEN_ENOTSUP;
+}
+
+int helmholtz_factor(int32_t N, int64_t nsys, const double* alpha, void* fac, const shen_opts* opts) {
+  return factored(SHEN_HELMHOLTZ, N, nsys, alpha, nullptr, fac, nullptr, nullptr, opts, 1);
+}
+int biharmonic_factor(int32_t N, int64_t nsys, const double* a, const double* b, void* fac, const shen_opts* opts) {
+  return factored(SHEN_BIHARMONIC, N, nsys, a, b, fac, nullptr, nullptr, opts, 1);
+}
+int helmholtz_solve_factored(int32_t N, int64_t nsys, const double* alpha, const void* fac, const shen_c128* f, shen_c128* u,
+                             const shen_opts* opts) {
+  return factored(SHEN_HELMHOLTZ, N, nsys, alpha, nullptr, const_cast<void*>(fac), f, u, opts, 2);
+}
+int biharmonic_solve_factored(int32_t N, int64_t nsys, const double* a, const double* b, const void* fac, const shen_c128* f,
+                              shen_c128* u, const shen_opts* opts) {
+  return factored(SHEN_BIHARMONIC, N, nsys, a, b, const_cast<void*>(fac), f, u, opts, 2);
 }
 
 int helmholtz_matvec(int32_t N, int64_t nsys, const double* alpha, const shen_c128* u, shen_c128* Hu, const shen_opts* opts) {

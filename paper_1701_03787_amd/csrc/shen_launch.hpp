@@ -50,6 +50,11 @@ struct WaveArgs {
   double* g0 = nullptr;
   double* g1 = nullptr;
   void* stream = nullptr;
+  // factor-once mode: fac holds the restart states, [nsys][2 G NS] double2
+  // (NS = 1 Helmholtz, 5 biharmonic).  fac_mode 1: only the boundary walk,
+  // into fac; 2: only the wave solve, states from fac (u may alias f).
+  void* fac = nullptr;
+  int fac_mode = 0;
 };
 
 struct WaveCfg {
@@ -59,6 +64,7 @@ __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);
+int64_t wave_state_slot(int family, int N, int chunk);
 
 size_t chain_bytes_per_system(ChainKind kind, int N);
 int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);

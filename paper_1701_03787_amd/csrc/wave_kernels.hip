@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int 
 // back to back, so that the cache combines them into whole lines.
 template <int C, int G>
 __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                       double2* __restrict__ u, int gl) {
+                                                       double2* __restrict__ S, int64_t sstride, int gl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * nsys) return;
   const int64_t w = t >> 1;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
       st[mm] = make_double2(pv.rd, pv.g);
     }
   }
-  double2* dst = u + w * (int64_t)N + p * G;  // states at (p G + m) of the row, 16 bytes each
+  double2* dst = S + w * sstride + p * G;  // states at (p G + m) of the system's slot, 16 bytes each
 #pragma unroll
   for (int mm = 1; mm < G; ++mm)
     if (mm < nchunks) dst[mm] = st[mm];
@@ -546,14 +546,15 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
 // one table, so that every block of the launch is resident at once.
 template <int C, int G, bool F32>
 __global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, const double* __restrict__ ca,
-                                                        const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+                                                        const double* __restrict__ cb, double2* __restrict__ S,
+                                                        int64_t sstride, int gl) {
   extern __shared__ double tab[];
   bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 512);
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 256 + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
-  bih_walk_tab<C, G, F32>(N, wv & 1, ca[w], cb[w], u + w * (int64_t)N, gl, tab);
+  bih_walk_tab<C, G, F32>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
 }
 
 // =========================================================================
@@ -566,7 +567,8 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
 
 template <int C, int G>
 __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
-                                               const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                               const double2* __restrict__ f, double2* __restrict__ u,
+                                               const double2* __restrict__ sts, int64_t sstride, int gl,
                                                int32_t* __restrict__ info) {
   // opaque lane index: when this body sits in a loop (batched kernels), the
   // per-row constants derived from it are not hoisted out and held across it
@@ -587,7 +589,7 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
   // restart state of the LU at the chunk start
   HelmPrev pv = {0.0, 0.0};
   if (wok && m > 0 && k0 < n) {
-    const double2 s = *reinterpret_cast<const double2*>(reinterpret_cast<const double*>(urow) + (p * G + m) * 2);
+    const double2 s = sts[w * sstride + p * G + m];
     pv.rd = s.x;
     pv.g = s.y;
   }
@@ -1293,8 +1295,8 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
 template <int C, int G, bool TAB = false>
 __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ ca,
                                               const double* __restrict__ cb, const double2* __restrict__ f,
-                                              double2* __restrict__ u, int gl, int32_t* __restrict__ info,
-                                              const double* tab = nullptr) {
+                                              double2* __restrict__ u, const double2* __restrict__ sts, int64_t sstride,
+                                              int gl, int32_t* __restrict__ info, const double* tab = nullptr) {
   int lane = threadIdx.x & 63;  // opaque, as in helm_wave_body
   asm volatile("" : "+v"(lane));
   lane &= 63;  // opaque, but known to be a lane index
@@ -1311,7 +1313,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
 
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   if (wok && m > 0 && k0 < n) {
-    const double2* s = reinterpret_cast<const double2*>(reinterpret_cast<const double*>(urow) + (p * G + m) * 10);
+    const double2* s = sts + w * sstride + (p * G + m) * 5;
     const double2 s0 = s[0], s1 = s[1], s2 = s[2], s3 = s[3], s4 = s[4];
     m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
     m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
@@ -1687,10 +1689,11 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
 
 template <int C, int G>
 __global__ __launch_bounds__(64) void helm_wave_solve(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                      const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                      const double2* __restrict__ f, double2* __restrict__ u,
+                                                      const double2* __restrict__ sts, int64_t sstride, int gl,
                                                       int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
-  helm_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, alpha, f, u, gl, info);
+  helm_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, alpha, f, u, sts, sstride, gl, info);
 }
 
 // =========================================================================
@@ -2340,22 +2343,24 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
 
 template <int C, int G>
 __global__ __launch_bounds__(256) void bih_wave_tab(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
-                                                    const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                    const double2* __restrict__ f, double2* __restrict__ u,
+                                                    const double2* __restrict__ sts, int64_t sstride, int gl,
                                                     int32_t* __restrict__ info) {
   extern __shared__ double tab[];
   constexpr int SPW = 64 / (2 * G);
   bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 256);
   __syncthreads();
   const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW;
-  bih_wave_body<C, G, true>(N, nsys, wbase, ca, cb, f, u, gl, info, tab);
+  bih_wave_body<C, G, true>(N, nsys, wbase, ca, cb, f, u, sts, sstride, gl, info, tab);
 }
 
 template <int C, int G>
 __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
-                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                     const double2* __restrict__ f, double2* __restrict__ u,
+                                                     const double2* __restrict__ sts, int64_t sstride, int gl,
                                                      int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
-  bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, gl, info);
+  bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, sts, sstride, gl, info);
 }
 
 // -------------------------------------------------------------------------
@@ -2399,10 +2404,11 @@ struct Tile {
 
 // Streams group g into tile T: C instructions of 64 consecutive rows each
 // (rows >= N and systems >= nsys clamped to valid addresses; the reader masks
-// them), then NS 16-byte restart words per lane from the solution rows.
+// them), then NS 16-byte restart words per lane from the state slots
+// (system w's slot at sts + w sstride).
 template <int C, int G, int NS>
 __device__ __forceinline__ void prefetch_tile(double2* T, int lane, int64_t g, int N, int64_t nsys, const double2* __restrict__ f,
-                                              const double2* __restrict__ u) {
+                                              const double2* __restrict__ sts, int64_t sstride) {
   using TL = Tile<C, G>;
 #pragma unroll
   for (int i = 0; i < C; ++i) {
@@ -2416,7 +2422,7 @@ __device__ __forceinline__ void prefetch_tile(double2* T, int lane, int64_t g, i
   const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
   const int64_t w = g * TL::SPW + sl;
   const int64_t wc = w < nsys ? w : nsys - 1;
-  const double2* st = u + wc * (int64_t)N + (p * G + m) * NS;
+  const double2* st = sts + wc * sstride + (p * G + m) * NS;
 #pragma unroll
   for (int t = 0; t < NS; ++t)
     __builtin_amdgcn_global_load_lds((const void*)(st + t), SHEN_LDS(T + 64 * (C + t)), 16, 0, 0);
@@ -2510,7 +2516,8 @@ __device__ __forceinline__ void store_tile(const double2* T, int lane, int64_t g
 
 template <int C, int G>
 __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                     const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                     const double2* __restrict__ f, double2* __restrict__ u,
+                                                     const double2* __restrict__ sts, int64_t sstride, int gl,
                                                      int32_t* __restrict__ info) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
@@ -2527,7 +2534,7 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
   double al;
   {
     const int lane = threadIdx.x & 63;
-    prefetch_tile<C, G, 1>(tile, lane, g0, N, nsys, f, u);
+    prefetch_tile<C, G, 1>(tile, lane, g0, N, nsys, f, sts, sstride);
     al = coef(g0, lane);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     read_tile<C, G, 1>(tile, lane, x, st);
@@ -2555,7 +2562,7 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
     store_tile<C, G>(tile, lane, g, N, n, nsys, u);
     const int64_t gn = g + gridDim.x;
     if (gn < ngroups) {
-      prefetch_tile<C, G, 1>(tile, lane, gn, N, nsys, f, u);
+      prefetch_tile<C, G, 1>(tile, lane, gn, N, nsys, f, sts, sstride);
       al = coef(gn, lane);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       read_tile<C, G, 1>(tile, lane, x, st);
@@ -2580,7 +2587,8 @@ struct PtabWaves {
 template <int C, int G>
 __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
                                                      const double* __restrict__ cb, const double2* __restrict__ f,
-                                                     double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+                                                     double2* __restrict__ u, const double2* __restrict__ sts,
+                                                     int64_t sstride, int gl, int32_t* __restrict__ info) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
   constexpr int RT = 2 * G * C;
@@ -2605,7 +2613,7 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
   double ca_, cb_, ca_n = 0.0, cb_n = 0.0;
   {
     const int lane = threadIdx.x & 63;
-    prefetch_tile<C, G, 5>(tile, lane, g, N, nsys, f, u);
+    prefetch_tile<C, G, 5>(tile, lane, g, N, nsys, f, sts, sstride);
     ca_ = ca[sysc(g, lane)];
     cb_ = cb[sysc(g, lane)];
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -2640,7 +2648,7 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     const int64_t gn = g + stride;
     auto prefetch_next = [&]() {
       if (gn < ngroups) {
-        prefetch_tile<C, G, 5>(tile, lane, gn, N, nsys, f, u);
+        prefetch_tile<C, G, 5>(tile, lane, gn, N, nsys, f, sts, sstride);
         ca_n = ca[sysc(gn, lane)];
         cb_n = cb[sysc(gn, lane)];
       }
@@ -2719,7 +2727,8 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const int64_t groups = (ns + SPW - 1) / SPW;
     if (a.adjoint) {
-      hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u, a.gl);
+      hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u,
+                         (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((helm_adjoint_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0,
                          a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr, a.gl, info);
       continue;
@@ -2730,12 +2739,21 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
                          a.tol);
       continue;
     }
-    hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u, a.gl);
+    // restart states: parked in u (one call), or in the caller's slots (factor-once mode)
+    constexpr int64_t kSlot = 2 * G;  // double2 per system
+    double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlot : u;
+    const int64_t sstride = a.fac_mode ? kSlot : (int64_t)a.N;
+    if (a.fac_mode != 2)
+      hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, sts,
+                         sstride, a.gl);
+    if (a.fac_mode == 1) continue;
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16) {
       const int64_t blocks = persistent_blocks((const void*)helm_wave_pipe<C, G>, groups);
-      hipLaunchKernelGGL((helm_wave_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);
+      hipLaunchKernelGGL((helm_wave_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, ns, c0, f, u, sts, sstride, a.gl,
+                         info);
     } else {
-      hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info);
+      hipLaunchKernelGGL((helm_wave_solve<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, sts, sstride, a.gl,
+                         info);
     }
   }
   return hipGetLastError();
@@ -2758,7 +2776,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds);
       (void)attra;
       hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
-                         a.gl);
+                         (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
                          c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
                          a.g1 ? a.g1 + s0 : nullptr, a.gl, info);
@@ -2770,7 +2788,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
       (void)attrm;
       hipLaunchKernelGGL((bih_boundary_tab<C, G, true>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
-                         a.gl);
+                         (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
                          c1, f, u, a.gl, info, a.it_max, a.tol);
       continue;
@@ -2779,8 +2797,14 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                              set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds) &&
                              set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
     (void)attr;
-    hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
-                       a.gl);
+    // restart states: parked in u (one call), or in the caller's slots (factor-once mode)
+    constexpr int64_t kSlot = 2 * G * 5;  // double2 per system
+    double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlot : u;
+    const int64_t sstride = a.fac_mode ? kSlot : (int64_t)a.N;
+    if (a.fac_mode != 2)
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1,
+                         sts, sstride, a.gl);
+    if (a.fac_mode == 1) continue;
     // gfx950: 160 KiB of LDS per work group
     constexpr int kWpb = PtabWaves<G>::value;
     constexpr size_t kPtabLds =
@@ -2792,14 +2816,21 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       const int64_t groups = (ns + SPW - 1) / SPW;
       const int64_t blocks =
           persistent_blocks((const void*)bih_wave_ptab<C, G>, (groups + kWpb - 1) / kWpb, 64 * kWpb, lds2);
-      hipLaunchKernelGGL((bih_wave_ptab<C, G>), dim3((unsigned)blocks), dim3(64 * kWpb), lds2, st, a.N, ns, c0, c1, f, u, a.gl,
-                         info);
+      hipLaunchKernelGGL((bih_wave_ptab<C, G>), dim3((unsigned)blocks), dim3(64 * kWpb), lds2, st, a.N, ns, c0, c1, f, u, sts,
+                         sstride, a.gl, info);
     } else {
       hipLaunchKernelGGL((bih_wave_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns, c0,
-                         c1, f, u, a.gl, info);
+                         c1, f, u, sts, sstride, a.gl, info);
     }
   }
   return hipGetLastError();
+}
+
+// double2 per system of the factor-once state slots (0: no wave kernel for N)
+int64_t wave_state_slot(int family, int N, int chunk) {
+  const WaveCfg c = pick_cfg((N + 1) / 2, family, N, chunk);
+  if (c.C == 0) return 0;
+  return (int64_t)2 * c.G * (family == 0 ? 1 : 5);
 }
 
 hipError_t launch_wave(const WaveArgs& a) {
@@ -2934,11 +2965,11 @@ __global__ __launch_bounds__(64) void batched_wave_cfg(const shen_problem* __res
     const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
     for (int64_t wb = w0; wb < wend; wb += SPW) {
       if constexpr (FAM == SHEN_HELMHOLTZ)
-        helm_wave_body<C, G>(d.N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u), gl,
-                             d.info);
+        helm_wave_body<C, G>(d.N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
+                             reinterpret_cast<const double2*>(d.u), d.N, gl, d.info);
       else
         bih_wave_body<C, G>(d.N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
-                            gl, d.info);
+                            reinterpret_cast<const double2*>(d.u), d.N, gl, d.info);
     }
   }
 }

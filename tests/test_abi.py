@@ -95,3 +95,37 @@ def test_valid_call_without_device_reports_device_error():
 def test_null_opts_uses_defaults():
     lib = L.lib()
     assert lib.helmholtz_solve(2, 4, ALIGNED, ALIGNED, ALIGNED, None) == L.SHEN_EINVAL
+
+
+def test_factor_bytes_host_only():
+    """Per-system size of the factor-once state: 2G restart states of 16 bytes (Helmholtz) or
+    80 bytes (biharmonic), G lanes per parity chain of the wave configuration for N."""
+    lib = L.lib()
+    o = L.default_opts()
+    assert lib.shen_factor_bytes(L.SHEN_HELMHOLTZ, 512, C.byref(o)) == 2 * 16 * 16
+    assert lib.shen_factor_bytes(L.SHEN_BIHARMONIC, 512, C.byref(o)) == 2 * 16 * 80
+    o.chunk = 8
+    assert lib.shen_factor_bytes(L.SHEN_BIHARMONIC, 512, C.byref(o)) == 2 * 32 * 80
+    o = L.default_opts()
+    assert lib.shen_factor_bytes(7, 512, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.shen_factor_bytes(L.SHEN_BIHARMONIC, 4, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.shen_factor_bytes(L.SHEN_HELMHOLTZ, 1 << 16, C.byref(o)) == L.SHEN_ENOTSUP  # beyond the wave kernels
+
+
+def test_factored_argument_errors():
+    lib = L.lib()
+    A = ALIGNED
+    o = L.default_opts()
+    assert lib.helmholtz_factor(16, 4, A, None, C.byref(o)) == L.SHEN_EINVAL            # NULL fac
+    assert lib.helmholtz_factor(16, 4, A, A + 8, C.byref(o)) == L.SHEN_EINVAL           # misaligned fac
+    assert lib.biharmonic_factor(16, 4, A, None, A, C.byref(o)) == L.SHEN_EINVAL        # NULL b
+    assert lib.helmholtz_factor(16, 0, None, None, C.byref(o)) == L.SHEN_OK             # empty batch
+    # fac overlapping u
+    assert lib.helmholtz_solve_factored(16, 4, A, A + 4096, A, A + 4096, C.byref(o)) == L.SHEN_EINVAL
+    # partial overlap of f and u
+    assert lib.biharmonic_solve_factored(16, 4, A, A, A + (1 << 16), A, A + 16, C.byref(o)) == L.SHEN_EINVAL
+    for field, val in (("precision", L.SHEN_FP32_REFINE), ("transpose", 1), ("variant", 1)):
+        o = L.default_opts()
+        setattr(o, field, val)
+        assert lib.helmholtz_factor(16, 4, A, A, C.byref(o)) == L.SHEN_ENOTSUP, field
+        assert lib.biharmonic_solve_factored(16, 4, A, A, A + (1 << 16), A, A, C.byref(o)) == L.SHEN_ENOTSUP, field
