@@ -1674,7 +1674,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         const int k = k0 + 2 * j;
-        if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+        if (k < N) urow[k] = (TAB || k < n) ? x[j] : zero2();  // table rows past n solve to zero
       }
     }
   }
@@ -1849,26 +1849,32 @@ __device__ __forceinline__ void bih_solve32(int lane, const BihFac32<C>& F, cons
 }
 
 // x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows; rows
-// from the table as in the factorisation.
-template <int C, int G>
+// from the table as in the factorisation.  Walking the chunk downwards, each
+// row's constants are read once and carried to the two rows below (which
+// need them as those of rows k-2 and k-4); q_k, s_k are the table's q4, s4 of
+// row k-4.
+template <int C, int G, typename FetchF>
 __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a, double b, int gl, const double* tab,
-                                             const double2 (&f)[C], const double2 (&u)[C], float2 (&x)[C]) {
+                                             FetchF fetch_f, const double2 (&u)[C], float2 (&x)[C]) {
   constexpr int RT = 2 * G * C;
   const int p = (lane / G) & 1, m = lane % G;
   const int n = N - 4;
   const int k0 = 2 * m * C + p;
-  auto qw = [](int k) { return fast_rcp((double)k + 3.0); };  // q_k = 1/(k+3)
-  auto sw = [](int k, double q) {                            // s_k = (k+2)^2/(k+3)
-    const double t = (double)k + 2.0;
-    return t * t * q;
-  };
+  // constants of rows k0 + 2(C-1) and the two below it
+  BihConst c = bih_const_at(tab, RT, C, k0 + 2 * (C - 1), N, gl);
+  BihConst c2 = bih_const_at(tab, RT, C, k0 + 2 * (C - 2), N, gl);
+  BihConst c4 = bih_const_at(tab, RT, C, k0 + 2 * (C - 3), N, gl);
   double2 TQ = zero2(), TS = zero2();
+  {
+    // q_k, s_k of every element: rows k-4 of the table
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const int k = k0 + 2 * j;
-    const double q = qw(k);
-    TQ = c_fma(q, u[j], TQ);
-    TS = c_fma(sw(k, q), u[j], TS);
+    for (int j = 0; j < C; ++j) {
+      const double2 qs = (j >= 2) ? bih_tab_qs(tab, C, k0 + 2 * (j - 2)) : make_double2(0.0, 0.0);
+      const BihConst cn = bih_const_at(tab, RT, C, k0 + 2 * j - 4, N, gl);
+      const double q = (j >= 2) ? qs.x : cn.q4, sv = (j >= 2) ? qs.y : cn.s4;
+      TQ = c_fma(q, u[j], TQ);
+      TS = c_fma(sv, u[j], TS);
+    }
   }
   const double2 pl1 = chain_lo<G, 1>(u[C - 1], m), pl2 = chain_lo<G, 1>(u[C - 2], m);  // rows k0-2, k0-4
   const double2 nx1 = chain_hi<G, 1>(u[0], m), nx2 = chain_hi<G, 1>(u[1], m);          // rows k0+2C, k0+2C+2
@@ -1884,18 +1890,17 @@ __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a
   if constexpr (G > 8) lvl(std::integral_constant<int, 8>{});
   if constexpr (G > 16) lvl(std::integral_constant<int, 16>{});
   const double2 EQ = chain_hi<G, 1>(iq, m), ES = chain_hi<G, 1>(is, m);
-  const int kn1 = k0 + 2 * C, kn2 = kn1 + 2;
-  const double qn1 = qw(kn1), qn2 = qw(kn2);
+  // q, s of rows k0+2C and k0+2C+2: q4, s4 of rows k0+2C-4 and k0+2C-2
+  const double2 qs1 = bih_tab_qs(tab, C, k0 + 2 * C - 4), qs2 = bih_tab_qs(tab, C, k0 + 2 * C - 2);
   // sliding suffix sums from elements j+3, j+2, j+1 (rows >= k+6, k+4, k+2)
-  double2 Q1 = EQ, S1 = ES;                                        // from element C
-  double2 Q2 = c_fnms(qn1, nx1, EQ), S2 = c_fnms(sw(kn1, qn1), nx1, ES);  // from element C+1
-  double2 Q3 = c_fnms(qn2, nx2, Q2), S3 = c_fnms(sw(kn2, qn2), nx2, S2);  // from element C+2
-  // rows k-2, k-4 of the chunk's last element: carried downwards
+  double2 Q1 = EQ, S1 = ES;                                          // from element C
+  double2 Q2 = c_fnms(qs1.x, nx1, EQ), S2 = c_fnms(qs1.y, nx1, ES);  // from element C+1
+  double2 Q3 = c_fnms(qs2.x, nx2, Q2), S3 = c_fnms(qs2.y, nx2, S2);  // from element C+2
 #pragma unroll
   for (int j = C - 1; j >= 0; --j) {
     const int k = k0 + 2 * j;
-    const BihConst c = bih_tab_get(tab, RT, C, k);
-    const BihConst c2 = bih_const_at(tab, RT, C, k - 2, N, gl), c4 = bih_const_at(tab, RT, C, k - 4, N, gl);
+    // constants of row k-6 for the next step down (rows < 0: q4, s4 only)
+    const BihConst c6 = bih_const_at(tab, RT, C, k - 6, N, gl);
     const BihRow h = bih_row_tab(k, a, b, c, c2.B2, c2.q4, c2.s4, c4.B4);
     const double2 um4 = (j >= 2) ? u[j >= 2 ? j - 2 : 0] : (j == 1 ? pl1 : pl2);
     const double2 um2 = (j >= 1) ? u[j >= 1 ? j - 1 : 0] : pl1;
@@ -1909,16 +1914,96 @@ __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a
     hu = c_fma(h.p, Q3, hu);
     hu = c_fma(h.r, S3, hu);
     const bool ok = wok && k < n;
-    x[j] = ok ? to_f2(c_sub(f[j], hu)) : make_float2(0.0f, 0.0f);
-    const double q = qw(k);
+    x[j] = ok ? to_f2(c_sub(fetch_f(j), hu)) : make_float2(0.0f, 0.0f);
+    const double q = c4.q4, sv = c4.s4;  // q_k, s_k
     Q3 = Q2;
     S3 = S2;
     Q2 = Q1;
     S2 = S1;
     Q1 = c_fma(q, u[j], Q1);
-    S1 = c_fma(sw(k, q), u[j], S1);
+    S1 = c_fma(sv, u[j], S1);
+    c = c2;
+    c2 = c4;
+    c4 = c6;
   }
 }
+
+// -------------------------------------------------------------------------
+// Persistent, software-pipelined form of the wave solve (G >= 16, C >= 8).
+//
+// Each wavefront loops over groups of SPW = 64/(2G) systems.  Two LDS tiles
+// per wavefront alternate: while one group is solved in registers, the next
+// group's right-hand sides stream from HBM straight into the other tile
+// (global_load_lds: no registers held, and each instruction covers 64
+// consecutive rows, so HBM and L2 see whole lines); the solution leaves
+// through the tile its group came in by, again as whole lines.
+//
+// Per iteration there is one wait on vector memory (after the arithmetic):
+// then the prefetched tile is complete and the stores of the previous group
+// are done, so the LDS traffic that follows (stage the solution, read the
+// next group, read the staged rows back for the stores) runs with nothing
+// outstanding, and only then is the tile refilled.
+//
+// Tile layout: system s, row k sits at entry 64 (s NB + k/64) + ((k mod 64)
+// xor (m mod 16)), m = k / 2C its chunk, NB = 2GC/64.  Each global_load_lds
+// instruction fills one 64-entry block; the xor spreads the 16 chunks that a
+// group of 16 lanes touches at one step over all 16 bank groups.  NS extra
+// 64-entry slots hold each lane's restart words.
+// -------------------------------------------------------------------------
+#define SHEN_LDS(ptr) ((__attribute__((address_space(3))) void*)(ptr))
+
+template <int C, int G>
+struct Tile {
+  static constexpr int SPW = 64 / (2 * G);
+  static constexpr int B = 2 * C;             // rows per chunk (both parities)
+  static constexpr int NB = (2 * G * C) / 64;  // 64-row blocks per system
+  static_assert(G >= 16 && C >= 8 && C % 4 == 0, "tile layout needs G >= 16 and C in {8, 16, ...}");
+  // entry of row k of system s
+  static __device__ __forceinline__ int pos(int s, int k) { return 64 * (s * NB + (k >> 6)) + ((k & 63) ^ ((k / B) & 15)); }
+  // row held by entry (block i, lane l): the xor is an involution on the block
+  static __device__ __forceinline__ int row(int i, int l) {
+    const int t = i % NB;
+    return 64 * t + (l ^ (((64 * t + l) / B) & 15));
+  }
+};
+
+// Streams group g into tile T: C instructions of 64 consecutive rows each
+// (rows >= N and systems >= nsys clamped to valid addresses; the reader masks
+// them), then NS 16-byte restart words per lane from the state slots
+// (system w's slot at sts + w sstride).
+template <int C, int G, int NS>
+__device__ __forceinline__ void prefetch_tile(double2* T, int lane, int64_t g, int N, int64_t nsys, const double2* __restrict__ f,
+                                              const double2* __restrict__ sts, int64_t sstride) {
+  using TL = Tile<C, G>;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int s = i / TL::NB;
+    const int64_t w = g * TL::SPW + s;
+    const int64_t wc = w < nsys ? w : nsys - 1;
+    const int k = TL::row(i, lane);
+    const int kc = k < N ? k : N - 1;
+    __builtin_amdgcn_global_load_lds((const void*)(f + wc * (int64_t)N + kc), SHEN_LDS(T + 64 * i), 16, 0, 0);
+  }
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int64_t w = g * TL::SPW + sl;
+  const int64_t wc = w < nsys ? w : nsys - 1;
+  const double2* st = sts + wc * sstride + (p * G + m) * NS;
+#pragma unroll
+  for (int t = 0; t < NS; ++t)
+    __builtin_amdgcn_global_load_lds((const void*)(st + t), SHEN_LDS(T + 64 * (C + t)), 16, 0, 0);
+}
+
+// f stays in LDS (one tile per wavefront, streamed in by LDS-DMA) where the
+// layout allows it (G >= 16), else in registers.
+template <int C, int G>
+struct MixedTile {
+  static constexpr size_t tile_bytes = (size_t)4 * C * 64 * sizeof(double2);
+  static constexpr size_t base_bytes =
+      (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * 64 * 10 * sizeof(double);
+  // gfx950: 160 KiB of LDS per work group
+  static constexpr bool value = (G >= 16 && C >= 8 && C % 4 == 0) && base_bytes + tile_bytes <= 160 * 1024;
+  static constexpr size_t bytes = value ? tile_bytes : 0;
+};
 
 template <int C, int G>
 __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const double* __restrict__ ca,
@@ -1927,17 +2012,22 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
                                                      double tol) {
   constexpr int SPW = 64 / (2 * G);
   constexpr int RT = 2 * G * C;
+  constexpr bool kTile = MixedTile<C, G>::value;
   extern __shared__ double smem[];
   const double* tab = smem;
   bih_tab_fill(smem, RT, C, N, gl, threadIdx.x, 256);
-  __syncthreads();
-  double* st64 = smem + 2 * kBihTabPairs * RT + (threadIdx.x >> 6) * 64 * 10;  // FP64 restart states (fallback)
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double* st64 = smem + 2 * kBihTabPairs * RT + wv * 64 * 10;  // FP64 restart states (fallback)
+  double2* ftile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT + 4 * 64 * 10) + wv * (C * 64);
   const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
-  const int64_t w = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + sl;
+  const int64_t g = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t w = g * SPW + sl;
   const bool wok = w < nsys;
   const int n = N - 4;
   const int k0 = 2 * m * C + p;
+  if constexpr (kTile) prefetch_tile<C, G, 0>(ftile, lane, g, N, nsys, f, nullptr, 0);
+  __syncthreads();  // the table
   const double a = wok ? ca[w] : 0.0, b = wok ? cb[w] : 0.0;
   const double2* frow = f + (wok ? w : 0) * (int64_t)N;
   double2* urow = u + (wok ? w : 0) * (int64_t)N;
@@ -1948,12 +2038,27 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     m2 = BihRowState32{s0.x, s0.y, s1.x, s1.y, s2.x};
     m4 = BihRowState32{s2.y, s3.x, s3.y, s4.x, s4.y};
   }
-  double2 fx[C];
+  // f of chunk element j (0 on padding rows)
+  double2 fx[kTile ? 1 : C];
+  if constexpr (kTile) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const int k = k0 + 2 * j;
-    fx[j] = (wok && k < n) ? frow[k] : zero2();
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      fx[j] = (wok && k < n) ? frow[k] : zero2();
+    }
   }
+  auto fget = [&](int j) -> double2 {
+    if constexpr (kTile) {
+      using TL = Tile<C, G>;
+      const int k = k0 + 2 * j;
+      const double2 v = ftile[TL::pos(sl, k)];
+      return (wok && k < n) ? v : zero2();
+    } else {
+      return fx[kTile ? 0 : j];
+    }
+  };
   // FP32 factorisation
   BihFac32<C> F;
   bool finite32 = true;
@@ -1987,7 +2092,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     ux[j] = zero2();
-    x[j] = to_f2(fx[j]);
+    x[j] = to_f2(fget(j));
   }
   bool running = wok && (sys_max<G>(finite32 ? 0.0 : 1.0) == 0.0);
   bool conv = false;
@@ -2016,9 +2121,18 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
       prev = dmax;
     }
     if (!__any(running)) break;
-    bih_residual<C, G>(N, lane, wok, a, b, gl, tab, fx, ux, x);
+    bih_residual<C, G>(N, lane, wok, a, b, gl, tab, fget, ux, x);
   }
   const bool failed = wok && !conv;
+  // the refined solutions leave first, so that the FP64 re-solve below does
+  // not hold them
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) urow[k] = (k < n) ? ux[j] : zero2();
+    }
+  }
   int bad = INT_MAX;
   if (__any(failed)) {
     // FP64 re-solve of this wavefront's systems: restart states by one
@@ -2036,19 +2150,14 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     }
     double2 x64[C];
 #pragma unroll
-    for (int j = 0; j < C; ++j) x64[j] = fx[j];
-    auto fetch = [&](int j) { return fx[j]; };
-    bad = bih_wave_core<C, G, true, true>(N, lane, w, wok, a, b, q2, q4, x64, fetch, urow, gl, nullptr, tab);
+    for (int j = 0; j < C; ++j) x64[j] = fget(j);
+    bad = bih_wave_core<C, G, true, true>(N, lane, w, wok, a, b, q2, q4, x64, fget, urow, gl, nullptr, tab);
     if (failed) {
 #pragma unroll
-      for (int j = 0; j < C; ++j) ux[j] = x64[j];
-    }
-  }
-  if (wok) {
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = k0 + 2 * j;
-      if (k < N) urow[k] = (k < n) ? ux[j] : zero2();
+      for (int j = 0; j < C; ++j) {
+        const int k = k0 + 2 * j;
+        if (k < N) urow[k] = (k < n) ? x64[j] : zero2();
+      }
     }
   }
   if (info != nullptr) {
@@ -2363,70 +2472,6 @@ __global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const 
   bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, sts, sstride, gl, info);
 }
 
-// -------------------------------------------------------------------------
-// Persistent, software-pipelined form of the wave solve (G >= 16, C >= 8).
-//
-// Each wavefront loops over groups of SPW = 64/(2G) systems.  Two LDS tiles
-// per wavefront alternate: while one group is solved in registers, the next
-// group's right-hand sides stream from HBM straight into the other tile
-// (global_load_lds: no registers held, and each instruction covers 64
-// consecutive rows, so HBM and L2 see whole lines); the solution leaves
-// through the tile its group came in by, again as whole lines.
-//
-// Per iteration there is one wait on vector memory (after the arithmetic):
-// then the prefetched tile is complete and the stores of the previous group
-// are done, so the LDS traffic that follows (stage the solution, read the
-// next group, read the staged rows back for the stores) runs with nothing
-// outstanding, and only then is the tile refilled.
-//
-// Tile layout: system s, row k sits at entry 64 (s NB + k/64) + ((k mod 64)
-// xor (m mod 16)), m = k / 2C its chunk, NB = 2GC/64.  Each global_load_lds
-// instruction fills one 64-entry block; the xor spreads the 16 chunks that a
-// group of 16 lanes touches at one step over all 16 bank groups.  NS extra
-// 64-entry slots hold each lane's restart words.
-// -------------------------------------------------------------------------
-#define SHEN_LDS(ptr) ((__attribute__((address_space(3))) void*)(ptr))
-
-template <int C, int G>
-struct Tile {
-  static constexpr int SPW = 64 / (2 * G);
-  static constexpr int B = 2 * C;             // rows per chunk (both parities)
-  static constexpr int NB = (2 * G * C) / 64;  // 64-row blocks per system
-  static_assert(G >= 16 && C >= 8 && C % 4 == 0, "tile layout needs G >= 16 and C in {8, 16, ...}");
-  // entry of row k of system s
-  static __device__ __forceinline__ int pos(int s, int k) { return 64 * (s * NB + (k >> 6)) + ((k & 63) ^ ((k / B) & 15)); }
-  // row held by entry (block i, lane l): the xor is an involution on the block
-  static __device__ __forceinline__ int row(int i, int l) {
-    const int t = i % NB;
-    return 64 * t + (l ^ (((64 * t + l) / B) & 15));
-  }
-};
-
-// Streams group g into tile T: C instructions of 64 consecutive rows each
-// (rows >= N and systems >= nsys clamped to valid addresses; the reader masks
-// them), then NS 16-byte restart words per lane from the state slots
-// (system w's slot at sts + w sstride).
-template <int C, int G, int NS>
-__device__ __forceinline__ void prefetch_tile(double2* T, int lane, int64_t g, int N, int64_t nsys, const double2* __restrict__ f,
-                                              const double2* __restrict__ sts, int64_t sstride) {
-  using TL = Tile<C, G>;
-#pragma unroll
-  for (int i = 0; i < C; ++i) {
-    const int s = i / TL::NB;
-    const int64_t w = g * TL::SPW + s;
-    const int64_t wc = w < nsys ? w : nsys - 1;
-    const int k = TL::row(i, lane);
-    const int kc = k < N ? k : N - 1;
-    __builtin_amdgcn_global_load_lds((const void*)(f + wc * (int64_t)N + kc), SHEN_LDS(T + 64 * i), 16, 0, 0);
-  }
-  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
-  const int64_t w = g * TL::SPW + sl;
-  const int64_t wc = w < nsys ? w : nsys - 1;
-  const double2* st = sts + wc * sstride + (p * G + m) * NS;
-#pragma unroll
-  for (int t = 0; t < NS; ++t)
-    __builtin_amdgcn_global_load_lds((const void*)(st + t), SHEN_LDS(T + 64 * (C + t)), 16, 0, 0);
-}
 
 // This lane's chunk (rows k0 + 2j of system sl) and restart words from tile T.
 template <int C, int G, int NS>
@@ -2783,7 +2828,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       continue;
     }
     if (a.mixed) {
-      const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double);
+      const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double) + MixedTile<C, G>::bytes;
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
       (void)attrm;
