@@ -401,23 +401,30 @@ __global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int 
 }
 
 // The same walk with the chunk geometry fixed at compile time: the restart
-// states are kept in registers and written at the end, one lane's states
-// back to back, so that the cache combines them into whole lines.
+// states are kept in registers and written at the end.  For G <= 16 they go
+// out through LDS, one parity at a time, so that every store instruction
+// writes whole 256-byte runs of consecutive slots (4 systems x G slots)
+// instead of 16-byte pieces of 64 different lines.
 template <int C, int G>
 __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
                                                        double2* __restrict__ S, int64_t sstride, int gl) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
-  const int64_t w = t >> 1;
+  const bool act = t < 2 * nsys;
+  if constexpr (G > 16) {
+    if (!act) return;
+  }
+  const int64_t w = act ? t >> 1 : 0;
   const int p = (int)(t & 1);
   const int n = N - 2;
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
   const double al = alpha[w];
   double2 st[G];
+  st[0] = zero2();
   HelmPrev pv = {0.0, 0.0};
 #pragma unroll
   for (int mm = 1; mm < G; ++mm) {
+    st[mm] = zero2();
     if (mm < nchunks) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
@@ -429,10 +436,36 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
       st[mm] = make_double2(pv.rd, pv.g);
     }
   }
-  double2* dst = S + w * sstride + p * G;  // states at (p G + m) of the system's slot, 16 bytes each
+  if constexpr (G > 16) {
+    double2* dst = S + w * sstride + p * G;  // states at (p G + m) of the system's slot, 16 bytes each
 #pragma unroll
-  for (int mm = 1; mm < G; ++mm)
-    if (mm < nchunks) dst[mm] = st[mm];
+    for (int mm = 1; mm < G; ++mm)
+      if (mm < nchunks) dst[mm] = st[mm];
+  } else {
+    // wavefront wv holds systems w0 .. w0+31, lane l system w0 + l/2, parity l&1
+    __shared__ double2 stage[4][32 * G];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + wv * 64) >> 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (p == h) {
+#pragma unroll
+        for (int mm = 0; mm < G; ++mm) stage[wv][(lane >> 1) * G + mm] = st[mm];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int r = 0; r < G / 2; ++r) {
+        const int idx = r * 64 + lane;
+        const int64_t ws = w0 + idx / G;
+        if (ws < nsys) S[ws * sstride + h * G + idx % G] = stage[wv][idx];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
@@ -2189,7 +2222,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
-  const int64_t w = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW + sl;
+  const int64_t w = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6))) * SPW + sl;
   const bool wok = w < nsys;
   const int n = N - 4;
   const int k0 = 2 * m * C + p;
@@ -2244,8 +2277,8 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   auto Rpp = [&](int j) { return j >= 2 ? rj[j >= 2 ? j - 2 : 0] : (j == 1 ? in2.R : in4.R); };
   auto qsj = [&](int j) {  // (q, s) of row k_j: q4, s4 of row k_j - 4
     const int k = k0 + 2 * j;
-    if (k >= 4) return bih_tab_qs(tab, C, k - 4);
-    const BihConst c = bih_const(k - 4, N, gl);
+    if (j >= 2) return bih_tab_qs(tab, C, k - 4);  // k - 4 >= 0
+    const BihConst c = bih_const_at(tab, RT, C, k - 4, N, gl);
     return make_double2(c.q4, c.s4);
   };
   // U^T z = gbar, local pass from a zero state with the chunk's 4x4 map
