@@ -1320,6 +1320,12 @@ __global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const
 struct NoHook {
   __device__ void operator()() const {}
 };
+// A fetch functor with a true static member `lazy` also serves the first
+// forward sweep: f is then read as the sweep goes, not held from the start.
+template <typename F, typename = void>
+struct LazyFetch : std::false_type {};
+template <typename F>
+struct LazyFetch<F, std::void_t<decltype(F::lazy)>> : std::bool_constant<F::lazy> {};
 template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
@@ -1431,7 +1437,13 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     u4j[j] = keep(o.rU0 * o.U4);
     pj[j] = keep(o.rU0 * o.P);
     rj[j] = keep(o.rU0 * o.R);
-    double2 y = c_fnms(l1, y1, x[j]);
+    double2 fj;
+    if constexpr (LazyFetch<FetchF>::value) {
+      fj = fetch_f(j);
+    } else {
+      fj = x[j];
+    }
+    double2 y = c_fnms(l1, y1, fj);
     y = c_fnms(l2, y2, y);
     x[j] = y;
     y2 = y1;
@@ -2563,6 +2575,45 @@ __device__ __forceinline__ void read_tile_asm(const double2* T, int lane, double
   for (int t = 0; t < NS; ++t) st[t] = tmp[C + t];
 }
 
+// Only the restart words of this lane from tile T (asm reads, as above).
+template <int C, int NS>
+__device__ __forceinline__ void read_states_asm(const double2* T, int lane, double2 (&st)[NS]) {
+  const uint32_t base = (uint32_t)(uintptr_t)SHEN_LDS(T);
+#pragma unroll
+  for (int t = 0; t < NS; t += 4) {
+    uint32_t ad[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ad[q] = base + 16u * (uint32_t)(64 * (C + (t + q < NS ? t + q : 0)) + lane);
+    v2d r[4];
+    lds_read4(ad[0], ad[1], ad[2], ad[3], r[0], r[1], r[2], r[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (t + q < NS) st[t + q] = make_double2(r[q].x, r[q].y);
+  }
+}
+
+// f of chunk element j from tile T, four elements per LDS round trip (0 on
+// padding rows and absent systems); serves both forward sweeps.
+template <int C, int G>
+struct TileFetch4 {
+  static constexpr bool lazy = true;
+  uint32_t base;
+  int sl, k0, n;
+  bool wok;
+  v2d b[4];
+  __device__ __forceinline__ double2 operator()(int j) {
+    using TL = Tile<C, G>;
+    if (j % 4 == 0) {
+      uint32_t ad[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ad[q] = base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * (j + q));
+      lds_read4(ad[0], ad[1], ad[2], ad[3], b[0], b[1], b[2], b[3]);
+    }
+    const v2d r = b[j % 4];
+    return (wok && k0 + 2 * j < n) ? make_double2(r.x, r.y) : zero2();
+  }
+};
+
 // Stages this lane's solution chunk in tile T.
 template <int C, int G>
 __device__ __forceinline__ void stage_tile(double2* T, int lane, const double2 (&x)[C]) {
@@ -2708,21 +2759,18 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     const int64_t w = g * SPW + sl;
     const bool wok = w < nsys;
     double2 x[C], st[5];
-    read_tile_asm<C, G, 5>(tile, lane, x, st);
-#pragma unroll
-    for (int j = 0; j < C; ++j) x[j] = (wok && k0 + 2 * j < n) ? x[j] : zero2();
+    read_states_asm<C, 5>(tile, lane, st);  // f is read by the sweeps themselves
     BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
     if (wok && m > 0 && k0 < n) {
       m2 = BihRowState{st[0].x, st[0].y, st[1].x, st[1].y, st[2].x};
       m4 = BihRowState{st[2].y, st[3].x, st[3].y, st[4].x, st[4].y};
     }
-    auto fetch = [&](int j) {
-      const int k = k0 + 2 * j;
-      uint32_t ad = (uint32_t)(uintptr_t)SHEN_LDS(tile) + 16u * (uint32_t)TL::pos(sl, k);
-      v2d r0;
-      asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(r0) : "v"(ad) : "memory");
-      return (wok && k < n) ? make_double2(r0.x, r0.y) : zero2();
-    };
+    TileFetch4<C, G> fetch;
+    fetch.base = (uint32_t)(uintptr_t)SHEN_LDS(tile);
+    fetch.sl = sl;
+    fetch.k0 = k0;
+    fetch.n = n;
+    fetch.wok = wok;
     const int64_t gn = g + stride;
     auto prefetch_next = [&]() {
       if (gn < ngroups) {
