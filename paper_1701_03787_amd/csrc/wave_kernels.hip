@@ -575,17 +575,22 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
   }
 }
 
-// 512 threads: eight wavefronts (four pairs of parities, 256 systems) share
-// one table, so that every block of the launch is resident at once.
+// Six wavefronts (three pairs of parities, 192 systems) share one table.  At
+// most three tables fit a CU, so every block of a channel-size launch is
+// resident at once; six-wavefront blocks spread the wavefronts over the SIMDs
+// more evenly (at most five per SIMD at 131,584 systems, where eight-wavefront
+// blocks leave six on the CUs that take a third block).
+static constexpr int kBihWalkThreads = 384;
+static constexpr int kBihWalkSystems = kBihWalkThreads / 2;
 template <int C, int G, bool F32>
-__global__ __launch_bounds__(512) void bih_boundary_tab(int N, int64_t nsys, const double* __restrict__ ca,
-                                                        const double* __restrict__ cb, double2* __restrict__ S,
-                                                        int64_t sstride, int gl) {
+__global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64_t nsys, const double* __restrict__ ca,
+                                                                    const double* __restrict__ cb, double2* __restrict__ S,
+                                                                    int64_t sstride, int gl) {
   extern __shared__ double tab[];
-  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 512);
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, kBihWalkThreads);
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 256 + (wv >> 1) * 64 + lane;
+  const int64_t w = (int64_t)blockIdx.x * kBihWalkSystems + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
   bih_walk_tab<C, G, F32>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
 }
@@ -2901,7 +2906,8 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds);
       (void)attra;
-      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
+                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u,
                          (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
                          c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
@@ -2913,7 +2919,8 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
       (void)attrm;
-      hipLaunchKernelGGL((bih_boundary_tab<C, G, true>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1, u,
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, true>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
+                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u,
                          (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
                          c1, f, u, a.gl, info, a.it_max, a.tol);
@@ -2928,7 +2935,8 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlot : u;
     const int64_t sstride = a.fac_mode ? kSlot : (int64_t)a.N;
     if (a.fac_mode != 2)
-      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + 255) / 256)), dim3(512), lds, st, a.N, ns, c0, c1,
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
+                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1,
                          sts, sstride, a.gl);
     if (a.fac_mode == 1) continue;
     // gfx950: 160 KiB of LDS per work group
