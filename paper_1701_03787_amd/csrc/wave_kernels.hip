@@ -2580,6 +2580,38 @@ __device__ __forceinline__ void read_tile_asm(const double2* T, int lane, double
   for (int t = 0; t < NS; ++t) st[t] = tmp[C + t];
 }
 
+// The two FP64 coefficients of each lane's system into a 1 KiB LDS area R by
+// LDS-DMA (four 4-byte transfers: low and high words of a, then of b), and
+// back out with asm reads.  Kept out of registers between the prefetch and
+// their use, a loaded coefficient can be neither waited for early nor
+// spilled (a spill would wait for every load in flight, the tile included).
+__device__ __forceinline__ void prefetch_coef2(double2* R, int lane, int64_t w, const double* __restrict__ ca,
+                                               const double* __restrict__ cb) {
+  const int* a32 = reinterpret_cast<const int*>(ca + w);
+  const int* b32 = reinterpret_cast<const int*>(cb + w);
+  int* r = reinterpret_cast<int*>(R);
+  __builtin_amdgcn_global_load_lds((const void*)a32, SHEN_LDS(r), 4, 0, 0);
+  __builtin_amdgcn_global_load_lds((const void*)(a32 + 1), SHEN_LDS(r + 64), 4, 0, 0);
+  __builtin_amdgcn_global_load_lds((const void*)b32, SHEN_LDS(r + 128), 4, 0, 0);
+  __builtin_amdgcn_global_load_lds((const void*)(b32 + 1), SHEN_LDS(r + 192), 4, 0, 0);
+  (void)lane;
+}
+__device__ __forceinline__ void read_coef2(const double2* R, int lane, double& a, double& b) {
+  const uint32_t base = (uint32_t)(uintptr_t)SHEN_LDS(R) + 4u * (uint32_t)lane;
+  int alo, ahi, blo, bhi;
+  asm volatile(
+      "ds_read_b32 %0, %4\n\t"
+      "ds_read_b32 %1, %4 offset:256\n\t"
+      "ds_read_b32 %2, %4 offset:512\n\t"
+      "ds_read_b32 %3, %4 offset:768\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(alo), "=&v"(ahi), "=&v"(blo), "=&v"(bhi)
+      : "v"(base)
+      : "memory");
+  a = __hiloint2double(ahi, alo);
+  b = __hiloint2double(bhi, blo);
+}
+
 // Only the restart words of this lane from tile T (asm reads, as above).
 template <int C, int NS>
 __device__ __forceinline__ void read_states_asm(const double2* T, int lane, double2 (&st)[NS]) {
@@ -2731,7 +2763,8 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
   // wavefront index as a scalar: the tile base (and with it the LDS-DMA
   // destinations) and the group loop stay in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 5) * 64);
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 6) * 64);
+  double2* coef = tile + (C + 5) * 64;  // the group's coefficients (prefetch_coef2)
   constexpr int WPB = PtabWaves<G>::value;
   bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 64 * WPB);
   __syncthreads();
@@ -2744,12 +2777,10 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     const int64_t w = gg * SPW + l / (2 * G);
     return w < nsys ? w : nsys - 1;
   };
-  double ca_, cb_, ca_n = 0.0, cb_n = 0.0;
   {
     const int lane = threadIdx.x & 63;
     prefetch_tile<C, G, 5>(tile, lane, g, N, nsys, f, sts, sstride);
-    ca_ = ca[sysc(g, lane)];
-    cb_ = cb[sysc(g, lane)];
+    prefetch_coef2(coef, lane, sysc(g, lane), ca, cb);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   for (; g < ngroups; g += stride) {
@@ -2765,6 +2796,8 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     const bool wok = w < nsys;
     double2 x[C], st[5];
     read_states_asm<C, 5>(tile, lane, st);  // f is read by the sweeps themselves
+    double ca_, cb_;
+    read_coef2(coef, lane, ca_, cb_);
     BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
     if (wok && m > 0 && k0 < n) {
       m2 = BihRowState{st[0].x, st[0].y, st[1].x, st[1].y, st[2].x};
@@ -2780,17 +2813,23 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     auto prefetch_next = [&]() {
       if (gn < ngroups) {
         prefetch_tile<C, G, 5>(tile, lane, gn, N, nsys, f, sts, sstride);
-        ca_n = ca[sysc(gn, lane)];
-        cb_n = cb[sysc(gn, lane)];
+        prefetch_coef2(coef, lane, sysc(gn, lane), ca, cb);
       }
     };
     double2* urow = u + (wok ? w : 0) * (int64_t)N;
-    bih_wave_core<C, G, false, true>(N, lane, w, wok, wok ? ca_ : 0.0, wok ? cb_ : 0.0, m2, m4, x, fetch, urow, gl, info, tab,
-                                     prefetch_next);
-    // the next group has landed (and the stores above are issued)
+    bih_wave_core<C, G, true, true>(N, lane, w, wok, wok ? ca_ : 0.0, wok ? cb_ : 0.0, m2, m4, x, fetch, urow, gl, info, tab,
+                                    prefetch_next);
+    // The next group has landed.  This group's solution is stored only after
+    // this wait, so that the wait does not include the acknowledgement of
+    // its stores; they complete while the next group is solved.
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    ca_ = ca_n;
-    cb_ = cb_n;
+    if (wok) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int k = k0 + 2 * j;
+        if (k < N) urow[k] = x[j];  // table rows past n solve to zero
+      }
+    }
   }
 }
 
@@ -2942,7 +2981,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     // gfx950: 160 KiB of LDS per work group
     constexpr int kWpb = PtabWaves<G>::value;
     constexpr size_t kPtabLds =
-        (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)kWpb * (C + 5) * 64 * sizeof(double2);
+        (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)kWpb * (C + 6) * 64 * sizeof(double2);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16 && kPtabLds <= 160 * 1024) {
       const size_t lds2 = kPtabLds;
       static const bool attr2 = set_dynamic_lds((const void*)bih_wave_ptab<C, G>, lds2);
