@@ -197,3 +197,27 @@ def test_wave_chunk_knob(dev, family, chunk):
         assert np.all(u[:, wl.n_unknowns(family, N):] == 0)
         e = so.rel_err_per_system(u, ref)
         assert e.max() <= TOL, (N, chunk, e.max())
+
+
+def test_streams(dev):
+    """Calls enqueue on torch's current stream: two solves on two side streams (default
+    priority) overlap with each other and with host work, and each matches the oracle."""
+    N = 512
+    g = wl.small_grid(N, 48, kmax=362, index=77, nu=5e-5, dt=5e-4)
+    from paper_1701_03787_amd import api
+    fams = ("helmholtz", "biharmonic")
+    host = {fam: (g.rhs(fam), g.coefficients(fam)) for fam in fams}
+    dev_in = {fam: (T(host[fam][0], dev), [T(c, dev) for c in host[fam][1]]) for fam in fams}
+    torch.cuda.synchronize()
+    streams = {fam: torch.cuda.Stream(device=dev) for fam in fams}
+    out = {}
+    _print_case(test="streams", N=N, nsys=g.nsys)
+    for fam in fams:
+        with torch.cuda.stream(streams[fam]):
+            f, cs = dev_in[fam]
+            fn = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
+            out[fam] = fn(f, *cs)
+    for fam in fams:
+        streams[fam].synchronize()
+        ref = so.solve(fam, N, host[fam][1], host[fam][0])
+        assert so.rel_err_per_system(out[fam].cpu().numpy(), ref).max() <= TOL
