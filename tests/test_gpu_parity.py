@@ -221,3 +221,26 @@ def test_streams(dev):
         streams[fam].synchronize()
         ref = so.solve(fam, N, host[fam][1], host[fam][0])
         assert so.rel_err_per_system(out[fam].cpu().numpy(), ref).max() <= TOL
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_maximum_n(dev, family):
+    """The largest N the library accepts on this device (shen_max_n: the chain kernels beyond the
+    wave kernels' 1024) solves to the FP64 bar; one more is refused before any launch."""
+    from paper_1701_03787_amd import _lib, api
+    fam = _lib.SHEN_HELMHOLTZ if family == "helmholtz" else _lib.SHEN_BIHARMONIC
+    nmax = int(_lib.lib().shen_max_n(fam, _lib.SHEN_FP64))
+    assert nmax > 1024
+    nsys = 3
+    _print_case(test="max_n", family=family, N=nmax, nsys=nsys)
+    g = wl.small_grid(nmax, nsys, kmax=200, index=5)
+    coeffs = g.coefficients(family)
+    f = g.rhs(family)
+    ref = so.solve(family, nmax, coeffs, f)
+    u = gpu_solve(family, nmax, coeffs, f, dev)
+    assert so.rel_err_per_system(u, ref).max() <= TOL
+    assert np.all(u[:, wl.n_unknowns(family, nmax):] == 0)
+    g1 = wl.small_grid(nmax + 1, 1, index=6)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    with pytest.raises(_lib.ShenError):
+        fn(T(g1.rhs(family), dev), *[T(c, dev) for c in g1.coefficients(family)])
