@@ -468,14 +468,6 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
   }
 }
 
-__global__ __launch_bounds__(256) void helm_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
-                                                     double2* __restrict__ u, int gl) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
-  const int64_t w = t >> 1;
-  helm_boundary_chain(N, C, G, (int)(t & 1), alpha[w], u + w * (int64_t)N, gl);
-}
-
 __device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
                                                    int gl) {
   const int n = N - 4;
@@ -505,14 +497,6 @@ __device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, d
       s[4] = make_double2(m4.P, m4.R);
     }
   }
-}
-
-__global__ __launch_bounds__(256) void bih_boundary(int N, int64_t nsys, int C, int G, const double* __restrict__ ca,
-                                                    const double* __restrict__ cb, double2* __restrict__ u, int gl) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
-  const int64_t w = t >> 1;
-  bih_boundary_chain(N, C, G, (int)(t & 1), ca[w], cb[w], u + w * (int64_t)N, gl);
 }
 
 // Table-driven form of the biharmonic boundary walk: the rows are assembled
@@ -2512,16 +2496,6 @@ __global__ __launch_bounds__(256) void bih_wave_tab(int N, int64_t nsys, const d
   const int64_t wbase = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * SPW;
   bih_wave_body<C, G, true>(N, nsys, wbase, ca, cb, f, u, sts, sstride, gl, info, tab);
 }
-
-template <int C, int G>
-__global__ __launch_bounds__(64) void bih_wave_solve(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
-                                                     const double2* __restrict__ f, double2* __restrict__ u,
-                                                     const double2* __restrict__ sts, int64_t sstride, int gl,
-                                                     int32_t* __restrict__ info) {
-  constexpr int SPW = 64 / (2 * G);
-  bih_wave_body<C, G>(N, nsys, (int64_t)blockIdx.x * SPW, ca, cb, f, u, sts, sstride, gl, info);
-}
-
 
 // This lane's chunk (rows k0 + 2j of system sl) and restart words from tile T.
 template <int C, int G, int NS>
