@@ -177,6 +177,21 @@ int biharmonic_solve_factored(int32_t N, int64_t nsys, const double* a, const do
                               shen_c128* u, const shen_opts* opts);
 
 /*
+ * Adjoints from the states of helmholtz_factor / biharmonic_factor (same
+ * coefficients, N, quad and chunk): as helmholtz_adjoint / biharmonic_adjoint,
+ * bitwise, without their boundary walk; a differentiable time step can thus
+ * factor once for its forward solve and its backward pass.  lambda may alias
+ * gbar here; fac must not overlap lambda.  Wave kernels only: SHEN_ENOTSUP
+ * for opts->variant == SHEN_VARIANT_CHAIN or an N without a wave
+ * configuration.
+ */
+int helmholtz_adjoint_factored(int32_t N, int64_t nsys, const double* alpha, const void* fac, const shen_c128* u,
+                               const shen_c128* gbar, shen_c128* lambda, double* grad_alpha, const shen_opts* opts);
+int biharmonic_adjoint_factored(int32_t N, int64_t nsys, const double* a, const double* b, const void* fac, const shen_c128* u,
+                                const shen_c128* gbar, shen_c128* lambda, double* grad_a, double* grad_b,
+                                const shen_opts* opts);
+
+/*
  * Matrix-vector products Hu (or H^T u) in O(N) per system, FP64: the banded
  * part plus same-parity suffix sums for the rank-structured tail (Sec. 3
  * right-hand sides; also the residual of the refinement).  Hu must not

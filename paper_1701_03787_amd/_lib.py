@@ -71,6 +71,9 @@ SIGNATURES = [
     ("biharmonic_factor", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("helmholtz_solve_factored", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("biharmonic_solve_factored", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("helmholtz_adjoint_factored", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("biharmonic_adjoint_factored", C.c_int,
+     [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("helmholtz_matvec", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("biharmonic_matvec", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("shen_batched_plan", C.c_int64, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),

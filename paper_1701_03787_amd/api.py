@@ -217,8 +217,10 @@ def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
     return y
 
 
-def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, variant="auto"):
-    """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None)."""
+def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, variant="auto", fac=None, chunk=0):
+    """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None).
+
+    With fac (from helmholtz_factor, same alpha, quad, chunk) the restart states are taken from it."""
     gbar = _rows(gbar, "gbar")
     N = gbar.shape[-1]
     lead = gbar.shape[:-1]
@@ -228,15 +230,23 @@ def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, v
     if coef_grad:
         u = _rows(u, "u")
     inf = _info_tensor(info, lead, gbar.device)
-    o = _opts(gbar.device, quad=quad, info=inf, variant=variant)
-    L.check(L.lib().helmholtz_adjoint(N, _nsys(lead), alpha.data_ptr(), u.data_ptr() if coef_grad else None,
-                                      gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
-                                      C.byref(o)), "helmholtz_adjoint")
+    o = _opts(gbar.device, quad=quad, info=inf, variant=variant, chunk=chunk)
+    up = u.data_ptr() if coef_grad else None
+    gp = ga.data_ptr() if ga is not None else None
+    if fac is not None:
+        fac = _check_fac(fac, "helmholtz", N, lead, gbar.device, chunk)
+        L.check(L.lib().helmholtz_adjoint_factored(N, _nsys(lead), alpha.data_ptr(), fac.data_ptr(), up, gbar.data_ptr(),
+                                                   lam.data_ptr(), gp, C.byref(o)), "helmholtz_adjoint_factored")
+    else:
+        L.check(L.lib().helmholtz_adjoint(N, _nsys(lead), alpha.data_ptr(), up, gbar.data_ptr(), lam.data_ptr(), gp,
+                                          C.byref(o)), "helmholtz_adjoint")
     return (lam, ga, inf) if inf is not None else (lam, ga)
 
 
-def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, variant="auto"):
-    """lambda = H^{-T} gbar, grad_a = -Re(lambda^H A u), grad_b = -Re(lambda^H B u)."""
+def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, variant="auto", fac=None, chunk=0):
+    """lambda = H^{-T} gbar, grad_a = -Re(lambda^H A u), grad_b = -Re(lambda^H B u).
+
+    With fac (from biharmonic_factor, same a, b, quad, chunk) the restart states are taken from it."""
     gbar = _rows(gbar, "gbar")
     N = gbar.shape[-1]
     lead = gbar.shape[:-1]
@@ -248,10 +258,18 @@ def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, v
     if coef_grad:
         u = _rows(u, "u")
     inf = _info_tensor(info, lead, gbar.device)
-    o = _opts(gbar.device, quad=quad, info=inf, variant=variant)
-    L.check(L.lib().biharmonic_adjoint(N, _nsys(lead), a.data_ptr(), b.data_ptr(), u.data_ptr() if coef_grad else None,
-                                       gbar.data_ptr(), lam.data_ptr(), ga.data_ptr() if ga is not None else None,
-                                       gb.data_ptr() if gb is not None else None, C.byref(o)), "biharmonic_adjoint")
+    o = _opts(gbar.device, quad=quad, info=inf, variant=variant, chunk=chunk)
+    up = u.data_ptr() if coef_grad else None
+    gap = ga.data_ptr() if ga is not None else None
+    gbp = gb.data_ptr() if gb is not None else None
+    if fac is not None:
+        fac = _check_fac(fac, "biharmonic", N, lead, gbar.device, chunk)
+        L.check(L.lib().biharmonic_adjoint_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), up,
+                                                    gbar.data_ptr(), lam.data_ptr(), gap, gbp, C.byref(o)),
+                "biharmonic_adjoint_factored")
+    else:
+        L.check(L.lib().biharmonic_adjoint(N, _nsys(lead), a.data_ptr(), b.data_ptr(), up, gbar.data_ptr(), lam.data_ptr(),
+                                           gap, gbp, C.byref(o)), "biharmonic_adjoint")
     return (lam, ga, gb, inf) if inf is not None else (lam, ga, gb)
 
 
@@ -259,14 +277,29 @@ def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, v
 # autograd
 # --------------------------------------------------------------------------
 
+def _factor_if_wave(family, N, make):
+    """The factor-once states when the wave kernels cover N, else None (the solve then walks itself)."""
+    o = L.default_opts()
+    fam = L.SHEN_HELMHOLTZ if family == "helmholtz" else L.SHEN_BIHARMONIC
+    if L.lib().shen_factor_bytes(fam, int(N), C.byref(o)) <= 0:
+        return None
+    return make()
+
+
 class HelmholtzSolve(torch.autograd.Function):
     """u = (S + alpha B)^{-1} f with a hand-written adjoint:
     grad_f = H^{-T} grad_u, grad_alpha = -Re(grad_f^H B u)."""
 
     @staticmethod
     def forward(ctx, f, alpha, quad="gc"):
-        u = helmholtz_solve(f.contiguous(), alpha.contiguous(), quad=quad)
+        f, alpha = f.contiguous(), alpha.contiguous()
+        fac = _factor_if_wave("helmholtz", f.shape[-1], lambda: helmholtz_factor(alpha, f.shape[-1], quad=quad))
+        if fac is not None:  # factor once for the forward solve and the backward pass
+            u = helmholtz_solve_factored(f, alpha, fac, quad=quad)
+        else:
+            u = helmholtz_solve(f, alpha, quad=quad)
         ctx.save_for_backward(u, alpha)
+        ctx.fac = fac
         ctx.quad = quad
         return u
 
@@ -274,7 +307,7 @@ class HelmholtzSolve(torch.autograd.Function):
     def backward(ctx, gu):
         u, alpha = ctx.saved_tensors
         need_c = ctx.needs_input_grad[1]
-        lam, ga = helmholtz_adjoint(u, gu.contiguous(), alpha, quad=ctx.quad, coef_grad=need_c)
+        lam, ga = helmholtz_adjoint(u, gu.contiguous(), alpha, quad=ctx.quad, coef_grad=need_c, fac=ctx.fac)
         return (lam if ctx.needs_input_grad[0] else None), (ga if need_c else None), None
 
 
@@ -284,8 +317,14 @@ class BiharmonicSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, f, a, b, quad="gc"):
-        u = biharmonic_solve(f.contiguous(), a.contiguous(), b.contiguous(), quad=quad)
+        f, a, b = f.contiguous(), a.contiguous(), b.contiguous()
+        fac = _factor_if_wave("biharmonic", f.shape[-1], lambda: biharmonic_factor(a, b, f.shape[-1], quad=quad))
+        if fac is not None:  # factor once for the forward solve and the backward pass
+            u = biharmonic_solve_factored(f, a, b, fac, quad=quad)
+        else:
+            u = biharmonic_solve(f, a, b, quad=quad)
         ctx.save_for_backward(u, a, b)
+        ctx.fac = fac
         ctx.quad = quad
         return u
 
@@ -293,7 +332,7 @@ class BiharmonicSolve(torch.autograd.Function):
     def backward(ctx, gu):
         u, a, b = ctx.saved_tensors
         need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
-        lam, ga, gb = biharmonic_adjoint(u, gu.contiguous(), a, b, quad=ctx.quad, coef_grad=need_c)
+        lam, ga, gb = biharmonic_adjoint(u, gu.contiguous(), a, b, quad=ctx.quad, coef_grad=need_c, fac=ctx.fac)
         return ((lam if ctx.needs_input_grad[0] else None), (ga if ctx.needs_input_grad[1] else None),
                 (gb if ctx.needs_input_grad[2] else None), None)
 

@@ -161,6 +161,51 @@ int factored(int family, int32_t N, int64_t nsys, const double* c0, const double
   return run_wave(w);
 }
 
+// Adjoint with the restart states of a factor call (no walk; lambda may alias gbar).
+int adjoint_factored(int family, int32_t N, int64_t nsys, const double* c0, const double* c1, const void* fac,
+                     const shen_c128* u, const shen_c128* gbar, shen_c128* lambda, double* g0, double* g1,
+                     const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (!fac || !aligned(fac, 16) || check_rows(gbar) || check_rows(lambda) || check_coef(c0) ||
+      (family == SHEN_BIHARMONIC && check_coef(c1)))
+    return SHEN_EINVAL;
+  const bool grads = g0 || g1;
+  if (grads && check_rows(u)) return SHEN_EINVAL;
+  if ((g0 && !aligned(g0, 8)) || (g1 && !aligned(g1, 8))) return SHEN_EINVAL;
+  if (rows_overlap_partially(gbar, lambda, nsys, N)) return SHEN_EINVAL;
+  if (u && grads && (u == lambda || rows_overlap_partially(u, lambda, nsys, N))) return SHEN_EINVAL;
+  const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
+  {
+    const uintptr_t pa = (uintptr_t)fac, pb = (uintptr_t)lambda;
+    const uintptr_t la = (uintptr_t)nsys * (uintptr_t)(slot > 0 ? slot : 1) * 16u, lb = (uintptr_t)nsys * (uintptr_t)N * 16u;
+    if (pa < pb + lb && pb < pa + la) return SHEN_EINVAL;
+  }
+  if (o.variant == SHEN_VARIANT_CHAIN || slot == 0) return SHEN_ENOTSUP;
+  shen::WaveArgs w;
+  w.family = family;
+  w.N = N;
+  w.nsys = nsys;
+  w.c0 = c0;
+  w.c1 = c1;
+  w.f = gbar;
+  w.u = lambda;
+  w.info = o.info;
+  w.gl = o.quad == SHEN_QUAD_GL;
+  w.chunk = o.chunk;
+  w.adjoint = 1;
+  w.ufwd = grads ? u : nullptr;
+  w.g0 = g0;
+  w.g1 = g1;
+  w.stream = o.stream;
+  w.fac = const_cast<void*>(fac);
+  w.fac_mode = 2;
+  return run_wave(w);
+}
+
 }  // namespace
 
 extern "C" {
@@ -379,6 +424,16 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* ca, const double* 
   a.gl = o.quad == SHEN_QUAD_GL;
   a.stream = o.stream;
   return run(a);
+}
+
+int helmholtz_adjoint_factored(int32_t N, int64_t nsys, const double* alpha, const void* fac, const shen_c128* u,
+                               const shen_c128* gbar, shen_c128* lambda, double* grad_alpha, const shen_opts* opts) {
+  return adjoint_factored(SHEN_HELMHOLTZ, N, nsys, alpha, nullptr, fac, u, gbar, lambda, grad_alpha, nullptr, opts);
+}
+int biharmonic_adjoint_factored(int32_t N, int64_t nsys, const double* a, const double* b, const void* fac, const shen_c128* u,
+                                const shen_c128* gbar, shen_c128* lambda, double* grad_a, double* grad_b,
+                                const shen_opts* opts) {
+  return adjoint_factored(SHEN_BIHARMONIC, N, nsys, a, b, fac, u, gbar, lambda, grad_a, grad_b, opts);
 }
 
 int64_t shen_factor_bytes(int32_t family, int32_t N, const shen_opts* opts) {

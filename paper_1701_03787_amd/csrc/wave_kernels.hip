@@ -799,7 +799,8 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
 template <int C, int G>
 __global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, const double* __restrict__ alpha,
                                                         const double2* __restrict__ ufwd, const double2* __restrict__ gbar,
-                                                        double2* __restrict__ lam, double* __restrict__ grad, int gl,
+                                                        double2* __restrict__ lam, const double2* __restrict__ sts,
+                                                        int64_t sstride, double* __restrict__ grad, int gl,
                                                         int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
   const int lane = threadIdx.x & 63;
@@ -814,7 +815,7 @@ __global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, con
   double2* lrow = lam + (wok ? w : 0) * (int64_t)N;
   HelmPrev pv = {0.0, 0.0};
   if (wok && m > 0 && k0 < n) {
-    const double2 s2 = *reinterpret_cast<const double2*>(reinterpret_cast<const double*>(lrow) + (p * G + m) * 2);
+    const double2 s2 = sts[w * sstride + p * G + m];
     pv.rd = s2.x;
     pv.g = s2.y;
   }
@@ -2214,6 +2215,7 @@ template <int C, int G>
 __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, const double* __restrict__ ca,
                                                        const double* __restrict__ cb, const double2* __restrict__ ufwd,
                                                        const double2* __restrict__ gbar, double2* __restrict__ lam,
+                                                       const double2* __restrict__ sts, int64_t sstride,
                                                        double* __restrict__ grad_a, double* __restrict__ grad_b, int gl,
                                                        int32_t* __restrict__ info) {
   constexpr int SPW = 64 / (2 * G);
@@ -2232,7 +2234,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   double2* lrow = lam + (wok ? w : 0) * (int64_t)N;
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   if (wok && m > 0 && k0 < n) {
-    const double2* sv = reinterpret_cast<const double2*>(reinterpret_cast<const double*>(lrow) + (p * G + m) * 10);
+    const double2* sv = sts + w * sstride + (p * G + m) * 5;
     const double2 s0 = sv[0], s1 = sv[1], s2 = sv[2], s3 = sv[3], s4 = sv[4];
     m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
     m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
@@ -2871,10 +2873,16 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const int64_t groups = (ns + SPW - 1) / SPW;
     if (a.adjoint) {
-      hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u,
-                         (int64_t)a.N, a.gl);
+      // restart states: parked in lambda, or the forward solve's (factor-once mode)
+      constexpr int64_t kSlotA = 2 * G;
+      double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlotA : u;
+      const int64_t sstride = a.fac_mode ? kSlotA : (int64_t)a.N;
+      if (a.fac_mode == 0)
+        hipLaunchKernelGGL((helm_boundary_t<C, G>), dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, c0, u,
+                           (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((helm_adjoint_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0,
-                         a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr, a.gl, info);
+                         a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, sts, sstride, a.g0 ? a.g0 + s0 : nullptr,
+                         a.gl, info);
       continue;
     }
     if (a.mixed) {
@@ -2919,12 +2927,16 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds);
       (void)attra;
-      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
-                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u,
-                         (int64_t)a.N, a.gl);
+      // restart states: parked in lambda, or the forward solve's (factor-once mode)
+      constexpr int64_t kSlotA = 2 * G * 5;
+      double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlotA : u;
+      const int64_t sstride = a.fac_mode ? kSlotA : (int64_t)a.N;
+      if (a.fac_mode == 0)
+        hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
+                           dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u, (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
-                         c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, a.g0 ? a.g0 + s0 : nullptr,
-                         a.g1 ? a.g1 + s0 : nullptr, a.gl, info);
+                         c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, sts, sstride,
+                         a.g0 ? a.g0 + s0 : nullptr, a.g1 ? a.g1 + s0 : nullptr, a.gl, info);
       continue;
     }
     if (a.mixed) {

@@ -129,3 +129,15 @@ def test_factored_argument_errors():
         setattr(o, field, val)
         assert lib.helmholtz_factor(16, 4, A, A, C.byref(o)) == L.SHEN_ENOTSUP, field
         assert lib.biharmonic_solve_factored(16, 4, A, A, A + (1 << 16), A, A, C.byref(o)) == L.SHEN_ENOTSUP, field
+
+
+def test_adjoint_factored_argument_errors():
+    lib = L.lib()
+    A = ALIGNED
+    o = L.default_opts()
+    # NULL fac; fac overlapping lambda; gradient without u
+    assert lib.helmholtz_adjoint_factored(16, 4, A, None, A, A, A + 4096, None, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.helmholtz_adjoint_factored(16, 4, A, A + 4096, None, A, A + 4096, None, C.byref(o)) == L.SHEN_EINVAL
+    assert lib.biharmonic_adjoint_factored(16, 4, A, A, A + (1 << 16), None, A, A, A + 8, None, C.byref(o)) == L.SHEN_EINVAL
+    o.variant = 1
+    assert lib.biharmonic_adjoint_factored(16, 4, A, A, A + (1 << 16), None, A, A, None, None, C.byref(o)) == L.SHEN_ENOTSUP
