@@ -224,6 +224,39 @@ def measure_factored(dev, args, grid, data, host, rows):
     return out
 
 
+def measure_matvec(dev, args, grid, data, host, rows):
+    """O(N) products H u on the bench workload (the residual / right-hand-side assembly kernel):
+    one read of u, one write of Hu per system; sampled rows against the oracle's dense product."""
+    import numpy as np
+    import torch
+    from oracle import shen_oracle as so
+    from paper_1701_03787_amd import api
+    N, nsys = grid.N, grid.nsys
+    out = {"workload": grid.name}
+    for fam, (f, cs, u) in data.items():
+        fn = api.helmholtz_matvec if fam == "helmholtz" else api.biharmonic_matvec
+        hu = torch.empty_like(f)
+        for _ in range(max(1, args.warmup)):
+            fn(f, *cs, out=hu)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(f, *cs, out=hu)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = nsys * (16 * N + 16 * N + 8 * len(cs))
+        fh, csh = host[fam]
+        ref = so.matvec(fam, N, tuple(c[rows] for c in csh), fh[rows], extended=True)
+        got = hu[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        out[fam] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err}
+        del hu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +371,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = {"factored": measure_factored(dev, args, grid, data, host, rows),
+                 "matvec": measure_matvec(dev, args, grid, data, host, rows),
                  "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
 
     cpu = None

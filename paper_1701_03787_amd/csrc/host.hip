@@ -468,6 +468,21 @@ int helmholtz_matvec(int32_t N, int64_t nsys, const double* alpha, const shen_c1
   if (nsys == 0) return SHEN_OK;
   if (check_rows(u) || check_rows(Hu) || check_coef(alpha)) return SHEN_EINVAL;
   if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
+  if (!o.transpose && o.variant != SHEN_VARIANT_CHAIN && shen::matvec_wave_supported(0, N)) {
+    shen::WaveArgs w;
+    w.family = 0;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = alpha;
+    w.f = u;
+    w.u = Hu;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    DevInfo d;
+    const int rc2 = device_info(&d);
+    if (rc2 != SHEN_OK) return rc2;
+    return shen::launch_matvec_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+  }
   ChainArgs a;
   a.kind = ChainKind::HelmMatvec;
   a.N = N;
@@ -490,6 +505,22 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* c
   if (nsys == 0) return SHEN_OK;
   if (check_rows(u) || check_rows(Hu) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
+  if (!o.transpose && o.variant != SHEN_VARIANT_CHAIN && shen::matvec_wave_supported(1, N)) {
+    shen::WaveArgs w;
+    w.family = 1;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = ca;
+    w.c1 = cb;
+    w.f = u;
+    w.u = Hu;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    DevInfo d;
+    const int rc2 = device_info(&d);
+    if (rc2 != SHEN_OK) return rc2;
+    return shen::launch_matvec_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+  }
   ChainArgs a;
   a.kind = ChainKind::BihMatvec;
   a.N = N;

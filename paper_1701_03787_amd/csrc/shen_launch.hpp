@@ -65,6 +65,8 @@ bool wave_supported(int family, int N);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);
 int64_t wave_state_slot(int family, int N, int chunk);
+bool matvec_wave_supported(int family, int N);
+hipError_t launch_matvec_wave(const WaveArgs& a);
 
 size_t chain_bytes_per_system(ChainKind kind, int N);
 int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);

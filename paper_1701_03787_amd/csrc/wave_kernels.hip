@@ -1113,12 +1113,13 @@ __device__ __forceinline__ void helm_solve32(int lane, bool wok, int n, float hm
   }
 }
 
-// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows.
-template <int C, int G>
-__device__ __forceinline__ void helm_residual(int N, int lane, bool wok, double al, int gl, const double2 (&f)[C],
-                                              const double2 (&u)[C], float2 (&x)[C]) {
+// (H u)_k of this lane's chunk elements in FP64, handed to sink(j, hu) from
+// the last element down: the banded part from the lane's own values and its
+// neighbours' (row shifts), the same-parity tail from suffix sums of chunk
+// totals.  u must be zero on padding rows.
+template <int C, int G, typename Sink>
+__device__ __forceinline__ void helm_apply(int N, int lane, double al, int gl, const double2 (&u)[C], Sink sink) {
   const int p = (lane / G) & 1, m = lane % G;
-  const int n = N - 2;
   const int k0 = 2 * m * C + p;
   double2 tot = zero2();
 #pragma unroll
@@ -1161,11 +1162,22 @@ __device__ __forceinline__ void helm_residual(int N, int lane, bool wok, double 
     hu = c_fma(hm, um, hu);
     hu = c_fma(h.hpp + hm, up, hu);
     hu = c_fma(h.hpp, R2, hu);
-    const bool ok = wok && k < n;
-    x[j] = ok ? to_f2(c_sub(f[j], hu)) : make_float2(0.0f, 0.0f);
+    sink(j, hu);
     R2 = R1;
     R1 = c_add(R1, u[j]);
   }
+}
+
+// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows.
+template <int C, int G>
+__device__ __forceinline__ void helm_residual(int N, int lane, bool wok, double al, int gl, const double2 (&f)[C],
+                                              const double2 (&u)[C], float2 (&x)[C]) {
+  const int n = N - 2;
+  const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
+  helm_apply<C, G>(N, lane, al, gl, u, [&](int j, double2 hu) {
+    const bool ok = wok && k0 + 2 * j < n;
+    x[j] = ok ? to_f2(c_sub(f[j], hu)) : make_float2(0.0f, 0.0f);
+  });
 }
 
 // Reduction over the 2G lanes of a system.
@@ -1883,17 +1895,16 @@ __device__ __forceinline__ void bih_solve32(int lane, const BihFac32<C>& F, cons
   }
 }
 
-// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows; rows
-// from the table as in the factorisation.  Walking the chunk downwards, each
-// row's constants are read once and carried to the two rows below (which
-// need them as those of rows k-2 and k-4); q_k, s_k are the table's q4, s4 of
-// row k-4.
-template <int C, int G, typename FetchF>
-__device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a, double b, int gl, const double* tab,
-                                             FetchF fetch_f, const double2 (&u)[C], float2 (&x)[C]) {
+// (H u)_k of this lane's chunk elements in FP64, handed to sink(j, hu) from
+// the last element down; rows from the table as in the factorisation.
+// Walking the chunk downwards, each row's constants are read once and carried
+// to the two rows below (which need them as those of rows k-2 and k-4);
+// q_k, s_k are the table's q4, s4 of row k-4.  u must be zero on padding rows.
+template <int C, int G, typename Sink>
+__device__ __forceinline__ void bih_apply(int N, int lane, double a, double b, int gl, const double* tab, const double2 (&u)[C],
+                                          Sink sink) {
   constexpr int RT = 2 * G * C;
   const int p = (lane / G) & 1, m = lane % G;
-  const int n = N - 4;
   const int k0 = 2 * m * C + p;
   // constants of rows k0 + 2(C-1) and the two below it
   BihConst c = bih_const_at(tab, RT, C, k0 + 2 * (C - 1), N, gl);
@@ -1948,8 +1959,7 @@ __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a
     hu = c_fma(h.hp4, up4, hu);
     hu = c_fma(h.p, Q3, hu);
     hu = c_fma(h.r, S3, hu);
-    const bool ok = wok && k < n;
-    x[j] = ok ? to_f2(c_sub(fetch_f(j), hu)) : make_float2(0.0f, 0.0f);
+    sink(j, hu);
     const double q = c4.q4, sv = c4.s4;  // q_k, s_k
     Q3 = Q2;
     S3 = S2;
@@ -1961,6 +1971,18 @@ __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a
     c2 = c4;
     c4 = c6;
   }
+}
+
+// x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows.
+template <int C, int G, typename FetchF>
+__device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a, double b, int gl, const double* tab,
+                                             FetchF fetch_f, const double2 (&u)[C], float2 (&x)[C]) {
+  const int n = N - 4;
+  const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
+  bih_apply<C, G>(N, lane, a, b, gl, tab, u, [&](int j, double2 hu) {
+    const bool ok = wok && k0 + 2 * j < n;
+    x[j] = ok ? to_f2(c_sub(fetch_f(j), hu)) : make_float2(0.0f, 0.0f);
+  });
 }
 
 // -------------------------------------------------------------------------
@@ -2811,6 +2833,135 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
 
 
 // =========================================================================
+// Matrix-vector products H u in the wave layout (right-hand-side assembly and
+// residuals, Sec. 3): persistent kernels that stream each group's u into an
+// LDS tile, take it into registers, start the next group's tile, form H u
+// from each lane's chunk and its neighbours (helm_apply / bih_apply) and
+// store it after the end-of-group wait (so that the wait does not include
+// the stores' acknowledgement).  Rows k >= n are written as 0.
+// =========================================================================
+template <int C, int G>
+__device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n, bool wok, double2 (&x)[C]) {
+  using TL = Tile<C, G>;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  const uint32_t base = (uint32_t)(uintptr_t)SHEN_LDS(T);
+#pragma unroll
+  for (int j = 0; j < C; j += 4) {
+    v2d r[4];
+    lds_read4(base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * j), base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * j + 2),
+              base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * j + 4), base + 16u * (uint32_t)TL::pos(sl, k0 + 2 * j + 6), r[0],
+              r[1], r[2], r[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[j + q] = (wok && k0 + 2 * (j + q) < n) ? make_double2(r[q].x, r[q].y) : zero2();
+  }
+}
+
+template <int C, int G, int FAM>
+__device__ __forceinline__ void matvec_store(int N, int n, int lane, bool wok, double2* __restrict__ row, const double2 (&y)[C]) {
+  const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
+  if (wok) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int k = k0 + 2 * j;
+      if (k < N) row[k] = (k < n) ? y[j] : zero2();
+    }
+  }
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                       const double2* __restrict__ uin, double2* __restrict__ hu, int gl) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  __shared__ double2 tile[(C + 1) * 64];
+  double2* coef = tile + C * 64;
+  const int64_t ngroups = (nsys + SPW - 1) / SPW;
+  int64_t g = blockIdx.x;
+  if (g >= ngroups) return;
+  const int n = N - 2;
+  auto sysc = [&](int64_t gg, int l) {
+    const int64_t w = gg * SPW + l / (2 * G);
+    return w < nsys ? w : nsys - 1;
+  };
+  {
+    const int lane = threadIdx.x & 63;
+    prefetch_tile<C, G, 0>(tile, lane, g, N, nsys, uin, nullptr, 0);
+    prefetch_coef2(coef, lane, sysc(g, lane), alpha, alpha);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  for (; g < ngroups; g += gridDim.x) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    lane &= 63;  // opaque, but known to be a lane index
+    const int64_t w = g * SPW + lane / (2 * G);
+    const bool wok = w < nsys;
+    double2 x[C], y[C];
+    read_tile_rows<C, G>(tile, lane, n, wok, x);
+    double al, unused;
+    read_coef2(coef, lane, al, unused);
+    const int64_t gn = g + gridDim.x;
+    if (gn < ngroups) {
+      prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
+      prefetch_coef2(coef, lane, sysc(gn, lane), alpha, alpha);
+    }
+    helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = v; });
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    matvec_store<C, G, 0>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
+  }
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, const double* __restrict__ ca,
+                                                       const double* __restrict__ cb, const double2* __restrict__ uin,
+                                                       double2* __restrict__ hu, int gl) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  constexpr int RT = 2 * G * C;
+  extern __shared__ double smem[];
+  double* tab = smem;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 1) * 64);
+  double2* coef = tile + C * 64;
+  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int n = N - 4;
+  const int64_t ngroups = (nsys + SPW - 1) / SPW;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  int64_t g = (int64_t)blockIdx.x * 4 + wv;
+  if (g >= ngroups) return;
+  auto sysc = [&](int64_t gg, int l) {
+    const int64_t w = gg * SPW + l / (2 * G);
+    return w < nsys ? w : nsys - 1;
+  };
+  {
+    const int lane = threadIdx.x & 63;
+    prefetch_tile<C, G, 0>(tile, lane, g, N, nsys, uin, nullptr, 0);
+    prefetch_coef2(coef, lane, sysc(g, lane), ca, cb);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  for (; g < ngroups; g += stride) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    lane &= 63;  // opaque, but known to be a lane index
+    const int64_t w = g * SPW + lane / (2 * G);
+    const bool wok = w < nsys;
+    double2 x[C], y[C];
+    read_tile_rows<C, G>(tile, lane, n, wok, x);
+    double a, b;
+    read_coef2(coef, lane, a, b);
+    const int64_t gn = g + stride;
+    if (gn < ngroups) {
+      prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
+      prefetch_coef2(coef, lane, sysc(gn, lane), ca, cb);
+    }
+    bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = v; });
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    matvec_store<C, G, 1>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
+  }
+}
+
+// =========================================================================
 // host side
 // =========================================================================
 
@@ -2983,6 +3134,58 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     }
   }
   return hipGetLastError();
+}
+
+template <int C, int G>
+static hipError_t launch_matvec_t(const WaveArgs& a) {
+  constexpr int SPW = 64 / (2 * G);
+  if constexpr (!(C >= 8 && C % 4 == 0 && G >= 16)) {
+    return hipErrorInvalidValue;
+  } else {
+    hipStream_t st = (hipStream_t)a.stream;
+    const int64_t groups = (a.nsys + SPW - 1) / SPW;
+    const double2* uin = (const double2*)a.f;
+    double2* hu = (double2*)a.u;
+    if (a.family == 0) {
+      const int64_t blocks = persistent_blocks((const void*)helm_matvec_pipe<C, G>, groups);
+      hipLaunchKernelGGL((helm_matvec_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, uin, hu, a.gl);
+    } else {
+      constexpr size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 1) * 64 * sizeof(double2);
+      if constexpr (lds > 160 * 1024) {
+        return hipErrorInvalidValue;
+      } else {
+        static const bool attr = set_dynamic_lds((const void*)bih_matvec_ptab<C, G>, lds);
+        (void)attr;
+        const int64_t blocks = persistent_blocks((const void*)bih_matvec_ptab<C, G>, (groups + 3) / 4, 256, lds);
+        hipLaunchKernelGGL((bih_matvec_ptab<C, G>), dim3((unsigned)blocks), dim3(256), lds, st, a.N, a.nsys, a.c0, a.c1, uin,
+                           hu, a.gl);
+      }
+    }
+    return hipGetLastError();
+  }
+}
+
+// Wave-layout matvec for (family, N): the configuration of the solves, when it
+// has the tile layout (G >= 16, C >= 8); false otherwise (the caller then uses
+// the chain kernels).
+bool matvec_wave_supported(int family, int N) {
+  const WaveCfg c = pick_cfg((N + 1) / 2, family, N, 0);
+  if (!(c.C >= 8 && c.C % 4 == 0 && c.G >= 16)) return false;
+  const size_t lds = (size_t)kBihTabPairs * 2 * c.G * c.C * sizeof(double2) + (size_t)4 * (c.C + 1) * 64 * sizeof(double2);
+  return family == 0 || lds <= 160 * 1024;
+}
+
+hipError_t launch_matvec_wave(const WaveArgs& a) {
+  if (a.nsys <= 0) return hipSuccess;
+  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N, 0);
+#define SHEN_MV(CC, GG) \
+  if (c.C == CC && c.G == GG) return launch_matvec_t<CC, GG>(a);
+  SHEN_MV(8, 16)
+  SHEN_MV(16, 16)
+  SHEN_MV(8, 32)
+  SHEN_MV(16, 32)
+#undef SHEN_MV
+  return hipErrorInvalidValue;
 }
 
 // double2 per system of the factor-once state slots (0: no wave kernel for N)

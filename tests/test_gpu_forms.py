@@ -173,19 +173,25 @@ def test_dot_product_identity(dev, family):
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-def test_matvec_vs_oracle(dev, family):
+@pytest.mark.parametrize("quad", ["gc", "gl"])
+def test_matvec_vs_oracle(dev, family, quad):
+    """H u and H^T u against the oracle's dense product in extended precision: the chain kernels
+    (small N, transposed) and the wave-layout kernels (N with a tiled configuration), over ragged
+    system counts."""
     from paper_1701_03787_amd import api
-    for N in (9, 64, 257):
+    qo = so.GL if quad == "gl" else so.GC
+    for N in (9, 64, 257, 512, 1024):
         g = wl.small_grid(N, 11, index=N)
         cs = g.coefficients(family)
         u = g.rhs(family)
         for tr in (False, True):
-            case(test="matvec", family=family, N=N, transpose=tr)
-            ref = so.matvec(family, N, cs, u, transpose=tr, extended=True)
+            case(test="matvec", family=family, N=N, transpose=tr, quad=quad)
+            ref = so.matvec(family, N, cs, u, quad=qo, transpose=tr, extended=True)
             fn = api.helmholtz_matvec if family == "helmholtz" else api.biharmonic_matvec
-            got = fn(T(u, dev), *[T(c, dev) for c in cs], transpose=tr).cpu().numpy()
+            got = fn(T(u, dev), *[T(c, dev) for c in cs], transpose=tr, quad=quad).cpu().numpy()
             scale = np.max(np.abs(ref), axis=1, keepdims=True)
-            assert np.max(np.abs(got - ref) / scale) <= 1e-13
+            assert np.max(np.abs(got - ref) / scale) <= 1e-13, (N, tr)
+            assert np.all(got[:, wl.n_unknowns(family, N):] == 0)
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
