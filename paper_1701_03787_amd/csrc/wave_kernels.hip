@@ -3165,11 +3165,25 @@ static hipError_t launch_matvec_t(const WaveArgs& a) {
   }
 }
 
-// Wave-layout matvec for (family, N): the configuration of the solves, when it
-// has the tile layout (G >= 16, C >= 8); false otherwise (the caller then uses
-// the chain kernels).
+// Configuration of the wave-layout matvec for (family, N).  The biharmonic
+// band product of a 16-row chunk does not fit the register file (it spills),
+// so that family takes 8-row chunks wherever G <= 32 lanes cover the chain;
+// Helmholtz takes the configuration of its solve.
+static WaveCfg matvec_cfg(int family, int N) {
+  const int nc = (N + 1) / 2;
+  if (family == 1) {
+    for (int G = 16; G <= 32; G *= 2)
+      if (8 * G >= nc && 20 * G <= 2 * N) return WaveCfg{8, G};
+  }
+  return pick_cfg(nc, family, N, 0);
+}
+
+// True when (family, N) has a wave-layout matvec (the tile layout needs
+// G >= 16 lanes per chain and C >= 8 rows per chunk, and the biharmonic row
+// table plus four tiles must fit the LDS); false otherwise (the caller then
+// uses the chain kernels).
 bool matvec_wave_supported(int family, int N) {
-  const WaveCfg c = pick_cfg((N + 1) / 2, family, N, 0);
+  const WaveCfg c = matvec_cfg(family, N);
   if (!(c.C >= 8 && c.C % 4 == 0 && c.G >= 16)) return false;
   const size_t lds = (size_t)kBihTabPairs * 2 * c.G * c.C * sizeof(double2) + (size_t)4 * (c.C + 1) * 64 * sizeof(double2);
   return family == 0 || lds <= 160 * 1024;
@@ -3177,7 +3191,7 @@ bool matvec_wave_supported(int family, int N) {
 
 hipError_t launch_matvec_wave(const WaveArgs& a) {
   if (a.nsys <= 0) return hipSuccess;
-  const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N, 0);
+  const WaveCfg c = matvec_cfg(a.family, a.N);
 #define SHEN_MV(CC, GG) \
   if (c.C == CC && c.G == GG) return launch_matvec_t<CC, GG>(a);
   SHEN_MV(8, 16)
