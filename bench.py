@@ -257,6 +257,41 @@ def measure_matvec(dev, args, grid, data, host, rows):
     return out
 
 
+def measure_mass(dev, args, grid, data, host, rows):
+    """Mass-matrix solves u = B^{-1} f (forward Shen transforms, Sec. 2) on the bench
+    workload, f standing in for the scalar products S(u): one read of f, one write of u
+    per system; sampled rows against the oracle."""
+    import numpy as np
+    import torch
+    from oracle import shen_oracle as so
+    from paper_1701_03787_amd import api
+    N, nsys = grid.N, grid.nsys
+    out = {"workload": grid.name}
+    for fam, (f, cs, u) in data.items():
+        fn = api.dirichlet_mass_solve if fam == "helmholtz" else api.biharmonic_mass_solve
+        v = torch.empty_like(f)
+        for _ in range(max(1, args.warmup)):
+            fn(f, out=v)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(f, out=v)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        n = N - 2 if fam == "helmholtz" else N - 4
+        nbytes = nsys * (16 * n + 16 * N)
+        ref = so.mass_solve(fam, N, host[fam][0][rows])
+        got = v[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        err = float(so.rel_err_per_system(got, ref).max())
+        key = "dirichlet" if fam == "helmholtz" else "biharmonic"
+        out[key] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err}
+        del v
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +407,7 @@ def main():
     if not args.no_forms:
         forms = {"factored": measure_factored(dev, args, grid, data, host, rows),
                  "matvec": measure_matvec(dev, args, grid, data, host, rows),
+                 "mass": measure_mass(dev, args, grid, data, host, rows),
                  "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
 
     cpu = None

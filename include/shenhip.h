@@ -203,6 +203,31 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* a, const double* b,
                       shen_c128* Hu, const shen_opts* opts);
 
 /*
+ * Mass-matrix solves u = B^{-1} f, FP64, for every system: the last step of
+ * a forward Shen transform (Sec. 2, the complete transformation
+ * u_hat = B^{-1} S(u), where S(u) holds the scalar products (u, phi_l)_sigma).
+ * dirichlet_mass_solve uses Bbar = (phi_j, phi_k) of the Dirichlet basis
+ * (three nonzero diagonals, appendix matrix table), biharmonic_mass_solve
+ * Bchk of the biharmonic basis (five); per parity chain they are tri- and
+ * pentadiagonal.  The matrix depends on N and opts->quad only, so there is
+ * no coefficient argument.
+ *
+ * f, u: DEVICE arrays [nsys][N] of complex128, caller-owned, 16-byte
+ *   aligned; entries k >= n of f are ignored, those of u written as 0.
+ *   u may equal f (in place) but must not overlap it otherwise.
+ * opts: quad and stream are used; transpose is accepted and changes nothing
+ *   (B is symmetric); info is not written (B is positive definite).
+ * Returns SHEN_OK once enqueued; SHEN_EINVAL for bad arguments; SHEN_ENOTSUP
+ *   for precision SHEN_FP32_REFINE, variant SHEN_VARIANT_CHAIN or N > 1024.
+ * Accuracy: B is ill-conditioned (condition number about 2.7e4 for Bbar and
+ *   9e7 for Bchk at N = 512, growing like N^2 and N^4), and the result carries
+ *   the error of a plain FP64 factorisation of B, a small multiple of
+ *   cond(B) times the unit roundoff relative to max |u|.
+ */
+int dirichlet_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts);
+int biharmonic_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts);
+
+/*
  * One batch of independent problems (many grids of uneven N, both
  * families) in a single persistent launch.
  *

@@ -45,6 +45,9 @@ Systems solved (Sec. 3, Crank-Nicolson matrices divided by +-nu*dt/2):
 * Helmholtz:  (Sbar + alpha_w Bbar) u = f
 * biharmonic: (Qchk + a_w Achk + b_w Bchk) u = f
 
+Also: the mass-matrix solves u = Bbar^{-1} f and u = Bchk^{-1} f of the
+forward Shen transforms (Sec. 2).
+
 Inputs: N, per-system coefficients, complex f of shape [nsys, N] whose
 entries k >= n are ignored.  Output: complex u [nsys, N] with the tail zero.
 """
@@ -294,6 +297,44 @@ def matvec(family: str, N: int, coeffs, u: np.ndarray, quad: int = GC, transpose
     else:
         out[:, :n] = np.einsum("wkj,wj->wk", H, u[:, :n])
     return out
+
+
+# ----------------------------------------------------------------------------
+# Mass-matrix solves: the last step of a forward Shen transform (Sec. 2, the
+# complete transformation u_hat = B^{-1} S(u), with S(u) the vector of scalar
+# products (u, phi_l)_sigma).  One matrix for every system: Bbar (three
+# nonzero diagonals) for the Dirichlet basis, Bchk (five) for the biharmonic
+# one.
+# ----------------------------------------------------------------------------
+
+def mass_matrix(family: str, N: int, quad: int = GC) -> np.ndarray:
+    """Bbar (family "helmholtz", the Dirichlet basis) or Bchk ("biharmonic")."""
+    op = Operators.get(N, quad)
+    return op.Bd if family == "helmholtz" else op.Bb
+
+
+def mass_solve(family: str, N: int, f: np.ndarray, quad: int = GC, refine: int = 2) -> np.ndarray:
+    """u = B^{-1} f for every system (row) of f; entries k >= n of f ignored, of u zero.
+
+    LAPACK gesv on the dense mass matrix, all systems as right-hand sides of
+    one factorisation, then ``refine`` steps of iterative refinement with the
+    residual in extended precision (as in ``solve``)."""
+    f = np.asarray(f, dtype=np.complex128)
+    nsys = f.shape[0]
+    n = n_of(family, N)
+    u = np.zeros_like(f)
+    if nsys == 0:
+        return u
+    B = mass_matrix(family, N, quad)
+    rhs = np.concatenate([f[:, :n].real, f[:, :n].imag], axis=0).T  # [n, 2 nsys]
+    x = np.linalg.solve(B, rhs)
+    Bl = B.astype(np.longdouble)
+    rl = rhs.astype(np.longdouble)
+    for _ in range(refine):
+        r = rl - Bl @ x.astype(np.longdouble)
+        x = x + np.linalg.solve(B, r.astype(np.float64))
+    u[:, :n] = x[:, :nsys].T + 1j * x[:, nsys:].T
+    return u
 
 
 # ----------------------------------------------------------------------------

@@ -217,6 +217,28 @@ def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
     return y
 
 
+
+def dirichlet_mass_solve(f, *, out=None, quad="gc"):
+    """u = Bbar^{-1} f per system, Bbar the Dirichlet-basis mass matrix (Sec. 2 transforms); out may be f."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    o = _opts(f.device, quad=quad)
+    L.check(L.lib().dirichlet_mass_solve(N, _nsys(f.shape[:-1]), f.data_ptr(), u.data_ptr(), C.byref(o)),
+            "dirichlet_mass_solve")
+    return u
+
+
+def biharmonic_mass_solve(f, *, out=None, quad="gc"):
+    """u = Bchk^{-1} f per system, Bchk the biharmonic-basis mass matrix (Sec. 2 transforms); out may be f."""
+    f = _rows(f, "f")
+    N = f.shape[-1]
+    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    o = _opts(f.device, quad=quad)
+    L.check(L.lib().biharmonic_mass_solve(N, _nsys(f.shape[:-1]), f.data_ptr(), u.data_ptr(), C.byref(o)),
+            "biharmonic_mass_solve")
+    return u
+
 def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, variant="auto", fac=None, chunk=0):
     """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None).
 

@@ -206,6 +206,31 @@ int adjoint_factored(int family, int32_t N, int64_t nsys, const double* c0, cons
   return run_wave(w);
 }
 
+// Mass-matrix solves u = B^{-1} f (wave kernels only; u may alias f).
+int mass_solve(int family, int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (o.variant == SHEN_VARIANT_CHAIN || !shen::mass_wave_supported(N)) return SHEN_ENOTSUP;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(f) || check_rows(u)) return SHEN_EINVAL;
+  if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
+  DevInfo d;
+  rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  shen::WaveArgs w;
+  w.family = family;
+  w.N = N;
+  w.nsys = nsys;
+  w.f = f;
+  w.u = u;
+  w.gl = o.quad == SHEN_QUAD_GL;
+  w.stream = o.stream;
+  return shen::launch_mass_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+}
+
 }  // namespace
 
 extern "C" {
@@ -533,6 +558,13 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* c
   a.trans = o.transpose;
   a.stream = o.stream;
   return run(a);
+}
+
+int dirichlet_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
+  return mass_solve(SHEN_HELMHOLTZ, N, nsys, f, u, opts);
+}
+int biharmonic_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
+  return mass_solve(SHEN_BIHARMONIC, N, nsys, f, u, opts);
 }
 
 int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* opts) {

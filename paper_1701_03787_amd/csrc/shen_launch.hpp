@@ -67,6 +67,8 @@ hipError_t launch_wave(const WaveArgs& a);
 int64_t wave_state_slot(int family, int N, int chunk);
 bool matvec_wave_supported(int family, int N);
 hipError_t launch_matvec_wave(const WaveArgs& a);
+bool mass_wave_supported(int N);
+hipError_t launch_mass_wave(const WaveArgs& a);  // family, N, nsys, f, u (may alias f), gl, stream
 
 size_t chain_bytes_per_system(ChainKind kind, int N);
 int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);

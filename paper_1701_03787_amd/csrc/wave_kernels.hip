@@ -2962,6 +2962,332 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
 }
 
 // =========================================================================
+// Mass-matrix solves u = B^{-1} f (the last step of a forward Shen transform,
+// Sec. 2: u_hat = B^{-1} S(u)).  One matrix serves every system: Bbar
+// (Dirichlet basis, FAM 0) couples rows k-2, k, k+2, and Bchk (biharmonic
+// basis, FAM 1) rows k-4 .. k+4, so per parity chain they are tri- and
+// pentadiagonal, with bandwidth S = 1 or 2 in chain index.
+//
+// Each work group factors both chains once (no pivoting: B is symmetric
+// positive definite) into an LDS table, and each lane keeps the factors of
+// its chunk in registers for the whole persistent loop.  Per group of systems
+// the forward and backward recurrences run as in the solves: a chunk sweep
+// from a zero state gives the chunk's affine map on the S-vector state (its
+// matrix depends on the factors only and is formed once per lane), a
+// Kogge-Stone scan over the chain's lanes combines the maps, and each lane
+// reruns its chunk from the scanned incoming state.  Rows k >= n are
+// identity rows with zero right-hand side, so they solve to zero unmasked.
+// =========================================================================
+template <int FAM>
+struct MassFields {
+  static constexpr int S = FAM == 0 ? 1 : 2;
+  static constexpr int NF = 2 * S + 1;  // l_1..l_S, 1/U0, U_1..U_S
+};
+
+// Band entries of rows k < RT into the table [NF][RT] (row slots swizzled
+// like the biharmonic row table), fields e_{-S} .. e_{-1}, e_0, e_{+1} ..
+// e_{+S} in chain offsets.  Rows k >= n are identity rows, and the couplings
+// of the last rows to columns >= n are dropped.
+template <int FAM>
+__device__ __forceinline__ void mass_entries_fill(double* tab, int RT, int C, int N, int gl, int tid, int nthreads) {
+  const int n = FAM == 0 ? N - 2 : N - 4;
+  for (int k = tid; k < RT; k += nthreads) {
+    const int r = bih_tab_row(k, C);
+    if constexpr (FAM == 0) {
+      const bool in = k < n;
+      tab[0 * RT + r] = in && k >= 2 ? -0.5 * kPi : 0.0;
+      tab[1 * RT + r] = in ? helm_mass_diag(k, N, gl) : 1.0;
+      tab[2 * RT + r] = in && k + 2 < n ? -0.5 * kPi : 0.0;
+    } else {
+      double e[5] = {0.0, 0.0, 1.0, 0.0, 0.0};
+      if (k < n) {
+        // B is ill-conditioned, so its entries are formed with IEEE divisions
+        // (a one-time cost per work group) rather than refined estimates.
+        const double K = (double)k;
+        Recip R;
+        R.m1 = k == 1 ? 0.0 : 1.0 / (K - 1.0);
+        R.p1 = 1.0 / (K + 1.0);
+        R.p3 = 1.0 / (K + 3.0);
+        R.p5 = 1.0 / (K + 5.0);
+        R.p7 = 1.0 / (K + 7.0);
+        const BihMats mm = bih_mats(k, N, gl, R);
+        e[0] = mm.Bm4;
+        e[1] = mm.Bm2;
+        e[2] = mm.B0;
+        e[3] = k + 2 < n ? mm.B2 : 0.0;
+        e[4] = k + 4 < n ? mm.B4 : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 5; ++t) tab[t * RT + r] = e[t];
+    }
+  }
+}
+
+// Sequential banded LU (no pivoting) of chain p, rows k = p, p+2, ... < RT,
+// in place over the band entries: fields l_1..l_S (multipliers of rows
+// i-1..i-S), 1/U0, U_1..U_S (the upper band of row i).
+template <int FAM>
+__device__ __forceinline__ void mass_lu_chain(double* tab, int RT, int C, int p) {
+  constexpr int S = MassFields<FAM>::S;
+  double rdp[2] = {0.0, 0.0}, U1p[2] = {0.0, 0.0}, U2p[2] = {0.0, 0.0};  // index 0: row i-1
+  for (int k = p; k < RT; k += 2) {
+    const int r = bih_tab_row(k, C);
+    double e2 = 0.0, u2 = 0.0;
+    if constexpr (S == 2) {
+      e2 = tab[0 * RT + r];
+      u2 = tab[4 * RT + r];
+    }
+    const double e1 = tab[(S - 1) * RT + r], e0 = tab[S * RT + r], u1 = tab[(S + 1) * RT + r];
+    double l2 = 0.0, t1 = e1, t0 = e0;
+    if constexpr (S == 2) {
+      l2 = e2 * rdp[1];
+      t1 = __builtin_fma(-l2, U1p[1], t1);
+      t0 = __builtin_fma(-l2, U2p[1], t0);
+    }
+    const double l1 = t1 * rdp[0];
+    t0 = __builtin_fma(-l1, U1p[0], t0);
+    const double U1 = S == 2 ? __builtin_fma(-l1, U2p[0], u1) : u1;
+    const double rd = 1.0 / t0;
+    tab[0 * RT + r] = l1;
+    if constexpr (S == 2) tab[1 * RT + r] = l2;
+    tab[S * RT + r] = rd;
+    tab[(S + 1) * RT + r] = U1;
+    if constexpr (S == 2) tab[(S + 2) * RT + r] = u2;
+    rdp[1] = rdp[0];
+    U1p[1] = U1p[0];
+    U2p[1] = U2p[0];
+    rdp[0] = rd;
+    U1p[0] = U1;
+    U2p[0] = u2;
+  }
+}
+
+// Affine map on an S-vector of complex states: s -> A s + c.
+template <int S>
+struct MassMap {
+  double A[S][S];
+  double2 c[S];
+};
+
+template <int S>
+__device__ __forceinline__ void mass_compose(MassMap<S>& m, const MassMap<S>& q) {  // m <- m o q
+  double2 c[S];
+  double A[S][S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    c[i] = m.c[i];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      c[i].x = __builtin_fma(m.A[i][t], q.c[t].x, c[i].x);
+      c[i].y = __builtin_fma(m.A[i][t], q.c[t].y, c[i].y);
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      double a = 0.0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) a = __builtin_fma(m.A[i][t], q.A[t][j], a);
+      A[i][j] = a;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    m.c[i] = c[i];
+#pragma unroll
+    for (int j = 0; j < S; ++j) m.A[i][j] = A[i][j];
+  }
+}
+
+// Inclusive scan of the chunk maps over the G lanes of a chain, towards
+// higher lanes (UP = false: partner m - D, the forward recurrence) or lower
+// ones (UP = true: partner m + D, the backward one); a partner past the chain
+// end arrives as the zero map, which leaves the offset unchanged.
+template <int G, int S, bool UP, int D>
+__device__ __forceinline__ void mass_scan_steps(int m, MassMap<S>& mp) {
+  if constexpr (D < G) {
+    MassMap<S> q;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      q.c[i] = UP ? chain_hi<G, D>(mp.c[i], m) : chain_lo<G, D>(mp.c[i], m);
+#pragma unroll
+      for (int j = 0; j < S; ++j) q.A[i][j] = UP ? chain_hi<G, D>(mp.A[i][j], m) : chain_lo<G, D>(mp.A[i][j], m);
+    }
+    mass_compose<S>(mp, q);
+    mass_scan_steps<G, S, UP, 2 * D>(m, mp);
+  }
+}
+// Incoming state of this lane's chunk: the combined map of the chunks before
+// it (in the direction of the recurrence) applied to a zero state.
+template <int G, int S, bool UP>
+__device__ __forceinline__ void mass_scan(int m, MassMap<S> mp, double2 (&sin)[S]) {
+  mass_scan_steps<G, S, UP, 1>(m, mp);
+#pragma unroll
+  for (int i = 0; i < S; ++i) sin[i] = UP ? chain_hi<G, 1>(mp.c[i], m) : chain_lo<G, 1>(mp.c[i], m);
+}
+
+template <int C, int G, int FAM>
+struct MassLds {
+  static constexpr int RT = 2 * G * C;
+  static constexpr size_t tab = (size_t)MassFields<FAM>::NF * RT * sizeof(double);
+  static constexpr size_t tile = (size_t)C * 64 * sizeof(double2);
+  // wavefronts per work group: eight tiles where they fit the 160 KiB, else four
+  static constexpr int WPB = tab + 8 * tile <= 160 * 1024 ? 8 : 4;
+  static constexpr size_t bytes = tab + WPB * tile;
+};
+
+template <int C, int G, int FAM>
+__global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe(int N, int64_t nsys, const double2* __restrict__ f,
+                                                      double2* __restrict__ u, int gl) {
+  using TL = Tile<C, G>;
+  using L = MassLds<C, G, FAM>;
+  constexpr int SPW = TL::SPW;
+  constexpr int S = MassFields<FAM>::S;
+  constexpr int RT = L::RT;
+  extern __shared__ double smem[];
+  double* tab = smem;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2* tile = reinterpret_cast<double2*>(smem + MassFields<FAM>::NF * RT) + wv * (C * 64);
+  mass_entries_fill<FAM>(tab, RT, C, N, gl, (int)threadIdx.x, (int)blockDim.x);
+  __syncthreads();
+  if (threadIdx.x < 2) mass_lu_chain<FAM>(tab, RT, C, (int)threadIdx.x);
+  const int n = FAM == 0 ? N - 2 : N - 4;
+  const int64_t ngroups = (nsys + SPW - 1) / SPW;
+  const int64_t stride = (int64_t)gridDim.x * L::WPB;
+  int64_t g = (int64_t)blockIdx.x * L::WPB + wv;
+  const int lane = threadIdx.x & 63;
+  if (g < ngroups) prefetch_tile<C, G, 0>(tile, lane, g, N, nsys, f, nullptr, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (g >= ngroups) return;
+  const int p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  // this lane's factors, and the homogeneous parts of its chunk maps
+  double lf[S][C], rd[C], uf[S][C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int r = bih_tab_row(k0 + 2 * j, C);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      lf[t][j] = tab[t * RT + r];
+      uf[t][j] = tab[(S + 1 + t) * RT + r];
+    }
+    rd[j] = tab[S * RT + r];
+  }
+  MassMap<S> fw, bw;  // A parts: state of the last (first) rows from the incoming state
+#pragma unroll
+  for (int b = 0; b < S; ++b) {
+    double st[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = t == b ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      double y = 0.0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) y = __builtin_fma(-lf[t][j], st[t], y);
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = y;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) fw.A[t][b] = st[t];
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = t == b ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) v = __builtin_fma(-uf[t][j], st[t], v);
+      v *= rd[j];
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) bw.A[t][b] = st[t];
+  }
+  for (; g < ngroups; g += stride) {
+    const int64_t w = g * SPW + lane / (2 * G);
+    const bool wok = w < nsys;
+    double2 x[C];
+    read_tile_rows<C, G>(tile, lane, n, wok, x);
+    const int64_t gn = g + stride;
+    if (gn < ngroups) prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, f, nullptr, 0);
+    // forward: y_i = x_i - sum_t l_t y_{i-1-t}; state (y_{i-1}, .., y_{i-S})
+    double2 st[S], sin[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = zero2();
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      double2 y = x[j];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        y.x = __builtin_fma(-lf[t][j], st[t].x, y.x);
+        y.y = __builtin_fma(-lf[t][j], st[t].y, y.y);
+      }
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = y;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) fw.c[t] = st[t];
+    mass_scan<G, S, false>(m, fw, sin);
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = sin[t];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      double2 y = x[j];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        y.x = __builtin_fma(-lf[t][j], st[t].x, y.x);
+        y.y = __builtin_fma(-lf[t][j], st[t].y, y.y);
+      }
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = y;
+      x[j] = y;
+    }
+    // backward: u_i = (y_i - sum_t U_t u_{i+1+t}) / U0; state (u_{i+1}, .., u_{i+S})
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = zero2();
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+      double2 v = x[j];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        v.x = __builtin_fma(-uf[t][j], st[t].x, v.x);
+        v.y = __builtin_fma(-uf[t][j], st[t].y, v.y);
+      }
+      v.x *= rd[j];
+      v.y *= rd[j];
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) bw.c[t] = st[t];
+    mass_scan<G, S, true>(m, bw, sin);
+#pragma unroll
+    for (int t = 0; t < S; ++t) st[t] = sin[t];
+#pragma unroll
+    for (int j = C - 1; j >= 0; --j) {
+      double2 v = x[j];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        v.x = __builtin_fma(-uf[t][j], st[t].x, v.x);
+        v.y = __builtin_fma(-uf[t][j], st[t].y, v.y);
+      }
+      v.x *= rd[j];
+      v.y *= rd[j];
+#pragma unroll
+      for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
+      st[0] = v;
+      x[j] = v;
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    matvec_store<C, G, FAM>(N, n, lane, wok, u + (wok ? w : 0) * (int64_t)N, x);
+  }
+}
+
+// =========================================================================
 // host side
 // =========================================================================
 
@@ -3199,6 +3525,47 @@ hipError_t launch_matvec_wave(const WaveArgs& a) {
   SHEN_MV(8, 32)
   SHEN_MV(16, 32)
 #undef SHEN_MV
+  return hipErrorInvalidValue;
+}
+
+// Mass-matrix solves: the configuration by family and N (the tile layout
+// needs G >= 16 lanes per chain and C >= 8 rows per chunk; the pentadiagonal
+// factors of 16-row chunks spill at two wavefronts per SIMD, so the
+// biharmonic family takes 8-row chunks up to N = 512); C = 0 beyond N = 1024.
+static WaveCfg mass_cfg(int family, int N) {
+  const int nc = (N + 1) / 2;
+  if (nc <= 128) return WaveCfg{8, 16};
+  if (nc <= 256) return family == 0 ? WaveCfg{16, 16} : WaveCfg{8, 32};
+  if (nc <= 512) return WaveCfg{16, 32};
+  return WaveCfg{0, 0};
+}
+bool mass_wave_supported(int N) { return mass_cfg(0, N).C != 0 && mass_cfg(1, N).C != 0; }
+
+template <int C, int G, int FAM>
+static hipError_t launch_mass_t(const WaveArgs& a) {
+  using L = MassLds<C, G, FAM>;
+  static_assert(L::bytes <= 160 * 1024, "mass-solve LDS beyond the work-group limit");
+  constexpr int SPW = 64 / (2 * G);
+  static const bool attr = set_dynamic_lds((const void*)mass_wave_pipe<C, G, FAM>, L::bytes);
+  (void)attr;
+  const int64_t groups = (a.nsys + SPW - 1) / SPW;
+  const int64_t blocks = persistent_blocks((const void*)mass_wave_pipe<C, G, FAM>, (groups + L::WPB - 1) / L::WPB,
+                                           64 * L::WPB, L::bytes);
+  hipLaunchKernelGGL((mass_wave_pipe<C, G, FAM>), dim3((unsigned)blocks), dim3(64 * L::WPB), L::bytes, (hipStream_t)a.stream,
+                     a.N, a.nsys, (const double2*)a.f, (double2*)a.u, a.gl);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass_wave(const WaveArgs& a) {
+  if (a.nsys <= 0) return hipSuccess;
+  const WaveCfg c = mass_cfg(a.family, a.N);
+#define SHEN_MASS(CC, GG) \
+  if (c.C == CC && c.G == GG) return a.family == 0 ? launch_mass_t<CC, GG, 0>(a) : launch_mass_t<CC, GG, 1>(a);
+  SHEN_MASS(8, 16)
+  SHEN_MASS(16, 16)
+  SHEN_MASS(8, 32)
+  SHEN_MASS(16, 32)
+#undef SHEN_MASS
   return hipErrorInvalidValue;
 }
 

@@ -212,3 +212,90 @@ def bih_chunked(a, b, f, N, C, G, gl=False):
                 aa, bb, cq, cs = ui, aa, cq + q4[i] * bb, cs + s4[i] * bb
         u[:, ks] = out[:, :nc]
     return u
+
+
+def mass_chunked(family, f, N, C, G, gl=False):
+    """u = B^{-1} f (Dirichlet or biharmonic mass matrix) by the chunked scheme of the
+    mass-solve kernels: one shared LU per parity chain (no pivoting), then per chunk
+    the forward and backward recurrences of bandwidth s = 1 or 2 as affine maps on
+    the s-vector state, combined by Kogge-Stone scans, and each chunk rerun from its
+    scanned incoming state."""
+    from oracle import shen_oracle as so
+    quad = so.GL if gl else so.GC
+    B = so.mass_matrix(family, N, quad)
+    n = B.shape[0]
+    s = 1 if family == "helmholtz" else 2
+    ns = f.shape[0]
+    u = np.zeros((ns, N), complex)
+    for p in (0, 1):
+        ks = np.arange(p, n, 2)
+        nc = ks.size
+        assert nc <= C * G
+        M = B[np.ix_(ks, ks)]
+        # banded LU without pivoting: lo[i, t] = L_{i, i-1-t}, up[i, t] = U_{i, i+1+t}
+        lo = np.zeros((C * G, s))
+        up = np.zeros((C * G, s))
+        rd = np.ones(C * G)
+        Uf = M.copy()
+        for i in range(nc):
+            # eliminate row i by rows i-s .. i-1 (in order)
+            for r in range(max(0, i - s), i):
+                lo[i, i - 1 - r] = Uf[i, r] / Uf[r, r]
+                Uf[i, r:r + s + 1] -= lo[i, i - 1 - r] * Uf[r, r:r + s + 1]
+            rd[i] = 1.0 / Uf[i, i]
+            for t in range(s):
+                if i + 1 + t < nc:
+                    up[i, t] = Uf[i, i + 1 + t]
+        x = np.zeros((ns, C * G), complex)
+        x[:, :nc] = f[:, ks]
+
+        # forward: y_i = x_i - sum_t lo[i, t] y_{i-1-t}; chunk map on (y_{i-1}, ..., y_{i-s})
+        def fwd_map(m):
+            rows = range(m * C, m * C + C)
+            A = np.eye(s)
+            c = np.zeros((ns, s), complex)
+            for i in rows:
+                comp = np.zeros((s, s))
+                comp[0, :] = -lo[i]
+                comp[1:, :-1] = np.eye(s)[:-1, :-1] if s > 1 else comp[1:, :-1]
+                A = comp @ A
+                c = c @ comp.T
+                c[:, 0] += x[:, i]
+            return A, c
+
+        items = [fwd_map(m) for m in range(G)]
+        comp_f = lambda b, a: (b[0] @ a[0], a[1] @ b[0].T + b[1])
+        inc = ks_prefix(items, comp_f, G)
+        y = np.zeros_like(x)
+        for m in range(G):
+            st = inc[m - 1][1] if m > 0 else np.zeros((ns, s), complex)
+            for i in range(m * C, m * C + C):
+                v = x[:, i] - sum(lo[i, t] * st[:, t] for t in range(s))
+                y[:, i] = v
+                st = np.concatenate([v[:, None], st[:, :-1]], axis=1)
+        # backward: u_i = rd_i (y_i - sum_t up[i, t] u_{i+1+t}); chunk map on (u_{i+1}, ..., u_{i+s})
+        def bwd_map(m):
+            A = np.eye(s)
+            c = np.zeros((ns, s), complex)
+            for i in range(m * C + C - 1, m * C - 1, -1):
+                comp = np.zeros((s, s))
+                comp[0, :] = -rd[i] * up[i]
+                if s > 1:
+                    comp[1, 0] = 1.0
+                A = comp @ A
+                c = c @ comp.T
+                c[:, 0] += rd[i] * y[:, i]
+            return A, c
+
+        items = [bwd_map(m) for m in range(G)]
+        comp_b = lambda lo_, hi: (lo_[0] @ hi[0], hi[1] @ lo_[0].T + lo_[1])
+        inc = ks_suffix(items, comp_b, G)
+        out = np.zeros_like(x)
+        for m in range(G):
+            st = inc[m + 1][1] if m + 1 < G else np.zeros((ns, s), complex)
+            for i in range(m * C + C - 1, m * C - 1, -1):
+                v = rd[i] * (y[:, i] - sum(up[i, t] * st[:, t] for t in range(s)))
+                out[:, i] = v
+                st = np.concatenate([v[:, None], st[:, :-1]], axis=1)
+        u[:, ks] = out[:, :nc]
+    return u

@@ -141,3 +141,26 @@ def test_adjoint_factored_argument_errors():
     assert lib.biharmonic_adjoint_factored(16, 4, A, A, A + (1 << 16), None, A, A, A + 8, None, C.byref(o)) == L.SHEN_EINVAL
     o.variant = 1
     assert lib.biharmonic_adjoint_factored(16, 4, A, A, A + (1 << 16), None, A, A, None, None, C.byref(o)) == L.SHEN_ENOTSUP
+
+
+@pytest.mark.parametrize("fam", ["dirichlet_mass_solve", "biharmonic_mass_solve"])
+def test_mass_solve_argument_errors(fam):
+    lib = L.lib()
+    fn = getattr(lib, fam)
+    o = L.default_opts()
+    nmin = 3 if fam.startswith("dirichlet") else 5
+    assert fn(nmin - 1, 4, ALIGNED, ALIGNED + 4096, C.byref(o)) == L.SHEN_EINVAL        # N too small
+    assert fn(16, -1, ALIGNED, ALIGNED + 4096, C.byref(o)) == L.SHEN_EINVAL             # nsys < 0
+    assert fn(16, 4, None, ALIGNED, C.byref(o)) == L.SHEN_EINVAL                        # NULL f
+    assert fn(16, 4, ALIGNED + 8, ALIGNED + 4096, C.byref(o)) == L.SHEN_EINVAL          # misaligned f
+    assert fn(16, 4, ALIGNED, ALIGNED + 16, C.byref(o)) == L.SHEN_EINVAL                # partial overlap
+    assert fn(1025, 4, ALIGNED, ALIGNED + (1 << 20), C.byref(o)) == L.SHEN_ENOTSUP      # beyond N = 1024
+    assert fn(16, 0, None, None, C.byref(o)) == L.SHEN_OK                               # empty batch
+    o32 = L.default_opts()
+    o32.precision = 1
+    assert fn(16, 4, ALIGNED, ALIGNED + 4096, C.byref(o32)) == L.SHEN_ENOTSUP           # FP64 only
+    oc = L.default_opts()
+    oc.variant = 1
+    assert fn(16, 4, ALIGNED, ALIGNED + 4096, C.byref(oc)) == L.SHEN_ENOTSUP            # no chain kernel
+    # in place is valid: with no device the call reaches the device query
+    assert fn(16, 4, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EDEVICE

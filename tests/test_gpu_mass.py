@@ -1,0 +1,84 @@
+"""GPU parity of the mass-matrix solves u = B^{-1} f (the last step of a forward Shen
+transform, Sec. 2) against the oracle, within the bar that the conditioning of B
+allows (mass_tol: 0.1 cond(B) eps relative to max |u|, floor 1e-13)."""
+import numpy as np
+import pytest
+
+from oracle import shen_oracle as so
+from paper_1701_03787_amd import workloads as wl
+from test_oracle_mass import mass_tol
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1701_03787_amd import _lib
+    _lib.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _fn(family):
+    from paper_1701_03787_amd import api
+    return api.dirichlet_mass_solve if family == "helmholtz" else api.biharmonic_mass_solve
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("quad", ["gc", "gl"])
+def test_mass_vs_oracle(dev, family, quad):
+    """Every configuration (8x16, 16x16 / 8x32, 16x32 lanes) with ragged system counts and
+    ragged chains, and garbage in the ignored tail of f."""
+    qo = so.GL if quad == "gl" else so.GC
+    for N in (5, 9, 40, 65, 130, 257, 300, 512, 513, 1000, 1024):
+        for nsys in (1, 13):
+            case(test="mass", family=family, N=N, nsys=nsys, quad=quad)
+            n = wl.n_unknowns(family, N)
+            f = wl.random_vector((nsys, N), (31, N, nsys))
+            f[:, n:] = 1.0e30  # must be ignored
+            ref = so.mass_solve(family, N, f, qo)
+            got = _fn(family)(T(f, dev), quad=quad).cpu().numpy()
+            assert np.all(got[:, n:] == 0), N
+            err = so.rel_err_per_system(got, ref).max()
+            assert err <= mass_tol(family, N, quad == "gl"), (N, nsys, err)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_mass_in_place_and_empty(dev, family):
+    for N in (64, 512, 1024):
+        case(test="mass_in_place", family=family, N=N)
+        f = T(wl.random_vector((5, N), (32, N)), dev)
+        u = _fn(family)(f)
+        g = f.clone()
+        v = _fn(family)(g, out=g)
+        assert v.data_ptr() == g.data_ptr()
+        assert torch.equal(u, g)
+    e = torch.empty((0, 64), dtype=torch.complex128, device=dev)
+    assert _fn(family)(e).shape == (0, 64)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_mass_full_size_sampled(dev, family):
+    """N = 512 on the 512x257 wavenumber grid (131,584 systems), the launch of bench.py;
+    sampled systems against the oracle."""
+    g = wl.config_grids(3)[0]
+    case(test="mass_full", family=family, N=g.N, nsys=g.nsys)
+    f = g.rhs(family)
+    u = _fn(family)(T(f, dev))
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(g.nsys, 48, replace=False))
+    rows[0], rows[-1] = 0, g.nsys - 1
+    got = u[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    ref = so.mass_solve(family, g.N, f[rows])
+    assert so.rel_err_per_system(got, ref).max() <= mass_tol(family, g.N)
+    assert torch.all(u[:, wl.n_unknowns(family, g.N):] == 0)
