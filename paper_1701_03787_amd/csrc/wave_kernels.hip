@@ -3209,8 +3209,6 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe
     const bool wok = w < nsys;
     double2 x[C];
     read_tile_rows<C, G>(tile, lane, n, wok, x);
-    const int64_t gn = g + stride;
-    if (gn < ngroups) prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, f, nullptr, 0);
     // forward: y_i = x_i - sum_t l_t y_{i-1-t}; state (y_{i-1}, .., y_{i-S})
     double2 st[S], sin[S];
 #pragma unroll
@@ -3282,8 +3280,14 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe
       st[0] = v;
       x[j] = v;
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    matvec_store<C, G, FAM>(N, n, lane, wok, u + (wok ? w : 0) * (int64_t)N, x);
+    // out through the tile as whole 64-row blocks, then the next group in
+    stage_tile<C, G>(tile, lane, x);
+    store_tile<C, G>(tile, lane, g, N, n, nsys, u);
+    const int64_t gn = g + stride;
+    if (gn < ngroups) {
+      prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, f, nullptr, 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
   }
 }
 
