@@ -2835,10 +2835,11 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
 // =========================================================================
 // Matrix-vector products H u in the wave layout (right-hand-side assembly and
 // residuals, Sec. 3): persistent kernels that stream each group's u into an
-// LDS tile, take it into registers, start the next group's tile, form H u
-// from each lane's chunk and its neighbours (helm_apply / bih_apply) and
-// store it after the end-of-group wait (so that the wait does not include
-// the stores' acknowledgement).  Rows k >= n are written as 0.
+// LDS tile, take it into registers, form H u from each lane's chunk and its
+// neighbours (helm_apply / bih_apply).  Helmholtz (several wavefronts per
+// SIMD) sends it out through the same tile as whole 64-row blocks before the
+// next group's tile comes in; the biharmonic kernel (one per SIMD) overlaps
+// the next tile with the product instead.  Rows k >= n are written as 0.
 // =========================================================================
 template <int C, int G>
 __device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n, bool wok, double2 (&x)[C]) {
@@ -2857,8 +2858,10 @@ __device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n
   }
 }
 
-template <int C, int G, int FAM>
-__device__ __forceinline__ void matvec_store(int N, int n, int lane, bool wok, double2* __restrict__ row, const double2 (&y)[C]) {
+// Stores a lane's chunk rows k < N of one system (zero for k >= n) straight
+// from registers.
+template <int C, int G>
+__device__ __forceinline__ void store_rows(int N, int n, int lane, bool wok, double2* __restrict__ row, const double2 (&y)[C]) {
   const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
   if (wok) {
 #pragma unroll
@@ -2900,14 +2903,15 @@ __global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double al, unused;
     read_coef2(coef, lane, al, unused);
+    helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = v; });
+    stage_tile<C, G>(tile, lane, y);
+    store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
     const int64_t gn = g + gridDim.x;
     if (gn < ngroups) {
       prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
       prefetch_coef2(coef, lane, sysc(gn, lane), alpha, alpha);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = v; });
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    matvec_store<C, G, 0>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
   }
 }
 
@@ -2950,6 +2954,9 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double a, b;
     read_coef2(coef, lane, a, b);
+    // one wavefront per SIMD here: the next group's tile is started before
+    // the product, and this group's rows are stored from registers after
+    // the end-of-group wait
     const int64_t gn = g + stride;
     if (gn < ngroups) {
       prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
@@ -2957,7 +2964,7 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
     }
     bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = v; });
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    matvec_store<C, G, 1>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
+    store_rows<C, G>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
   }
 }
 
