@@ -288,6 +288,22 @@ def measure_mass(dev, args, grid, data, host, rows):
         err = float(so.rel_err_per_system(got, ref).max())
         key = "dirichlet" if fam == "helmholtz" else "biharmonic"
         out[key] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err}
+        if fam == "biharmonic":
+            # Bbar fhat = Cbar uhat, uhat = these biharmonic-basis rows
+            for _ in range(max(1, args.warmup)):
+                api.dirichlet_derivative_solve(f, out=v)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                api.dirichlet_derivative_solve(f, out=v)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = nsys * (16 * (N - 4) + 16 * N)
+            ref = so.derivative_solve(N, host[fam][0][rows])
+            got = v[torch.from_numpy(rows).to(dev)].cpu().numpy()
+            out["derivative"] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+                                 "max_rel_err_sampled": float(so.rel_err_per_system(got, ref).max())}
         del v
     return out
 

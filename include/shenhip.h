@@ -228,6 +228,21 @@ int dirichlet_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128*
 int biharmonic_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts);
 
 /*
+ * Derivative projection fhat = Bbar^{-1} Cbar uhat for every system (Sec. 3,
+ * the last wall-normal system of a time step): uhat holds coefficients in the
+ * biharmonic basis, fhat receives the Dirichlet-basis Galerkin coefficients of
+ * du/dx.  Cbar_kj = (phichk_j', phibar_k)_sigma (appendix matrix table)
+ * couples Dirichlet row k to the biharmonic coefficients k-3, k-1, k+1.
+ *
+ * uhat, fhat: DEVICE arrays [nsys][N] of complex128, caller-owned, 16-byte
+ *   aligned; entries k >= N-4 of uhat are ignored, entries k >= N-2 of fhat
+ *   written as 0.  fhat may equal uhat (in place) but must not overlap it
+ *   otherwise.  N >= 5.
+ * opts, return codes and accuracy: as for dirichlet_mass_solve.
+ */
+int dirichlet_derivative_solve(int32_t N, int64_t nsys, const shen_c128* uhat, shen_c128* fhat, const shen_opts* opts);
+
+/*
  * One batch of independent problems (many grids of uneven N, both
  * families) in a single persistent launch.
  *

@@ -46,7 +46,8 @@ Systems solved (Sec. 3, Crank-Nicolson matrices divided by +-nu*dt/2):
 * biharmonic: (Qchk + a_w Achk + b_w Bchk) u = f
 
 Also: the mass-matrix solves u = Bbar^{-1} f and u = Bchk^{-1} f of the
-forward Shen transforms (Sec. 2).
+forward Shen transforms (Sec. 2), and the derivative projection
+Bbar fhat = Cbar uhat (Sec. 3).
 
 Inputs: N, per-system coefficients, complex f of shape [nsys, N] whose
 entries k >= n are ignored.  Output: complex u [nsys, N] with the tail zero.
@@ -335,6 +336,35 @@ def mass_solve(family: str, N: int, f: np.ndarray, quad: int = GC, refine: int =
         x = x + np.linalg.solve(B, r.astype(np.float64))
     u[:, :n] = x[:, :nsys].T + 1j * x[:, nsys:].T
     return u
+
+
+def derivative_matrix(N: int) -> np.ndarray:
+    """Cbar_kj = (phichk_j', phibar_k)_sigma, Dirichlet rows k < N-2 by biharmonic columns
+    j < N-4 (appendix matrix table): pi (k-2)(k+1)/k at j = k-3, -2 pi (k+1)^2/(k+2) at
+    j = k-1, pi (k+1) at j = k+1.  The same for GC and GL (the quadrature is exact for
+    these products)."""
+    nd, nb = N - 2, N - 4
+    C = np.zeros((nd, nb))
+    for k in range(nd):
+        if 0 <= k - 3 < nb:
+            C[k, k - 3] = PI * (k - 2) * (k + 1) / k
+        if 0 <= k - 1 < nb:
+            C[k, k - 1] = -2.0 * PI * (k + 1) ** 2 / (k + 2)
+        if k + 1 < nb:
+            C[k, k + 1] = PI * (k + 1)
+    return C
+
+
+def derivative_solve(N: int, uhat: np.ndarray, quad: int = GC) -> np.ndarray:
+    """fhat with Bbar fhat = Cbar uhat (Sec. 3, the last of the wall-normal systems):
+    the Dirichlet-basis Galerkin coefficients of du/dx for u = sum_j uhat_j phichk_j.
+    uhat: [nsys, N], entries k >= N-4 ignored; result [nsys, N], entries k >= N-2 zero."""
+    uhat = np.asarray(uhat, dtype=np.complex128)
+    nb = N - 4
+    rhs = np.zeros_like(uhat)
+    C = derivative_matrix(N)
+    rhs[:, :N - 2] = uhat[:, :nb] @ C.T
+    return mass_solve("helmholtz", N, rhs, quad)
 
 
 # ----------------------------------------------------------------------------

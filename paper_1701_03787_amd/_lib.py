@@ -78,6 +78,7 @@ SIGNATURES = [
     ("biharmonic_matvec", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("dirichlet_mass_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
     ("biharmonic_mass_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("dirichlet_derivative_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
     ("shen_batched_plan", C.c_int64, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),
     ("shen_batched_work_bytes", C.c_int64, [C.c_int32]),
     ("batched_solve", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, _VP, C.POINTER(ShenOpts)]),

@@ -239,6 +239,18 @@ def biharmonic_mass_solve(f, *, out=None, quad="gc"):
             "biharmonic_mass_solve")
     return u
 
+
+def dirichlet_derivative_solve(uhat, *, out=None, quad="gc"):
+    """fhat = Bbar^{-1} Cbar uhat per system: Dirichlet-basis coefficients of du/dx for u in the
+    biharmonic basis (Sec. 3); out may be uhat."""
+    uhat = _rows(uhat, "uhat")
+    N = uhat.shape[-1]
+    fhat = torch.empty_like(uhat) if out is None else _rows(out, "out")
+    o = _opts(uhat.device, quad=quad)
+    L.check(L.lib().dirichlet_derivative_solve(N, _nsys(uhat.shape[:-1]), uhat.data_ptr(), fhat.data_ptr(), C.byref(o)),
+            "dirichlet_derivative_solve")
+    return fhat
+
 def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, variant="auto", fac=None, chunk=0):
     """lambda = H^{-T} gbar and grad_alpha = -Re(lambda^H B u); returns (lambda, grad_alpha or None).
 

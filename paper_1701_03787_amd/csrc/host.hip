@@ -207,11 +207,11 @@ int adjoint_factored(int family, int32_t N, int64_t nsys, const double* c0, cons
 }
 
 // Mass-matrix solves u = B^{-1} f (wave kernels only; u may alias f).
-int mass_solve(int family, int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
+int mass_solve(int family, int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts, int deriv = 0) {
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ && !deriv ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
   if (o.precision != SHEN_FP64) return SHEN_ENOTSUP;
   if (o.variant == SHEN_VARIANT_CHAIN || !shen::mass_wave_supported(N)) return SHEN_ENOTSUP;
   if (nsys == 0) return SHEN_OK;
@@ -228,6 +228,7 @@ int mass_solve(int family, int32_t N, int64_t nsys, const shen_c128* f, shen_c12
   w.u = u;
   w.gl = o.quad == SHEN_QUAD_GL;
   w.stream = o.stream;
+  w.deriv = deriv;
   return shen::launch_mass_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
 }
 
@@ -565,6 +566,9 @@ int dirichlet_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128*
 }
 int biharmonic_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
   return mass_solve(SHEN_BIHARMONIC, N, nsys, f, u, opts);
+}
+int dirichlet_derivative_solve(int32_t N, int64_t nsys, const shen_c128* uhat, shen_c128* fhat, const shen_opts* opts) {
+  return mass_solve(SHEN_HELMHOLTZ, N, nsys, uhat, fhat, opts, 1);
 }
 
 int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* opts) {

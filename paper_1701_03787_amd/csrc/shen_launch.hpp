@@ -55,6 +55,8 @@ struct WaveArgs {
   // into fac; 2: only the wave solve, states from fac (u may alias f).
   void* fac = nullptr;
   int fac_mode = 0;
+  // mass solves (family 0 only): right-hand side Cbar f instead of f
+  int deriv = 0;
 };
 
 struct WaveCfg {

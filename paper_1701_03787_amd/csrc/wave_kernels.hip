@@ -3131,29 +3131,83 @@ __device__ __forceinline__ void mass_scan(int m, MassMap<S> mp, double2 (&sin)[S
   for (int i = 0; i < S; ++i) sin[i] = UP ? chain_hi<G, 1>(mp.c[i], m) : chain_lo<G, 1>(mp.c[i], m);
 }
 
-template <int C, int G, int FAM>
+// Rows of Cbar = (phichk_j', phibar_k)_sigma (appendix matrix table): Dirichlet
+// row k couples the biharmonic coefficients j = k-3, k-1, k+1 of the other
+// parity, with entries pi (k-2)(k+1)/k, -2 pi (k+1)^2/(k+2) and pi (k+1).
+// Tabulated per row k < RT (zero outside rows < N-2 and columns < N-4), in
+// three fields swizzled like the factor table.
+__device__ __forceinline__ void deriv_entries_fill(double* ct, int RT, int C, int N, int tid, int nthreads) {
+  const int nd = N - 2, nb = N - 4;
+  for (int k = tid; k < RT; k += nthreads) {
+    const int r = bih_tab_row(k, C);
+    const double K = (double)k;
+    const bool row = k < nd;
+    ct[0 * RT + r] = row && k >= 3 ? kPi * (K - 2.0) * (K + 1.0) / K : 0.0;
+    ct[1 * RT + r] = row && k >= 1 && k - 1 < nb ? -2.0 * kPi * (K + 1.0) * (K + 1.0) / (K + 2.0) : 0.0;
+    ct[2 * RT + r] = row && k + 1 < nb ? kPi * (K + 1.0) : 0.0;
+  }
+}
+
+// x_j = (Cbar uhat)_k for this lane's rows k = k0 + 2j, uhat read from the
+// group's tile at rows of the other parity (selected to zero outside 0 .. N-5,
+// so that whatever the ignored entries hold never enters).
+template <int C, int G>
+__device__ __forceinline__ void deriv_rows(const double2* T, const double* ct, int RT, int lane, int N, bool wok,
+                                           double2 (&x)[C]) {
+  using TL = Tile<C, G>;
+  const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+  const int k0 = 2 * m * C + p;
+  const int nb = N - 4;
+  auto U = [&](int j) {
+    const bool in = j >= 0 && j < nb;
+    const double2 v = T[TL::pos(sl, in ? j : 0)];  // rows past 2GC lie outside the tile
+    return in ? v : zero2();
+  };
+  double2 um3 = U(k0 - 3), um1 = U(k0 - 1);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    const int r = bih_tab_row(k, C);
+    const double2 up1 = U(k + 1);
+    const double c3 = ct[0 * RT + r], c1 = ct[1 * RT + r], cp = ct[2 * RT + r];
+    double2 v;
+    v.x = __builtin_fma(c3, um3.x, __builtin_fma(c1, um1.x, cp * up1.x));
+    v.y = __builtin_fma(c3, um3.y, __builtin_fma(c1, um1.y, cp * up1.y));
+    x[j] = wok ? v : zero2();
+    um3 = um1;
+    um1 = up1;
+  }
+}
+
+// Derivative right-hand side (OP = 1): the three entries of row k of Cbar,
+// at columns k-3, k-1, k+1, follow the factors in the table.
+template <int C, int G, int FAM, int OP = 0>
 struct MassLds {
   static constexpr int RT = 2 * G * C;
-  static constexpr size_t tab = (size_t)MassFields<FAM>::NF * RT * sizeof(double);
+  static constexpr int NT = MassFields<FAM>::NF + (OP ? 3 : 0);  // table fields
+  static constexpr size_t tab = (size_t)NT * RT * sizeof(double);
   static constexpr size_t tile = (size_t)C * 64 * sizeof(double2);
   // wavefronts per work group: eight tiles where they fit the 160 KiB, else four
   static constexpr int WPB = tab + 8 * tile <= 160 * 1024 ? 8 : 4;
   static constexpr size_t bytes = tab + WPB * tile;
 };
 
-template <int C, int G, int FAM>
-__global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe(int N, int64_t nsys, const double2* __restrict__ f,
-                                                      double2* __restrict__ u, int gl) {
+template <int C, int G, int FAM, int OP>
+__global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_pipe(int N, int64_t nsys,
+                                                                                     const double2* __restrict__ f,
+                                                                                     double2* __restrict__ u, int gl) {
+  static_assert(OP == 0 || FAM == 0, "the derivative right-hand side belongs to the Dirichlet solve");
   using TL = Tile<C, G>;
-  using L = MassLds<C, G, FAM>;
+  using L = MassLds<C, G, FAM, OP>;
   constexpr int SPW = TL::SPW;
   constexpr int S = MassFields<FAM>::S;
   constexpr int RT = L::RT;
   extern __shared__ double smem[];
   double* tab = smem;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2* tile = reinterpret_cast<double2*>(smem + MassFields<FAM>::NF * RT) + wv * (C * 64);
+  double2* tile = reinterpret_cast<double2*>(smem + L::NT * RT) + wv * (C * 64);
   mass_entries_fill<FAM>(tab, RT, C, N, gl, (int)threadIdx.x, (int)blockDim.x);
+  if constexpr (OP == 1) deriv_entries_fill(tab + MassFields<FAM>::NF * RT, RT, C, N, (int)threadIdx.x, (int)blockDim.x);
   __syncthreads();
   if (threadIdx.x < 2) mass_lu_chain<FAM>(tab, RT, C, (int)threadIdx.x);
   const int n = FAM == 0 ? N - 2 : N - 4;
@@ -3212,10 +3266,18 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe
     for (int t = 0; t < S; ++t) bw.A[t][b] = st[t];
   }
   for (; g < ngroups; g += stride) {
-    const int64_t w = g * SPW + lane / (2 * G);
+    // tile indices are re-derived every iteration from an opaque copy of the
+    // lane (hoisted out of the loop they would hold registers across it)
+    int ln = threadIdx.x & 63;
+    asm volatile("" : "+v"(ln));
+    ln &= 63;
+    const int64_t w = g * SPW + ln / (2 * G);
     const bool wok = w < nsys;
     double2 x[C];
-    read_tile_rows<C, G>(tile, lane, n, wok, x);
+    if constexpr (OP == 0)
+      read_tile_rows<C, G>(tile, ln, n, wok, x);
+    else
+      deriv_rows<C, G>(tile, tab + MassFields<FAM>::NF * RT, RT, ln, N, wok, x);
     // forward: y_i = x_i - sum_t l_t y_{i-1-t}; state (y_{i-1}, .., y_{i-S})
     double2 st[S], sin[S];
 #pragma unroll
@@ -3288,11 +3350,11 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM>::WPB)) void mass_wave_pipe
       x[j] = v;
     }
     // out through the tile as whole 64-row blocks, then the next group in
-    stage_tile<C, G>(tile, lane, x);
-    store_tile<C, G>(tile, lane, g, N, n, nsys, u);
+    stage_tile<C, G>(tile, ln, x);
+    store_tile<C, G>(tile, ln, g, N, n, nsys, u);
     const int64_t gn = g + stride;
     if (gn < ngroups) {
-      prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, f, nullptr, 0);
+      prefetch_tile<C, G, 0>(tile, ln, gn, N, nsys, f, nullptr, 0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
   }
@@ -3552,17 +3614,17 @@ static WaveCfg mass_cfg(int family, int N) {
 }
 bool mass_wave_supported(int N) { return mass_cfg(0, N).C != 0 && mass_cfg(1, N).C != 0; }
 
-template <int C, int G, int FAM>
+template <int C, int G, int FAM, int OP>
 static hipError_t launch_mass_t(const WaveArgs& a) {
-  using L = MassLds<C, G, FAM>;
+  using L = MassLds<C, G, FAM, OP>;
   static_assert(L::bytes <= 160 * 1024, "mass-solve LDS beyond the work-group limit");
   constexpr int SPW = 64 / (2 * G);
-  static const bool attr = set_dynamic_lds((const void*)mass_wave_pipe<C, G, FAM>, L::bytes);
+  static const bool attr = set_dynamic_lds((const void*)mass_wave_pipe<C, G, FAM, OP>, L::bytes);
   (void)attr;
   const int64_t groups = (a.nsys + SPW - 1) / SPW;
-  const int64_t blocks = persistent_blocks((const void*)mass_wave_pipe<C, G, FAM>, (groups + L::WPB - 1) / L::WPB,
+  const int64_t blocks = persistent_blocks((const void*)mass_wave_pipe<C, G, FAM, OP>, (groups + L::WPB - 1) / L::WPB,
                                            64 * L::WPB, L::bytes);
-  hipLaunchKernelGGL((mass_wave_pipe<C, G, FAM>), dim3((unsigned)blocks), dim3(64 * L::WPB), L::bytes, (hipStream_t)a.stream,
+  hipLaunchKernelGGL((mass_wave_pipe<C, G, FAM, OP>), dim3((unsigned)blocks), dim3(64 * L::WPB), L::bytes, (hipStream_t)a.stream,
                      a.N, a.nsys, (const double2*)a.f, (double2*)a.u, a.gl);
   return hipGetLastError();
 }
@@ -3571,7 +3633,8 @@ hipError_t launch_mass_wave(const WaveArgs& a) {
   if (a.nsys <= 0) return hipSuccess;
   const WaveCfg c = mass_cfg(a.family, a.N);
 #define SHEN_MASS(CC, GG) \
-  if (c.C == CC && c.G == GG) return a.family == 0 ? launch_mass_t<CC, GG, 0>(a) : launch_mass_t<CC, GG, 1>(a);
+  if (c.C == CC && c.G == GG)                                                                              \
+    return a.family == 1 ? launch_mass_t<CC, GG, 1, 0>(a) : a.deriv ? launch_mass_t<CC, GG, 0, 1>(a) : launch_mass_t<CC, GG, 0, 0>(a);
   SHEN_MASS(8, 16)
   SHEN_MASS(16, 16)
   SHEN_MASS(8, 32)

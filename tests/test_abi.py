@@ -164,3 +164,14 @@ def test_mass_solve_argument_errors(fam):
     assert fn(16, 4, ALIGNED, ALIGNED + 4096, C.byref(oc)) == L.SHEN_ENOTSUP            # no chain kernel
     # in place is valid: with no device the call reaches the device query
     assert fn(16, 4, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EDEVICE
+
+
+def test_derivative_solve_argument_errors():
+    lib = L.lib()
+    o = L.default_opts()
+    fn = lib.dirichlet_derivative_solve
+    assert fn(4, 4, ALIGNED, ALIGNED + 4096, C.byref(o)) == L.SHEN_EINVAL              # N < 5
+    assert fn(16, 4, ALIGNED, ALIGNED + 16, C.byref(o)) == L.SHEN_EINVAL               # partial overlap
+    assert fn(1025, 4, ALIGNED, ALIGNED + (1 << 20), C.byref(o)) == L.SHEN_ENOTSUP     # beyond N = 1024
+    assert fn(16, 0, None, None, C.byref(o)) == L.SHEN_OK
+    assert fn(16, 4, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EDEVICE                  # in place reaches the device

@@ -82,3 +82,46 @@ def test_mass_full_size_sampled(dev, family):
     ref = so.mass_solve(family, g.N, f[rows])
     assert so.rel_err_per_system(got, ref).max() <= mass_tol(family, g.N)
     assert torch.all(u[:, wl.n_unknowns(family, g.N):] == 0)
+
+
+# --------------------------------------------------------- Bbar fhat = Cbar uhat
+
+def _deriv_tol(N, gl=False):
+    """The right-hand side Cbar uhat is formed in FP64 (three terms), then solved with Bbar:
+    the solve's bar, with room for the rounding of the product (entries growing like k)."""
+    return 10 * mass_tol("helmholtz", N, gl)
+
+
+@pytest.mark.parametrize("quad", ["gc", "gl"])
+def test_derivative_vs_oracle(dev, quad):
+    from paper_1701_03787_amd import api
+    qo = so.GL if quad == "gl" else so.GC
+    for N in (5, 8, 9, 40, 65, 257, 300, 512, 513, 1000, 1024):
+        for nsys in (1, 13):
+            case(test="derivative", N=N, nsys=nsys, quad=quad)
+            uhat = wl.random_vector((nsys, N), (33, N, nsys))
+            uhat[:, N - 4:] = 1.0e30  # must be ignored
+            ref = so.derivative_solve(N, uhat, qo)
+            got = api.dirichlet_derivative_solve(T(uhat, dev), quad=quad).cpu().numpy()
+            assert np.all(got[:, N - 2:] == 0), N
+            err = so.rel_err_per_system(got, ref).max()
+            assert err <= _deriv_tol(N, quad == "gl"), (N, nsys, err)
+
+
+def test_derivative_in_place_and_full_size(dev):
+    from paper_1701_03787_amd import api
+    for N in (64, 512, 1024):
+        case(test="derivative_in_place", N=N)
+        x = T(wl.random_vector((5, N), (34, N)), dev)
+        y = api.dirichlet_derivative_solve(x)
+        z = x.clone()
+        api.dirichlet_derivative_solve(z, out=z)
+        assert torch.equal(y, z)
+    g = wl.config_grids(3)[0]
+    case(test="derivative_full", N=g.N, nsys=g.nsys)
+    uhat = g.rhs("biharmonic")
+    f = api.dirichlet_derivative_solve(T(uhat, dev))
+    rows = np.sort(np.random.default_rng(6).choice(g.nsys, 48, replace=False))
+    got = f[torch.from_numpy(rows).to(dev)].cpu().numpy()
+    ref = so.derivative_solve(g.N, uhat[rows])
+    assert so.rel_err_per_system(got, ref).max() <= _deriv_tol(g.N)

@@ -116,3 +116,72 @@ def test_chunked_mass_scheme(family, N, C, G):
     ref = so.mass_solve(family, N, f)
     u = ca.mass_chunked(family, f, N, C, G)
     assert so.rel_err_per_system(u, ref).max() <= mass_tol(family, N)
+
+
+# --------------------------------------------------------------- Bbar fhat = Cbar uhat
+
+@pytest.mark.parametrize("N", [8, 9, 12, 17])
+@pytest.mark.parametrize("gl", [False, True])
+def test_derivative_matrix_exact(N, gl):
+    """Cbar_kj = (phichk_j', phibar_k)_sigma from exact rational algebra."""
+    ph_d = [cx.basis("dirichlet", k) for k in range(N - 2)]
+    dph_b = [cx.nderiv(cx.basis("biharmonic", j), 1) for j in range(N - 4)]
+    exact = np.array([[float(cx.inner_over_pi(dph_b[j], ph_d[k], N, gl)) for j in range(N - 4)]
+                      for k in range(N - 2)]) * np.pi
+    np.testing.assert_allclose(so.derivative_matrix(N), exact, rtol=1e-14, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [16, 33])
+@pytest.mark.parametrize("gl", [False, True])
+def test_derivative_projection_by_quadrature(N, gl):
+    """fhat solves Bbar fhat = ((u', phibar_k)_sigma)_k, the scalar products formed by
+    quadrature of numpy.polynomial derivative values of u = sum_j uhat_j phichk_j."""
+    rng = np.random.default_rng(11 * N + gl)
+    nb, nd = N - 4, N - 2
+    x, w = _quad(N, gl)
+    Phi_d = np.array([Ch.chebval(x, np.array([float(v) for v in cx.basis("dirichlet", k)])) for k in range(nd)])
+    dPhi_b = np.array([Ch.chebval(x, Ch.chebder(np.array([float(v) for v in cx.basis("biharmonic", j)])))
+                       for j in range(nb)])
+    uhat = np.zeros((2, N), complex)
+    uhat[:, :nb] = rng.standard_normal((2, nb)) + 1j * rng.standard_normal((2, nb))
+    du = uhat[:, :nb] @ dPhi_b                      # u'(x_i)
+    S = np.zeros((2, N), complex)
+    S[:, :nd] = (du * w) @ Phi_d.T                  # (u', phibar_k)_sigma
+    ref = so.mass_solve("helmholtz", N, S, so.GL if gl else so.GC)
+    got = so.derivative_solve(N, uhat, so.GL if gl else so.GC)
+    assert np.all(got[:, nd:] == 0)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_derivative_of_a_dirichlet_function_is_reproduced():
+    """u = (1 - x^2)^2 q(x) lies in the biharmonic space, and u' vanishes at both walls, so u'
+    lies in the Dirichlet space and its Galerkin projection is u' itself: fhat must be the
+    Dirichlet coefficients of u'."""
+    N = 24
+    q = np.array([0.3, -0.2, 0.5])                       # power series of q
+    u_pow = np.polynomial.polynomial.polymul(np.polynomial.polynomial.polypow([1.0, 0.0, -1.0], 2), q)
+    du_pow = np.polynomial.polynomial.polyder(u_pow)
+    u_ch = np.polynomial.chebyshev.poly2cheb(u_pow)
+    du_ch = np.polynomial.chebyshev.poly2cheb(du_pow)
+    nb, nd = N - 4, N - 2
+    # coefficients in the two bases by least squares on the Chebyshev coefficients (exact here)
+    Bb = np.zeros((N, nb))
+    for j in range(nb):
+        c = np.array([float(v) for v in cx.basis("biharmonic", j)])
+        Bb[:c.size, j] = c
+    Bd = np.zeros((N, nd))
+    for k in range(nd):
+        c = np.array([float(v) for v in cx.basis("dirichlet", k)])
+        Bd[:c.size, k] = c
+    tgt = np.zeros(N)
+    tgt[:u_ch.size] = u_ch
+    uh = np.linalg.lstsq(Bb, tgt, rcond=None)[0]
+    assert np.allclose(Bb @ uh, tgt, atol=1e-13)
+    tgt_d = np.zeros(N)
+    tgt_d[:du_ch.size] = du_ch
+    fd = np.linalg.lstsq(Bd, tgt_d, rcond=None)[0]
+    assert np.allclose(Bd @ fd, tgt_d, atol=1e-13)
+    uhat = np.zeros((1, N), complex)
+    uhat[0, :nb] = uh
+    got = so.derivative_solve(N, uhat)
+    np.testing.assert_allclose(got[0, :nd].real, fd, atol=1e-12)
