@@ -125,3 +125,41 @@ def test_derivative_in_place_and_full_size(dev):
     got = f[torch.from_numpy(rows).to(dev)].cpu().numpy()
     ref = so.derivative_solve(g.N, uhat[rows])
     assert so.rel_err_per_system(got, ref).max() <= _deriv_tol(g.N)
+
+
+def test_transform_kernels_in_a_graph(dev):
+    """The mass solves, the derivative projection and the matvec enqueue only kernels on the
+    caller's stream (no memset, no allocation with out=), so they can be captured in a hipGraph:
+    three replays, with eager work and synchronisations between them, each equal bit for bit to
+    the eager result."""
+    from paper_1701_03787_amd import api
+    N, nsys = 512, 37
+    f = T(wl.random_vector((nsys, N), (35,)), dev)
+    uh = T(wl.random_vector((nsys, N), (36,)), dev)
+    al = T(np.linspace(1.0, 1e4, nsys), dev)
+    outs = [torch.empty_like(f) for _ in range(4)]
+
+    def work():
+        api.dirichlet_mass_solve(f, out=outs[0])
+        api.biharmonic_mass_solve(f, out=outs[1])
+        api.dirichlet_derivative_solve(uh, out=outs[2])
+        api.helmholtz_matvec(f, al, out=outs[3])
+
+    case(test="graph", N=N, nsys=nsys)
+    work()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        work()
+    for r in range(3):
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, ref):
+            assert torch.equal(o, e), r
+        junk = api.biharmonic_mass_solve(uh)  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
