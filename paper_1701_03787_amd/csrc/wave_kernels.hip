@@ -3221,18 +3221,39 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
   if (g >= ngroups) return;
   const int p = (lane / G) & 1, m = lane % G;
   const int k0 = 2 * m * C + p;
-  // this lane's factors, and the homogeneous parts of its chunk maps
-  double lf[S][C], rd[C], uf[S][C];
+  // This lane's factors stay in registers for the whole loop where they are
+  // few enough; otherwise (the pentadiagonal factors of 16-row chunks) every
+  // sweep reads them from the table, which keeps the kernel at two
+  // wavefronts per SIMD without spills.
+  constexpr bool kRegF = MassFields<FAM>::NF * C <= 48;
+  constexpr int CR = kRegF ? C : 1;
+  double lf[S][CR], rd[CR], uf[S][CR];
+  if constexpr (kRegF) {
 #pragma unroll
-  for (int j = 0; j < C; ++j) {
-    const int r = bih_tab_row(k0 + 2 * j, C);
+    for (int j = 0; j < C; ++j) {
+      const int r = bih_tab_row(k0 + 2 * j, C);
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      lf[t][j] = tab[t * RT + r];
-      uf[t][j] = tab[(S + 1 + t) * RT + r];
+      for (int t = 0; t < S; ++t) {
+        lf[t][j] = tab[t * RT + r];
+        uf[t][j] = tab[(S + 1 + t) * RT + r];
+      }
+      rd[j] = tab[S * RT + r];
     }
-    rd[j] = tab[S * RT + r];
   }
+  // factor accessors for the lane whose first row is kb
+  auto LF = [&](int kb, int t, int j) -> double {
+    if constexpr (kRegF) return lf[t][j];
+    else return tab[t * RT + bih_tab_row(kb + 2 * j, C)];
+  };
+  auto UF = [&](int kb, int t, int j) -> double {
+    if constexpr (kRegF) return uf[t][j];
+    else return tab[(S + 1 + t) * RT + bih_tab_row(kb + 2 * j, C)];
+  };
+  auto RD = [&](int kb, int j) -> double {
+    if constexpr (kRegF) return rd[j];
+    else return tab[S * RT + bih_tab_row(kb + 2 * j, C)];
+  };
+  // the homogeneous parts of this lane's chunk maps
   MassMap<S> fw, bw;  // A parts: state of the last (first) rows from the incoming state
 #pragma unroll
   for (int b = 0; b < S; ++b) {
@@ -3243,7 +3264,7 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
     for (int j = 0; j < C; ++j) {
       double y = 0.0;
 #pragma unroll
-      for (int t = 0; t < S; ++t) y = __builtin_fma(-lf[t][j], st[t], y);
+      for (int t = 0; t < S; ++t) y = __builtin_fma(-LF(k0, t, j), st[t], y);
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
       st[0] = y;
@@ -3256,8 +3277,8 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
     for (int j = C - 1; j >= 0; --j) {
       double v = 0.0;
 #pragma unroll
-      for (int t = 0; t < S; ++t) v = __builtin_fma(-uf[t][j], st[t], v);
-      v *= rd[j];
+      for (int t = 0; t < S; ++t) v = __builtin_fma(-UF(k0, t, j), st[t], v);
+      v *= RD(k0, j);
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
       st[0] = v;
@@ -3273,6 +3294,12 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
     ln &= 63;
     const int64_t w = g * SPW + ln / (2 * G);
     const bool wok = w < nsys;
+    const int kl = 2 * (ln % G) * C + ((ln / G) & 1);
+    // without register-resident factors, each sweep reads its own (no value
+    // is kept live from one sweep to the next)
+    auto sweep_fence = [&]() {
+      if constexpr (!kRegF) asm volatile("" ::: "memory");
+    };
     double2 x[C];
     if constexpr (OP == 0)
       read_tile_rows<C, G>(tile, ln, n, wok, x);
@@ -3287,8 +3314,9 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
       double2 y = x[j];
 #pragma unroll
       for (int t = 0; t < S; ++t) {
-        y.x = __builtin_fma(-lf[t][j], st[t].x, y.x);
-        y.y = __builtin_fma(-lf[t][j], st[t].y, y.y);
+        const double l = LF(kl, t, j);
+        y.x = __builtin_fma(-l, st[t].x, y.x);
+        y.y = __builtin_fma(-l, st[t].y, y.y);
       }
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
@@ -3297,6 +3325,7 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
 #pragma unroll
     for (int t = 0; t < S; ++t) fw.c[t] = st[t];
     mass_scan<G, S, false>(m, fw, sin);
+    sweep_fence();
 #pragma unroll
     for (int t = 0; t < S; ++t) st[t] = sin[t];
 #pragma unroll
@@ -3304,14 +3333,16 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
       double2 y = x[j];
 #pragma unroll
       for (int t = 0; t < S; ++t) {
-        y.x = __builtin_fma(-lf[t][j], st[t].x, y.x);
-        y.y = __builtin_fma(-lf[t][j], st[t].y, y.y);
+        const double l = LF(kl, t, j);
+        y.x = __builtin_fma(-l, st[t].x, y.x);
+        y.y = __builtin_fma(-l, st[t].y, y.y);
       }
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
       st[0] = y;
       x[j] = y;
     }
+    sweep_fence();
     // backward: u_i = (y_i - sum_t U_t u_{i+1+t}) / U0; state (u_{i+1}, .., u_{i+S})
 #pragma unroll
     for (int t = 0; t < S; ++t) st[t] = zero2();
@@ -3320,11 +3351,13 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
       double2 v = x[j];
 #pragma unroll
       for (int t = 0; t < S; ++t) {
-        v.x = __builtin_fma(-uf[t][j], st[t].x, v.x);
-        v.y = __builtin_fma(-uf[t][j], st[t].y, v.y);
+        const double uu = UF(kl, t, j);
+        v.x = __builtin_fma(-uu, st[t].x, v.x);
+        v.y = __builtin_fma(-uu, st[t].y, v.y);
       }
-      v.x *= rd[j];
-      v.y *= rd[j];
+      const double r = RD(kl, j);
+      v.x *= r;
+      v.y *= r;
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
       st[0] = v;
@@ -3332,6 +3365,7 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
 #pragma unroll
     for (int t = 0; t < S; ++t) bw.c[t] = st[t];
     mass_scan<G, S, true>(m, bw, sin);
+    sweep_fence();
 #pragma unroll
     for (int t = 0; t < S; ++t) st[t] = sin[t];
 #pragma unroll
@@ -3339,11 +3373,13 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
       double2 v = x[j];
 #pragma unroll
       for (int t = 0; t < S; ++t) {
-        v.x = __builtin_fma(-uf[t][j], st[t].x, v.x);
-        v.y = __builtin_fma(-uf[t][j], st[t].y, v.y);
+        const double uu = UF(kl, t, j);
+        v.x = __builtin_fma(-uu, st[t].x, v.x);
+        v.y = __builtin_fma(-uu, st[t].y, v.y);
       }
-      v.x *= rd[j];
-      v.y *= rd[j];
+      const double r = RD(kl, j);
+      v.x *= r;
+      v.y *= r;
 #pragma unroll
       for (int t = S - 1; t > 0; --t) st[t] = st[t - 1];
       st[0] = v;
@@ -3601,14 +3637,12 @@ hipError_t launch_matvec_wave(const WaveArgs& a) {
   return hipErrorInvalidValue;
 }
 
-// Mass-matrix solves: the configuration by family and N (the tile layout
-// needs G >= 16 lanes per chain and C >= 8 rows per chunk; the pentadiagonal
-// factors of 16-row chunks spill at two wavefronts per SIMD, so the
-// biharmonic family takes 8-row chunks up to N = 512); C = 0 beyond N = 1024.
+// Mass-matrix solves: the configuration by N (the tile layout needs G >= 16
+// lanes per chain and C >= 8 rows per chunk); C = 0 beyond N = 1024.
 static WaveCfg mass_cfg(int family, int N) {
   const int nc = (N + 1) / 2;
   if (nc <= 128) return WaveCfg{8, 16};
-  if (nc <= 256) return family == 0 ? WaveCfg{16, 16} : WaveCfg{8, 32};
+  if (nc <= 256) return WaveCfg{16, 16};
   if (nc <= 512) return WaveCfg{16, 32};
   return WaveCfg{0, 0};
 }
