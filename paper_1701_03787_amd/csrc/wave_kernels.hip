@@ -1970,6 +1970,9 @@ __device__ __forceinline__ void bih_apply(int N, int lane, double a, double b, i
     c = c2;
     c2 = c4;
     c4 = c6;
+    // keep each row's table reads in its own step: hoisted ahead for all rows
+    // they would hold some 11 registers per row
+    asm volatile("" ::: "memory");
   }
 }
 
