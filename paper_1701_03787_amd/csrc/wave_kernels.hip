@@ -2839,10 +2839,9 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
 // Matrix-vector products H u in the wave layout (right-hand-side assembly and
 // residuals, Sec. 3): persistent kernels that stream each group's u into an
 // LDS tile, take it into registers, form H u from each lane's chunk and its
-// neighbours (helm_apply / bih_apply).  Helmholtz (several wavefronts per
-// SIMD) sends it out through the same tile as whole 64-row blocks before the
-// next group's tile comes in; the biharmonic kernel (one per SIMD) overlaps
-// the next tile with the product instead.  Rows k >= n are written as 0.
+// neighbours (helm_apply / bih_apply), and send it out through the same tile
+// as whole 64-row blocks before the next group's tile comes in.  Rows
+// k >= n are written as 0.
 // =========================================================================
 template <int C, int G>
 __device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n, bool wok, double2 (&x)[C]) {
@@ -2858,20 +2857,6 @@ __device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n
               r[1], r[2], r[3]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) x[j + q] = (wok && k0 + 2 * (j + q) < n) ? make_double2(r[q].x, r[q].y) : zero2();
-  }
-}
-
-// Stores a lane's chunk rows k < N of one system (zero for k >= n) straight
-// from registers.
-template <int C, int G>
-__device__ __forceinline__ void store_rows(int N, int n, int lane, bool wok, double2* __restrict__ row, const double2 (&y)[C]) {
-  const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
-  if (wok) {
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = k0 + 2 * j;
-      if (k < N) row[k] = (k < n) ? y[j] : zero2();
-    }
   }
 }
 
@@ -2957,17 +2942,15 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double a, b;
     read_coef2(coef, lane, a, b);
-    // one wavefront per SIMD here: the next group's tile is started before
-    // the product, and this group's rows are stored from registers after
-    // the end-of-group wait
+    bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = v; });
+    stage_tile<C, G>(tile, lane, y);
+    store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
     const int64_t gn = g + stride;
     if (gn < ngroups) {
       prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
       prefetch_coef2(coef, lane, sysc(gn, lane), ca, cb);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = v; });
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    store_rows<C, G>(N, n, lane, wok, hu + (wok ? w : 0) * (int64_t)N, y);
   }
 }
 
@@ -3603,16 +3586,9 @@ static hipError_t launch_matvec_t(const WaveArgs& a) {
   }
 }
 
-// Configuration of the wave-layout matvec for (family, N).  The biharmonic
-// band product of a 16-row chunk does not fit the register file (it spills),
-// so that family takes 8-row chunks wherever G <= 32 lanes cover the chain;
-// Helmholtz takes the configuration of its solve.
+// Configuration of the wave-layout matvec for (family, N): that of the solve.
 static WaveCfg matvec_cfg(int family, int N) {
   const int nc = (N + 1) / 2;
-  if (family == 1) {
-    for (int G = 16; G <= 32; G *= 2)
-      if (8 * G >= nc && 20 * G <= 2 * N) return WaveCfg{8, G};
-  }
   return pick_cfg(nc, family, N, 0);
 }
 
