@@ -35,12 +35,16 @@
  * per-device table of device properties filled on first use.
  *
  * Errors: argument errors return a negative SHEN_E* code before anything is
- * enqueued.  Numerical failures never return an error code; when
- * opts->info is non-NULL the kernels write one int32 per system: 0 = ok,
- * k+1 = a zero or non-finite pivot first met at row k (the system is
- * singular for the unpivoted LU, or its inputs are not finite; u is then
- * unspecified), SHEN_INFO_REFINE_FALLBACK = the FP32 refinement did not
- * converge and the system was re-solved in FP64.
+ * enqueued (nsys must lie in [0, SHEN_MAX_NSYS]).  Numerical failures never
+ * return an error code; when opts->info is non-NULL the kernels write one
+ * int32 per system: 0 = ok, k+1 = an unusable pivot first met at row k (u is
+ * then unspecified), SHEN_INFO_REFINE_FALLBACK = the FP32 refinement did not
+ * converge and the system was re-solved in FP64.  The LU has no pivoting
+ * (Sec. 4), so a pivot is unusable when it is zero, not finite, or no larger
+ * than 2^-40 times |H_kk| plus the magnitudes of the subdiagonal entries of
+ * row k: a singular or numerically singular leading block (an alpha at minus
+ * a generalised eigenvalue of the leading rows of (S, B), say) or non-finite
+ * inputs.
  */
 #ifndef SHENHIP_H
 #define SHENHIP_H
@@ -51,11 +55,14 @@
 extern "C" {
 #endif
 
-#define SHENHIP_ABI_VERSION 1
+#define SHENHIP_ABI_VERSION 2
 
 typedef struct {
   double re, im;
 } shen_c128;
+
+/* largest nsys any entry point accepts */
+#define SHEN_MAX_NSYS ((int64_t)2147483646)
 
 /* return codes */
 #define SHEN_OK 0
@@ -84,15 +91,29 @@ typedef struct {
   int32_t precision;  /* SHEN_FP64 (default) or SHEN_FP32_REFINE             */
   int32_t transpose;  /* 0: H u = f; 1: H^T u = f (the adjoint system)       */
   int32_t quad;       /* SHEN_QUAD_GC (default) or SHEN_QUAD_GL              */
-  int32_t refine_max; /* FP32_REFINE: max corrections, <= 0 means 8          */
-  double refine_tol;  /* FP32_REFINE: stop at max|du| <= tol max|u|; <= 0
-                         means 1e-14.  Refinement also stops once a
-                         correction fails to halve (rounding floor).         */
+  int32_t refine_max; /* FP32_REFINE: corrections at most (<= 64); < 0 means
+                         8; 0 returns the uncorrected FP32 solution (no
+                         residual, no FP64 re-solve unless the FP32 result is
+                         not finite)                                          */
+  double refine_tol;  /* FP32_REFINE: converged at max|du| <= tol max|u|;
+                         <= 0 means 1e-14.  Refinement also stops once a
+                         correction fails to halve (the rounding floor,
+                         where corrections are noise of about the size of
+                         the error left): the system is then accepted if
+                         that correction is at most max(tol, 5e-13) max|u|,
+                         else re-solved in FP64.                              */
   int32_t* info;      /* optional DEVICE int32[nsys] status per system       */
   int32_t variant;    /* kernel choice: 0 = automatic (SHEN_VARIANT_*)       */
-  int32_t chunk;      /* wave kernels: preferred chunk length (coefficients
-                         per lane and parity chain, 8 or 16); 0 = automatic.
-                         A tuning knob: results agree to rounding.            */
+  int32_t chunk;      /* wave kernels of the solves, adjoints and factor
+                         calls: chunk length (coefficients per lane and
+                         parity chain); 0 = automatic.  Nonzero values must
+                         be offered for the family and N (8 or 16 for most
+                         N, 4 for Helmholtz N <= 64), else SHEN_EINVAL.  A
+                         tuning knob: results agree to rounding.  Ignored by
+                         the other entry points.                             */
+  int32_t* iters;     /* optional DEVICE int32[nsys]: FP32_REFINE solves
+                         write the number of corrections applied per system
+                         (0 .. refine_max); not written otherwise            */
 } shen_opts;
 
 /* kernel variants (opts.variant); 0 picks per N and mode */

@@ -392,6 +392,58 @@ def solve_grads(family: str, N: int, coeffs, f: np.ndarray, gu: np.ndarray, quad
 
 
 # ----------------------------------------------------------------------------
+# Singular coefficients (failure cases of the unpivoted LU of Sec. 4)
+# ----------------------------------------------------------------------------
+
+def chain_rows(k: int):
+    """Rows p, p+2, ..., k of the parity chain that ends at row k (p = k mod 2)."""
+    return np.arange(k % 2, k + 1, 2)
+
+
+def singular_coefficient(family: str, N: int, k: int, quad: int = GC, a: float = 0.0) -> float:
+    """A coefficient that makes the leading block of row k's parity chain singular.
+
+    Odd and even rows decouple (Sec. 4), so the leading block of the unpivoted LU up to
+    row k is singular exactly when the block of rows chain_rows(k) is.  Helmholtz: the
+    alpha with Sbar + alpha Bbar singular there, i.e. minus a generalised eigenvalue of
+    (Sbar, Bbar) restricted to those rows; biharmonic: the b with (Qchk + a Achk) + b Bchk
+    singular there.  The eigenvalue taken is the largest, whose eigenvector needs every
+    row of the block (the smooth modes are already resolved by shorter blocks).  It is
+    polished to the FP64 neighbour pair across which det changes sign (bisection on the
+    sign of det from pivoted LU), and the member with the smaller |det| is returned.
+    With k the last row of its chain this is a singular coefficient of the whole system.
+    """
+    op = Operators.get(N, quad)
+    if family == "helmholtz":
+        M0, M1 = op.Sd, op.Bd
+    else:
+        M0, M1 = op.Qb + a * op.Ab, op.Bb
+    idx = chain_rows(k)
+    A0 = M0[np.ix_(idx, idx)]
+    A1 = M1[np.ix_(idx, idx)]
+    lam = np.linalg.eigvals(np.linalg.solve(A1, A0))
+    lam = lam[np.abs(lam.imag) <= 1e-9 * np.abs(lam)].real
+    c = -float(np.max(lam))
+
+    def sgn(x):
+        return np.linalg.slogdet(A0 + x * A1)
+
+    lo, hi = c * (1 + 1e-8), c * (1 - 1e-8)
+    slo = sgn(lo)[0]
+    if sgn(hi)[0] == slo:
+        raise ValueError("no sign change of det around the eigenvalue")
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        if sgn(mid)[0] == slo:
+            lo = mid
+        else:
+            hi = mid
+    return lo if sgn(lo)[1] <= sgn(hi)[1] else hi
+
+
+# ----------------------------------------------------------------------------
 # Error metrics
 # ----------------------------------------------------------------------------
 

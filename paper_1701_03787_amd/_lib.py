@@ -36,6 +36,7 @@ class ShenOpts(C.Structure):
         ("info", C.c_void_p),
         ("variant", C.c_int32),
         ("chunk", C.c_int32),
+        ("iters", C.c_void_p),
     ]
 
 

@@ -23,7 +23,7 @@ def _stream_handle(device) -> int:
 
 
 def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8, refine_tol=1e-14,
-          variant="auto", chunk=0) -> L.ShenOpts:
+          variant="auto", chunk=0, iters=None) -> L.ShenOpts:
     o = L.default_opts()
     o.stream = _stream_handle(device)
     o.precision = _PREC[precision]
@@ -34,6 +34,7 @@ def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refin
     o.info = info.data_ptr() if info is not None else None
     o.variant = _VARIANT[variant] if isinstance(variant, str) else int(variant)
     o.chunk = int(chunk)
+    o.iters = iters.data_ptr() if iters is not None else None
     return o
 
 
@@ -49,6 +50,29 @@ def _rows(x: torch.Tensor, name: str) -> torch.Tensor:
     return x
 
 
+def _out(out, like: torch.Tensor, name: str = "out") -> torch.Tensor:
+    """A fresh result like `like`, or the caller's tensor after checking it matches."""
+    if out is None:
+        return torch.empty_like(like)
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.complex128:
+        raise TypeError(f"{name} must be a complex128 tensor")
+    if tuple(out.shape) != tuple(like.shape):
+        raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(like.shape)}")
+    if out.device != like.device:
+        raise ValueError(f"{name} must be on {like.device}")
+    return _rows(out, name)
+
+
+def _like(x, ref: torch.Tensor, name: str) -> torch.Tensor:
+    """An input that must match ref's shape and device (complex128, contiguous)."""
+    x = _rows(x, name)
+    if x.device != ref.device:
+        raise ValueError(f"{name} must be on {ref.device}")
+    if tuple(x.shape) != tuple(ref.shape):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(ref.shape)}")
+    return x
+
+
 def _coef(c: torch.Tensor, lead, device, name: str) -> torch.Tensor:
     if not isinstance(c, torch.Tensor) or c.dtype != torch.float64:
         raise TypeError(f"{name} must be a float64 tensor")
@@ -61,14 +85,14 @@ def _coef(c: torch.Tensor, lead, device, name: str) -> torch.Tensor:
     return c
 
 
-def _info_tensor(want, lead, device):
+def _info_tensor(want, lead, device, name="info"):
     if want is None or want is False:
         return None
     if isinstance(want, torch.Tensor):
         if want.dtype != torch.int32 or tuple(want.shape) != tuple(lead) or not want.is_contiguous() or want.device != device:
-            raise ValueError("info must be a contiguous int32 tensor of the batch shape on the same device")
+            raise ValueError(f"{name} must be a contiguous int32 tensor of the batch shape on the same device")
         return want
-    return torch.empty(lead, dtype=torch.int32, device=device)
+    return torch.zeros(lead, dtype=torch.int32, device=device)
 
 
 def _nsys(lead) -> int:
@@ -78,37 +102,49 @@ def _nsys(lead) -> int:
     return n
 
 
+def _result(u, inf, its):
+    out = (u,)
+    if inf is not None:
+        out += (inf,)
+    if its is not None:
+        out += (its,)
+    return out if len(out) > 1 else u
+
+
 def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                    refine_tol=1e-14, variant="auto", chunk=0):
+                    refine_tol=1e-14, variant="auto", chunk=0, iters=None):
     """u = (S + alpha B)^{-1} f per system (or the transposed system).
 
-    Returns u, or (u, info) when info is requested (True or an int32 tensor)."""
+    Returns u, then info and iters when requested (True or an int32 tensor of the batch
+    shape): info per system, and for precision="fp32_refine" the corrections applied."""
     f = _rows(f, "f")
     N = f.shape[-1]
     lead = f.shape[:-1]
     alpha = _coef(alpha, lead, f.device, "alpha")
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk)
+    its = _info_tensor(iters, lead, f.device, "iters")
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its)
     L.check(L.lib().helmholtz_solve(N, _nsys(lead), alpha.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "helmholtz_solve")
-    return (u, inf) if inf is not None else u
+    return _result(u, inf, its)
 
 
 def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                     refine_tol=1e-14, variant="auto", chunk=0):
-    """u = (Q + a A + b B)^{-1} f per system (or the transposed system)."""
+                     refine_tol=1e-14, variant="auto", chunk=0, iters=None):
+    """u = (Q + a A + b B)^{-1} f per system (or the transposed system); returns as helmholtz_solve."""
     f = _rows(f, "f")
     N = f.shape[-1]
     lead = f.shape[:-1]
     a = _coef(a, lead, f.device, "a")
     b = _coef(b, lead, f.device, "b")
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk)
+    its = _info_tensor(iters, lead, f.device, "iters")
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its)
     L.check(L.lib().biharmonic_solve(N, _nsys(lead), a.data_ptr(), b.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "biharmonic_solve")
-    return (u, inf) if inf is not None else u
+    return _result(u, inf, its)
 
 
 def factor_bytes(family, N, *, chunk=0):
@@ -122,21 +158,52 @@ def factor_bytes(family, N, *, chunk=0):
     return int(nb)
 
 
+class ShenFactor:
+    """The factor-once state of one batch (helmholtz_factor / biharmonic_factor) with the
+    configuration it was made for: family, N, quadrature and chunk length.  The factored
+    calls take these from it and refuse a factor of another configuration, whose restart
+    states would sit at other chunk boundaries or belong to other matrices."""
+
+    def __init__(self, data: torch.Tensor, family: str, N: int, quad: str, chunk: int):
+        self.data = data
+        self.family = family
+        self.N = int(N)
+        self.quad = quad
+        self.chunk = int(chunk)
+
+    @property
+    def shape(self):
+        return self.data.shape
+
+    def data_ptr(self) -> int:
+        return self.data.data_ptr()
+
+
 def _fac_tensor(family, N, lead, device, chunk):
     nb = factor_bytes(family, N, chunk=chunk)
     return torch.empty(tuple(lead) + (nb // 8,), dtype=torch.float64, device=device)
 
 
-def _check_fac(fac, family, N, lead, device, chunk):
+def _check_fac(fac, family, N, lead, device, quad=None, chunk=None):
+    """fac's state tensor after checking that it was made for this call; returns (data, quad, chunk)."""
+    if not isinstance(fac, ShenFactor):
+        raise ValueError("fac must be the ShenFactor returned by helmholtz_factor / biharmonic_factor")
+    quad = fac.quad if quad is None else quad
+    chunk = fac.chunk if chunk is None else int(chunk)
+    want = (family, int(N), quad, chunk)
+    have = (fac.family, fac.N, fac.quad, fac.chunk)
+    if want != have:
+        raise ValueError(f"fac was made for (family, N, quad, chunk) = {have}, this call is {want}")
     nb = factor_bytes(family, N, chunk=chunk)
-    if (not isinstance(fac, torch.Tensor) or fac.dtype != torch.float64 or fac.device != device
-            or tuple(fac.shape) != tuple(lead) + (nb // 8,) or not fac.is_contiguous()):
-        raise ValueError(f"fac must be a contiguous float64 tensor of shape {tuple(lead) + (nb // 8,)} on {device}")
-    return fac
+    d = fac.data
+    if (not isinstance(d, torch.Tensor) or d.dtype != torch.float64 or d.device != device
+            or tuple(d.shape) != tuple(lead) + (nb // 8,) or not d.is_contiguous()):
+        raise ValueError(f"fac must hold a contiguous float64 tensor of shape {tuple(lead) + (nb // 8,)} on {device}")
+    return d, quad, chunk
 
 
 def helmholtz_factor(alpha, N, *, quad="gc", chunk=0):
-    """Factor-once: the LU restart states of (S + alpha B) for every system."""
+    """Factor-once: the LU restart states of (S + alpha B) for every system (a ShenFactor)."""
     if not isinstance(alpha, torch.Tensor) or not alpha.is_cuda:
         raise ValueError("alpha must be a float64 tensor on a HIP device (no CPU path)")
     lead = alpha.shape
@@ -144,11 +211,11 @@ def helmholtz_factor(alpha, N, *, quad="gc", chunk=0):
     fac = _fac_tensor("helmholtz", N, lead, alpha.device, chunk)
     o = _opts(alpha.device, quad=quad, chunk=chunk)
     L.check(L.lib().helmholtz_factor(int(N), _nsys(lead), alpha.data_ptr(), fac.data_ptr(), C.byref(o)), "helmholtz_factor")
-    return fac
+    return ShenFactor(fac, "helmholtz", N, quad, chunk)
 
 
 def biharmonic_factor(a, b, N, *, quad="gc", chunk=0):
-    """Factor-once: the LU restart states of (Q + a A + b B) for every system."""
+    """Factor-once: the LU restart states of (Q + a A + b B) for every system (a ShenFactor)."""
     if not isinstance(a, torch.Tensor) or not a.is_cuda:
         raise ValueError("a must be a float64 tensor on a HIP device (no CPU path)")
     lead = a.shape
@@ -158,36 +225,38 @@ def biharmonic_factor(a, b, N, *, quad="gc", chunk=0):
     o = _opts(a.device, quad=quad, chunk=chunk)
     L.check(L.lib().biharmonic_factor(int(N), _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), C.byref(o)),
             "biharmonic_factor")
-    return fac
+    return ShenFactor(fac, "biharmonic", N, quad, chunk)
 
 
-def helmholtz_solve_factored(f, alpha, fac, *, out=None, quad="gc", info=None, chunk=0):
-    """u = (S + alpha B)^{-1} f from the states of helmholtz_factor (same alpha, quad, chunk)."""
+def helmholtz_solve_factored(f, alpha, fac, *, out=None, quad=None, info=None, chunk=None):
+    """u = (S + alpha B)^{-1} f from the states of helmholtz_factor (same alpha; quad and chunk
+    are the factor's, and must match it when given)."""
     f = _rows(f, "f")
     N = f.shape[-1]
     lead = f.shape[:-1]
     alpha = _coef(alpha, lead, f.device, "alpha")
-    fac = _check_fac(fac, "helmholtz", N, lead, f.device, chunk)
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    facd, quad, chunk = _check_fac(fac, "helmholtz", N, lead, f.device, quad, chunk)
+    u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
     o = _opts(f.device, quad=quad, info=inf, chunk=chunk)
-    L.check(L.lib().helmholtz_solve_factored(N, _nsys(lead), alpha.data_ptr(), fac.data_ptr(), f.data_ptr(), u.data_ptr(),
+    L.check(L.lib().helmholtz_solve_factored(N, _nsys(lead), alpha.data_ptr(), facd.data_ptr(), f.data_ptr(), u.data_ptr(),
                                              C.byref(o)), "helmholtz_solve_factored")
     return (u, inf) if inf is not None else u
 
 
-def biharmonic_solve_factored(f, a, b, fac, *, out=None, quad="gc", info=None, chunk=0):
-    """u = (Q + a A + b B)^{-1} f from the states of biharmonic_factor (same a, b, quad, chunk)."""
+def biharmonic_solve_factored(f, a, b, fac, *, out=None, quad=None, info=None, chunk=None):
+    """u = (Q + a A + b B)^{-1} f from the states of biharmonic_factor (same a, b; quad and
+    chunk are the factor's)."""
     f = _rows(f, "f")
     N = f.shape[-1]
     lead = f.shape[:-1]
     a = _coef(a, lead, f.device, "a")
     b = _coef(b, lead, f.device, "b")
-    fac = _check_fac(fac, "biharmonic", N, lead, f.device, chunk)
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    facd, quad, chunk = _check_fac(fac, "biharmonic", N, lead, f.device, quad, chunk)
+    u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
     o = _opts(f.device, quad=quad, info=inf, chunk=chunk)
-    L.check(L.lib().biharmonic_solve_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), f.data_ptr(),
+    L.check(L.lib().biharmonic_solve_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), facd.data_ptr(), f.data_ptr(),
                                               u.data_ptr(), C.byref(o)), "biharmonic_solve_factored")
     return (u, inf) if inf is not None else u
 
@@ -197,7 +266,7 @@ def helmholtz_matvec(u, alpha, *, out=None, quad="gc", transpose=False):
     N = u.shape[-1]
     lead = u.shape[:-1]
     alpha = _coef(alpha, lead, u.device, "alpha")
-    y = torch.empty_like(u) if out is None else _rows(out, "out")
+    y = _out(out, u)
     o = _opts(u.device, quad=quad, transpose=transpose)
     L.check(L.lib().helmholtz_matvec(N, _nsys(lead), alpha.data_ptr(), u.data_ptr(), y.data_ptr(), C.byref(o)),
             "helmholtz_matvec")
@@ -210,7 +279,7 @@ def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
     lead = u.shape[:-1]
     a = _coef(a, lead, u.device, "a")
     b = _coef(b, lead, u.device, "b")
-    y = torch.empty_like(u) if out is None else _rows(out, "out")
+    y = _out(out, u)
     o = _opts(u.device, quad=quad, transpose=transpose)
     L.check(L.lib().biharmonic_matvec(N, _nsys(lead), a.data_ptr(), b.data_ptr(), u.data_ptr(), y.data_ptr(), C.byref(o)),
             "biharmonic_matvec")
@@ -222,7 +291,7 @@ def dirichlet_mass_solve(f, *, out=None, quad="gc"):
     """u = Bbar^{-1} f per system, Bbar the Dirichlet-basis mass matrix (Sec. 2 transforms); out may be f."""
     f = _rows(f, "f")
     N = f.shape[-1]
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    u = _out(out, f)
     o = _opts(f.device, quad=quad)
     L.check(L.lib().dirichlet_mass_solve(N, _nsys(f.shape[:-1]), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "dirichlet_mass_solve")
@@ -233,7 +302,7 @@ def biharmonic_mass_solve(f, *, out=None, quad="gc"):
     """u = Bchk^{-1} f per system, Bchk the biharmonic-basis mass matrix (Sec. 2 transforms); out may be f."""
     f = _rows(f, "f")
     N = f.shape[-1]
-    u = torch.empty_like(f) if out is None else _rows(out, "out")
+    u = _out(out, f)
     o = _opts(f.device, quad=quad)
     L.check(L.lib().biharmonic_mass_solve(N, _nsys(f.shape[:-1]), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "biharmonic_mass_solve")
@@ -245,7 +314,7 @@ def dirichlet_derivative_solve(uhat, *, out=None, quad="gc"):
     biharmonic basis (Sec. 3); out may be uhat."""
     uhat = _rows(uhat, "uhat")
     N = uhat.shape[-1]
-    fhat = torch.empty_like(uhat) if out is None else _rows(out, "out")
+    fhat = _out(out, uhat)
     o = _opts(uhat.device, quad=quad)
     L.check(L.lib().dirichlet_derivative_solve(N, _nsys(uhat.shape[:-1]), uhat.data_ptr(), fhat.data_ptr(), C.byref(o)),
             "dirichlet_derivative_solve")
@@ -262,14 +331,14 @@ def helmholtz_adjoint(u, gbar, alpha, *, quad="gc", coef_grad=True, info=None, v
     lam = torch.empty_like(gbar)
     ga = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
     if coef_grad:
-        u = _rows(u, "u")
+        u = _like(u, gbar, "u")
     inf = _info_tensor(info, lead, gbar.device)
     o = _opts(gbar.device, quad=quad, info=inf, variant=variant, chunk=chunk)
     up = u.data_ptr() if coef_grad else None
     gp = ga.data_ptr() if ga is not None else None
     if fac is not None:
-        fac = _check_fac(fac, "helmholtz", N, lead, gbar.device, chunk)
-        L.check(L.lib().helmholtz_adjoint_factored(N, _nsys(lead), alpha.data_ptr(), fac.data_ptr(), up, gbar.data_ptr(),
+        facd, _, _ = _check_fac(fac, "helmholtz", N, lead, gbar.device, quad, chunk)
+        L.check(L.lib().helmholtz_adjoint_factored(N, _nsys(lead), alpha.data_ptr(), facd.data_ptr(), up, gbar.data_ptr(),
                                                    lam.data_ptr(), gp, C.byref(o)), "helmholtz_adjoint_factored")
     else:
         L.check(L.lib().helmholtz_adjoint(N, _nsys(lead), alpha.data_ptr(), up, gbar.data_ptr(), lam.data_ptr(), gp,
@@ -290,15 +359,15 @@ def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, v
     ga = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
     gb = torch.empty(lead, dtype=torch.float64, device=gbar.device) if coef_grad else None
     if coef_grad:
-        u = _rows(u, "u")
+        u = _like(u, gbar, "u")
     inf = _info_tensor(info, lead, gbar.device)
     o = _opts(gbar.device, quad=quad, info=inf, variant=variant, chunk=chunk)
     up = u.data_ptr() if coef_grad else None
     gap = ga.data_ptr() if ga is not None else None
     gbp = gb.data_ptr() if gb is not None else None
     if fac is not None:
-        fac = _check_fac(fac, "biharmonic", N, lead, gbar.device, chunk)
-        L.check(L.lib().biharmonic_adjoint_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), fac.data_ptr(), up,
+        facd, _, _ = _check_fac(fac, "biharmonic", N, lead, gbar.device, quad, chunk)
+        L.check(L.lib().biharmonic_adjoint_factored(N, _nsys(lead), a.data_ptr(), b.data_ptr(), facd.data_ptr(), up,
                                                     gbar.data_ptr(), lam.data_ptr(), gap, gbp, C.byref(o)),
                 "biharmonic_adjoint_factored")
     else:

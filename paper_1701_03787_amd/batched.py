@@ -38,16 +38,28 @@ class BatchedProblem:
     def __post_init__(self):
         if self.family not in ("helmholtz", "biharmonic"):
             raise ValueError(self.family)
-        if self.f.dtype != torch.complex128 or self.f.dim() != 2 or not self.f.is_contiguous() or not self.f.is_cuda:
+        f = self.f
+        if (not isinstance(f, torch.Tensor) or f.dtype != torch.complex128 or f.dim() != 2 or not f.is_contiguous()
+                or not f.is_cuda):
             raise ValueError("f must be a contiguous complex128 [nsys, N] device tensor")
         need = 1 if self.family == "helmholtz" else 2
         if len(self.coeffs) != need:
             raise ValueError(f"{self.family} needs {need} coefficient arrays")
         for c in self.coeffs:
-            if c.dtype != torch.float64 or tuple(c.shape) != (self.f.shape[0],) or not c.is_contiguous():
-                raise ValueError("coefficients must be contiguous float64 [nsys]")
+            if (not isinstance(c, torch.Tensor) or c.dtype != torch.float64 or tuple(c.shape) != (f.shape[0],)
+                    or not c.is_contiguous() or c.device != f.device):
+                raise ValueError(f"coefficients must be contiguous float64 [nsys] tensors on {f.device}")
         if self.u is None:
-            self.u = torch.empty_like(self.f)
+            self.u = torch.empty_like(f)
+        u = self.u
+        if (not isinstance(u, torch.Tensor) or u.dtype != torch.complex128 or tuple(u.shape) != tuple(f.shape)
+                or not u.is_contiguous() or u.device != f.device):
+            raise ValueError(f"u must be a contiguous complex128 tensor of shape {tuple(f.shape)} on {f.device}")
+        if self.info is not None:
+            i = self.info
+            if (not isinstance(i, torch.Tensor) or i.dtype != torch.int32 or tuple(i.shape) != (f.shape[0],)
+                    or not i.is_contiguous() or i.device != f.device):
+                raise ValueError(f"info must be a contiguous int32 [nsys] tensor on {f.device}")
 
     @property
     def N(self) -> int:
@@ -135,6 +147,8 @@ class BatchedSolver:
         if not problems:
             raise ValueError("empty batch")
         self.device = problems[0].f.device
+        if any(p.f.device != self.device for p in problems):
+            raise ValueError(f"every problem of a batch must be on {self.device}")
         # largest work first: better balance of the dynamic work queue
         self.problems = sorted(problems, key=lambda p: -p.N)
         self.quad = quad

@@ -82,7 +82,7 @@ __device__ __forceinline__ int helm_fwd64(double2* x, double2* fac, int p, int n
       g = __builtin_fma(-l, gp, h.hpp);
       y = c_fnms(l, yp, fk);
     }
-    if (bad_pivot(d) && bad == INT_MAX) bad = k;
+    if (bad_pivot(d, row_scale(h)) && bad == INT_MAX) bad = k;
     const double rd = 1.0 / d;
     fac[k] = make_double2(rd, g);
     x[k] = y;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_adjoint(int N, int64
         r = c_fnms(gp + h.hm, zp, r);
       }
       r = c_sub(r, Zacc);
-      if (bad_pivot(d) && bad == INT_MAX) bad = k;
+      if (bad_pivot(d, row_scale(h)) && bad == INT_MAX) bad = k;
       const double rd = 1.0 / d;
       const double2 z = c_mul(rd, r);
       x[k] = z;
@@ -355,9 +355,17 @@ __device__ __forceinline__ double helm_residual(const double2* fv, const double2
   return umax;
 }
 
+// every entry of one parity chain of x finite
+__device__ __forceinline__ bool finite_rows(const double2* x, int p, int n) {
+  bool ok = true;
+  for (int k = p; k < n; k += 2) ok = ok && isfinite(x[k].x) && isfinite(x[k].y);
+  return ok;
+}
+
 __global__ __launch_bounds__(kChainThreads) void helm_chain_mixed(int N, int64_t nsys, int S, int NP, const double* __restrict__ alpha,
                                                                    const double2* __restrict__ f, double2* __restrict__ u, int gl,
-                                                                   int32_t* __restrict__ info, int it_max, double tol) {
+                                                                   int32_t* __restrict__ info, int32_t* __restrict__ iters,
+                                                                   int it_max, double tol) {
   extern __shared__ double2 lds[];
   const int64_t w0 = (int64_t)blockIdx.x * S;
   const int Sb = (int)min((int64_t)S, nsys - w0);
@@ -383,7 +391,13 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_mixed(int N, int64_t
   // refinement (the two lanes of a system decide together)
   bool running = act, converged = false;
   double prev = 1e300;
-  for (int it = 0; it < it_max; ++it) {
+  int ncorr = 0;
+  if (it_max == 0) {  // the uncorrected FP32 solution, when finite
+    running = false;
+    const int fin = (act && finite_rows(uu, p, n)) ? 1 : 0;
+    converged = act && (fin & __shfl_xor(fin, 1)) != 0;
+  }
+  for (int it = 1; it <= it_max; ++it) {
     double umax = 0.0, dmax = 0.0;
     if (running) {
       umax = helm_residual(fv, uu, wk, p, n, N, gl, al);
@@ -394,18 +408,13 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_mixed(int N, int64_t
     umax = fmax(umax, __shfl_xor(umax, 1));
     dmax = fmax(dmax, __shfl_xor(dmax, 1));
     if (running) {
-      if (dmax <= tol * umax) {
-        running = false;
-        converged = true;
-      } else if (dmax > 0.5 * prev) {
-        running = false;
-        converged = dmax <= 1e-11 * umax;
-      }
-      prev = dmax;
+      ncorr = it;
+      refine_decide(it, it_max, dmax, umax, prev, tol, running, converged);
     }
     if (!__any(running)) break;
   }
   if (act && running) converged = false;
+  if (iters != nullptr && act && p == 0) iters[w0 + s] = ncorr;
   // FP64 fallback for systems that did not converge
   if (act && !converged) {
     double2* x = uu;
@@ -467,7 +476,7 @@ __device__ __forceinline__ int bih_fwd64(double2* x, double* fac, int NP, int p,
       Rr = __builtin_fma(-l1, m2.R, Rr);
       y = c_fnms(l1, y2, y);
     }
-    if (bad_pivot(t0) && bad == INT_MAX) bad = k;
+    if (bad_pivot(t0, row_scale(h)) && bad == INT_MAX) bad = k;
     const double rU0 = 1.0 / t0;
     fac[k] = rU0;
     fac[NP + k] = t2;
@@ -587,7 +596,7 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_adjoint(int N, int64_
       const double qk = R.p3, sk = ((double)k + 2.0) * ((double)k + 2.0) * R.p3;
       r = c_fnms(qk, SP, r);
       r = c_fnms(sk, SR, r);
-      if (bad_pivot(t0) && bad == INT_MAX) bad = k;
+      if (bad_pivot(t0, row_scale(h)) && bad == INT_MAX) bad = k;
       const double rU0 = 1.0 / t0;
       const double2 z = c_mul(rU0, r);
       x[k] = z;
@@ -855,8 +864,8 @@ __device__ __forceinline__ double bih_residual(const double2* fv, const double2*
 
 __global__ __launch_bounds__(kChainThreads) void bih_chain_mixed(int N, int64_t nsys, int S, int NP, const double* __restrict__ ca,
                                                                   const double* __restrict__ cb, const double2* __restrict__ f,
-                                                                  double2* __restrict__ u, int gl, int32_t* __restrict__ info, int it_max,
-                                                                  double tol) {
+                                                                  double2* __restrict__ u, int gl, int32_t* __restrict__ info,
+                                                                  int32_t* __restrict__ iters, int it_max, double tol) {
   extern __shared__ double2 lds[];
   const int64_t w0 = (int64_t)blockIdx.x * S;
   const int Sb = (int)min((int64_t)S, nsys - w0);
@@ -882,7 +891,13 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_mixed(int N, int64_t 
   }
   bool running = act, converged = false;
   double prev = 1e300;
-  for (int it = 0; it < it_max; ++it) {
+  int ncorr = 0;
+  if (it_max == 0) {  // the uncorrected FP32 solution, when finite
+    running = false;
+    const int fin = (act && finite_rows(uu, p, n)) ? 1 : 0;
+    converged = act && (fin & __shfl_xor(fin, 1)) != 0;
+  }
+  for (int it = 1; it <= it_max; ++it) {
     double umax = 0.0, dmax = 0.0;
     if (running) {
       umax = bih_residual(fv, uu, wk, p, n, N, gl, a, b);
@@ -892,18 +907,13 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_mixed(int N, int64_t 
     umax = fmax(umax, __shfl_xor(umax, 1));
     dmax = fmax(dmax, __shfl_xor(dmax, 1));
     if (running) {
-      if (dmax <= tol * umax) {
-        running = false;
-        converged = true;
-      } else if (dmax > 0.5 * prev) {
-        running = false;
-        converged = dmax <= 1e-11 * umax;
-      }
-      prev = dmax;
+      ncorr = it;
+      refine_decide(it, it_max, dmax, umax, prev, tol, running, converged);
     }
     if (!__any(running)) break;
   }
   if (act && running) converged = false;
+  if (iters != nullptr && act && p == 0) iters[w0 + s] = ncorr;
   if (act && !converged) {
     double2* x = uu;
     double* fac = reinterpret_cast<double*>(wk);
@@ -990,7 +1000,8 @@ hipError_t launch_chain(const ChainArgs& a) {
       hipLaunchKernelGGL(helm_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.trans);
       break;
     case ChainKind::HelmMixed:
-      hipLaunchKernelGGL(helm_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.info, a.it_max, a.tol);
+      hipLaunchKernelGGL(helm_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.info, a.iters, a.it_max,
+                         a.tol);
       break;
     case ChainKind::BihSolve:
       hipLaunchKernelGGL(bih_chain_solve, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.info);
@@ -1003,7 +1014,8 @@ hipError_t launch_chain(const ChainArgs& a) {
       hipLaunchKernelGGL(bih_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.trans);
       break;
     case ChainKind::BihMixed:
-      hipLaunchKernelGGL(bih_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.info, a.it_max, a.tol);
+      hipLaunchKernelGGL(bih_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.info, a.iters,
+                         a.it_max, a.tol);
       break;
   }
   return hipGetLastError();

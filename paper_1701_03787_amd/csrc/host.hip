@@ -45,7 +45,7 @@ shen_opts resolve(const shen_opts* o) {
   shen_opts r;
   shen_opts_default(&r);
   if (o) r = *o;
-  if (r.refine_max <= 0) r.refine_max = 8;
+  if (r.refine_max < 0) r.refine_max = 8;
   if (!(r.refine_tol > 0.0)) r.refine_tol = 1e-14;
   return r;
 }
@@ -56,10 +56,20 @@ int check_opts(const shen_opts& o) {
   if (o.transpose != 0 && o.transpose != 1) return SHEN_EINVAL;
   if (o.variant < 0 || o.variant > 2) return SHEN_EINVAL;
   if (o.info && !aligned(o.info, 4)) return SHEN_EINVAL;
+  if (o.iters && !aligned(o.iters, 4)) return SHEN_EINVAL;
   if (o.refine_max > 64) return SHEN_EINVAL;
   if (o.chunk < 0 || o.chunk > 64) return SHEN_EINVAL;
   return SHEN_OK;
 }
+
+// opts.chunk: 0, or a chunk length that a wave configuration of (family, N)
+// offers; anything else is refused rather than silently replaced.
+int check_chunk(const shen_opts& o, int family, int32_t N) {
+  return shen::wave_chunk_ok(family, N, o.chunk) ? SHEN_OK : SHEN_EINVAL;
+}
+
+// nsys beyond SHEN_MAX_NSYS is refused before anything is launched
+inline bool bad_nsys(int64_t nsys) { return nsys < 0 || nsys > SHEN_MAX_NSYS; }
 
 bool rows_overlap_partially(const void* a, const void* b, int64_t nsys, int32_t N) {
   if (a == b) return false;
@@ -130,7 +140,7 @@ int factored(int family, int32_t N, int64_t nsys, const double* c0, const double
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || bad_nsys(nsys) || check_chunk(o, family, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (!fac || !aligned(fac, 16) || check_coef(c0) || (family == SHEN_BIHARMONIC && check_coef(c1))) return SHEN_EINVAL;
   const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
@@ -168,7 +178,7 @@ int adjoint_factored(int family, int32_t N, int64_t nsys, const double* c0, cons
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || bad_nsys(nsys) || check_chunk(o, family, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (!fac || !aligned(fac, 16) || check_rows(gbar) || check_rows(lambda) || check_coef(c0) ||
       (family == SHEN_BIHARMONIC && check_coef(c1)))
@@ -211,7 +221,7 @@ int mass_solve(int family, int32_t N, int64_t nsys, const shen_c128* f, shen_c12
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < (family == SHEN_HELMHOLTZ && !deriv ? 3 : 5) || nsys < 0) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ && !deriv ? 3 : 5) || bad_nsys(nsys)) return SHEN_EINVAL;
   if (o.precision != SHEN_FP64) return SHEN_ENOTSUP;
   if (o.variant == SHEN_VARIANT_CHAIN || !shen::mass_wave_supported(N)) return SHEN_ENOTSUP;
   if (nsys == 0) return SHEN_OK;
@@ -275,7 +285,7 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (N < 3 || bad_nsys(nsys) || check_chunk(o, SHEN_HELMHOLTZ, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
@@ -293,12 +303,14 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
     w.f = f;
     w.u = u;
     w.info = o.info;
+    w.iters = w.mixed ? o.iters : nullptr;
     w.gl = o.quad == SHEN_QUAD_GL;
     w.chunk = o.chunk;
     w.stream = o.stream;
     return run_wave(w);
   }
   ChainArgs a;
+  a.iters = o.precision == SHEN_FP32_REFINE ? o.iters : nullptr;
   a.kind = o.transpose ? ChainKind::HelmAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::HelmMixed : ChainKind::HelmSolve);
   a.N = N;
   a.nsys = nsys;
@@ -318,7 +330,7 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (N < 5 || bad_nsys(nsys) || check_chunk(o, SHEN_BIHARMONIC, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
@@ -337,12 +349,14 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
     w.f = f;
     w.u = u;
     w.info = o.info;
+    w.iters = w.mixed ? o.iters : nullptr;
     w.gl = o.quad == SHEN_QUAD_GL;
     w.chunk = o.chunk;
     w.stream = o.stream;
     return run_wave(w);
   }
   ChainArgs a;
+  a.iters = o.precision == SHEN_FP32_REFINE ? o.iters : nullptr;
   a.kind = o.transpose ? ChainKind::BihAdjoint : (o.precision == SHEN_FP32_REFINE ? ChainKind::BihMixed : ChainKind::BihSolve);
   a.N = N;
   a.nsys = nsys;
@@ -363,7 +377,7 @@ int helmholtz_adjoint(int32_t N, int64_t nsys, const double* alpha, const shen_c
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (N < 3 || bad_nsys(nsys) || check_chunk(o, SHEN_HELMHOLTZ, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(gbar) || check_rows(lambda) || check_coef(alpha)) return SHEN_EINVAL;
   if (grad_alpha && (check_rows(u) || !aligned(grad_alpha, 8))) return SHEN_EINVAL;
@@ -407,7 +421,7 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* ca, const double* 
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (N < 5 || bad_nsys(nsys) || check_chunk(o, SHEN_BIHARMONIC, N)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(gbar) || check_rows(lambda) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   const bool grads = grad_a || grad_b;
@@ -466,7 +480,7 @@ int64_t shen_factor_bytes(int32_t family, int32_t N, const shen_opts* opts) {
   const shen_opts o = resolve(opts);
   if (check_opts(o)) return SHEN_EINVAL;
   if (family != SHEN_HELMHOLTZ && family != SHEN_BIHARMONIC) return SHEN_EINVAL;
-  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || check_chunk(o, family, N)) return SHEN_EINVAL;
   const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
   return slot > 0 ? slot * 16 : SHEN_ENOTSUP;
 }
@@ -490,7 +504,7 @@ int helmholtz_matvec(int32_t N, int64_t nsys, const double* alpha, const shen_c1
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 3 || nsys < 0) return SHEN_EINVAL;
+  if (N < 3 || bad_nsys(nsys)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(u) || check_rows(Hu) || check_coef(alpha)) return SHEN_EINVAL;
   if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
@@ -527,7 +541,7 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* c
   const shen_opts o = resolve(opts);
   int rc = check_opts(o);
   if (rc) return rc;
-  if (N < 5 || nsys < 0) return SHEN_EINVAL;
+  if (N < 5 || bad_nsys(nsys)) return SHEN_EINVAL;
   if (nsys == 0) return SHEN_OK;
   if (check_rows(u) || check_rows(Hu) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (u == Hu || rows_overlap_partially(u, Hu, nsys, N)) return SHEN_EINVAL;
@@ -579,7 +593,7 @@ int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* op
   for (int32_t i = 0; i < ndesc; ++i) {
     shen_problem& d = desc[i];
     if (d.family != SHEN_HELMHOLTZ && d.family != SHEN_BIHARMONIC) return SHEN_EINVAL;
-    if (d.nsys < 0 || d.N < (d.family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
+    if (bad_nsys(d.nsys) || d.N < (d.family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
     if (d.nsys > 0) {
       if (check_rows(d.f) || check_rows(d.u) || check_coef(d.c0)) return SHEN_EINVAL;
       if (d.family == SHEN_BIHARMONIC && check_coef(d.c1)) return SHEN_EINVAL;

@@ -21,6 +21,7 @@ struct ChainArgs {
   double* g0 = nullptr;        // adjoint: grad alpha / grad a
   double* g1 = nullptr;        // adjoint: grad b
   int32_t* info = nullptr;
+  int32_t* iters = nullptr;  // mixed: corrections applied per system
   int gl = 0;
   int trans = 0;
   int it_max = 8;
@@ -38,6 +39,7 @@ struct WaveArgs {
   const void* f = nullptr;
   void* u = nullptr;  // must not alias f (restart states are parked in it)
   int32_t* info = nullptr;
+  int32_t* iters = nullptr;  // mixed: corrections applied per system
   int gl = 0;
   int chunk = 0;   // preferred chunk length C (0: automatic)
   int mixed = 0;   // FP32 factor/solve + FP64 refinement
@@ -64,6 +66,7 @@ struct WaveCfg {
 };
 __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
+bool wave_chunk_ok(int family, int N, int chunk);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
 hipError_t launch_wave(const WaveArgs& a);
 int64_t wave_state_slot(int family, int N, int chunk);

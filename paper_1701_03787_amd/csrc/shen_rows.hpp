@@ -234,6 +234,43 @@ __device__ __forceinline__ double c_abs1(double2 a) { return fmax(fabs(a.x), fab
 __device__ __forceinline__ double c_absf(float2 a) { return fmax(fabs((double)a.x), fabs((double)a.y)); }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
 
-__device__ __forceinline__ bool bad_pivot(double d) { return !(fabs(d) > 0.0) || !isfinite(d); }
+// A pivot is unusable when it is zero, not finite, or numerically zero: no
+// larger than 2^-40 times the magnitude of its row's entries left of and on
+// the diagonal (the unpivoted LU would then grow its factors by 2^40 or more,
+// far beyond the FP64 accuracy it is meant to deliver).  Scale: |H_kk| plus
+// the subdiagonal entries of row k.
+constexpr double kPivTiny = 0x1p-40;
+__device__ __forceinline__ bool bad_pivot(double d, double scale) { return !(fabs(d) > kPivTiny * scale) || !isfinite(d); }
+__device__ __forceinline__ double row_scale(const HelmRow& h) { return fabs(h.h0) + fabs(h.hm); }
+__device__ __forceinline__ double row_scale(const BihRow& h) { return fabs(h.h0) + fabs(h.hm2) + fabs(h.hm4); }
+
+// Stopping rule of the FP64-residual refinement, shared by every mixed
+// kernel.  After solve number `it` (0: the first FP32 solve, then one per
+// correction) with correction size dmax and iterate size umax:
+//  * a non-finite correction stops the iteration unconverged (FP64 re-solve);
+//  * it_max == 0 asks for the uncorrected FP32 solution: accepted as it is;
+//  * dmax <= tol umax: converged;
+//  * a correction that fails to halve marks the rounding floor, where the
+//    corrections are noise of about the size of the error left: accepted
+//    when it is at most max(tol, 5e-13) umax (inside the 1e-12 target), else
+//    unconverged (an ill-conditioned system whose floor lies higher);
+//  * otherwise the iteration goes on (the caller stops after it_max).
+constexpr double kStagTol = 5e-13;
+__device__ __forceinline__ void refine_decide(int it, int it_max, double dmax, double umax, double& prev, double tol,
+                                              bool& running, bool& conv) {
+  if (!(dmax <= 1e300)) {
+    running = false;
+  } else if (it_max == 0) {
+    running = false;
+    conv = true;
+  } else if (dmax <= tol * umax) {
+    running = false;
+    conv = true;
+  } else if (it > 0 && dmax > 0.5 * prev) {
+    running = false;
+    conv = dmax <= fmax(tol, kStagTol) * umax;
+  }
+  prev = dmax;
+}
 
 }  // namespace shen

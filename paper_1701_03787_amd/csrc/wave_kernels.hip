@@ -159,8 +159,9 @@ struct HelmPrev {
   double rd, g;  // 1/d and g of row k-2 (ignored for k < 2)
 };
 __device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const HelmPrev& pv, double& l, double& g, double& rd,
-                                          double& d) {
+                                          double& d, double& sc) {
   const HelmRow h = helm_row(k, al, N, gl);
+  sc = row_scale(h);
   if (k < 2) {
     l = 0.0;
     d = h.h0;
@@ -171,6 +172,11 @@ __device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const
     g = __builtin_fma(-l, pv.g, h.hpp);
   }
   rd = fast_rcp(d);
+}
+__device__ __forceinline__ void helm_step(int k, double al, int N, int gl, const HelmPrev& pv, double& l, double& g, double& rd,
+                                          double& d) {
+  double sc;
+  helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
 }
 
 // The same step in FP32 (mixed-precision form): entries formed in FP64,
@@ -202,7 +208,8 @@ struct BihRowState {
   double rU0, U2, U4, P, R;
 };
 __device__ __forceinline__ void bih_step_row(const BihRow& h, const BihRowState& m2, const BihRowState& m4, BihRowState& o,
-                                             double& l1, double& l2, double& t0out) {
+                                             double& l1, double& l2, double& t0out, double& sc) {
+  sc = row_scale(h);
   double tm2 = h.hm2, t0 = h.h0, t2 = h.hp2, t4 = h.hp4, P = h.p, Rr = h.r;
   l2 = h.hm4 * m4.rU0;
   tm2 = __builtin_fma(-l2, m4.U2, tm2);
@@ -224,9 +231,20 @@ __device__ __forceinline__ void bih_step_row(const BihRow& h, const BihRowState&
   o.R = Rr;
   t0out = t0;
 }
+__device__ __forceinline__ void bih_step_row(const BihRow& h, const BihRowState& m2, const BihRowState& m4, BihRowState& o,
+                                             double& l1, double& l2, double& t0out) {
+  double sc;
+  bih_step_row(h, m2, m4, o, l1, l2, t0out, sc);
+}
+__device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
+                                         const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out,
+                                         double& sc) {
+  bih_step_row(bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out, sc);
+}
 __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
                                          const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
-  bih_step_row(bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out);
+  double sc;
+  bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0out, sc);
 }
 
 // The same step in FP32 (mixed-precision form): row entries formed in FP64
@@ -647,9 +665,9 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
   for (int j = 0; j < C; ++j) {
     const int k = k0 + 2 * j;
     const bool ok = wok && k < n;
-    double l, g, rd, d;
-    helm_step(k, al, N, gl, pv, l, g, rd, d);
-    if (ok && bad_pivot(d) && bad == INT_MAX) bad = k;
+    double l, g, rd, d, sc;
+    helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
+    if (ok && bad_pivot(d, sc) && bad == INT_MAX) bad = k;
     pv.rd = rd;
     pv.g = g;
     l = ok ? l : 0.0;
@@ -834,9 +852,9 @@ __global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, con
   for (int j = 0; j < C; ++j) {
     const int k = k0 + 2 * j;
     const bool ok = wok && k < n;
-    double l, g, r, d;
-    helm_step(k, al, N, gl, pv, l, g, r, d);
-    if (ok && bad_pivot(d) && bad == INT_MAX) bad = k;
+    double l, g, r, d, sc;
+    helm_step(k, al, N, gl, pv, l, g, r, d, sc);
+    if (ok && bad_pivot(d, sc) && bad == INT_MAX) bad = k;
     pv.rd = r;
     pv.g = g;
     rdj[j] = ok ? r : 0.0;
@@ -1191,7 +1209,8 @@ __device__ __forceinline__ double sys_max(double v) {
 template <int C, int G>
 __global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const double* __restrict__ alpha,
                                                       const double2* __restrict__ f, double2* __restrict__ u, int gl,
-                                                      int32_t* __restrict__ info, int it_max, double tol) {
+                                                      int32_t* __restrict__ info, int32_t* __restrict__ iters, int it_max,
+                                                      double tol) {
   constexpr int SPW = 64 / (2 * G);
   __shared__ double2 st64[64];
   const int lane = threadIdx.x & 63;
@@ -1243,6 +1262,7 @@ __global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const
   bool running = wok && (sys_max<G>(finite32 ? 0.0 : 1.0) == 0.0);
   bool conv = false;
   double prev = 1e300;
+  int ncorr = 0;
   for (int it = 0; it <= it_max; ++it) {  // the first solve, then it_max corrections at most
     helm_solve32<C, G>(lane, wok, n, hm32, rd_in, rd, gg, x);
     double dmax = 0.0, umax = 0.0;
@@ -1255,16 +1275,8 @@ __global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const
     dmax = sys_max<G>(dmax);
     umax = sys_max<G>(umax);
     if (running) {
-      if (!(dmax <= 1e300)) {
-        running = false;  // non-finite: FP64 below
-      } else if (dmax <= tol * umax) {
-        running = false;
-        conv = true;
-      } else if (dmax > 0.5 * prev) {  // rounding floor reached
-        running = false;
-        conv = dmax <= 1e-11 * umax;
-      }
-      prev = dmax;
+      ncorr = it;
+      refine_decide(it, it_max, dmax, umax, prev, tol, running, conv);
     }
     if (!__any(running)) break;
     helm_residual<C, G>(N, lane, wok, al, gl, fx, ux, x);
@@ -1314,6 +1326,7 @@ __global__ __launch_bounds__(64) void helm_mixed_wave(int N, int64_t nsys, const
     for (int d = 1; d < 2 * G; d <<= 1) b = min(b, __shfl_xor(b, d, 2 * G));
     if (wok && (lane % (2 * G)) == 0) info[w] = failed ? (b == INT_MAX ? SHEN_INFO_REFINE_FALLBACK : b + 1) : 0;
   }
+  if (iters != nullptr && wok && (lane % (2 * G)) == 0) iters[w] = ncorr;
 }
 
 // =========================================================================
@@ -1410,18 +1423,18 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     const int k = k0 + 2 * j;
     const bool ok = wok && k < n;
     BihRowState o;
-    double l1, l2, t0;
+    double l1, l2, t0, sc;
     if constexpr (TAB) {
       const BihConst c = bih_tab_get(tab, RT, C, k);
-      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
+      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0, sc);
       cm4 = cm2;
       cm2 = c;
     } else {
       if (j > 0) Rc.advance(k);
-      bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
+      bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0, sc);
       q4j[TAB ? 0 : j] = Rc.p7;  // q_{k+4} = 1/(k+7)
     }
-    if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
+    if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
     m4 = m2;
     m2 = o;
     // Table rows past the system are identity rows (zero l, unit pivot, no
@@ -2068,8 +2081,8 @@ struct MixedTile {
 template <int C, int G>
 __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const double* __restrict__ ca,
                                                      const double* __restrict__ cb, const double2* __restrict__ f,
-                                                     double2* __restrict__ u, int gl, int32_t* __restrict__ info, int it_max,
-                                                     double tol) {
+                                                     double2* __restrict__ u, int gl, int32_t* __restrict__ info,
+                                                     int32_t* __restrict__ iters, int it_max, double tol) {
   constexpr int SPW = 64 / (2 * G);
   constexpr int RT = 2 * G * C;
   constexpr bool kTile = MixedTile<C, G>::value;
@@ -2157,6 +2170,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
   bool running = wok && (sys_max<G>(finite32 ? 0.0 : 1.0) == 0.0);
   bool conv = false;
   double prev = 1e300;
+  int ncorr = 0;
   for (int it = 0; it <= it_max; ++it) {  // the first solve, then it_max corrections at most
     bih_solve32<C, G>(lane, F, tab, x);
     double dmax = 0.0, umax = 0.0;
@@ -2169,16 +2183,8 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     dmax = sys_max<G>(dmax);
     umax = sys_max<G>(umax);
     if (running) {
-      if (!(dmax <= 1e300)) {
-        running = false;
-      } else if (dmax <= tol * umax) {
-        running = false;
-        conv = true;
-      } else if (dmax > 0.5 * prev) {
-        running = false;
-        conv = dmax <= 1e-11 * umax;
-      }
-      prev = dmax;
+      ncorr = it;
+      refine_decide(it, it_max, dmax, umax, prev, tol, running, conv);
     }
     if (!__any(running)) break;
     bih_residual<C, G>(N, lane, wok, a, b, gl, tab, fget, ux, x);
@@ -2226,6 +2232,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     for (int d = 1; d < 2 * G; d <<= 1) bq = min(bq, __shfl_xor(bq, d, 2 * G));
     if (wok && (lane % (2 * G)) == 0) info[w] = failed ? (bq == INT_MAX ? SHEN_INFO_REFINE_FALLBACK : bq + 1) : 0;
   }
+  if (iters != nullptr && wok && (lane % (2 * G)) == 0) iters[w] = ncorr;
 }
 
 // =========================================================================
@@ -2282,9 +2289,9 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
       const bool ok = wok && k < n;
       const BihConst c = bih_tab_get(tab, RT, C, k);
       BihRowState o;
-      double l1, l2, t0;
-      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
-      if (ok && bad_pivot(t0) && bad == INT_MAX) bad = k;
+      double l1, l2, t0, sc;
+      bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0, sc);
+      if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
       cm4 = cm2;
       cm2 = c;
       m4 = m2;
@@ -3405,6 +3412,14 @@ __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC) {
   return WaveCfg{0, 0};
 }
 
+// opts.chunk: 0 (automatic) or a chunk length some configuration of (family,
+// N) is built with
+bool wave_chunk_ok(int family, int N, int chunk) {
+  if (chunk == 0) return true;
+  const WaveCfg c = pick_cfg((N + 1) / 2, family, N, chunk);
+  return c.C == chunk;
+}
+
 bool wave_supported(int family, int N) {
   const int n = family == 0 ? N - 2 : N - 4;
   if (n < 1) return false;
@@ -3459,8 +3474,8 @@ static hipError_t launch_helm_t(const WaveArgs& a) {
     }
     if (a.mixed) {
       hipLaunchKernelGGL(helm_boundary32, dim3((unsigned)((2 * ns + 255) / 256)), dim3(256), 0, st, a.N, ns, C, G, c0, u, a.gl);
-      hipLaunchKernelGGL((helm_mixed_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info, a.it_max,
-                         a.tol);
+      hipLaunchKernelGGL((helm_mixed_wave<C, G>), dim3((unsigned)groups), dim3(64), 0, st, a.N, ns, c0, f, u, a.gl, info,
+                         a.iters ? a.iters + s0 : nullptr, a.it_max, a.tol);
       continue;
     }
     // restart states: parked in u (one call), or in the caller's slots (factor-once mode)
@@ -3520,7 +3535,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                          dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u,
                          (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
-                         c1, f, u, a.gl, info, a.it_max, a.tol);
+                         c1, f, u, a.gl, info, a.iters ? a.iters + s0 : nullptr, a.it_max, a.tol);
       continue;
     }
     static const bool attr = set_dynamic_lds((const void*)bih_wave_tab<C, G>, lds) &&
@@ -3668,7 +3683,6 @@ hipError_t launch_wave(const WaveArgs& a) {
   (void)n;
   const WaveCfg c = pick_cfg((a.N + 1) / 2, a.family, a.N, a.chunk);
   if (a.nsys <= 0) return hipSuccess;
-  if ((a.nsys + 1) > 0x7fffffffLL) return hipErrorInvalidValue;
 #define SHEN_DISPATCH(CC, GG)                                                         \
   if (c.C == CC && c.G == GG) return a.family == 0 ? launch_helm_t<CC, GG>(a) : launch_bih_t<CC, GG>(a);
   SHEN_DISPATCH(4, 8)

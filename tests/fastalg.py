@@ -275,8 +275,15 @@ def bih_matvec(a, b, u, N, gl=False):
 
 # --------------------------- mixed precision --------------------------------
 
+STAG_TOL = 5e-13  # rounding-floor acceptance bound of the kernels' refinement
+
+
 def refine_solve(family, coeffs, f, N, gl=False, tol=1e-14, it_max=8):
-    """u = solve32(f); repeat r = f - H u (FP64), u += solve32(r) until |du| <= tol |u|."""
+    """u = solve32(f); repeat r = f - H u (FP64), u += solve32(r), with the kernels' stopping
+    rule: converged at |du| <= tol |u|; a correction that fails to halve ends the iteration
+    (the rounding floor, where the corrections are noise of about the size of the error left)
+    and is accepted only when |du| <= max(tol, STAG_TOL) |u|; it_max corrections at most.
+    Returns (u, u0 = the uncorrected FP32 solution, corrections applied, converged)."""
     if family == "helmholtz":
         s32 = lambda rhs: helmholtz_solve(coeffs[0], rhs.astype(np.complex64), N, gl, np.float32).astype(np.complex128)
         mv = lambda uu: helm_matvec(coeffs[0], uu, N, gl)
@@ -287,9 +294,12 @@ def refine_solve(family, coeffs, f, N, gl=False, tol=1e-14, it_max=8):
     u = u0.copy()
     ns = f.shape[0]
     iters = np.zeros(ns, int)
+    conv = np.zeros(ns, bool)
     active = np.ones(ns, bool)
-    prev = np.max(np.abs(u0), axis=1)
-    for it in range(it_max):
+    prev = np.full(ns, 1e300)
+    if it_max == 0:
+        return u, u0, iters, np.all(np.isfinite(u0), axis=1)
+    for it in range(1, it_max + 1):
         if not active.any():
             break
         r = f - mv(u)
@@ -299,8 +309,12 @@ def refine_solve(family, coeffs, f, N, gl=False, tol=1e-14, it_max=8):
         iters += active
         dn = np.max(np.abs(du), axis=1)
         un = np.max(np.abs(u), axis=1)
-        # stop on convergence, or once the correction stops shrinking (residual noise floor)
-        done = (dn <= tol * un) | (dn > 0.5 * prev)
-        active &= ~done
-        prev = dn
-    return u, u0, iters
+        bad = ~(dn <= 1e300)
+        ok = dn <= tol * un
+        stag = ~bad & ~ok & (dn > 0.5 * prev)
+        floor = stag & (dn <= max(tol, STAG_TOL) * un)
+        conv |= active & (ok | floor)
+        act_before = active.copy()
+        active &= ~(bad | ok | stag)
+        prev = np.where(act_before, dn, prev)
+    return u, u0, iters, conv

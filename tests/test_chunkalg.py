@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import chunkalg as ca
+import fastalg as fa
 from oracle import shen_oracle as so
 from paper_1701_03787_amd import workloads as wl
 
@@ -34,3 +35,24 @@ def test_chunked_roundoff_protocol():
         assert e <= 1.5 * table[("biharmonic", z)][512], (z, e)
         e = roundoff_protocol(lambda fam, N, c, f: ca.helm_chunked(c[0], f, N, 16, 16), "helmholtz", 512, z, 4)
         assert e <= 4 * table[("helmholtz", z)][512], (z, e)
+
+
+def test_refinement_stagnation_is_not_accepted():
+    """The FP32-solve / FP64-residual refinement on a near-singular system (alpha 0.1% off a
+    singular coefficient, condition number about 1e8): the corrections stop halving while the
+    error is still above the 1e-12 target, so the stopping rule of the kernels must not accept
+    the result (it goes to the FP64 re-solve); regular systems of the same batch converge."""
+    N = 64
+    c = so.singular_coefficient("helmholtz", N, N - 3)
+    g = wl.small_grid(N, 4, kmax=64)
+    alpha = g.alpha().copy()
+    alpha[1] = c * (1 + 1e-3)
+    f = wl.random_vector((4, N), (3, 1))
+    f[:, N - 2:] = 0
+    u, u0, iters, conv = fa.refine_solve("helmholtz", (alpha,), f, N, it_max=8)
+    ref = so.solve("helmholtz", N, (alpha,), f)
+    e = so.rel_err_per_system(u, ref)
+    assert not conv[1] and iters[1] < 8, (conv, iters)  # stopped by stagnation, not by it_max
+    assert e[1] > 1e-12, e  # accepting it would have broken the target
+    ok = np.arange(4) != 1
+    assert conv[ok].all() and e[ok].max() <= 1e-12, (conv, e)

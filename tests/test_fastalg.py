@@ -68,11 +68,12 @@ def test_mixed_refinement(family, N):
     g = wl.small_grid(N, 8, kmax=256)
     coeffs = g.coefficients(family)
     f = g.rhs(family)
-    u, u0, iters = fa.refine_solve(family, coeffs, f, N)
+    u, u0, iters, conv = fa.refine_solve(family, coeffs, f, N)
     ref = so.solve(family, N, coeffs, f)
     e0 = so.rel_err_per_system(u0, ref).max()
     e = so.rel_err_per_system(u, ref).max()
     assert e < 1e-12, (e0, e, iters)
+    assert conv.all()
     assert iters.max() <= 6
 
 

@@ -128,8 +128,19 @@ def test_factored_rejects_mismatched_state(dev):
     g = wl.small_grid(64, 5)
     cs = [T(c, dev) for c in g.coefficients("biharmonic")]
     fac = api.biharmonic_factor(cs[0], cs[1], 64)
-    with pytest.raises(ValueError):
-        api.biharmonic_solve_factored(T(g.rhs("biharmonic"), dev), cs[0], cs[1], fac[:, :-1].contiguous())
+    f = T(g.rhs("biharmonic"), dev)
+    with pytest.raises(ValueError):  # a bare state tensor carries no configuration
+        api.biharmonic_solve_factored(f, cs[0], cs[1], fac.data)
+    with pytest.raises(ValueError):  # a truncated state
+        api.biharmonic_solve_factored(f, cs[0], cs[1], api.ShenFactor(fac.data[:, :-1].contiguous(), "biharmonic", 64,
+                                                                      "gc", 0))
+    with pytest.raises(ValueError):  # made for GC, asked for GL
+        api.biharmonic_solve_factored(f, cs[0], cs[1], fac, quad="gl")
+    with pytest.raises(ValueError):  # made with the automatic chunk, asked for another
+        api.biharmonic_solve_factored(f, cs[0], cs[1], fac, chunk=8)
+    fh = api.helmholtz_factor(cs[0], 64)
+    with pytest.raises(ValueError):  # another family
+        api.biharmonic_solve_factored(f, cs[0], cs[1], fh)
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])

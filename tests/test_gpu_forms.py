@@ -398,3 +398,97 @@ def test_gauss_lobatto_mixed_and_adjoint(dev, family, N):
     assert so.rel_err_per_system(lam.cpu().numpy(), lam_ref).max() <= TOL
     for gg, gr in zip(grads, grads_ref):
         np.testing.assert_allclose(gg.cpu().numpy(), gr, rtol=1e-10, atol=1e-300)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_mixed_precision_config3_full_size(dev, family):
+    """The headline FP32 + refinement launch: all 131,584 systems of N=512, 512x257 in one call
+    (the bench's launch), info == 0 and 1..refine_max corrections on every system, and sampled
+    rows (first, last, K2 = 0, the largest K2, random) against the oracle at the 1e-12 bar."""
+    from paper_1701_03787_amd import api
+    g = wl.config_grids(3)[0]
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    case(test="mixed_config3", family=family, nsys=g.nsys)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    u, info, its = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, iters=True)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    its = its.cpu().numpy()
+    print("info", np.unique(info, return_counts=True), "iters", np.bincount(its), flush=True)
+    assert np.all(info == 0)
+    assert its.min() >= 1 and its.max() <= 8
+    rng = np.random.default_rng([1701, 3, 11])
+    K2 = g.K2
+    rows = np.unique(np.concatenate([[0, g.nsys - 1, int(np.argmin(K2)), int(np.argmax(K2))],
+                                     rng.choice(g.nsys, 60, replace=False)]))
+    un = u.cpu().numpy()
+    ref = so.solve(family, g.N, tuple(c[rows] for c in cs), f[rows])
+    assert so.rel_err_per_system(un[rows], ref).max() <= TOL
+    assert np.all(un[:, wl.n_unknowns(family, g.N):] == 0)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+def test_mixed_unrefined_and_iteration_counts(dev, family, variant):
+    """refine_max = 0 returns the FP32 solution itself (no correction, no FP64 re-solve): its error
+    is that of FP32 arithmetic, far above the refined one; with refinement every system reports
+    the corrections it took, and the refined answer meets the 1e-12 bar."""
+    from paper_1701_03787_amd import api
+    N = 256
+    g = wl.small_grid(N, 40, kmax=256, index=9)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    case(test="mixed_unrefined", family=family, variant=variant)
+    ref = so.solve(family, N, cs, f)
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    ct = [T(c, dev) for c in cs]
+    u0, info0, it0 = fn(T(f, dev), *ct, precision="fp32_refine", refine_max=0, info=True, iters=True, variant=variant)
+    u, info, it = fn(T(f, dev), *ct, precision="fp32_refine", info=True, iters=True, variant=variant)
+    torch.cuda.synchronize()
+    e0 = so.rel_err_per_system(u0.cpu().numpy(), ref)
+    e = so.rel_err_per_system(u.cpu().numpy(), ref)
+    print("unrefined", e0.max(), "refined", e.max(), "iters", np.bincount(it.cpu().numpy()), flush=True)
+    assert np.all(info0.cpu().numpy() == 0) and np.all(it0.cpu().numpy() == 0)
+    assert 1e-9 <= e0.max() <= 1e-2
+    assert np.all(info.cpu().numpy() == 0)
+    assert e.max() <= TOL
+    itn = it.cpu().numpy()
+    assert itn.min() >= 1 and itn.max() <= 8
+
+
+def test_binding_refuses_mismatched_buffers(dev):
+    """Argument marshalling refuses buffers the kernels would overrun or could not reach: a short or
+    CPU-resident out, an adjoint u of another shape, batched coefficients / u / info of the wrong
+    dtype, shape or device, and one batch spread over two devices.  Nothing is launched."""
+    from paper_1701_03787_amd import api
+    from paper_1701_03787_amd.batched import BatchedProblem, BatchedSolver
+    g = wl.small_grid(64, 8)
+    f = T(g.rhs("biharmonic"), dev)
+    a, b = (T(c, dev) for c in g.coefficients("biharmonic"))
+    case(test="binding_checks")
+    for bad in (torch.empty((7, 64), dtype=torch.complex128, device=dev),
+                torch.empty((8, 64), dtype=torch.complex128)):
+        with pytest.raises(ValueError):
+            api.biharmonic_solve(f, a, b, out=bad)
+        with pytest.raises(ValueError):
+            api.biharmonic_matvec(f, a, b, out=bad)
+        with pytest.raises(ValueError):
+            api.biharmonic_mass_solve(f, out=bad)
+    with pytest.raises(ValueError):
+        api.biharmonic_adjoint(f[:4].contiguous(), f, a, b)
+    with pytest.raises(ValueError):
+        BatchedProblem("biharmonic", f, [a.cpu(), b])
+    with pytest.raises(ValueError):
+        BatchedProblem("biharmonic", f, [a, b], u=torch.empty((7, 64), dtype=torch.complex128, device=dev))
+    with pytest.raises(ValueError):
+        BatchedProblem("biharmonic", f, [a, b], u=torch.empty((8, 64), dtype=torch.complex64, device=dev))
+    with pytest.raises(ValueError):
+        BatchedProblem("biharmonic", f, [a, b], info=torch.empty((8,), dtype=torch.int64, device=dev))
+    with pytest.raises(ValueError):
+        BatchedProblem("biharmonic", f, [a, b], info=torch.empty((4,), dtype=torch.int32, device=dev))
+    p = BatchedProblem("biharmonic", f, [a, b])
+    q = BatchedProblem("biharmonic", f, [a, b])
+    q.f = torch.empty((8, 64), dtype=torch.complex128, device="meta")
+    with pytest.raises(ValueError):
+        BatchedSolver([p, q])

@@ -39,7 +39,7 @@ def gpu_solve(family, N, coeffs, f, dev, **kw):
         out = api.biharmonic_solve(ft, cs[0], cs[1], **kw)
     torch.cuda.synchronize()
     if isinstance(out, tuple):
-        return out[0].cpu().numpy(), out[1].cpu().numpy()
+        return tuple(x.cpu().numpy() for x in out)
     return out.cpu().numpy()
 
 
@@ -152,6 +152,63 @@ def test_info_codes(dev, family):
     assert so.rel_err_per_system(u[ok], ref).max() <= TOL
 
 
+def _singular_batch(family, N):
+    """Six regular channel systems, with system 2 made singular in the leading block of row 10's
+    chain (a mid-chain zero pivot) and system 4 singular as a whole (its last odd or even row);
+    the coefficients come from the oracle (minus a generalised eigenvalue, polished)."""
+    g = wl.small_grid(N, 6, kmax=64, index=41)
+    coeffs = [c.copy() for c in g.coefficients(family)]
+    n = wl.n_unknowns(family, N)
+    rows = {2: 10, 4: n - 1}
+    for w, k in rows.items():
+        if family == "helmholtz":
+            coeffs[0][w] = so.singular_coefficient(family, N, k)
+        else:
+            coeffs[0][w] = -1000.0 if w == 2 else 0.0
+            coeffs[1][w] = so.singular_coefficient(family, N, k, a=coeffs[0][w])
+    expect = np.zeros(6, np.int32)
+    for w, k in rows.items():
+        expect[w] = k + 1
+    return g, coeffs, g.rhs(family), expect
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+@pytest.mark.parametrize("variant", ["auto", "chain"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_info_singular(dev, family, variant, precision):
+    """A coefficient at minus a generalised eigenvalue (oracle): the unpivoted LU meets a
+    numerically zero pivot at the last row of the singular block; info reports that row + 1
+    (FP32 + refinement: after its FP64 re-solve), the kernel exits normally, and the regular
+    systems of the batch still match the oracle."""
+    N = 40
+    g, coeffs, f, expect = _singular_batch(family, N)
+    _print_case(test="info_singular", family=family, variant=variant, precision=precision)
+    u, info = gpu_solve(family, N, coeffs, f, dev, info=True, variant=variant, precision=precision)
+    assert np.array_equal(info, expect), (info, expect)
+    ok = expect == 0
+    ref = so.solve(family, N, tuple(c[ok] for c in coeffs), f[ok])
+    assert so.rel_err_per_system(u[ok], ref).max() <= TOL
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_info_singular_factored(dev, family):
+    """The same per-system status from the factor-once form (the pivots are re-derived from the
+    factor call's restart states)."""
+    from paper_1701_03787_amd import api
+    N = 40
+    g, coeffs, f, expect = _singular_batch(family, N)
+    cs = [T(c, dev) for c in coeffs]
+    _print_case(test="info_singular_factored", family=family)
+    if family == "helmholtz":
+        fac = api.helmholtz_factor(cs[0], N)
+        u, info = api.helmholtz_solve_factored(T(f, dev), cs[0], fac, info=True)
+    else:
+        fac = api.biharmonic_factor(cs[0], cs[1], N)
+        u, info = api.biharmonic_solve_factored(T(f, dev), cs[0], cs[1], fac, info=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(info.cpu().numpy(), expect)
+
+
 def test_empty_batch(dev):
     from paper_1701_03787_amd import api
     f = torch.zeros((0, 32), dtype=torch.complex128, device=dev)
@@ -181,12 +238,23 @@ def test_wave_variant_rules(dev, family):
     assert e.max() <= TOL
 
 
+# chunk lengths the wave kernels are built with, per family: (chunk, the N it covers)
+# (restart states must fit in one output row, so short rows take short chunks only)
+CHUNK_CASES = {
+    "helmholtz": [(4, (16, 33, 64)), (8, (17, 65, 130, 257, 512)), (16, (33, 130, 257, 512, 1024))],
+    "biharmonic": [(8, (64, 100, 128, 512)), (16, (65, 130, 257, 512, 1024))],
+}
+
+
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-@pytest.mark.parametrize("chunk", [4, 8, 16])
-def test_wave_chunk_knob(dev, family, chunk):
-    """Every chunk length the wave kernels accept gives the oracle's answer, over ragged N
-    and at the channel size (the knob only changes the lane/chunk split)."""
-    for N in (65, 130, 257, 512, 1024):
+@pytest.mark.parametrize("ci", [0, 1, 2])
+def test_wave_chunk_knob(dev, family, ci):
+    """Every chunk length the wave kernels offer gives the oracle's answer, over ragged N and at the
+    channel size (the knob only changes the lane/chunk split)."""
+    if ci >= len(CHUNK_CASES[family]):
+        pytest.skip("the biharmonic wave kernels offer two chunk lengths")
+    chunk, Ns = CHUNK_CASES[family][ci]
+    for N in Ns:
         nsys = 37
         _print_case(test="chunk", family=family, N=N, nsys=nsys, chunk=chunk)
         g = wl.small_grid(N, nsys, kmax=200, index=N)
@@ -197,6 +265,26 @@ def test_wave_chunk_knob(dev, family, chunk):
         assert np.all(u[:, wl.n_unknowns(family, N):] == 0)
         e = so.rel_err_per_system(u, ref)
         assert e.max() <= TOL, (N, chunk, e.max())
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_wave_chunk_refused(dev, family):
+    """A chunk length no configuration of (family, N) is built with is refused (SHEN_EINVAL)
+    instead of silently replaced, by the solve and by the factor call."""
+    from paper_1701_03787_amd import _lib, api
+    cases = ([(512, 4), (9, 4), (1024, 8), (64, 12)] if family == "helmholtz"
+             else [(512, 4), (65, 8), (1024, 8), (128, 12)])
+    for N, chunk in cases:
+        g = wl.small_grid(N, 3)
+        cs = [T(c, dev) for c in g.coefficients(family)]
+        f = T(g.rhs(family), dev)
+        fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+        with pytest.raises(_lib.ShenError) as ei:
+            fn(f, *cs, chunk=chunk)
+        assert ei.value.code == _lib.SHEN_EINVAL, (N, chunk)
+        with pytest.raises(_lib.ShenError) as ei:
+            api.factor_bytes(family, N, chunk=chunk)
+        assert ei.value.code == _lib.SHEN_EINVAL, (N, chunk)
 
 
 def test_streams(dev):
