@@ -46,8 +46,9 @@ Systems solved (Sec. 3, Crank-Nicolson matrices divided by +-nu*dt/2):
 * biharmonic: (Qchk + a_w Achk + b_w Bchk) u = f
 
 Also: the mass-matrix solves u = Bbar^{-1} f and u = Bchk^{-1} f of the
-forward Shen transforms (Sec. 2), and the derivative projection
-Bbar fhat = Cbar uhat (Sec. 3).
+forward Shen transforms (Sec. 2), the derivative projection
+Bbar fhat = Cbar uhat (Sec. 3), and the right-hand sides of one Crank-Nicolson
+step (Sec. 3, eqs. ufin / gfin).
 
 Inputs: N, per-system coefficients, complex f of shape [nsys, N] whose
 entries k >= n are ignored.  Output: complex u [nsys, N] with the tail zero.
@@ -365,6 +366,69 @@ def derivative_solve(N: int, uhat: np.ndarray, quad: int = GC) -> np.ndarray:
     C = derivative_matrix(N)
     rhs[:, :N - 2] = uhat[:, :nb] @ C.T
     return mass_solve("helmholtz", N, rhs, quad)
+
+
+# ----------------------------------------------------------------------------
+# Right-hand sides of one Crank-Nicolson step (Sec. 3, eqs. ufin and gfin),
+# written with the paper's unscaled matrices.  Per wavenumber pair, with
+# z2 = m^2 + n^2 the squared wavenumber:
+#
+#   biharmonic (eq. ufin):  Hchk uhat' = (2 Achk - 2 z2 Bchk - Hchk) uhat + dt S(h_v)
+#       Hchk = -(nu dt/2) Qchk + (1 + nu dt z2) Achk - (2 z2 + nu dt z2^2)/2 Bchk
+#   Helmholtz (eq. gfin):   Hbar ghat' = (2 Bbar - Hbar) ghat + dt S(h_g)
+#       Hbar = -(nu dt/2) Abar + (1 + nu dt z2/2) Bbar,   Abar = (phi'', phi) = -Sbar
+#
+# (the sign of A as read for the Crank-Nicolson matrices: the matrices are
+# consistent with A = +(phi'', phi) only).  The solves of this library take the
+# systems divided by -nu dt/2 (biharmonic) and nu dt/2 (Helmholtz), so the
+# right-hand side returned here is the paper's one times -2/(nu dt) or
+# 2/(nu dt): exactly what makes solve(rhs) the step's new coefficients.
+# ----------------------------------------------------------------------------
+
+def cn_matrix_paper(family: str, N: int, z2: float, nu: float, dt: float, quad: int = GC) -> np.ndarray:
+    """The paper's unscaled Crank-Nicolson matrix of one wavenumber pair (Sec. 3)."""
+    op = Operators.get(N, quad)
+    if family == "helmholtz":
+        Abar = -op.Sd
+        return -(nu * dt / 2.0) * Abar + (1.0 + nu * dt * z2 / 2.0) * op.Bd
+    return (-(nu * dt / 2.0) * op.Qb + (1.0 + nu * dt * z2) * op.Ab
+            - ((2.0 * z2 + nu * dt * z2 * z2) / 2.0) * op.Bb)
+
+
+def cn_explicit_matrix_paper(family: str, N: int, z2: float, nu: float, dt: float, quad: int = GC) -> np.ndarray:
+    """The matrix acting on the old coefficients in eqs. ufin / gfin:
+    2 Achk - 2 z2 Bchk - Hchk (biharmonic), 2 Bbar - Hbar (Helmholtz)."""
+    op = Operators.get(N, quad)
+    H = cn_matrix_paper(family, N, z2, nu, dt, quad)
+    if family == "helmholtz":
+        return 2.0 * op.Bd - H
+    return 2.0 * op.Ab - 2.0 * z2 * op.Bb - H
+
+
+def rhs_assemble(family: str, N: int, K2, nu: float, dt: float, uhat: np.ndarray, sh=None,
+                 quad: int = GC, extended: bool = False) -> np.ndarray:
+    """Right-hand side of one Crank-Nicolson step in the scaling of ``solve``:
+    -2/(nu dt) [(2 Achk - 2 z2 Bchk - Hchk) uhat + dt S(h)] (biharmonic) or
+    2/(nu dt) [(2 Bbar - Hbar) ghat + dt S(h)] (Helmholtz), per system with z2 = K2[w].
+    uhat, sh: complex [nsys, N] (entries k >= n ignored; sh=None omits the term).
+    Result [nsys, N] with the tail zero.  extended=True forms the product and the
+    sum in long double (a reference for the device's FP64 result)."""
+    uhat = np.asarray(uhat, dtype=np.complex128)
+    nsys = uhat.shape[0]
+    n = n_of(family, N)
+    K2 = np.asarray(K2, dtype=np.float64).reshape(nsys)
+    scale = (2.0 if family == "helmholtz" else -2.0) / (nu * dt)
+    dtype = np.longdouble if extended else np.float64
+    out = np.zeros_like(uhat)
+    for w in range(nsys):
+        M = cn_explicit_matrix_paper(family, N, float(K2[w]), nu, dt, quad).astype(dtype)
+        re = M @ uhat[w, :n].real.astype(dtype)
+        im = M @ uhat[w, :n].imag.astype(dtype)
+        if sh is not None:
+            re = re + dtype(dt) * np.asarray(sh[w, :n].real, dtype=dtype)
+            im = im + dtype(dt) * np.asarray(sh[w, :n].imag, dtype=dtype)
+        out[w, :n] = (dtype(scale) * re).astype(np.float64) + 1j * (dtype(scale) * im).astype(np.float64)
+    return out
 
 
 # ----------------------------------------------------------------------------
