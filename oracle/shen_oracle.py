@@ -47,8 +47,9 @@ Systems solved (Sec. 3, Crank-Nicolson matrices divided by +-nu*dt/2):
 
 Also: the mass-matrix solves u = Bbar^{-1} f and u = Bchk^{-1} f of the
 forward Shen transforms (Sec. 2), the derivative projection
-Bbar fhat = Cbar uhat (Sec. 3), and the right-hand sides of one Crank-Nicolson
-step (Sec. 3, eqs. ufin / gfin).
+Bbar fhat = Cbar uhat (Sec. 3), the right-hand sides of one Crank-Nicolson
+step (Sec. 3, eqs. ufin / gfin), and the wall-normal Shen transforms (Sec. 2:
+scalar products, forward and inverse transforms).
 
 Inputs: N, per-system coefficients, complex f of shape [nsys, N] whose
 entries k >= n are ignored.  Output: complex u [nsys, N] with the tail zero.
@@ -366,6 +367,111 @@ def derivative_solve(N: int, uhat: np.ndarray, quad: int = GC) -> np.ndarray:
     C = derivative_matrix(N)
     rhs[:, :N - 2] = uhat[:, :nb] @ C.T
     return mass_solve("helmholtz", N, rhs, quad)
+
+
+# ----------------------------------------------------------------------------
+# Shen transforms in the wall-normal direction (Sec. 2; appendix algorithms for
+# the forward scalar products / transforms and the inverse transforms), by
+# plain dense evaluation of the basis functions at the quadrature points.
+#
+# Points and weights (Sec. 2): Chebyshev-Gauss x_j = cos(pi (2j+1)/(2N)),
+# sigma_j = pi/N; Chebyshev-Gauss-Lobatto x_j = cos(pi j/(N-1)),
+# sigma_j = pi/(c_j (N-1)) with c_0 = c_{N-1} = 2.  Spaces: "chebyshev"
+# (T_k, k < N), "dirichlet" (T_k - T_{k+2}, k < N-2), "biharmonic"
+# (T_k - 2(k+2)/(k+3) T_{k+2} + (k+1)/(k+3) T_{k+4}, k < N-4).
+#   scalar product  S(u)_k = sum_j u(x_j) phi_k(x_j) sigma_j
+#   forward         uhat = B^{-1} S(u),  B_kl = (phi_l, phi_k)_sigma
+#   inverse         u(x_j) = sum_k uhat_k phi_k(x_j)
+# T_k(x_j) = cos(k theta_j) is evaluated with the integer multiple of the
+# angle reduced exactly, in long double.
+# ----------------------------------------------------------------------------
+
+SPACES = ("chebyshev", "dirichlet", "biharmonic")
+
+
+def n_space(space: str, N: int) -> int:
+    return {"chebyshev": N, "dirichlet": N - 2, "biharmonic": N - 4}[space]
+
+
+def quad_weights(N: int, quad: int = GC) -> np.ndarray:
+    if quad == GC:
+        return np.full(N, PI / N)
+    c = np.ones(N)
+    c[0] = c[-1] = 2.0
+    return PI / (c * (N - 1))
+
+
+def quad_points(N: int, quad: int = GC) -> np.ndarray:
+    j = np.arange(N)
+    if quad == GC:
+        return np.cos(PI * (2 * j + 1) / (2 * N))
+    return np.cos(PI * j / (N - 1))
+
+
+def cheb_at_points(N: int, quad: int = GC, kmax=None) -> np.ndarray:
+    """T_k(x_j) for k < kmax (default N), j < N, as long double [kmax, N]."""
+    kmax = N if kmax is None else kmax
+    k = np.arange(kmax, dtype=np.int64)[:, None]
+    j = np.arange(N, dtype=np.int64)[None, :]
+    if quad == GC:
+        m = (k * (2 * j + 1)) % (4 * N)  # angle pi m / (2N)
+        ang = np.pi * m.astype(np.longdouble) / np.longdouble(2 * N)
+    else:
+        m = (k * j) % (2 * (N - 1))  # angle pi m / (N-1)
+        ang = np.pi * m.astype(np.longdouble) / np.longdouble(N - 1)
+    return np.cos(ang)
+
+
+def basis_at_points(space: str, N: int, quad: int = GC) -> np.ndarray:
+    """phi_k(x_j) for the space's k, as long double [n, N] (basis definitions, Sec. 2)."""
+    T = cheb_at_points(N, quad)
+    if space == "chebyshev":
+        return T
+    n = n_space(space, N)
+    k = np.arange(n)
+    if space == "dirichlet":
+        return T[:n] - T[2:n + 2]
+    g1 = (2.0 * (k + 2) / (k + 3)).astype(np.longdouble)[:, None]
+    g2 = ((k + 1) / (k + 3)).astype(np.longdouble)[:, None]
+    return T[:n] - g1 * T[2:n + 2] + g2 * T[4:n + 4]
+
+
+def scalar_product(space: str, N: int, u: np.ndarray, quad: int = GC) -> np.ndarray:
+    """S(u)_k = (u, phi_k)_sigma for point values u [nsys, N]; entries k >= n zero.
+    The sums run in long double."""
+    u = np.asarray(u, dtype=np.complex128)
+    n = n_space(space, N)
+    P = basis_at_points(space, N, quad) * quad_weights(N, quad).astype(np.longdouble)[None, :]
+    out = np.zeros_like(u)
+    re = u.real.astype(np.longdouble) @ P.T
+    im = u.imag.astype(np.longdouble) @ P.T
+    out[:, :n] = re.astype(np.float64) + 1j * im.astype(np.float64)
+    return out
+
+
+def space_mass_solve(space: str, N: int, f: np.ndarray, quad: int = GC) -> np.ndarray:
+    """B^{-1} f with B the space's mass matrix: diagonal c_k pi/2 for "chebyshev" (c_0 = 2,
+    and c_{N-1} = 2 for GL), else the Dirichlet / biharmonic mass solves above."""
+    if space == "chebyshev":
+        f = np.asarray(f, dtype=np.complex128)
+        return f / (0.5 * PI * ck(np.arange(N), N, quad))[None, :]
+    return mass_solve("helmholtz" if space == "dirichlet" else "biharmonic", N, f, quad)
+
+
+def forward_transform(space: str, N: int, u: np.ndarray, quad: int = GC) -> np.ndarray:
+    """uhat = B^{-1} S(u) (Sec. 2, the complete transformation)."""
+    return space_mass_solve(space, N, scalar_product(space, N, u, quad), quad)
+
+
+def backward_transform(space: str, N: int, uhat: np.ndarray, quad: int = GC) -> np.ndarray:
+    """u(x_j) = sum_k uhat_k phi_k(x_j) for coefficients uhat [nsys, N] (entries k >= n
+    ignored); sums in long double."""
+    uhat = np.asarray(uhat, dtype=np.complex128)
+    n = n_space(space, N)
+    P = basis_at_points(space, N, quad)
+    re = uhat[:, :n].real.astype(np.longdouble) @ P
+    im = uhat[:, :n].imag.astype(np.longdouble) @ P
+    return re.astype(np.float64) + 1j * im.astype(np.float64)
 
 
 # ----------------------------------------------------------------------------
