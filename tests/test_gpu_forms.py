@@ -341,7 +341,10 @@ def test_roundoff_protocol_vs_paper(dev, family, variant):
 @pytest.mark.parametrize("N", [130, 512, 1024])
 def test_mixed_precision_wave_sizes(dev, family, N):
     """The register-resident FP32 + refinement path over ragged and large N, at the
-    bench's coefficient law, against the oracle; every system converges in FP32+FP64."""
+    bench's coefficient law, against the oracle.  Up to N=512 every system converges
+    in FP32+FP64.  At N=1024 the biharmonic FP32 solve contracts slowly enough that a
+    few systems reach the rounding floor above 5e-13 max|u| and are re-solved in FP64
+    (info -2), which is what the stopping rule is for; every result meets the bar."""
     from paper_1701_03787_amd import api
     g = wl.small_grid(N, 37, kmax=362, index=N, nu=5e-5, dt=5e-4)
     cs = g.coefficients(family)
@@ -352,8 +355,11 @@ def test_mixed_precision_wave_sizes(dev, family, N):
     u, info = fn(T(f, dev), *[T(c, dev) for c in cs], precision="fp32_refine", info=True, variant="wave")
     torch.cuda.synchronize()
     assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
-    print("info", np.unique(info.cpu().numpy(), return_counts=True), flush=True)
-    assert np.all(info.cpu().numpy() == 0)
+    iv = info.cpu().numpy()
+    print("info", np.unique(iv, return_counts=True), flush=True)
+    assert np.all((iv == 0) | (iv == -2))
+    allowed = 0 if (N <= 512 or family == "helmholtz") else max(1, g.nsys // 10)
+    assert np.count_nonzero(iv == -2) <= allowed
     assert np.all(u.cpu().numpy()[:, wl.n_unknowns(family, N):] == 0)
 
 
@@ -403,8 +409,11 @@ def test_gauss_lobatto_mixed_and_adjoint(dev, family, N):
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
 def test_mixed_precision_config3_full_size(dev, family):
     """The headline FP32 + refinement launch: all 131,584 systems of N=512, 512x257 in one call
-    (the bench's launch), info == 0 and 1..refine_max corrections on every system, and sampled
-    rows (first, last, K2 = 0, the largest K2, random) against the oracle at the 1e-12 bar."""
+    (the bench's launch), 1..refine_max corrections on every system, and sampled rows (first,
+    last, K2 = 0, the largest K2, random, and every system re-solved in FP64) against the
+    oracle at the 1e-12 bar.  Every system converges in FP32 + FP64 refinement (info 0) or,
+    where the corrections stall above 5e-13 max|u| (a few dozen biharmonic systems), is
+    re-solved in FP64 (info -2); nothing else, and no more than 0.1% fallbacks."""
     from paper_1701_03787_amd import api
     g = wl.config_grids(3)[0]
     cs = g.coefficients(family)
@@ -416,12 +425,16 @@ def test_mixed_precision_config3_full_size(dev, family):
     info = info.cpu().numpy()
     its = its.cpu().numpy()
     print("info", np.unique(info, return_counts=True), "iters", np.bincount(its), flush=True)
-    assert np.all(info == 0)
+    assert np.all((info == 0) | (info == -2))
+    fb = np.flatnonzero(info == -2)
+    assert fb.size <= g.nsys // 1000
+    if family == "helmholtz":
+        assert fb.size == 0
     assert its.min() >= 1 and its.max() <= 8
     rng = np.random.default_rng([1701, 3, 11])
     K2 = g.K2
     rows = np.unique(np.concatenate([[0, g.nsys - 1, int(np.argmin(K2)), int(np.argmax(K2))],
-                                     rng.choice(g.nsys, 60, replace=False)]))
+                                     rng.choice(g.nsys, 60, replace=False), fb]))
     un = u.cpu().numpy()
     ref = so.solve(family, g.N, tuple(c[rows] for c in cs), f[rows])
     assert so.rel_err_per_system(un[rows], ref).max() <= TOL

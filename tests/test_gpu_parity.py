@@ -179,13 +179,27 @@ def test_info_singular(dev, family, variant, precision):
     """A coefficient at minus a generalised eigenvalue (oracle): the unpivoted LU meets a
     numerically zero pivot at the last row of the singular block; info reports that row + 1
     (FP32 + refinement: after its FP64 re-solve), the kernel exits normally, and the regular
-    systems of the batch still match the oracle."""
+    systems of the batch still match the oracle.
+
+    FP32 + refinement and the mid-chain case (system 2, whose whole matrix is regular): FP32
+    rounding moves that pivot off zero, so the FP32 LU may not meet it as unusable; the
+    FP64-residual refinement then either converges to the solution of the regular system
+    (info 0, and the result must meet the bar) or stalls and the FP64 re-solve reports the
+    pivot (info 11)."""
     N = 40
     g, coeffs, f, expect = _singular_batch(family, N)
     _print_case(test="info_singular", family=family, variant=variant, precision=precision)
     u, info = gpu_solve(family, N, coeffs, f, dev, info=True, variant=variant, precision=precision)
-    assert np.array_equal(info, expect), (info, expect)
     ok = expect == 0
+    if precision == "fp32_refine":
+        assert info[2] in (0, expect[2]), info
+        if info[2] == 0:
+            ok[2] = True
+        keep = np.ones(6, bool)
+        keep[2] = False
+        assert np.array_equal(info[keep], expect[keep]), (info, expect)
+    else:
+        assert np.array_equal(info, expect), (info, expect)
     ref = so.solve(family, N, tuple(c[ok] for c in coeffs), f[ok])
     assert so.rel_err_per_system(u[ok], ref).max() <= TOL
 
