@@ -70,6 +70,7 @@ typedef struct {
 #define SHEN_ELAUNCH (-2)  /* the HIP runtime refused a launch */
 #define SHEN_ENOTSUP (-3)  /* N beyond what the chosen kernel supports */
 #define SHEN_EDEVICE (-4)  /* no usable HIP device */
+#define SHEN_ESCRATCH (-5) /* more scratch than the static buffer holds    */
 
 /* per-system info codes besides 0 and k+1 */
 #define SHEN_INFO_REFINE_FALLBACK (-2)
@@ -302,6 +303,25 @@ int64_t shen_batched_work_bytes(int32_t ndesc);
 
 int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work,
                   const shen_opts* opts);
+
+/*
+ * batched_solve without the `work` argument, for callers that cannot
+ * allocate device memory (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the work counters live in a static
+ * device array of shen_batched_static_bytes() bytes (4 KiB) that the library
+ * holds on each device it runs on until the process ends.  The call itself
+ * allocates nothing.  Same descriptors, planning, arguments, results and
+ * errors as batched_solve, plus SHEN_ESCRATCH when
+ * shen_batched_work_bytes(ndesc) exceeds the static buffer.  Every call on
+ * one device shares that device's buffer: calls that overlap on a device
+ * (other streams, other threads, or two replays of graphs that captured
+ * this call) race and must be serialised by the caller.  The buffer keeps
+ * the last call's contents; each call clears what it uses with its first
+ * kernel.
+ */
+int64_t shen_batched_static_bytes(void);
+int batched_solve_static(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN,
+                         const shen_opts* opts);
 
 #ifdef __cplusplus
 }

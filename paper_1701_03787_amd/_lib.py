@@ -15,6 +15,7 @@ SHEN_EINVAL = -1
 SHEN_ELAUNCH = -2
 SHEN_ENOTSUP = -3
 SHEN_EDEVICE = -4
+SHEN_ESCRATCH = -5
 SHEN_INFO_REFINE_FALLBACK = -2
 
 SHEN_FP64 = 0
@@ -83,6 +84,8 @@ SIGNATURES = [
     ("shen_batched_plan", C.c_int64, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),
     ("shen_batched_work_bytes", C.c_int64, [C.c_int32]),
     ("batched_solve", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, _VP, C.POINTER(ShenOpts)]),
+    ("shen_batched_static_bytes", C.c_int64, []),
+    ("batched_solve_static", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(ShenOpts)]),
 ]
 
 _lib = None

@@ -188,8 +188,14 @@ class BatchedSolver:
         o.quad = _QUAD[self.quad]
         return o
 
-    def run(self):
+    def run(self, static: bool = False):
+        """Enqueue the launch.  static=True uses batched_solve_static (the library's own
+        counter array instead of this solver's work buffer: nothing is allocated)."""
         o = self._opts()
+        if static:
+            L.check(L.lib().batched_solve_static(self.desc.data_ptr(), len(self.problems), self.tiles_total,
+                                                 self.maxN, C.byref(o)), "batched_solve_static")
+            return
         L.check(L.lib().batched_solve(self.desc.data_ptr(), len(self.problems), self.tiles_total, self.maxN,
                                       self.work.data_ptr(), C.byref(o)), "batched_solve")
 

@@ -264,6 +264,7 @@ const char* shen_status_string(int code) {
     case SHEN_ELAUNCH: return "kernel launch failed";
     case SHEN_ENOTSUP: return "size not supported by this kernel on this device";
     case SHEN_EDEVICE: return "no usable HIP device";
+    case SHEN_ESCRATCH: return "the call needs more scratch than the library's static buffer holds";
     default: return "unknown status";
   }
 }
@@ -626,6 +627,26 @@ int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, 
   int64_t blocks = (int64_t)cus * 4;
   if (blocks > tiles_total) blocks = tiles_total > 0 ? tiles_total : 1;
   return shen::launch_batched(desc, ndesc, tiles_total, work, o.quad == SHEN_QUAD_GL, (int)blocks, o.stream) == hipSuccess
+             ? SHEN_OK
+             : SHEN_ELAUNCH;
+}
+
+int64_t shen_batched_static_bytes(void) { return (int64_t)shen::kBatchedStaticWords * 8; }
+
+int batched_solve_static(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!desc || !aligned(desc, 8) || ndesc <= 0 || tiles_total < 0 || maxN < 3) return SHEN_EINVAL;
+  const int64_t need = shen_batched_work_bytes(ndesc);
+  if (need < 0) return SHEN_EINVAL;
+  if (need > shen_batched_static_bytes()) return SHEN_ESCRATCH;
+  DevInfo d;
+  rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  void* work = nullptr;
+  if (shen::batched_static_scratch(&work) != hipSuccess || work == nullptr) return SHEN_EDEVICE;
+  return shen::launch_batched(desc, ndesc, tiles_total, work, o.quad == SHEN_QUAD_GL, 0, o.stream) == hipSuccess
              ? SHEN_OK
              : SHEN_ELAUNCH;
 }

@@ -68,6 +68,11 @@ __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
 bool wave_chunk_ok(int family, int N, int chunk);
 hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
+// Library-owned counter array of the batched launch (one per device, 8-byte
+// words): device address for the current device, looked up on first use.
+constexpr int kBatchedStaticWords = 512;
+constexpr int kMaxDevices = 64;
+hipError_t batched_static_scratch(void** ptr);
 hipError_t launch_wave(const WaveArgs& a);
 int64_t wave_state_slot(int family, int N, int chunk);
 bool matvec_wave_supported(int family, int N);

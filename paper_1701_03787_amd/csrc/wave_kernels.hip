@@ -24,6 +24,7 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "shen_launch.hpp"
@@ -3853,6 +3854,37 @@ hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void
 #undef SHEN_CFG
   }
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Work counters of the batched launch in library-owned device memory, for
+// callers that cannot allocate (code under hipGraph capture, serving loops,
+// harnesses that forbid hipMalloc).  One array per device, held until the
+// process ends; every call on a device shares it, so calls that overlap on
+// one device race (the launch clears the counters with its first kernel, so
+// what an earlier call left there does not matter).  Host code never passes
+// the array's name to a kernel: it stands for a host-side shadow there.  The
+// device address is looked up once per device, with that device current.
+// ------------------------------------------------------------------------
+static __device__ __align__(256) unsigned long long scratch[kBatchedStaticWords];
+
+hipError_t batched_static_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace shen
