@@ -55,6 +55,18 @@ def measured_traffic(workload: str, family: str):
     return int(v) if v else None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def alg_bytes(family: str, N: int, nsys: int) -> int:
     """Algorithmic HBM bytes of one solve: read f[k<n], write u[0:N], read coefficients."""
     if family == "helmholtz":
@@ -160,8 +172,15 @@ def measure_adjoint(dev, args):
         n = wl.n_unknowns(fam, g.N)
         gb[:, n:] = 0
         err = _sampled_err(fam, g.N, csh, gb, f.grad, rows, transpose=True)
+        # algorithmic bytes of forward + backward per system: the solve reads f[k<n] and the
+        # coefficients and writes u; the adjoint reads gbar[k<n], u[k<n] and the coefficients and
+        # writes lambda and one gradient per coefficient
+        nc = len(csh)
+        per = (16 * n + 16 * g.N + 8 * nc) + (16 * n + 16 * n + 16 * g.N + 8 * nc + 8 * nc)
+        gbs = g.nsys * per / (ms * 1e-3) / 1e9
         out[fam] = {"ms_forward_backward": round(ms, 4), "value": round(g.nsys * g.N / (ms * 1e-3), 2),
-                    "unit": "system·N/s", "max_rel_err_grad_f_sampled": err}
+                    "unit": "system·N/s", "bytes_per_step": int(g.nsys * per), "hbm_gbps": round(gbs, 2),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "max_rel_err_grad_f_sampled": err}
         del f, cs, gbar
     torch.cuda.empty_cache()
     return out
@@ -214,7 +233,7 @@ def measure_factored(dev, args, grid, data, host, rows):
                 "unit": "system·N/s", "kernel_ms": {k: round(v, 4) for k, v in kms.items()},
                 "factor_ms": {k: round(v, 4) for k, v in fac_ms.items()}})
     for fam in data:
-        state = facs[fam].numel() * 8
+        state = facs[fam].data.numel() * 8
         out[fam] = {"hbm_gbps_algorithmic": round(alg_bytes(fam, N, nsys) / (kms[fam] * 1e-3) / 1e9, 2),
                     "state_bytes": int(state),
                     "hbm_gbps_with_states": round((alg_bytes(fam, N, nsys) + state) / (kms[fam] * 1e-3) / 1e9, 2),
@@ -254,6 +273,106 @@ def measure_matvec(dev, args, grid, data, host, rows):
         err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
         out[fam] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err}
         del hu
+    return out
+
+
+def measure_rhs(dev, args, grid, data, host, rows):
+    """Crank-Nicolson right-hand sides (Sec. 3, eqs. gfin / ufin) on the bench workload, with the
+    S(h) term fused in: read uhat and S(h), write rhs per system (K2 per system); sampled rows
+    against the oracle's extended-precision right-hand side from the paper's matrices."""
+    import numpy as np
+    import torch
+    from oracle import shen_oracle as so
+    from paper_1701_03787_amd import api
+    from paper_1701_03787_amd import workloads as wl
+    N, nsys = grid.N, grid.nsys
+    K2h = grid.K2
+    K2 = torch.from_numpy(K2h).to(dev)
+    out = {"workload": grid.name, "nu": grid.nu, "dt": grid.dt}
+    for fam, (f, cs, u) in data.items():
+        fn = api.helmholtz_rhs if fam == "helmholtz" else api.biharmonic_rhs
+        shh = wl.random_vector((len(rows), N), (66,))
+        sh = torch.empty_like(f)
+        sh.copy_(f)  # any resident S(h) rows of the workload's shape
+        r = torch.empty_like(f)
+        for _ in range(max(1, args.warmup)):
+            fn(f, K2, grid.nu, grid.dt, sh, out=r)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(f, K2, grid.nu, grid.dt, sh, out=r)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        n = wl.n_unknowns(fam, N)
+        nbytes = nsys * (16 * n + 16 * n + 16 * N + 8)
+        # accuracy on sampled rows, with distinct S(h) rows for them
+        idx = torch.from_numpy(rows).to(dev)
+        shs = torch.from_numpy(shh).to(dev)
+        got = fn(f[idx].contiguous(), K2[idx].contiguous(), grid.nu, grid.dt, shs).cpu().numpy()
+        fh = host[fam][0]
+        ref = so.rhs_assemble(fam, N, K2h[rows], grid.nu, grid.dt, fh[rows], shh, extended=True)
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        key = "helmholtz_gfin" if fam == "helmholtz" else "biharmonic_ufin"
+        out[key] = {"ms": round(ms, 4), "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2),
+                    "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes),
+                    "max_rel_err_sampled": err}
+        del sh, r
+    return out
+
+
+def measure_transforms(dev, args, grid, data, host, rows):
+    """Wall-normal Shen transforms (Sec. 2) on the bench workload's shape, Gauss points: the inverse
+    (coefficients -> point values: one read, one write per system), the scalar products (point values ->
+    S(u)) and the forward transform (scalar products, then the mass solve in place), per space; sampled
+    rows against the oracle."""
+    import numpy as np
+    import torch
+    from oracle import shen_oracle as so
+    from paper_1701_03787_amd import api
+    N, nsys = grid.N, grid.nsys
+    out = {"workload": grid.name, "quad": "GC"}
+    reps = max(3, min(args.steps, 10))
+    for fam, (f, cs, u) in data.items():
+        space = "dirichlet" if fam == "helmholtz" else "biharmonic"
+        n = so.n_space(space, N)
+        phys = torch.empty_like(f)
+        coef = torch.empty_like(f)
+        ops = {"backward": (lambda: api.backward_transform(f, space, out=phys), 16 * n + 16 * N),
+               "scalar_product": (lambda: api.scalar_product(phys, space, out=coef), 16 * N + 16 * N),
+               "forward": (lambda: api.forward_transform(phys, space, out=coef), 16 * N + 16 * N)}
+        res = {}
+        for name, (fn, per) in ops.items():
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = nsys * per / (ms * 1e-3) / 1e9
+            res[name] = {"ms": round(ms, 4), "hbm_gbps": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_launch": int(nsys * per)}
+        idx = torch.from_numpy(rows).to(dev)
+        api.backward_transform(f, space, out=phys)
+        p = phys[idx].cpu().numpy()
+        fh = host[fam][0][rows]
+        ref = so.backward_transform(space, N, fh)
+        res["backward"]["max_rel_err_sampled"] = float(np.max(np.abs(p - ref)) / np.max(np.abs(ref)))
+        api.scalar_product(phys, space, out=coef)
+        refs = so.scalar_product(space, N, p)
+        got = coef[idx].cpu().numpy()
+        res["scalar_product"]["max_rel_err_sampled"] = float(np.max(np.abs(got - refs)) / np.max(np.abs(refs)))
+        api.forward_transform(phys, space, out=coef)
+        got = coef[idx].cpu().numpy()
+        res["forward"]["max_rel_err_sampled"] = float(so.rel_err_per_system(got, so.forward_transform(space, N, p)).max())
+        out[space] = res
+        del phys, coef
     return out
 
 
@@ -415,14 +534,40 @@ def main():
             ref = so.solve(fam, N, tuple(c[rows] for c in cs), f[rows])
             acc_m[fam] = float(so.rel_err_per_system(u, ref).max())
         ms_m = 1e3 * wall_m / args.steps
+        # Per-system status and corrections of one full mixed launch (outside the timed
+        # region), and the error of the uncorrected FP32 solve (refine_max = 0) on the
+        # sampled rows: the pre-refinement error.
+        status, pre = {}, {}
+        for fam in fams:
+            f, cs, u = data[fam]
+            fn = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
+            _, inf, its = fn(f, *cs, out=u, precision="fp32_refine", variant=args.variant, chunk=args.chunk,
+                             info=True, iters=True)
+            torch.cuda.synchronize()
+            iv, it = inf.cpu().numpy(), its.cpu().numpy()
+            vals, cnts = np.unique(iv, return_counts=True)
+            status[fam] = {"info_histogram": {str(int(v)): int(c) for v, c in zip(vals, cnts)},
+                           "fp64_fallbacks": int(np.count_nonzero(iv == -2)),
+                           "iters_mean": round(float(it.mean()), 4), "iters_max": int(it.max()),
+                           "iters_histogram": {str(int(v)): int(c) for v, c in zip(*np.unique(it, return_counts=True))}}
+            fn(f, *cs, out=u, precision="fp32_refine", variant=args.variant, chunk=args.chunk, refine_max=0)
+            torch.cuda.synchronize()
+            got = u[torch.from_numpy(rows).to(dev)].cpu().numpy()
+            fh, csh = host[fam]
+            ref = so.solve(fam, N, tuple(c[rows] for c in csh), fh[rows])
+            pre[fam] = float(so.rel_err_per_system(got, ref).max())
+            del inf, its
         mixed = {"value": units / (ms_m / 1e3), "ms_per_step": round(ms_m, 4),
                  "kernel_ms": {k: round(v, 4) for k, v in kms_m.items()},
-                 "speedup_vs_fp64": round(ms_per_step / ms_m, 4), "max_rel_err": acc_m}
+                 "speedup_vs_fp64": round(ms_per_step / ms_m, 4), "max_rel_err": acc_m,
+                 "pre_refine_err": pre, "status": status}
 
     forms = None
     if not args.no_forms:
         forms = {"factored": measure_factored(dev, args, grid, data, host, rows),
                  "matvec": measure_matvec(dev, args, grid, data, host, rows),
+                 "rhs": measure_rhs(dev, args, grid, data, host, rows),
+                 "transforms": measure_transforms(dev, args, grid, data, host, rows),
                  "mass": measure_mass(dev, args, grid, data, host, rows),
                  "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
 
@@ -439,7 +584,7 @@ def main():
                 dt, used, _ = so.time_solve(fam, N, tuple(c[sample] for c in cs), f[sample], threads=threads)
                 t_cpu += dt
         cpu = {"value": round(len(fams) * per_fam * N / t_cpu, 2), "unit": "system·N/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{per_fam} random systems per family of {grid.name} (same inputs), dense LU + refinement, "
                          f"{t_cpu:.1f} s on {threads} threads"}
 

@@ -87,6 +87,11 @@ typedef struct {
 #define SHEN_HELMHOLTZ 0
 #define SHEN_BIHARMONIC 1
 
+/* bases of the wall-normal transforms (Sec. 2) */
+#define SHEN_SPACE_CHEBYSHEV 0  /* T_k, k < N                                */
+#define SHEN_SPACE_DIRICHLET 1  /* T_k - T_{k+2}, k < N-2                    */
+#define SHEN_SPACE_BIHARMONIC 2 /* T_k - 2(k+2)/(k+3) T_{k+2} + (k+1)/(k+3) T_{k+4}, k < N-4 */
+
 typedef struct {
   void* stream;       /* hipStream_t to enqueue on; NULL = null stream       */
   int32_t precision;  /* SHEN_FP64 (default) or SHEN_FP32_REFINE             */
@@ -263,6 +268,73 @@ int biharmonic_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128
  * opts, return codes and accuracy: as for dirichlet_mass_solve.
  */
 int dirichlet_derivative_solve(int32_t N, int64_t nsys, const shen_c128* uhat, shen_c128* fhat, const shen_opts* opts);
+
+/*
+ * Wall-normal Shen transforms (Sec. 2, the forward transform uhat = B^{-1} S(u)
+ * and the inverse u = S^{-1} uhat; the appendix algorithms for the forward
+ * scalar products / transforms and the inverse transforms), one per
+ * wavenumber pair, at the N Chebyshev-Gauss points x_j = cos(pi (2j+1)/(2N))
+ * (opts.quad = SHEN_QUAD_GC, weights pi/N) or Chebyshev-Gauss-Lobatto points
+ * x_j = cos(pi j/(N-1)) (SHEN_QUAD_GL, weights pi/(c_j (N-1)), c_0 = c_{N-1}
+ * = 2), in the space SHEN_SPACE_*:
+ *
+ *   shen_scalar_product:    s_k = sum_j u(x_j) phi_k(x_j) sigma_j, k < n
+ *   shen_forward_transform: uhat = B^{-1} s, B_kl = (phi_l, phi_k)_sigma
+ *                           (Chebyshev: diagonal; Dirichlet, biharmonic: the
+ *                           mass solves above, N <= 1024)
+ *   shen_backward_transform: u(x_j) = sum_{k<n} uhat_k phi_k(x_j)
+ *
+ * with n = N, N-2, N-4.  Gauss points and N a power of two in 8 .. 2048 take
+ * an FFT of length N per system; other N and Gauss-Lobatto points take
+ * O(N^2) cosine sums.
+ *
+ * u: DEVICE complex128 [nsys][N] point values (index j); uhat, s: DEVICE
+ *   complex128 [nsys][N] coefficients, entries k >= n written as 0 (read
+ *   as ignored).  Input and output must not overlap (they may not be the same
+ *   array either).  N <= 2048 (forward transform of the Dirichlet and
+ *   biharmonic spaces: N <= 1024); N >= 1, 3, 5 for the three spaces.
+ * Returns SHEN_EINVAL for bad sizes, pointers or space, SHEN_ENOTSUP for N
+ * beyond the limits.
+ */
+int shen_scalar_product(int32_t N, int64_t nsys, int32_t space, const shen_c128* u, shen_c128* s, const shen_opts* opts);
+int shen_forward_transform(int32_t N, int64_t nsys, int32_t space, const shen_c128* u, shen_c128* uhat,
+                           const shen_opts* opts);
+int shen_backward_transform(int32_t N, int64_t nsys, int32_t space, const shen_c128* uhat, shen_c128* u,
+                            const shen_opts* opts);
+
+/*
+ * Right-hand sides of one Crank-Nicolson step of the channel solver (Sec. 3,
+ * eq. gfin for the Dirichlet-basis g equation, eq. ufin for the
+ * biharmonic-basis u equation), in the scaling of helmholtz_solve and
+ * biharmonic_solve, so that solving with alpha = K2 + 2/(nu dt), resp.
+ * a = -(2 K2 + 2/(nu dt)), b = K2 (K2 + 2/(nu dt)), advances one step:
+ *
+ *   helmholtz_rhs:  rhs = 2/(nu dt) [ (2 Bbar - Hbar) ghat + dt S(h_g) ]
+ *                       = (2/nu) S(h_g) - (S + (K2 - 2/(nu dt)) B) ghat
+ *   biharmonic_rhs: rhs = -2/(nu dt) [ (2 Achk - 2 K2 Bchk - Hchk) uhat + dt S(h_u) ]
+ *                       = (-2/nu) S(h_u) - (Q + a' A + b' B) uhat,
+ *                         a' = 2/(nu dt) - 2 K2,  b' = K2 (K2 - 2/(nu dt))
+ *
+ * with Hbar, Hchk the paper's Crank-Nicolson matrices (eqs.
+ * Helmholtz_matrix, Biharmonic_matrix) at z^2 = K2.  One O(N) product per
+ * system; nothing is allocated.
+ *
+ * K2: DEVICE float64 [nsys], the squared wavenumber m^2 + n^2 per system.
+ * nu, dt: viscosity and time step (> 0; 2/(nu dt) finite).
+ * ghat / uhat: DEVICE complex128 [nsys][N], the current coefficients
+ *   (entries k >= n ignored).
+ * sh: DEVICE complex128 [nsys][N], the scalar products S(h) of the
+ *   explicit terms (entries k >= n ignored), or NULL to omit that term.
+ * rhs: DEVICE complex128 [nsys][N], written (entries k >= n as 0).  It must
+ *   not overlap ghat / uhat; it may equal sh (accumulate in place) but not
+ *   overlap it otherwise.
+ * opts: stream, quad (GC / GL mass matrix), variant; transpose must be 0.
+ * Returns SHEN_EINVAL for bad sizes, pointers, nu or dt.
+ */
+int helmholtz_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double dt, const shen_c128* ghat,
+                  const shen_c128* sh, shen_c128* rhs, const shen_opts* opts);
+int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double dt, const shen_c128* uhat,
+                   const shen_c128* sh, shen_c128* rhs, const shen_opts* opts);
 
 /*
  * One batch of independent problems (many grids of uneven N, both

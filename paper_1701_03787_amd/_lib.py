@@ -24,6 +24,7 @@ SHEN_QUAD_GC = 0
 SHEN_QUAD_GL = 1
 SHEN_HELMHOLTZ = 0
 SHEN_BIHARMONIC = 1
+SHEN_SPACE = {"chebyshev": 0, "dirichlet": 1, "biharmonic": 2}
 
 
 class ShenOpts(C.Structure):
@@ -81,6 +82,11 @@ SIGNATURES = [
     ("dirichlet_mass_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
     ("biharmonic_mass_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
     ("dirichlet_derivative_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("helmholtz_rhs", C.c_int, [C.c_int32, C.c_int64, _VP, C.c_double, C.c_double, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("biharmonic_rhs", C.c_int, [C.c_int32, C.c_int64, _VP, C.c_double, C.c_double, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("shen_scalar_product", C.c_int, [C.c_int32, C.c_int64, C.c_int32, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("shen_forward_transform", C.c_int, [C.c_int32, C.c_int64, C.c_int32, _VP, _VP, C.POINTER(ShenOpts)]),
+    ("shen_backward_transform", C.c_int, [C.c_int32, C.c_int64, C.c_int32, _VP, _VP, C.POINTER(ShenOpts)]),
     ("shen_batched_plan", C.c_int64, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),
     ("shen_batched_work_bytes", C.c_int64, [C.c_int32]),
     ("batched_solve", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, _VP, C.POINTER(ShenOpts)]),

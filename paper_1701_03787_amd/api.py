@@ -286,6 +286,64 @@ def biharmonic_matvec(u, a, b, *, out=None, quad="gc", transpose=False):
     return y
 
 
+def _rhs(fn, name, u, K2, nu, dt, sh, out, quad, variant):
+    u = _rows(u, "uhat")
+    N = u.shape[-1]
+    lead = u.shape[:-1]
+    K2 = _coef(K2, lead, u.device, "K2")
+    if sh is not None:
+        sh = _like(sh, u, "sh")
+    y = _out(out, u)
+    o = _opts(u.device, quad=quad, variant=variant)
+    L.check(fn(N, _nsys(lead), K2.data_ptr(), float(nu), float(dt), u.data_ptr(),
+               sh.data_ptr() if sh is not None else None, y.data_ptr(), C.byref(o)), name)
+    return y
+
+
+def helmholtz_rhs(ghat, K2, nu, dt, sh=None, *, out=None, quad="gc", variant="auto"):
+    """Right-hand side of one Crank-Nicolson step of the g equation (Sec. 3, eq. gfin), scaled so
+    that helmholtz_solve(rhs, K2 + 2/(nu dt)) advances the step: (2/nu) S(h) - (S + (K2 - 2/(nu dt)) B) ghat.
+    sh = S(h_g) (None omits it); out may be sh."""
+    return _rhs(L.lib().helmholtz_rhs, "helmholtz_rhs", ghat, K2, nu, dt, sh, out, quad, variant)
+
+
+def biharmonic_rhs(uhat, K2, nu, dt, sh=None, *, out=None, quad="gc", variant="auto"):
+    """Right-hand side of one Crank-Nicolson step of the u equation (Sec. 3, eq. ufin), scaled so
+    that biharmonic_solve(rhs, -(2 K2 + 2/(nu dt)), K2 (K2 + 2/(nu dt))) advances the step:
+    (-2/nu) S(h) - (Q + (2/(nu dt) - 2 K2) A + K2 (K2 - 2/(nu dt)) B) uhat.  sh = S(h_u) (None omits
+    it); out may be sh."""
+    return _rhs(L.lib().biharmonic_rhs, "biharmonic_rhs", uhat, K2, nu, dt, sh, out, quad, variant)
+
+
+def _transform(fn, name, x, space, out, quad):
+    x = _rows(x, "input")
+    if space not in L.SHEN_SPACE:
+        raise ValueError(f"space must be one of {sorted(L.SHEN_SPACE)}")
+    N = x.shape[-1]
+    y = _out(out, x)
+    if y.data_ptr() == x.data_ptr():
+        raise ValueError(f"{name}: output must not be the input")
+    o = _opts(x.device, quad=quad)
+    L.check(fn(N, _nsys(x.shape[:-1]), L.SHEN_SPACE[space], x.data_ptr(), y.data_ptr(), C.byref(o)), name)
+    return y
+
+
+def scalar_product(u, space, *, out=None, quad="gc"):
+    """S(u)_k = sum_j u(x_j) phi_k(x_j) sigma_j for point values u [..., N] at the Gauss ("gc") or
+    Gauss-Lobatto ("gl") points, phi the basis of space "chebyshev", "dirichlet" or "biharmonic"
+    (Sec. 2); entries k >= n are 0."""
+    return _transform(L.lib().shen_scalar_product, "shen_scalar_product", u, space, out, quad)
+
+
+def forward_transform(u, space, *, out=None, quad="gc"):
+    """uhat = B^{-1} S(u): the space's coefficients of the point values u (Sec. 2)."""
+    return _transform(L.lib().shen_forward_transform, "shen_forward_transform", u, space, out, quad)
+
+
+def backward_transform(uhat, space, *, out=None, quad="gc"):
+    """u(x_j) = sum_k uhat_k phi_k(x_j): point values of the series with coefficients uhat (Sec. 2)."""
+    return _transform(L.lib().shen_backward_transform, "shen_backward_transform", uhat, space, out, quad)
+
 
 def dirichlet_mass_solve(f, *, out=None, quad="gc"):
     """u = Bbar^{-1} f per system, Bbar the Dirichlet-basis mass matrix (Sec. 2 transforms); out may be f."""

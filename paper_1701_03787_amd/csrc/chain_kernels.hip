@@ -221,9 +221,13 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_adjoint(int N, int64
 
 // Hu (or H^T u) with one backward / forward sweep per chain.
 // Layout per system: x[NP] (double2).
+// With rhs != 0 (and trans == 0): alpha holds K2 per system and the result is
+// the Crank-Nicolson right-hand side sigma S(h) - (S + alpha' B) u, alpha' =
+// K2 - inv (sh = S(h) rows, or null).
 __global__ __launch_bounds__(kChainThreads) void helm_chain_matvec(int N, int64_t nsys, int S, int NP, const double* __restrict__ alpha,
                                                                     const double2* __restrict__ uin, double2* __restrict__ out, int gl,
-                                                                    int trans) {
+                                                                    int trans, int rhs, double inv, double sigma,
+                                                                    const double2* __restrict__ sh) {
   extern __shared__ double2 lds[];
   const int64_t w0 = (int64_t)blockIdx.x * S;
   const int Sb = (int)min((int64_t)S, nsys - w0);
@@ -236,7 +240,8 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_matvec(int N, int64_
     const int s = t >> 1, p = t & 1;
     const double2* x = lds + s * stride;
     double2* o = out + (w0 + s) * (int64_t)N;
-    const double al = alpha[w0 + s];
+    const double2* so = sh ? sh + (w0 + s) * (int64_t)N : nullptr;
+    const double al = rhs ? rhs_alpha(alpha[w0 + s], inv) : alpha[w0 + s];
     if (!trans) {
       double2 S4 = zero2(), u2 = zero2();  // S_{k+4}, u_{k+2}
       for (int k = last_of_parity(n, p); k >= 0; k -= 2) {
@@ -246,6 +251,7 @@ __global__ __launch_bounds__(kChainThreads) void helm_chain_matvec(int N, int64_
         v = c_fma(h.hpp + h.hm, u2, v);
         v = c_fma(h.hpp, S4, v);
         if (k >= 2) v = c_fma(h.hm, x[k - 2], v);
+        if (rhs) v = rhs_combine(v, sigma, so ? so + k : nullptr);
         o[k] = v;
         S4 = c_add(S4, u2);
         u2 = uk;
@@ -657,9 +663,13 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_adjoint(int N, int64_
 }
 
 // Hu (or H^T u) for the biharmonic matrix.  Layout per system: x double2[NP].
+// With rhs != 0 (and trans == 0): ca holds K2 per system and the result is
+// the Crank-Nicolson right-hand side sigma S(h) - (Q + a' A + b' B) u, a' =
+// inv - 2 K2, b' = K2 (K2 - inv) (sh = S(h) rows, or null).
 __global__ __launch_bounds__(kChainThreads) void bih_chain_matvec(int N, int64_t nsys, int S, int NP, const double* __restrict__ ca,
                                                                    const double* __restrict__ cb, const double2* __restrict__ uin,
-                                                                   double2* __restrict__ out, int gl, int trans) {
+                                                                   double2* __restrict__ out, int gl, int trans, int rhs, double inv,
+                                                                   double sigma, const double2* __restrict__ sh) {
   extern __shared__ double2 lds[];
   const int64_t w0 = (int64_t)blockIdx.x * S;
   const int Sb = (int)min((int64_t)S, nsys - w0);
@@ -672,7 +682,9 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_matvec(int N, int64_t
     const int s = t >> 1, p = t & 1;
     const double2* x = lds + s * stride;
     double2* o = out + (w0 + s) * (int64_t)N;
-    const double a = ca[w0 + s], b = cb[w0 + s];
+    const double2* so = sh ? sh + (w0 + s) * (int64_t)N : nullptr;
+    const double a = rhs ? rhs_a(ca[w0 + s], inv) : ca[w0 + s];
+    const double b = rhs ? rhs_b(ca[w0 + s], inv) : cb[w0 + s];
     if (!trans) {
       double2 sq = zero2(), ss = zero2(), u2 = zero2(), u4 = zero2();
       const int kl = last_of_parity(n, p);
@@ -689,6 +701,7 @@ __global__ __launch_bounds__(kChainThreads) void bih_chain_matvec(int N, int64_t
         v = c_fma(h.r, ss, v);
         if (k >= 2) v = c_fma(h.hm2, x[k - 2], v);
         if (k >= 4) v = c_fma(h.hm4, x[k - 4], v);
+        if (rhs) v = rhs_combine(v, sigma, so ? so + k : nullptr);
         o[k] = v;
         sq = c_fma(h.q4, u4, sq);
         ss = c_fma(h.s4, u4, ss);
@@ -997,7 +1010,8 @@ hipError_t launch_chain(const ChainArgs& a) {
                          a.gl, a.info);
       break;
     case ChainKind::HelmMatvec:
-      hipLaunchKernelGGL(helm_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.trans);
+      hipLaunchKernelGGL(helm_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.trans, a.rhs, a.inv,
+                         a.sigma, (const double2*)a.sh);
       break;
     case ChainKind::HelmMixed:
       hipLaunchKernelGGL(helm_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, f, u, a.gl, a.info, a.iters, a.it_max,
@@ -1011,7 +1025,8 @@ hipError_t launch_chain(const ChainArgs& a) {
                          a.g1, a.gl, a.info);
       break;
     case ChainKind::BihMatvec:
-      hipLaunchKernelGGL(bih_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.trans);
+      hipLaunchKernelGGL(bih_chain_matvec, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.trans, a.rhs,
+                         a.inv, a.sigma, (const double2*)a.sh);
       break;
     case ChainKind::BihMixed:
       hipLaunchKernelGGL(bih_chain_mixed, grid, block, lds, st, a.N, a.nsys, S, NP, a.c0, a.c1, f, u, a.gl, a.info, a.iters,

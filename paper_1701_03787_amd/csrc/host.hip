@@ -1,6 +1,8 @@
 // C-ABI layer: argument validation, kernel selection, launch on the caller's
 // stream.  See include/shenhip.h for the contract of every entry point.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -574,6 +576,130 @@ int biharmonic_matvec(int32_t N, int64_t nsys, const double* ca, const double* c
   a.trans = o.transpose;
   a.stream = o.stream;
   return run(a);
+}
+
+// Crank-Nicolson right-hand sides (Sec. 3, eqs. gfin and ufin) on the matvec
+// kernels: the coefficients the step maps K2 and 2/(nu dt) to are formed in
+// the kernels, the product is negated and sigma S(h) added on the way out.
+static int rhs_assemble(int family, int32_t N, int64_t nsys, const double* K2, double nu, double dt, const shen_c128* uhat,
+                        const shen_c128* sh, shen_c128* rhs, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (o.transpose) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || bad_nsys(nsys)) return SHEN_EINVAL;
+  if (!(nu > 0.0) || !(dt > 0.0) || !std::isfinite(2.0 / (nu * dt)) || !std::isfinite(2.0 / nu)) return SHEN_EINVAL;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(uhat) || check_rows(rhs) || check_coef(K2) || (sh && check_rows(sh))) return SHEN_EINVAL;
+  if ((const void*)uhat == (const void*)rhs || rows_overlap_partially(uhat, rhs, nsys, N)) return SHEN_EINVAL;
+  if (sh && (const void*)sh != (const void*)rhs && rows_overlap_partially(sh, rhs, nsys, N)) return SHEN_EINVAL;
+  const double inv = 2.0 / (nu * dt);
+  const double sigma = (family == SHEN_HELMHOLTZ ? 2.0 : -2.0) / nu;
+  if (o.variant != SHEN_VARIANT_CHAIN && shen::matvec_wave_supported(family, N)) {
+    shen::WaveArgs w;
+    w.family = family;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = K2;
+    w.c1 = K2;
+    w.f = uhat;
+    w.u = rhs;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    w.rhs = 1;
+    w.inv = inv;
+    w.sigma = sigma;
+    w.sh = sh;
+    DevInfo d;
+    const int rc2 = device_info(&d);
+    if (rc2 != SHEN_OK) return rc2;
+    return shen::launch_matvec_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+  }
+  ChainArgs a;
+  a.kind = family == SHEN_HELMHOLTZ ? ChainKind::HelmMatvec : ChainKind::BihMatvec;
+  a.N = N;
+  a.nsys = nsys;
+  a.c0 = K2;
+  a.c1 = K2;
+  a.f = uhat;
+  a.u = rhs;
+  a.gl = o.quad == SHEN_QUAD_GL;
+  a.trans = 0;
+  a.stream = o.stream;
+  a.rhs = 1;
+  a.inv = inv;
+  a.sigma = sigma;
+  a.sh = sh;
+  return run(a);
+}
+
+int helmholtz_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double dt, const shen_c128* ghat,
+                  const shen_c128* sh, shen_c128* rhs, const shen_opts* opts) {
+  return rhs_assemble(SHEN_HELMHOLTZ, N, nsys, K2, nu, dt, ghat, sh, rhs, opts);
+}
+int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double dt, const shen_c128* uhat,
+                   const shen_c128* sh, shen_c128* rhs, const shen_opts* opts) {
+  return rhs_assemble(SHEN_BIHARMONIC, N, nsys, K2, nu, dt, uhat, sh, rhs, opts);
+}
+
+// Shen transforms: validation, then the transform kernel (and, for the
+// forward transform of the Dirichlet and biharmonic spaces, the mass solve
+// in place on the scalar products).
+static int transform_args(int32_t N, int64_t nsys, int32_t space, const void* in, const void* out, const shen_opts& o,
+                          int dir, int forward_solve) {
+  if (check_opts(o)) return SHEN_EINVAL;
+  if (space != SHEN_SPACE_CHEBYSHEV && space != SHEN_SPACE_DIRICHLET && space != SHEN_SPACE_BIHARMONIC) return SHEN_EINVAL;
+  const int nmin = space == SHEN_SPACE_CHEBYSHEV ? 1 : (space == SHEN_SPACE_DIRICHLET ? 3 : 5);
+  if (N < nmin || bad_nsys(nsys) || o.transpose) return SHEN_EINVAL;
+  if (N > 2048) return SHEN_ENOTSUP;
+  if (dir == 0 && forward_solve && space != SHEN_SPACE_CHEBYSHEV && !shen::mass_wave_supported(N)) return SHEN_ENOTSUP;
+  if (nsys == 0) return SHEN_OK;
+  if (check_rows(in) || check_rows(out)) return SHEN_EINVAL;
+  if (in == out || rows_overlap_partially(in, out, nsys, N)) return SHEN_EINVAL;
+  const int gl = o.quad == SHEN_QUAD_GL;
+  if (!shen::transform_fft_ok(N, gl) && shen::transform_direct_lds(N, gl, nullptr) > 160 * 1024) return SHEN_ENOTSUP;
+  return SHEN_OK + 1;  // valid, work to do
+}
+
+int shen_scalar_product(int32_t N, int64_t nsys, int32_t space, const shen_c128* u, shen_c128* s, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  const int rc = transform_args(N, nsys, space, u, s, o, 0, 0);
+  if (rc <= 0) return rc;
+  DevInfo d;
+  const int rc2 = device_info(&d);
+  if (rc2 != SHEN_OK) return rc2;
+  return shen::launch_transform(N, nsys, space, 0, 0, o.quad == SHEN_QUAD_GL, u, s, o.stream) == hipSuccess ? SHEN_OK
+                                                                                                             : SHEN_ELAUNCH;
+}
+
+int shen_forward_transform(int32_t N, int64_t nsys, int32_t space, const shen_c128* u, shen_c128* uhat,
+                           const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  const int rc = transform_args(N, nsys, space, u, uhat, o, 0, 1);
+  if (rc <= 0) return rc;
+  DevInfo d;
+  const int rc2 = device_info(&d);
+  if (rc2 != SHEN_OK) return rc2;
+  const int chebyshev = space == SHEN_SPACE_CHEBYSHEV;
+  if (shen::launch_transform(N, nsys, space, 0, chebyshev, o.quad == SHEN_QUAD_GL, u, uhat, o.stream) != hipSuccess)
+    return SHEN_ELAUNCH;
+  if (chebyshev) return SHEN_OK;
+  shen_opts om = o;
+  om.variant = 0;
+  return mass_solve(space == SHEN_SPACE_DIRICHLET ? SHEN_HELMHOLTZ : SHEN_BIHARMONIC, N, nsys, uhat, uhat, &om);
+}
+
+int shen_backward_transform(int32_t N, int64_t nsys, int32_t space, const shen_c128* uhat, shen_c128* u,
+                            const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  const int rc = transform_args(N, nsys, space, uhat, u, o, 1, 0);
+  if (rc <= 0) return rc;
+  DevInfo d;
+  const int rc2 = device_info(&d);
+  if (rc2 != SHEN_OK) return rc2;
+  return shen::launch_transform(N, nsys, space, 1, 0, o.quad == SHEN_QUAD_GL, uhat, u, o.stream) == hipSuccess
+             ? SHEN_OK
+             : SHEN_ELAUNCH;
 }
 
 int dirichlet_mass_solve(int32_t N, int64_t nsys, const shen_c128* f, shen_c128* u, const shen_opts* opts) {

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "shenhip.h"
+
 namespace shen {
 
 enum class ChainKind { HelmSolve, HelmAdjoint, HelmMatvec, HelmMixed, BihSolve, BihAdjoint, BihMatvec, BihMixed };
@@ -28,6 +30,11 @@ struct ChainArgs {
   double tol = 1e-14;
   size_t lds_budget = 65536;
   void* stream = nullptr;
+  // matvec kernels: Crank-Nicolson right-hand side instead of H u (see RhsTerms)
+  int rhs = 0;
+  double inv = 0.0;
+  double sigma = 0.0;
+  const void* sh = nullptr;
 };
 
 struct WaveArgs {
@@ -59,6 +66,13 @@ struct WaveArgs {
   int fac_mode = 0;
   // mass solves (family 0 only): right-hand side Cbar f instead of f
   int deriv = 0;
+  // matvec kernels: Crank-Nicolson right-hand side sigma S(h) - H' u, where c0
+  // holds K2 per system and H' is the system matrix at the coefficients the
+  // step maps K2 and inv = 2/(nu dt) to; sh = S(h) rows or null
+  int rhs = 0;
+  double inv = 0.0;
+  double sigma = 0.0;
+  const void* sh = nullptr;
 };
 
 struct WaveCfg {
@@ -79,6 +93,13 @@ bool matvec_wave_supported(int family, int N);
 hipError_t launch_matvec_wave(const WaveArgs& a);
 bool mass_wave_supported(int N);
 hipError_t launch_mass_wave(const WaveArgs& a);  // family, N, nsys, f, u (may alias f), gl, stream
+
+// Shen transforms: dir 0 point values -> scalar products (solve: Chebyshev
+// coefficients), dir 1 Shen coefficients -> point values
+bool transform_fft_ok(int N, int gl);
+size_t transform_direct_lds(int N, int gl, int* sb_out);
+hipError_t launch_transform(int N, int64_t nsys, int space, int dir, int solve, int gl, const void* in, void* out,
+                            void* stream);
 
 size_t chain_bytes_per_system(ChainKind kind, int N);
 int chain_systems_per_block(ChainKind kind, int N, size_t lds_budget);

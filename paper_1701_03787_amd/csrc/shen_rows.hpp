@@ -230,6 +230,12 @@ __device__ __forceinline__ double2 c_fma(double s, double2 b, double2 a) {  // a
 __device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 c_mul(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// sigma s - v: a Crank-Nicolson right-hand side from the product v = H' u and
+// the scalar products s = S(h) (s == nullptr: -v)
+__device__ __forceinline__ double2 rhs_combine(double2 v, double sigma, const double2* s) {
+  const double2 m = make_double2(-v.x, -v.y);
+  return s ? c_fma(sigma, *s, m) : m;
+}
 __device__ __forceinline__ double c_abs1(double2 a) { return fmax(fabs(a.x), fabs(a.y)); }
 __device__ __forceinline__ double c_absf(float2 a) { return fmax(fabs((double)a.x), fabs((double)a.y)); }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
@@ -243,6 +249,19 @@ constexpr double kPivTiny = 0x1p-40;
 __device__ __forceinline__ bool bad_pivot(double d, double scale) { return !(fabs(d) > kPivTiny * scale) || !isfinite(d); }
 __device__ __forceinline__ double row_scale(const HelmRow& h) { return fabs(h.h0) + fabs(h.hm); }
 __device__ __forceinline__ double row_scale(const BihRow& h) { return fabs(h.h0) + fabs(h.hm2) + fabs(h.hm4); }
+
+// Right-hand side of one Crank-Nicolson step (Sec. 3, eqs. ufin and gfin) in
+// the scaling of the solves (the systems divided by nu dt/2, -nu dt/2).  With
+// inv = 2/(nu dt) and K2 the squared wavenumber:
+//   Helmholtz:  rhs = (2/nu) S(h) - (S + alpha' B) g,        alpha' = K2 - inv
+//   biharmonic: rhs = (-2/nu) S(h) - (Q + a' A + b' B) u,    a' = inv - 2 K2,
+//                                                           b' = K2 (K2 - inv)
+// (2/(nu dt) (2B - Hbar) = -(S + alpha' B) and -2/(nu dt) (2A - 2 K2 B - Hchk)
+// = -(Q + a' A + b' B) for the matrices of eqs. Helmholtz_matrix and
+// Biharmonic_matrix.)
+__device__ __forceinline__ double rhs_alpha(double K2, double inv) { return K2 - inv; }
+__device__ __forceinline__ double rhs_a(double K2, double inv) { return __builtin_fma(-2.0, K2, inv); }
+__device__ __forceinline__ double rhs_b(double K2, double inv) { return K2 * (K2 - inv); }
 
 // Stopping rule of the FP64-residual refinement, shared by every mixed
 // kernel.  After solve number `it` (0: the first FP32 solve, then one per

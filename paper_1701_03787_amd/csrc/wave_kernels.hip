@@ -2689,6 +2689,34 @@ __device__ __forceinline__ void store_tile(const double2* T, int lane, int64_t g
   }
 }
 
+// As store_tile, for the Crank-Nicolson right-hand side: the staged rows hold
+// -H'u, and sigma S(h) (rows of sh, when given) is added on the way out.
+template <int C, int G>
+__device__ __forceinline__ void store_tile_rhs(const double2* T, int lane, int64_t g, int N, int n, int64_t nsys,
+                                               double2* __restrict__ u, double sigma, const double2* __restrict__ sh) {
+  using TL = Tile<C, G>;
+  double2 v[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) v[i] = T[64 * i + lane];
+  asm volatile("" ::: "memory");
+  if (sh != nullptr) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const int s = i / TL::NB;
+      const int64_t w = g * TL::SPW + s;
+      const int k = TL::row(i, lane);
+      if (w < nsys && k < n) v[i] = c_fma(sigma, sh[w * (int64_t)N + k], v[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int s = i / TL::NB;
+    const int64_t w = g * TL::SPW + s;
+    const int k = TL::row(i, lane);
+    if (w < nsys && k < N) u[w * (int64_t)N + k] = (k < n) ? v[i] : zero2();
+  }
+}
+
 template <int C, int G>
 __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
                                                      const double2* __restrict__ f, double2* __restrict__ u,
@@ -2868,9 +2896,14 @@ __device__ __forceinline__ void read_tile_rows(const double2* T, int lane, int n
   }
 }
 
-template <int C, int G>
+// RHS: alpha holds K2 per system, and the kernel writes the Crank-Nicolson
+// right-hand side sigma S(h) - (S + alpha' B) u, alpha' = K2 - inv (sh = S(h)
+// rows, or null), instead of H u.
+template <int C, int G, bool RHS = false>
 __global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                       const double2* __restrict__ uin, double2* __restrict__ hu, int gl) {
+                                                       const double2* __restrict__ uin, double2* __restrict__ hu, int gl,
+                                                       double inv = 0.0, double sigma = 0.0,
+                                                       const double2* __restrict__ sh = nullptr) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
   __shared__ double2 tile[(C + 1) * 64];
@@ -2899,9 +2932,14 @@ __global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double al, unused;
     read_coef2(coef, lane, al, unused);
-    helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = v; });
+    if constexpr (RHS) al = rhs_alpha(al, inv);
+    helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = RHS ? make_double2(-v.x, -v.y) : v; });
     stage_tile<C, G>(tile, lane, y);
-    store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
+    if constexpr (RHS) {
+      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, sh);
+    } else {
+      store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
+    }
     const int64_t gn = g + gridDim.x;
     if (gn < ngroups) {
       prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
@@ -2911,10 +2949,14 @@ __global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, cons
   }
 }
 
-template <int C, int G>
+// RHS: ca holds K2 per system, and the kernel writes the Crank-Nicolson
+// right-hand side sigma S(h) - (Q + a' A + b' B) u, a' = inv - 2 K2,
+// b' = K2 (K2 - inv) (sh = S(h) rows, or null), instead of H u.
+template <int C, int G, bool RHS = false>
 __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, const double* __restrict__ ca,
                                                        const double* __restrict__ cb, const double2* __restrict__ uin,
-                                                       double2* __restrict__ hu, int gl) {
+                                                       double2* __restrict__ hu, int gl, double inv = 0.0, double sigma = 0.0,
+                                                       const double2* __restrict__ sh = nullptr) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
   constexpr int RT = 2 * G * C;
@@ -2950,9 +2992,18 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double a, b;
     read_coef2(coef, lane, a, b);
-    bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = v; });
+    if constexpr (RHS) {
+      const double K2 = a;
+      a = rhs_a(K2, inv);
+      b = rhs_b(K2, inv);
+    }
+    bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = RHS ? make_double2(-v.x, -v.y) : v; });
     stage_tile<C, G>(tile, lane, y);
-    store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
+    if constexpr (RHS) {
+      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, sh);
+    } else {
+      store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
+    }
     const int64_t gn = g + stride;
     if (gn < ngroups) {
       prefetch_tile<C, G, 0>(tile, lane, gn, N, nsys, uin, nullptr, 0);
@@ -3583,19 +3634,33 @@ static hipError_t launch_matvec_t(const WaveArgs& a) {
     const int64_t groups = (a.nsys + SPW - 1) / SPW;
     const double2* uin = (const double2*)a.f;
     double2* hu = (double2*)a.u;
+    const double2* sh = (const double2*)a.sh;
     if (a.family == 0) {
-      const int64_t blocks = persistent_blocks((const void*)helm_matvec_pipe<C, G>, groups);
-      hipLaunchKernelGGL((helm_matvec_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, uin, hu, a.gl);
+      if (a.rhs) {
+        const int64_t blocks = persistent_blocks((const void*)helm_matvec_pipe<C, G, true>, groups);
+        hipLaunchKernelGGL((helm_matvec_pipe<C, G, true>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, uin, hu,
+                           a.gl, a.inv, a.sigma, sh);
+      } else {
+        const int64_t blocks = persistent_blocks((const void*)helm_matvec_pipe<C, G>, groups);
+        hipLaunchKernelGGL((helm_matvec_pipe<C, G>), dim3((unsigned)blocks), dim3(64), 0, st, a.N, a.nsys, a.c0, uin, hu, a.gl,
+                           0.0, 0.0, nullptr);
+      }
     } else {
       constexpr size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 1) * 64 * sizeof(double2);
       if constexpr (lds > 160 * 1024) {
         return hipErrorInvalidValue;
+      } else if (a.rhs) {
+        static const bool attr = set_dynamic_lds((const void*)bih_matvec_ptab<C, G, true>, lds);
+        (void)attr;
+        const int64_t blocks = persistent_blocks((const void*)bih_matvec_ptab<C, G, true>, (groups + 3) / 4, 256, lds);
+        hipLaunchKernelGGL((bih_matvec_ptab<C, G, true>), dim3((unsigned)blocks), dim3(256), lds, st, a.N, a.nsys, a.c0, a.c0,
+                           uin, hu, a.gl, a.inv, a.sigma, sh);
       } else {
         static const bool attr = set_dynamic_lds((const void*)bih_matvec_ptab<C, G>, lds);
         (void)attr;
         const int64_t blocks = persistent_blocks((const void*)bih_matvec_ptab<C, G>, (groups + 3) / 4, 256, lds);
         hipLaunchKernelGGL((bih_matvec_ptab<C, G>), dim3((unsigned)blocks), dim3(256), lds, st, a.N, a.nsys, a.c0, a.c1, uin,
-                           hu, a.gl);
+                           hu, a.gl, 0.0, 0.0, nullptr);
       }
     }
     return hipGetLastError();

@@ -226,3 +226,22 @@ def test_derivative_solve_argument_errors():
     assert fn(1025, 4, ALIGNED, ALIGNED + (1 << 20), C.byref(o)) == L.SHEN_ENOTSUP     # beyond N = 1024
     assert fn(16, 0, None, None, C.byref(o)) == L.SHEN_OK
     assert fn(16, 4, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EDEVICE                  # in place reaches the device
+
+
+def test_rhs_argument_errors():
+    """Crank-Nicolson right-hand sides: nu, dt > 0, no transpose, no aliasing of uhat."""
+    lib = L.lib()
+    A, B, S = ALIGNED, ALIGNED + (1 << 16), ALIGNED + (2 << 16)
+    for fn in (lib.helmholtz_rhs, lib.biharmonic_rhs):
+        o = L.default_opts()
+        assert fn(16, 4, A, 0.0, 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL       # nu = 0
+        assert fn(16, 4, A, 5e-5, -1.0, B, None, S, C.byref(o)) == L.SHEN_EINVAL      # dt < 0
+        assert fn(16, 4, A, float("nan"), 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL
+        assert fn(16, 4, A, 1e-300, 1e-300, B, None, S, C.byref(o)) == L.SHEN_EINVAL  # 2/(nu dt) overflows
+        assert fn(16, 4, A, 5e-5, 5e-4, B, None, B, C.byref(o)) == L.SHEN_EINVAL      # rhs == uhat
+        assert fn(16, 4, A, 5e-5, 5e-4, B, S + 16, S, C.byref(o)) == L.SHEN_EINVAL    # sh overlaps rhs partially
+        assert fn(16, 4, A + 4, 5e-5, 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL  # misaligned K2
+        assert fn(2, 4, A, 5e-5, 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL
+        assert fn(16, 0, None, 5e-5, 5e-4, None, None, None, C.byref(o)) == L.SHEN_OK
+        o.transpose = 1
+        assert fn(16, 4, A, 5e-5, 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL
