@@ -524,42 +524,49 @@ __device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, d
 // States of chunk m go to st[(p G + m) 10 + 0..9] (FP64, or FP32 with F32).
 // Each wavefront of a block walks chains of one parity, so every step reads
 // one table row for the whole wavefront (broadcast).
+// The FP64 walk (F32 false) also checks every pivot of the chain, the last
+// chunk's included, with the wave solves' rule, and leaves the first unusable
+// row (or -1) in the unused state slot of chunk 0, so that the wave solves
+// need not check their rows again.
 template <int C, int G, bool F32>
 __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, void* st, int gl, const double* tab) {
   constexpr int RT = 2 * G * C;
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
   const int nchunks = (nc + C - 1) / C;
-  if (nchunks <= 1) return;
+  if (F32 && nchunks <= 1) return;
   // only the constants of rows k-2 (B2, q4, s4) and k-4 (B4) are carried
   const BihConst c2 = bih_const_at(tab, RT, C, p - 2, N, gl), c4 = bih_const_at(tab, RT, C, p - 4, N, gl);
   double B2m2 = c2.B2, q4m2 = c2.q4, s4m2 = c2.s4, B4m2 = c2.B4, B4m4 = c4.B4;
   using State = typename std::conditional<F32, BihRowState32, BihRowState>::type;
   State m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  int bad = INT_MAX;
+  auto row = [&](int i) {
+    const int k = 2 * i + p;
+    const BihConst c = bih_tab_get(tab, RT, C, k);
+    const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
+    State o;
+    if constexpr (F32) {
+      float l1, l2, t0;
+      bih_step_row32(h, m2, m4, o, l1, l2, t0);
+    } else {
+      double l1, l2, t0, sc;
+      bih_step_row(h, m2, m4, o, l1, l2, t0, sc);
+      if (i < nc && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+    }
+    m4 = m2;
+    m2 = o;
+    B4m4 = B4m2;
+    B4m2 = c.B4;
+    B2m2 = c.B2;
+    q4m2 = c.q4;
+    s4m2 = c.s4;
+  };
   // one chunk of rows per iteration (unrolled, so the carried state is
   // renamed rather than copied), then the restart state of the next chunk
   for (int mm = 1; mm < nchunks; ++mm) {
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const int k = 2 * ((mm - 1) * C + j) + p;
-      const BihConst c = bih_tab_get(tab, RT, C, k);
-      const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
-      State o;
-      if constexpr (F32) {
-        float l1, l2, t0;
-        bih_step_row32(h, m2, m4, o, l1, l2, t0);
-      } else {
-        double l1, l2, t0;
-        bih_step_row(h, m2, m4, o, l1, l2, t0);
-      }
-      m4 = m2;
-      m2 = o;
-      B4m4 = B4m2;
-      B4m2 = c.B4;
-      B2m2 = c.B2;
-      q4m2 = c.q4;
-      s4m2 = c.s4;
-    }
+    for (int j = 0; j < C; ++j) row((mm - 1) * C + j);
     if constexpr (F32) {
       float2* sv = reinterpret_cast<float2*>(reinterpret_cast<float*>(st) + (p * G + mm) * 10);
       sv[0] = make_float2(m2.rU0, m2.U2);
@@ -576,7 +583,17 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
       sv[4] = make_double2(m4.P, m4.R);
     }
   }
+  if constexpr (!F32) {
+    const int i0 = (nchunks > 1 ? nchunks - 1 : 0) * C;
+    for (int i = i0; i < nc; ++i) row(i);
+    double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G) * 10);
+    sv[0] = make_double2(bad == INT_MAX ? -1.0 : (double)bad, 0.0);
+  }
 }
+
+// First unusable row of chain lane (m == 0) from the walk's slot of chunk 0
+// (INT_MAX: none, or not a chunk-0 lane).
+__device__ __forceinline__ int walk_bad_of(double v, bool chunk0) { return (chunk0 && v >= 0.0) ? (int)v : INT_MAX; }
 
 // Six wavefronts (three pairs of parities, 192 systems) share one table.  At
 // most three tables fit a CU, so every block of a channel-size launch is
@@ -1342,10 +1359,11 @@ template <typename F, typename = void>
 struct LazyFetch : std::false_type {};
 template <typename F>
 struct LazyFetch<F, std::void_t<decltype(F::lazy)>> : std::bool_constant<F::lazy> {};
-template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook>
+template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook, bool WALKINFO = false>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
-                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook());
+                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook(),
+                                              std::bool_constant<WALKINFO> = {}, int walk_bad = INT_MAX);
 
 template <int C, int G, bool TAB = false>
 __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ ca,
@@ -1373,6 +1391,9 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
     m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
   }
+  // the table-driven walk has checked the pivots (slot of chunk 0)
+  int wb = INT_MAX;
+  if (TAB && wok && m == 0) wb = walk_bad_of(sts[w * sstride + p * G * 5].x, true);
   double2 x[C];
 #pragma unroll
   for (int j = 0; j < C; ++j) {
@@ -1383,17 +1404,23 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
     const int k = k0 + 2 * j;
     return (wok && k < n) ? frow[k] : zero2();
   };
-  bih_wave_core<C, G, false, TAB>(N, lane, w, wok, a, b, m2, m4, x, fetch, urow, gl, info, tab);
+  bih_wave_core<C, G, false, TAB>(N, lane, w, wok, a, b, m2, m4, x, fetch, urow, gl, info, tab, NoHook(),
+                                  std::bool_constant<TAB>{}, wb);
 }
 
 // Everything after the loads: x holds f of this lane's chunk (0 where k >= n),
 // m2/m4 the restart state, fetch_f(j) gives f of chunk element j again (the
 // forward refinement sweep).  Without PIPE the solution is stored to urow;
 // with PIPE it is left in x for the caller.
-template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook>
+// WALKINFO: the boundary walk has already checked every pivot of the chain
+// (it runs the same factorisation) and walk_bad holds, on the lanes of chunk
+// 0, the first unusable row of the lane's chain (INT_MAX: none); the rows of
+// the chunk are then not checked again.
+template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook, bool WALKINFO>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
-                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f) {
+                                              int gl, int32_t* __restrict__ info, const double* tab, Hook after_f,
+                                              std::bool_constant<WALKINFO>, int walk_bad) {
   const int p = (lane / G) & 1;
   const int m = lane % G;
   const int n = N - 4;
@@ -1408,7 +1435,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     const double k6 = (double)(k0 + 2 * j) + 6.0;
     return make_double2(q4j[TAB ? 0 : j], k6 * k6 * q4j[TAB ? 0 : j]);
   };
-  int bad = INT_MAX;
+  int bad = WALKINFO ? walk_bad : INT_MAX;
   double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
   double2 y1 = zero2(), y2 = zero2();  // y_{i-1}, y_{i-2}
   Recip Rc;
@@ -1435,7 +1462,9 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0, sc);
       q4j[TAB ? 0 : j] = Rc.p7;  // q_{k+4} = 1/(k+7)
     }
-    if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+    if constexpr (!WALKINFO) {
+      if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+    }
     m4 = m2;
     m2 = o;
     // Table rows past the system are identity rows (zero l, unit pivot, no
@@ -2855,7 +2884,7 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
     };
     double2* urow = u + (wok ? w : 0) * (int64_t)N;
     bih_wave_core<C, G, true, true>(N, lane, w, wok, wok ? ca_ : 0.0, wok ? cb_ : 0.0, m2, m4, x, fetch, urow, gl, info, tab,
-                                    prefetch_next);
+                                    prefetch_next, std::true_type{}, walk_bad_of(st[0].x, wok && m == 0));
     // The next group has landed.  This group's solution is stored only after
     // this wait, so that the wait does not include the acknowledgement of
     // its stores; they complete while the next group is solved.
