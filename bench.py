@@ -105,7 +105,7 @@ def measure_batched(dev, args):
             units += g.nsys * g.N
             nbytes += alg_bytes(fam, g.N, g.nsys)
             del f
-    solver = BatchedSolver(probs)
+    solver = BatchedSolver(probs)  # autotuned (chunk, systems per work item) per (family, N)
     solver.capture()
     for _ in range(max(1, args.warmup)):
         solver.replay()
@@ -125,7 +125,9 @@ def measure_batched(dev, args):
         err = max(err, float(so.rel_err_per_system(u, so.solve(fam, N, cs, f)).max()))
     out = {"workload": "48 grids, N in {64..1024}, both families", "problems": len(probs), "ms_per_launch": round(ms, 4),
            "value": round(units / (ms * 1e-3), 2), "unit": "system·N/s",
-           "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "max_rel_err_sampled": err, "graph_replays": reps}
+           "hbm_gbps": round(nbytes / (ms * 1e-3) / 1e9, 2), "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "bytes_per_launch": int(nbytes), "max_rel_err_sampled": err, "graph_replays": reps,
+           "autotuned": solver.configurations()}
     del solver, probs
     torch.cuda.empty_cache()
     return out

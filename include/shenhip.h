@@ -140,6 +140,13 @@ const char* shen_status_string(int code);
  * family and precision (depends on the device's LDS size). */
 int32_t shen_max_n(int32_t family, int32_t precision);
 
+/* The wave-kernel configuration the solves of (family, N) use with chunk
+ * length `chunk` (0 = automatic): *C rows per lane and parity chain, *G lanes
+ * per chain (2G lanes per system).  Returns SHEN_OK, or SHEN_EINVAL when the
+ * chunk is not offered for (family, N), or SHEN_ENOTSUP when (family, N) has
+ * no wave configuration (the chain kernels serve it). */
+int shen_wave_config(int32_t family, int32_t N, int32_t chunk, int32_t* C, int32_t* G);
+
 /*
  * Helmholtz solve (Sec. 4, the odd/even upper-Hessenberg LU with the
  * constant tail of U):  (S + alpha_w B) u_w = f_w  for w < nsys,
@@ -361,8 +368,9 @@ typedef struct {
   shen_c128* u;
   int32_t* info;
   int64_t tile_begin; /* filled by shen_batched_plan: first work item       */
-  int32_t sys_per_tile; /* filled by shen_batched_plan                      */
-  int32_t reserved;
+  int32_t sys_per_tile; /* systems per work item; 0 = 32 (plan fills it)    */
+  int32_t chunk;        /* wave-kernel chunk length for this grid (as
+                           opts.chunk of the solves); 0 = automatic         */
 } shen_problem;
 
 /* Host-side planning: fills tile_begin / sys_per_tile of each HOST

@@ -54,7 +54,7 @@ class ShenProblem(C.Structure):
         ("info", C.c_void_p),
         ("tile_begin", C.c_int64),
         ("sys_per_tile", C.c_int32),
-        ("reserved", C.c_int32),
+        ("chunk", C.c_int32),
     ]
 
 
@@ -65,6 +65,7 @@ SIGNATURES = [
     ("shen_abi_version", C.c_int, []),
     ("shen_status_string", C.c_char_p, [C.c_int]),
     ("shen_max_n", C.c_int32, [C.c_int32, C.c_int32]),
+    ("shen_wave_config", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("helmholtz_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("biharmonic_solve", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),
     ("helmholtz_adjoint", C.c_int, [C.c_int32, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.POINTER(ShenOpts)]),

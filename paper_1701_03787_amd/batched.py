@@ -1,13 +1,17 @@
 """Batched form: many independent grids (uneven N, both families) in one
 persistent launch, optionally captured once in a hipGraph and replayed.
 
-Tile sizes (systems per work item) are chosen per (family, N) by a small
-autotuner that times candidate tiles on the device and caches the winners in
-a JSON file (env SHENHIP_AUTOTUNE_CACHE, default ~/.cache/shenhip/autotune.json).
+Per (family, N) an autotuner picks the two knobs of the launch: the chunk
+length of the wave kernels, which fixes their configuration (C rows per lane
+and parity chain, G lanes per chain, hence systems per wavefront), and the
+number of systems per work item of the dynamic queue.  It times every offered
+combination on the device and caches the winners in a JSON file (env
+SHENHIP_AUTOTUNE_CACHE, default ~/.cache/shenhip/autotune.json).
 """
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import json
 import os
 import time
@@ -19,8 +23,28 @@ import torch
 from . import _lib as L
 from .api import _QUAD
 
-TILE_CANDIDATES = (4, 8, 16, 32, 64)
+TILE_CANDIDATES = (8, 16, 32, 64, 128)
+CHUNK_CANDIDATES = (4, 8, 16)
 DEFAULT_TILE = 32
+
+
+def wave_config(family: str, N: int, chunk: int = 0):
+    """(C, G) of the wave kernels for (family, N) at this chunk length, or None if not offered."""
+    c, g = C.c_int32(0), C.c_int32(0)
+    fam = L.SHEN_HELMHOLTZ if family == "helmholtz" else L.SHEN_BIHARMONIC
+    rc = L.lib().shen_wave_config(fam, int(N), int(chunk), C.byref(c), C.byref(g))
+    return (int(c.value), int(g.value)) if rc == L.SHEN_OK else None
+
+
+def chunk_candidates(family: str, N: int):
+    """The chunk lengths offered for (family, N), one per distinct configuration."""
+    out, seen = [], set()
+    for ch in CHUNK_CANDIDATES:
+        cfg = wave_config(family, N, ch)
+        if cfg is not None and cfg[0] == ch and cfg not in seen:
+            seen.add(cfg)
+            out.append(ch)
+    return out or [0]
 
 
 @dataclass
@@ -34,6 +58,7 @@ class BatchedProblem:
     u: Optional[torch.Tensor] = None
     info: Optional[torch.Tensor] = None
     tile: int = 0
+    chunk: int = 0
 
     def __post_init__(self):
         if self.family not in ("helmholtz", "biharmonic"):
@@ -81,7 +106,7 @@ def _arch(device) -> str:
 
 
 class Autotuner:
-    """Per (arch, family, N) choice of the tile size of the persistent kernel."""
+    """Per (arch, family, N, quadrature) choice of the chunk length and the systems per work item."""
 
     def __init__(self, path: Optional[str] = None):
         self.path = path or _cache_path()
@@ -93,15 +118,18 @@ class Autotuner:
             except (OSError, ValueError):
                 self.table = {}
 
-    def key(self, device, family, N) -> str:
-        return f"{_arch(device)}|{family}|{N}"
+    def key(self, device, family, N, quad="gc") -> str:
+        return f"{_arch(device)}|{family}|{N}|{quad}"
 
-    def get(self, device, family, N) -> Optional[int]:
-        v = self.table.get(self.key(device, family, N))
-        return int(v["tile"]) if v else None
+    def get(self, device, family, N, quad="gc"):
+        """(chunk, tile) from the cache, or None."""
+        v = self.table.get(self.key(device, family, N, quad))
+        if not v or "chunk" not in v:
+            return None
+        return int(v["chunk"]), int(v["tile"])
 
-    def tune(self, device, family: str, N: int, nsys: int = 4096, reps: int = 3, quad="gc") -> int:
-        """Time every candidate tile on a synthetic grid of the given shape; store the best."""
+    def tune(self, device, family: str, N: int, nsys: int = 4096, reps: int = 3, quad="gc"):
+        """Time every offered (chunk, tile) on a synthetic grid of the given shape; store and return the best."""
         g = torch.Generator(device="cpu").manual_seed(1701 + N)
         f = torch.randn((nsys, N), dtype=torch.complex128, generator=g).to(device)
         K2 = torch.arange(nsys, dtype=torch.float64) % 4096
@@ -110,21 +138,22 @@ class Autotuner:
             coeffs = [(K2 + inv).to(device)]
         else:
             coeffs = [(-(2 * K2 + inv)).to(device), (K2 * (K2 + inv)).to(device)]
-        best, best_t = DEFAULT_TILE, float("inf")
+        best, best_t = (0, DEFAULT_TILE), float("inf")
         timings = {}
-        for tile in TILE_CANDIDATES:
-            solver = BatchedSolver([BatchedProblem(family, f, coeffs, tile=tile)], quad=quad, autotune=False)
+        for chunk, tile in itertools.product(chunk_candidates(family, N), TILE_CANDIDATES):
+            solver = BatchedSolver([BatchedProblem(family, f, coeffs, tile=tile, chunk=chunk)], quad=quad, autotune=False)
             solver.run()
-            torch.cuda.synchronize()
+            torch.cuda.synchronize(device)
             t0 = time.perf_counter()
             for _ in range(reps):
                 solver.run()
-            torch.cuda.synchronize()
+            torch.cuda.synchronize(device)
             dt = (time.perf_counter() - t0) / reps
-            timings[tile] = dt
+            timings[f"{chunk},{tile}"] = dt
             if dt < best_t:
-                best, best_t = tile, dt
-        self.table[self.key(device, family, N)] = {"tile": best, "seconds": timings}
+                best, best_t = (chunk, tile), dt
+            del solver
+        self.table[self.key(device, family, N, quad)] = {"chunk": best[0], "tile": best[1], "seconds": timings}
         self.save()
         return best
 
@@ -142,8 +171,10 @@ class Autotuner:
 class BatchedSolver:
     """Plans a batch of problems once; run() enqueues the single persistent launch."""
 
-    def __init__(self, problems: List[BatchedProblem], quad: str = "gc", autotune: bool = False,
+    def __init__(self, problems: List[BatchedProblem], quad: str = "gc", autotune: bool = True,
                  tuner: Optional[Autotuner] = None):
+        """autotune: pick (chunk, tile) per (family, N) with the tuner where a problem leaves them
+        at 0 (cached per device); otherwise chunk 0 (automatic) and DEFAULT_TILE."""
         if not problems:
             raise ValueError("empty batch")
         self.device = problems[0].f.device
@@ -165,10 +196,13 @@ class BatchedSolver:
             d.f = p.f.data_ptr()
             d.u = p.u.data_ptr()
             d.info = p.info.data_ptr() if p.info is not None else None
-            tile = p.tile
-            if tile <= 0 and tuner is not None:
-                tile = tuner.get(self.device, p.family, p.N) or tuner.tune(self.device, p.family, p.N, quad=quad)
+            tile, chunk = p.tile, p.chunk
+            if tuner is not None and (tile <= 0 or chunk <= 0):
+                got = tuner.get(self.device, p.family, p.N, quad) or tuner.tune(self.device, p.family, p.N, quad=quad)
+                chunk = chunk if chunk > 0 else got[0]
+                tile = tile if tile > 0 else got[1]
             d.sys_per_tile = tile if tile > 0 else DEFAULT_TILE
+            d.chunk = max(0, chunk)
         o = self._opts()
         total = L.lib().shen_batched_plan(host, n, C.byref(o))
         if total < 0:
@@ -180,7 +214,17 @@ class BatchedSolver:
         nbytes = int(L.lib().shen_batched_work_bytes(n))
         self.work = torch.zeros((nbytes + 7) // 8, dtype=torch.int64, device=self.device)
         self.tiles = [host[i].sys_per_tile for i in range(n)]
+        self.chunks = [host[i].chunk for i in range(n)]
         self.graph = None
+
+    def configurations(self):
+        """The chosen knobs per (family, N): chunk, the (C, G) it gives, systems per work item."""
+        out = {}
+        for p, tile, chunk in zip(self.problems, self.tiles, self.chunks):
+            cfg = wave_config(p.family, p.N, chunk)
+            out[f"{p.family}|{p.N}"] = {"chunk": chunk, "C": cfg[0] if cfg else None, "G": cfg[1] if cfg else None,
+                                        "sys_per_tile": tile}
+        return out
 
     def _opts(self):
         o = L.default_opts()

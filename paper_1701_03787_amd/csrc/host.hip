@@ -271,6 +271,17 @@ const char* shen_status_string(int code) {
   }
 }
 
+int shen_wave_config(int32_t family, int32_t N, int32_t chunk, int32_t* C, int32_t* G) {
+  if (family != SHEN_HELMHOLTZ && family != SHEN_BIHARMONIC) return SHEN_EINVAL;
+  if (N < (family == SHEN_HELMHOLTZ ? 3 : 5) || chunk < 0 || chunk > 64) return SHEN_EINVAL;
+  if (!shen::wave_supported(family, N)) return SHEN_ENOTSUP;
+  if (!shen::wave_chunk_ok(family, N, chunk)) return SHEN_EINVAL;
+  const shen::WaveCfg c = shen::pick_cfg((N + 1) / 2, family, N, chunk);
+  if (C) *C = c.C;
+  if (G) *G = c.G;
+  return SHEN_OK;
+}
+
 int32_t shen_max_n(int32_t family, int32_t precision) {
   DevInfo d;
   if (device_info(&d) != SHEN_OK) return SHEN_EDEVICE;
@@ -728,6 +739,7 @@ int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* op
       if ((const void*)d.f == (const void*)d.u || rows_overlap_partially(d.f, d.u, d.nsys, d.N)) return SHEN_EINVAL;
     }
     if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
+    if (d.chunk < 0 || d.chunk > 64 || !shen::wave_chunk_ok(d.family, d.N, d.chunk)) return SHEN_EINVAL;
     if (d.sys_per_tile <= 0) d.sys_per_tile = 32;
     if (d.sys_per_tile > 1024) return SHEN_EINVAL;
     d.tile_begin = total;

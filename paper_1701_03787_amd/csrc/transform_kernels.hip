@@ -51,7 +51,7 @@ __device__ __forceinline__ double2 rot90(double2 a) {
 
 // In-register DFTs of length 2, 4, 8 with kernel exp(-+2 pi i r k / R).
 template <int R, bool INV>
-__device__ __forceinline__ void dft(double2 (&v)[8]) {
+__device__ __forceinline__ void dft(double2 (&v)[R]) {
   if constexpr (R == 2) {
     const double2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
@@ -65,7 +65,7 @@ __device__ __forceinline__ void dft(double2 (&v)[8]) {
     v[3] = csub(d02, d13);
   } else {
     // two length-4 DFTs over the even and odd samples, then one radix-2 step
-    double2 e[8] = {v[0], v[2], v[4], v[6]}, o[8] = {v[1], v[3], v[5], v[7]};
+    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
     dft<4, INV>(e);
     dft<4, INV>(o);
     constexpr double h = 0.70710678118654752440084436210485;  // 1/sqrt(2)
@@ -83,39 +83,56 @@ __device__ __forceinline__ void dft(double2 (&v)[8]) {
   }
 }
 
+// LDS slot of point e of the batch: one pad slot per 8 points, so that the
+// first pass's writes (stride R points) and every other access (consecutive
+// points per 8-lane group) fall in distinct 16-byte bank groups.
+__device__ __forceinline__ int lp(int e) { return e + (e >> 3); }
+constexpr int kTfSlots = kTfPoints + kTfPoints / 8;
+
+// Radix of pass number `pass` (Ns = product of the earlier radices): 8 while
+// at least 8 points per sequence remain, then 4 or 2.
+__device__ __host__ __forceinline__ int pass_radix(int N, int Ns) {
+  const int left = N / Ns;
+  return left >= 8 ? 8 : left;
+}
+
 // One Stockham pass of radix R over SB sequences of length N held in buf:
 // butterfly j of a sequence reads x[j + r N/R], multiplies by w^(r (j mod Ns))
 // with w = exp(-+2 pi i / (Ns R)), transforms, and writes
 // y[(j / Ns) Ns R + (j mod Ns) + r Ns].  The pass reads everything into
 // registers, waits, then overwrites buf (one buffer, two barriers).
-// tw[q] = exp(-2 pi i q / N), q < N.
+// tw: this pass's twiddles, w^(jm r) at tw[jm (R-1) + r - 1], jm < Ns.
+// N, Ns and R are powers of two: lgN = log2 N, lgNs = log2 Ns (index
+// arithmetic by shifts and masks).
 template <int R, bool INV>
-__device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int N, int Ns, int SB) {
+__device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lgN, int lgNs, int SB, int tid) {
   constexpr int PER = 8 / R;  // butterflies per thread (8 points per thread)
-  const int nb = N / R;       // butterflies per sequence
+  constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  const int N = 1 << lgN, Ns = 1 << lgNs;
+  const int lgnb = lgN - lgR;
+  const int nb = 1 << lgnb;  // butterflies per sequence
   const int total = SB * nb;
-  double2 v[PER][8];
+  double2 v[PER][R];
   int dst[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int b = threadIdx.x + t * kTfThreads;
+    const int b = tid + t * kTfThreads;
     dst[t] = -1;
     if (b < total) {
-      const int s = b / nb, j = b - s * nb;
-      double2* x = buf + s * N;
-      const int jm = j % Ns;
-      const int step = (N / (Ns * R)) * jm;  // twiddle index step per r
+      const int s = b >> lgnb, j = b & (nb - 1);
+      const int base = s << lgN;
+      const int jm = j & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double2 a = x[j + r * nb];
+        double2 a = buf[lp(base + j + r * nb)];
         if (r > 0 && jm > 0) {
-          const double2 w = tw[(step * r) & (N - 1)];
+          const double2 w = tw[jm * (R - 1) + r - 1];
           a = cmul(a, INV ? cconj(w) : w);
         }
         v[t][r] = a;
       }
       dft<R, INV>(v[t]);
-      dst[t] = s * N + (j / Ns) * Ns * R + jm;
+      dst[t] = base + ((j >> lgNs) << (lgNs + lgR)) + jm;
     }
   }
   __syncthreads();
@@ -123,27 +140,48 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int N,
   for (int t = 0; t < PER; ++t) {
     if (dst[t] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[t] + r * Ns] = v[t][r];
+      for (int r = 0; r < R; ++r) buf[lp(dst[t] + r * Ns)] = v[t][r];
     }
   }
   __syncthreads();
 }
 
 template <bool INV>
-__device__ __forceinline__ void fft_all(double2* buf, const double2* tw, int N, int SB) {
-  int Ns = 1;
-  while (Ns < N) {
-    const int left = N / Ns;
-    if (left >= 8) {
-      fft_pass<8, INV>(buf, tw, N, Ns, SB);
-      Ns *= 8;
-    } else if (left == 4) {
-      fft_pass<4, INV>(buf, tw, N, Ns, SB);
-      Ns *= 4;
+__device__ __forceinline__ void fft_all(double2* buf, const double2* tw, int lgN, int SB, int tid) {
+  int lgNs = 0, off = 0;
+  while (lgNs < lgN) {
+    const int left = lgN - lgNs;
+    if (left >= 3) {
+      fft_pass<8, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      off += 7 << lgNs;
+      lgNs += 3;
+    } else if (left == 2) {
+      fft_pass<4, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      off += 3 << lgNs;
+      lgNs += 2;
     } else {
-      fft_pass<2, INV>(buf, tw, N, Ns, SB);
-      Ns *= 2;
+      fft_pass<2, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      off += 1 << lgNs;
+      lgNs += 1;
     }
+  }
+}
+
+// Twiddles of every pass, pass after pass: exp(-2 pi i jm r / (Ns R)) at
+// off + jm (R-1) + r - 1 (N - 1 entries in all).
+__device__ __forceinline__ void fill_twiddles(double2* tw, int N) {
+  int Ns = 1, off = 0;
+  while (Ns < N) {
+    const int R = pass_radix(N, Ns);
+    const int cnt = Ns * (R - 1);
+    for (int i = threadIdx.x; i < cnt; i += kTfThreads) {
+      const int jm = i / (R - 1), r = i - jm * (R - 1) + 1;
+      double sn, cs;
+      sincospi(2.0 * (double)(jm * r) / (double)(Ns * R), &sn, &cs);
+      tw[off + i] = make_double2(cs, -sn);
+    }
+    off += cnt;
+    Ns *= R;
   }
 }
 
@@ -194,110 +232,155 @@ __device__ __forceinline__ double2 forward_out(const double2* c, int k, int N, i
 // ---------------------------------------------------------------- FFT path
 // dir 0: point values -> scalar products (or Chebyshev coefficients with
 // solve); dir 1: Shen coefficients -> point values.  Gauss points, N = 2^m.
-__global__ __launch_bounds__(kTfThreads) void cheb_fft(int N, int64_t nsys, int space, int dir, int solve,
+// Each thread moves 8 points of a batch; the next batch's rows are loaded
+// into registers while the current one is transformed.
+template <int DIR>
+__global__ __launch_bounds__(kTfThreads) void cheb_fft(int N, int64_t nsys, int space, int solve,
                                                        const double2* __restrict__ in, double2* __restrict__ out) {
+  constexpr int dir = DIR;
   extern __shared__ double2 lds[];
-  double2* buf = lds;                 // kTfPoints
-  double2* tw = lds + kTfPoints;      // N: exp(-2 pi i q / N)
-  double2* wq = tw + N;               // N: exp(-i pi k / (2N))
-  const int SB = kTfPoints / N < 1 ? 1 : kTfPoints / N;
+  constexpr int PT = kTfPoints / kTfThreads;  // points per thread
+  double2* buf = lds;                         // kTfSlots (padded points)
+  double2* tw = lds + kTfSlots;               // N - 1 pass twiddles (+1 spare)
+  double2* wq = tw + N;                       // N: exp(-i pi k / (2N))
+  const int SB = kTfPoints / N;               // N <= kTfPoints, a power of two
+  const int lgN = 31 - __builtin_clz(N);
+  fill_twiddles(tw, N);
   for (int q = threadIdx.x; q < N; q += kTfThreads) {
-    double s, c;
-    sincospi(2.0 * (double)q / (double)N, &s, &c);
-    tw[q] = make_double2(c, -s);
-    sincospi((double)q / (2.0 * (double)N), &s, &c);
-    wq[q] = make_double2(c, -s);
+    double sn, cs;
+    sincospi((double)q / (2.0 * (double)N), &sn, &cs);
+    wq[q] = make_double2(cs, -sn);
   }
-  __syncthreads();
   const int64_t nbatch = (nsys + SB - 1) / SB;
-  const int P = SB * N;
   const int n = space_n(space, N);
-  for (int64_t bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+  const double wsc = 0.5 * kPi / (double)N;
+  // rows of batch bt into registers (point i = threadIdx.x + t * kTfThreads)
+  double2 nx[PT];
+  auto load = [&](int64_t bt, int tid) {
+    const int64_t w0 = bt * SB;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int i = tid + t * kTfThreads;
+      const int s = i >> lgN, k = i & (N - 1);
+      const bool ok = w0 + s < nsys && (dir == 0 || k < n);
+      nx[t] = ok ? in[(w0 + s) * (int64_t)N + k] : zero2();
+    }
+  };
+  int64_t bt = blockIdx.x;
+  if (bt < nbatch) load(bt, threadIdx.x);
+  for (; bt < nbatch; bt += gridDim.x) {
+    // the thread index is re-derived every batch from an opaque copy, so that
+    // the per-point constants (indices, combination weights) are not hoisted
+    // out of the loop and held in registers across it
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    tid &= kTfThreads - 1;
     const int64_t w0 = bt * SB;
     const int sb = (int)((nsys - w0) < SB ? (nsys - w0) : SB);
-    if (dir == 0) {
-      // load with Makhoul's reordering: v_q = u_{2q}, v_{N-1-q} = u_{2q+1}
-      for (int i = threadIdx.x; i < P; i += kTfThreads) {
-        const int s = i / N, j = i - s * N;
+    __syncthreads();  // the previous batch is out of buf (and the tables are in)
+    if constexpr (dir == 0) {
+      // Makhoul's reordering: v_q = u_{2q}, v_{N-1-q} = u_{2q+1}
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, j = i & (N - 1);
         const int q = (j & 1) ? N - 1 - (j >> 1) : (j >> 1);
-        buf[s * N + q] = s < sb ? in[(w0 + s) * (int64_t)N + j] : zero2();
-      }
-      __syncthreads();
-      fft_all<false>(buf, tw, N, SB);
-      // C_k = (W_k V_k + conj(W_k) V_{N-k}) / 2 times the Gauss weight pi/N
-      double2 cv[kTfPoints / kTfThreads];
-#pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) {
-          const int s = i / N, k = i - s * N;
-          const double2 Vk = buf[s * N + k], Vm = buf[s * N + ((N - k) & (N - 1))];
-          const double2 W = wq[k];
-          cv[t] = cscale(0.5 * kPi / (double)N, cadd(cmul(W, Vk), cmul(cconj(W), Vm)));
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) buf[i] = cv[t];
-      }
-      __syncthreads();
-      for (int i = threadIdx.x; i < P; i += kTfThreads) {
-        const int s = i / N, k = i - s * N;
-        if (s < sb) out[(w0 + s) * (int64_t)N + k] = forward_out(buf + s * N, k, N, space, solve, 0);
+        buf[lp((s << lgN) + q)] = nx[t];
       }
     } else {
-      // Shen coefficients in, Chebyshev coefficients z, then
+#pragma unroll
+      for (int t = 0; t < PT; ++t) buf[lp(tid + t * kTfThreads)] = nx[t];
+    }
+    if (bt + gridDim.x < nbatch) load(bt + gridDim.x, tid);
+    __syncthreads();
+    double2 cv[PT];
+    if constexpr (dir == 0) {
+      fft_all<false>(buf, tw, lgN, SB, tid);
+      // C_k = (W_k V_k + conj(W_k) V_{N-k}) / 2 times the Gauss weight pi/N,
+      // formed where the space's combination needs it (rows k, k+2, k+4)
+      auto cheb = [&](int s, int k) {
+        const double2 Vk = buf[lp((s << lgN) + k)], Vm = buf[lp((s << lgN) + ((N - k) & (N - 1)))];
+        const double2 W = wq[k];
+        return cscale(wsc, cadd(cmul(W, Vk), cmul(cconj(W), Vm)));
+      };
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, k = i & (N - 1);
+        double2 r = zero2();
+        if (k < n) {
+          if (space == SHEN_SPACE_CHEBYSHEV) {
+            r = cheb(s, k);
+            if (solve) r = cscale(2.0 / ((k == 0 ? 2.0 : 1.0) * kPi), r);
+          } else if (space == SHEN_SPACE_DIRICHLET) {
+            r = csub(cheb(s, k), cheb(s, k + 2));
+          } else {
+            const double K = (double)k, r3 = fast_rcp(K + 3.0);
+            r = c_fma((K + 1.0) * r3, cheb(s, k + 4), c_fma(-2.0 * (K + 2.0) * r3, cheb(s, k + 2), cheb(s, k)));
+          }
+        }
+        cv[t] = r;
+      }
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, k = i & (N - 1);
+        if (s < sb) out[(w0 + s) * (int64_t)N + k] = cv[t];
+      }
+    } else {
+      // Shen -> Chebyshev coefficients z (the transposed combination), then
       // V_k = exp(i pi k / (2N)) (Z_k - i Z_{N-k}) with Z_0 = z_0, Z_k = z_k / 2
-      for (int i = threadIdx.x; i < P; i += kTfThreads) {
-        const int s = i / N, k = i - s * N;
-        buf[i] = (s < sb && k < n) ? in[(w0 + s) * (int64_t)N + k] : zero2();
-      }
-      __syncthreads();
-      double2 zv[kTfPoints / kTfThreads];
-#pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) {
-          const int s = i / N, k = i - s * N;
-          const double2 z = shen_to_cheb(buf + s * N, k, n, space);
-          zv[t] = k == 0 ? z : cscale(0.5, z);
+      auto zc = [&](int s, int k) {
+        const int i = (s << lgN) + k;
+        double2 z;
+        if (space == SHEN_SPACE_CHEBYSHEV) {
+          z = buf[lp(i)];
+        } else {
+          z = k < n ? buf[lp(i)] : zero2();
+          if (space == SHEN_SPACE_DIRICHLET) {
+            if (k >= 2 && k - 2 < n) z = csub(z, buf[lp(i - 2)]);
+          } else {
+            if (k >= 2 && k - 2 < n) {
+              const double K = (double)(k - 2);
+              z = c_fma(-2.0 * (K + 2.0) * fast_rcp(K + 3.0), buf[lp(i - 2)], z);
+            }
+            if (k >= 4 && k - 4 < n) {
+              const double K = (double)(k - 4);
+              z = c_fma((K + 1.0) * fast_rcp(K + 3.0), buf[lp(i - 4)], z);
+            }
+          }
         }
+        return k == 0 ? z : cscale(0.5, z);
+      };
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, k = i & (N - 1);
+        const double2 Zk = zc(s, k);
+        const double2 Zm = k == 0 ? zero2() : zc(s, N - k);
+        const double2 d = make_double2(Zk.x + Zm.y, Zk.y - Zm.x);  // Z_k - i Z_{N-k}
+        cv[t] = cmul(cconj(wq[k]), d);
       }
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) buf[i] = zv[t];
-      }
+      for (int t = 0; t < PT; ++t) buf[lp(tid + t * kTfThreads)] = cv[t];
       __syncthreads();
-#pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) {
-          const int s = i / N, k = i - s * N;
-          const double2 Zm = k == 0 ? zero2() : buf[s * N + (N - k)];
-          const double2 d = make_double2(buf[i].x + Zm.y, buf[i].y - Zm.x);  // Z_k - i Z_{N-k}
-          zv[t] = cmul(cconj(wq[k]), d);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < kTfPoints / kTfThreads; ++t) {
-        const int i = threadIdx.x + t * kTfThreads;
-        if (i < P) buf[i] = zv[t];
-      }
-      __syncthreads();
-      fft_all<true>(buf, tw, N, SB);
+      fft_all<true>(buf, tw, lgN, SB, tid);
       // u_{2q} = v_q, u_{2q+1} = v_{N-1-q}
-      for (int i = threadIdx.x; i < P; i += kTfThreads) {
-        const int s = i / N, j = i - s * N;
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, j = i & (N - 1);
         const int q = (j & 1) ? N - 1 - (j >> 1) : (j >> 1);
-        if (s < sb) out[(w0 + s) * (int64_t)N + j] = buf[s * N + q];
+        cv[t] = buf[lp((s << lgN) + q)];
+      }
+#pragma unroll
+      for (int t = 0; t < PT; ++t) {
+        const int i = tid + t * kTfThreads;
+        const int s = i >> lgN, j = i & (N - 1);
+        if (s < sb) out[(w0 + s) * (int64_t)N + j] = cv[t];
       }
     }
-    __syncthreads();
   }
 }
 
@@ -393,15 +476,21 @@ hipError_t launch_transform(int N, int64_t nsys, int space, int dir, int solve, 
   if (nsys <= 0) return hipSuccess;
   hipStream_t st = (hipStream_t)stream;
   if (transform_fft_ok(N, gl)) {
-    const size_t lds = (size_t)(kTfPoints + 2 * N) * sizeof(double2);
+    const size_t lds = (size_t)(kTfSlots + 2 * N) * sizeof(double2);
     static const bool attr =
-        hipFuncSetAttribute((const void*)cheb_fft, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+        hipFuncSetAttribute((const void*)cheb_fft<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess &&
+        hipFuncSetAttribute((const void*)cheb_fft<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
     (void)attr;
     const int SB = kTfPoints / N;
     const int64_t batches = (nsys + SB - 1) / SB;
-    const int grid = grid_for((const void*)cheb_fft, batches, lds);
-    hipLaunchKernelGGL(cheb_fft, dim3((unsigned)grid), dim3(kTfThreads), lds, st, N, nsys, space, dir, solve,
-                       (const double2*)in, (double2*)out);
+    const void* k = dir == 0 ? (const void*)cheb_fft<0> : (const void*)cheb_fft<1>;
+    const int grid = grid_for(k, batches, lds);
+    if (dir == 0)
+      hipLaunchKernelGGL(cheb_fft<0>, dim3((unsigned)grid), dim3(kTfThreads), lds, st, N, nsys, space, solve,
+                         (const double2*)in, (double2*)out);
+    else
+      hipLaunchKernelGGL(cheb_fft<1>, dim3((unsigned)grid), dim3(kTfThreads), lds, st, N, nsys, space, solve,
+                         (const double2*)in, (double2*)out);
     return hipGetLastError();
   }
   int SB = 1;

@@ -3856,7 +3856,7 @@ __global__ __launch_bounds__(64) void batched_boundary(const shen_problem* __res
   for (int64_t t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile); t < tiles_total;
        t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile)) {
     const shen_problem d = desc[find_desc(desc, ndesc, t)];
-    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, 0);
+    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, d.chunk);
     if (c.C == 0) continue;
     int64_t w0, wend;
     tile_range(d, t, w0, wend);
@@ -3889,7 +3889,7 @@ __global__ __launch_bounds__(64) void batched_wave_cfg(const shen_problem* __res
     for (int i = 0; i < ndesc; ++i) {
       const shen_problem& e = desc[i];
       if (e.family != FAM || e.nsys <= 0) continue;
-      const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, 0);
+      const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, e.chunk);
       if (!(c.C == C && c.G == G)) continue;
       const int64_t nt = (e.nsys + e.sys_per_tile - 1) / e.sys_per_tile;
       if (t < base + nt) {

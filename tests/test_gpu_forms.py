@@ -106,13 +106,43 @@ def test_batched_graph_replays(dev):
 
 
 def test_autotuner_cache(dev, tmp_path):
-    from paper_1701_03787_amd.batched import Autotuner, TILE_CANDIDATES
+    """The tuner searches the chunk length (hence the wave configuration) and the systems per
+    work item, caches the winner, and a batch planned with it solves to the bar."""
+    from paper_1701_03787_amd.batched import (Autotuner, BatchedSolver, TILE_CANDIDATES, chunk_candidates,
+                                              wave_config)
     case(test="autotune")
     t = Autotuner(str(tmp_path / "tune.json"))
-    tile = t.tune(dev, "biharmonic", 256, nsys=2048, reps=2)
-    assert tile in TILE_CANDIDATES
+    chunk, tile = t.tune(dev, "biharmonic", 256, nsys=2048, reps=2)
+    assert tile in TILE_CANDIDATES and chunk in chunk_candidates("biharmonic", 256)
+    assert len(t.table[t.key(dev, "biharmonic", 256)]["seconds"]) == len(chunk_candidates("biharmonic", 256)) * len(
+        TILE_CANDIDATES)
+    assert wave_config("biharmonic", 256, chunk) is not None
     t2 = Autotuner(str(tmp_path / "tune.json"))
-    assert t2.get(dev, "biharmonic", 256) == tile
+    assert t2.get(dev, "biharmonic", 256) == (chunk, tile)
+    g = wl.small_grid(256, 50, index=3)
+    probs, host = _problems([g], dev)
+    s = BatchedSolver(probs, tuner=t2)
+    assert s.configurations()["biharmonic|256"]["chunk"] == chunk
+    s.run()
+    torch.cuda.synchronize()
+    _check(probs, host)
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_batched_every_offered_chunk(dev, family):
+    """Every chunk length offered for (family, N) gives the same solutions to the bar."""
+    from paper_1701_03787_amd.batched import BatchedProblem, BatchedSolver, chunk_candidates
+    for N in (64, 256, 512, 1024):
+        g = wl.small_grid(N, 29, index=N + 5)
+        f = g.rhs(family)
+        cs = g.coefficients(family)
+        ref = so.solve(family, N, cs, f)
+        for ch in chunk_candidates(family, N):
+            case(test="batched_chunk", family=family, N=N, chunk=ch)
+            p = BatchedProblem(family, T(f, dev), [T(c, dev) for c in cs], tile=16, chunk=ch)
+            BatchedSolver([p], autotune=False).run()
+            torch.cuda.synchronize()
+            assert so.rel_err_per_system(p.u.cpu().numpy(), ref).max() <= TOL, (N, ch)
 
 
 # -------------------------------------------------------- differentiation
