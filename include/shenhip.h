@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SHENHIP_ABI_VERSION 2
+#define SHENHIP_ABI_VERSION 3
 
 typedef struct {
   double re, im;
@@ -345,18 +345,25 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
 
 /*
  * One batch of independent problems (many grids of uneven N, both
- * families) in a single persistent launch.
+ * families, every (kx, kz) of each) in one call: the grids are grouped by
+ * class (family, N, wave configuration), and each class is solved by the
+ * kernels of the single-grid path over all of its grids at once (the
+ * boundary walk, then the persistent LDS-streamed wave solve, which pulls
+ * work items of sys_per_tile systems from a queue).  Every kernel is
+ * enqueued on opts->stream; the call may be captured in a hipGraph and
+ * replayed (the descriptors are read at capture).
  *
- * desc: DEVICE array of ndesc descriptors (built once by the caller and
- *   reused; the library never reads it on the host).  c0 = alpha (Helmholtz)
- *   or a (biharmonic), c1 = b (biharmonic, else unused); info may be NULL.
+ * desc: HOST array of ndesc descriptors, planned by shen_batched_plan and
+ *   read by the library at every call.  c0 = alpha (Helmholtz) or a
+ *   (biharmonic), c1 = b (biharmonic, else unused), all DEVICE pointers;
+ *   info may be NULL.  f and u must not overlap (restart states are parked
+ *   in u).
  * work: DEVICE scratch of shen_batched_work_bytes(ndesc) bytes, owned by the
- *   caller; its contents on entry do not matter (the library clears it
- *   with a kernel, so the call may be captured in a hipGraph and replayed).
- * tiles_total: value returned by shen_batched_plan() for the same
- *   descriptors (host copy), the total number of work items.
- * maxN: the largest N among the descriptors.
- * Concurrent calls must not share `work`.
+ *   caller; its contents on entry do not matter (the library clears the
+ *   counters it uses with its first kernel).  Concurrent calls must not
+ *   share `work`.
+ * Returns SHEN_EINVAL for a descriptor the plan would refuse or that was not
+ * planned, SHEN_ENOTSUP for an N without a wave configuration.
  */
 typedef struct {
   int32_t family;  /* SHEN_HELMHOLTZ or SHEN_BIHARMONIC */
@@ -367,22 +374,23 @@ typedef struct {
   const shen_c128* f;
   shen_c128* u;
   int32_t* info;
-  int64_t tile_begin; /* filled by shen_batched_plan: first work item       */
-  int32_t sys_per_tile; /* systems per work item; 0 = 32 (plan fills it)    */
+  int64_t tile_begin;   /* filled by shen_batched_plan: first work item      */
+  int32_t sys_per_tile; /* systems per work item of the queue (rounded up to
+                           whole wavefront groups); 0 = 32 (plan fills it)  */
   int32_t chunk;        /* wave-kernel chunk length for this grid (as
                            opts.chunk of the solves); 0 = automatic         */
 } shen_problem;
 
-/* Host-side planning: fills tile_begin / sys_per_tile of each HOST
- * descriptor and returns the total number of work items (or a negative
- * code).  Choose tiles per (family, N) for the current device. */
+/* Host-side planning: checks each HOST descriptor, fills tile_begin and a
+ * default sys_per_tile, and returns the total number of work items (or a
+ * negative code). */
 int64_t shen_batched_plan(shen_problem* desc_host, int32_t ndesc, const shen_opts* opts);
 
-/* Bytes of the `work` scratch for batched_solve. */
+/* Bytes of the `work` scratch for batched_solve (8 per descriptor, at least
+ * 256). */
 int64_t shen_batched_work_bytes(int32_t ndesc);
 
-int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work,
-                  const shen_opts* opts);
+int batched_solve(const shen_problem* desc, int32_t ndesc, void* work, const shen_opts* opts);
 
 /*
  * batched_solve without the `work` argument, for callers that cannot
@@ -400,8 +408,7 @@ int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, 
  * kernel.
  */
 int64_t shen_batched_static_bytes(void);
-int batched_solve_static(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN,
-                         const shen_opts* opts);
+int batched_solve_static(const shen_problem* desc, int32_t ndesc, const shen_opts* opts);
 
 #ifdef __cplusplus
 }

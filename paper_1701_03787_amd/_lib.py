@@ -90,9 +90,9 @@ SIGNATURES = [
     ("shen_backward_transform", C.c_int, [C.c_int32, C.c_int64, C.c_int32, _VP, _VP, C.POINTER(ShenOpts)]),
     ("shen_batched_plan", C.c_int64, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),
     ("shen_batched_work_bytes", C.c_int64, [C.c_int32]),
-    ("batched_solve", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, _VP, C.POINTER(ShenOpts)]),
+    ("batched_solve", C.c_int, [C.POINTER(ShenProblem), C.c_int32, _VP, C.POINTER(ShenOpts)]),
     ("shen_batched_static_bytes", C.c_int64, []),
-    ("batched_solve_static", C.c_int, [_VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(ShenOpts)]),
+    ("batched_solve_static", C.c_int, [C.POINTER(ShenProblem), C.c_int32, C.POINTER(ShenOpts)]),
 ]
 
 _lib = None

@@ -14,7 +14,6 @@ import ctypes as C
 import itertools
 import json
 import os
-import time
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -128,8 +127,9 @@ class Autotuner:
             return None
         return int(v["chunk"]), int(v["tile"])
 
-    def tune(self, device, family: str, N: int, nsys: int = 4096, reps: int = 3, quad="gc"):
-        """Time every offered (chunk, tile) on a synthetic grid of the given shape; store and return the best."""
+    def tune(self, device, family: str, N: int, nsys: int = 16384, reps: int = 5, quad="gc"):
+        """Time every offered (chunk, tile) on a synthetic grid of the given shape (HIP events on
+        the launching stream, best of reps); store and return the fastest."""
         g = torch.Generator(device="cpu").manual_seed(1701 + N)
         f = torch.randn((nsys, N), dtype=torch.complex128, generator=g).to(device)
         K2 = torch.arange(nsys, dtype=torch.float64) % 4096
@@ -140,15 +140,17 @@ class Autotuner:
             coeffs = [(-(2 * K2 + inv)).to(device), (K2 * (K2 + inv)).to(device)]
         best, best_t = (0, DEFAULT_TILE), float("inf")
         timings = {}
+        stream = torch.cuda.current_stream(device)
         for chunk, tile in itertools.product(chunk_candidates(family, N), TILE_CANDIDATES):
             solver = BatchedSolver([BatchedProblem(family, f, coeffs, tile=tile, chunk=chunk)], quad=quad, autotune=False)
             solver.run()
-            torch.cuda.synchronize(device)
-            t0 = time.perf_counter()
-            for _ in range(reps):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for a, b in ev:
+                a.record(stream)
                 solver.run()
+                b.record(stream)
             torch.cuda.synchronize(device)
-            dt = (time.perf_counter() - t0) / reps
+            dt = min(a.elapsed_time(b) for a, b in ev) * 1e-3
             timings[f"{chunk},{tile}"] = dt
             if dt < best_t:
                 best, best_t = (chunk, tile), dt
@@ -169,7 +171,8 @@ class Autotuner:
 
 
 class BatchedSolver:
-    """Plans a batch of problems once; run() enqueues the single persistent launch."""
+    """Plans a batch of problems once; run() enqueues its launches (one walk and one persistent
+    solve per class of grids with the same family, N and wave configuration)."""
 
     def __init__(self, problems: List[BatchedProblem], quad: str = "gc", autotune: bool = True,
                  tuner: Optional[Autotuner] = None):
@@ -209,8 +212,7 @@ class BatchedSolver:
             raise L.ShenError(int(total), "shen_batched_plan")
         self.tiles_total = int(total)
         self.maxN = max(p.N for p in self.problems)
-        raw = bytes(C.string_at(C.addressof(host), C.sizeof(host)))
-        self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        self.desc = host  # the planned HOST descriptors, read by the library at every call
         nbytes = int(L.lib().shen_batched_work_bytes(n))
         self.work = torch.zeros((nbytes + 7) // 8, dtype=torch.int64, device=self.device)
         self.tiles = [host[i].sys_per_tile for i in range(n)]
@@ -237,11 +239,9 @@ class BatchedSolver:
         counter array instead of this solver's work buffer: nothing is allocated)."""
         o = self._opts()
         if static:
-            L.check(L.lib().batched_solve_static(self.desc.data_ptr(), len(self.problems), self.tiles_total,
-                                                 self.maxN, C.byref(o)), "batched_solve_static")
+            L.check(L.lib().batched_solve_static(self.desc, len(self.problems), C.byref(o)), "batched_solve_static")
             return
-        L.check(L.lib().batched_solve(self.desc.data_ptr(), len(self.problems), self.tiles_total, self.maxN,
-                                      self.work.data_ptr(), C.byref(o)), "batched_solve")
+        L.check(L.lib().batched_solve(self.desc, len(self.problems), self.work.data_ptr(), C.byref(o)), "batched_solve")
 
     def capture(self):
         """Capture run() in a hipGraph once (warm up first); replay() re-launches it."""

@@ -723,6 +723,23 @@ int dirichlet_derivative_solve(int32_t N, int64_t nsys, const shen_c128* uhat, s
   return mass_solve(SHEN_HELMHOLTZ, N, nsys, uhat, fhat, opts, 1);
 }
 
+// Checks one batched descriptor (shared by the plan and the solves, which
+// re-read the host descriptors at every call).
+static int check_desc(const shen_problem& d) {
+  if (d.family != SHEN_HELMHOLTZ && d.family != SHEN_BIHARMONIC) return SHEN_EINVAL;
+  if (bad_nsys(d.nsys) || d.N < (d.family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
+  if (d.nsys > 0) {
+    if (check_rows(d.f) || check_rows(d.u) || check_coef(d.c0)) return SHEN_EINVAL;
+    if (d.family == SHEN_BIHARMONIC && check_coef(d.c1)) return SHEN_EINVAL;
+    if (d.info && !aligned(d.info, 4)) return SHEN_EINVAL;
+    if ((const void*)d.f == (const void*)d.u || rows_overlap_partially(d.f, d.u, d.nsys, d.N)) return SHEN_EINVAL;
+  }
+  if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
+  if (d.chunk < 0 || d.chunk > 64 || !shen::wave_chunk_ok(d.family, d.N, d.chunk)) return SHEN_EINVAL;
+  if (d.sys_per_tile < 0 || d.sys_per_tile > 1 << 20) return SHEN_EINVAL;
+  return SHEN_OK;
+}
+
 int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* opts) {
   const shen_opts o = resolve(opts);
   if (check_opts(o)) return SHEN_EINVAL;
@@ -730,63 +747,56 @@ int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* op
   int64_t total = 0;
   for (int32_t i = 0; i < ndesc; ++i) {
     shen_problem& d = desc[i];
-    if (d.family != SHEN_HELMHOLTZ && d.family != SHEN_BIHARMONIC) return SHEN_EINVAL;
-    if (bad_nsys(d.nsys) || d.N < (d.family == SHEN_HELMHOLTZ ? 3 : 5)) return SHEN_EINVAL;
-    if (d.nsys > 0) {
-      if (check_rows(d.f) || check_rows(d.u) || check_coef(d.c0)) return SHEN_EINVAL;
-      if (d.family == SHEN_BIHARMONIC && check_coef(d.c1)) return SHEN_EINVAL;
-      if (d.info && !aligned(d.info, 4)) return SHEN_EINVAL;
-      if ((const void*)d.f == (const void*)d.u || rows_overlap_partially(d.f, d.u, d.nsys, d.N)) return SHEN_EINVAL;
-    }
-    if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
-    if (d.chunk < 0 || d.chunk > 64 || !shen::wave_chunk_ok(d.family, d.N, d.chunk)) return SHEN_EINVAL;
-    if (d.sys_per_tile <= 0) d.sys_per_tile = 32;
-    if (d.sys_per_tile > 1024) return SHEN_EINVAL;
+    if (d.sys_per_tile == 0) d.sys_per_tile = 32;
+    const int rc = check_desc(d);
+    if (rc) return rc;
     d.tile_begin = total;
     total += (d.nsys + d.sys_per_tile - 1) / d.sys_per_tile;
   }
   return total;
 }
 
-int64_t shen_batched_work_bytes(int32_t ndesc) { return ndesc < 0 ? SHEN_EINVAL : 256; }
+int64_t shen_batched_work_bytes(int32_t ndesc) {
+  if (ndesc < 0) return SHEN_EINVAL;
+  const int64_t bytes = 8 * (int64_t)shen::batched_counters(ndesc);
+  return bytes < 256 ? 256 : (bytes + 255) / 256 * 256;
+}
 
-int batched_solve(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, void* work, const shen_opts* opts) {
-  const shen_opts o = resolve(opts);
+static int batched_common(const shen_problem* desc, int32_t ndesc, const shen_opts& o) {
   int rc = check_opts(o);
   if (rc) return rc;
-  if (!desc || !aligned(desc, 8) || ndesc <= 0 || tiles_total < 0 || maxN < 3) return SHEN_EINVAL;
-  if (!work || !aligned(work, 8)) return SHEN_EINVAL;
+  if (!desc || !aligned(desc, 8) || ndesc <= 0) return SHEN_EINVAL;
+  for (int32_t i = 0; i < ndesc; ++i) {
+    if (desc[i].sys_per_tile <= 0) return SHEN_EINVAL;  // not planned
+    rc = check_desc(desc[i]);
+    if (rc) return rc;
+  }
   DevInfo d;
-  rc = device_info(&d);
-  if (rc != SHEN_OK) return rc;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return SHEN_EDEVICE;
-  int64_t blocks = (int64_t)cus * 4;
-  if (blocks > tiles_total) blocks = tiles_total > 0 ? tiles_total : 1;
-  return shen::launch_batched(desc, ndesc, tiles_total, work, o.quad == SHEN_QUAD_GL, (int)blocks, o.stream) == hipSuccess
-             ? SHEN_OK
-             : SHEN_ELAUNCH;
+  return device_info(&d);
+}
+
+int batched_solve(const shen_problem* desc, int32_t ndesc, void* work, const shen_opts* opts) {
+  const shen_opts o = resolve(opts);
+  if (!work || !aligned(work, 8)) return SHEN_EINVAL;
+  const int rc = batched_common(desc, ndesc, o);
+  if (rc) return rc;
+  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
 }
 
 int64_t shen_batched_static_bytes(void) { return (int64_t)shen::kBatchedStaticWords * 8; }
 
-int batched_solve_static(const shen_problem* desc, int32_t ndesc, int64_t tiles_total, int32_t maxN, const shen_opts* opts) {
+int batched_solve_static(const shen_problem* desc, int32_t ndesc, const shen_opts* opts) {
   const shen_opts o = resolve(opts);
-  int rc = check_opts(o);
-  if (rc) return rc;
-  if (!desc || !aligned(desc, 8) || ndesc <= 0 || tiles_total < 0 || maxN < 3) return SHEN_EINVAL;
+  if (check_opts(o)) return SHEN_EINVAL;
+  if (!desc || !aligned(desc, 8) || ndesc <= 0) return SHEN_EINVAL;
   const int64_t need = shen_batched_work_bytes(ndesc);
   if (need < 0) return SHEN_EINVAL;
   if (need > shen_batched_static_bytes()) return SHEN_ESCRATCH;
-  DevInfo d;
-  rc = device_info(&d);
-  if (rc != SHEN_OK) return rc;
+  const int rc = batched_common(desc, ndesc, o);
+  if (rc) return rc;
   void* work = nullptr;
   if (shen::batched_static_scratch(&work) != hipSuccess || work == nullptr) return SHEN_EDEVICE;
-  return shen::launch_batched(desc, ndesc, tiles_total, work, o.quad == SHEN_QUAD_GL, 0, o.stream) == hipSuccess
-             ? SHEN_OK
-             : SHEN_ELAUNCH;
+  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
 }
 
 }  // extern "C"

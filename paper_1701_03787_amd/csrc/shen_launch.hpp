@@ -81,7 +81,10 @@ struct WaveCfg {
 __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
 bool wave_chunk_ok(int family, int N, int chunk);
-hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream);
+// Batched form: the host descriptors (validated, planned), one launch pair
+// per class; `work` holds batched_counters(ndesc) queue counters.
+hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream);
+int batched_counters(int ndesc);
 // Library-owned counter array of the batched launch (one per device, 8-byte
 // words): device address for the current device, looked up on first use.
 constexpr int kBatchedStaticWords = 512;

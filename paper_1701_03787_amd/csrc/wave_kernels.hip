@@ -26,6 +26,7 @@
 
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "shen_launch.hpp"
 #include "shen_rows.hpp"
@@ -424,10 +425,11 @@ __global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int 
 // out through LDS, one parity at a time, so that every store instruction
 // writes whole 256-byte runs of consecutive slots (4 systems x G slots)
 // instead of 16-byte pieces of 64 different lines.
+// Block blk of the walk over one grid's systems (256 threads, 128 systems).
 template <int C, int G>
-__global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
-                                                       double2* __restrict__ S, int64_t sstride, int gl) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void helm_walk_block(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                double2* __restrict__ S, int64_t sstride, int gl, int64_t blk) {
+  const int64_t t = blk * 256 + threadIdx.x;
   const bool act = t < 2 * nsys;
   if constexpr (G > 16) {
     if (!act) return;
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
     // wavefront wv holds systems w0 .. w0+31, lane l system w0 + l/2, parity l&1
     __shared__ double2 stage[4][32 * G];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + wv * 64) >> 1;
+    const int64_t w0 = (blk * 256 + wv * 64) >> 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (p == h) {
@@ -485,6 +487,12 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
+                                                       double2* __restrict__ S, int64_t sstride, int gl) {
+  helm_walk_block<C, G>(N, nsys, alpha, S, sstride, gl, blockIdx.x);
 }
 
 __device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
@@ -3795,157 +3803,403 @@ hipError_t launch_wave(const WaveArgs& a) {
 
 
 // =========================================================================
-// Batched form: many grids of uneven N and both families, one descriptor
-// table, persistent kernels enqueued back to back (one graph launch):
-//
-//  1. batched_boundary<family>: work item = a tile of consecutive systems of
-//     one descriptor; its lanes walk the LU recurrences of the tile's chains
-//     and park the restart states (small kernels, so many wavefronts per SIMD
-//     hide the latency of the sequential walk);
-//  2. batched_wave_cfg<C, G, family>: the wave solves of the tiles of one
-//     configuration, one kernel per configuration (its own register budget).
-//
-// Every kernel pulls items from its own atomic counter until the queue is
-// empty; every wavefront reaches that exit.
+// Batched form: many grids of uneven N and both families.  The host groups
+// the grids by class (family, N, wave configuration) and enqueues, per class,
+// the kernels of the single-grid path over all of the class's grids at once:
+// the boundary walk, then the wave solve (the persistent LDS-streamed
+// helm_wave_pipe / table-driven bih_wave_ptab bodies where the configuration
+// has them, the per-group kernels otherwise).  A launch takes up to kMaxSeg
+// grids in a segment table passed by value; their groups (and walk blocks)
+// are numbered grid after grid.  The persistent solves pull work items of
+// `gpi` consecutive groups of one grid from their own counter in the caller's
+// work buffer (cleared by the first kernel of the call), so every launch is
+// graph-capturable and every wavefront reaches the exit once the queue is
+// empty.
 // =========================================================================
-// Descriptor of work item t: the last one whose first tile is <= t.
-__device__ __forceinline__ int find_desc(const shen_problem* __restrict__ desc, int ndesc, int64_t t) {
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].tile_begin <= t)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
+// Arrays of one grid of a batched launch (restart states parked in u).
+struct GridRef {
+  int64_t nsys;
+  const double* c0;
+  const double* c1;
+  const double2* f;
+  double2* u;
+  int32_t* info;
+};
+
+static constexpr int kMaxSeg = 16;
+// The grids of one batched launch: items (of gpi groups) and walk blocks
+// numbered one grid after the other; ibeg[nseg] and bbeg[nseg] are the totals.
+struct SegSrc {
+  int nseg;
+  int gpi;  // groups per work item of the persistent solves
+  int64_t ibeg[kMaxSeg + 1];
+  int64_t bbeg[kMaxSeg + 1];
+  GridRef r[kMaxSeg];
+};
+
+// Segment holding virtual index v of a prefix table (uniform: scalar loads
+// of the kernel argument).
+__device__ __forceinline__ int seg_of(const int64_t* beg, int nseg, int64_t v) {
+  int s = 0;
+  for (int i = 1; i < nseg; ++i) s = (v >= beg[i]) ? i : s;
+  return s;
 }
 
-__device__ __forceinline__ long long next_item(unsigned long long* __restrict__ counter, long long* s_tile) {
+__global__ void batched_clear(unsigned long long* __restrict__ counter, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) counter[i] = 0ULL;
+}
+
+// Next work item for this wavefront (one atomic per item, lane 0).
+__device__ __forceinline__ int64_t pull_item(unsigned long long* __restrict__ counter) {
+  unsigned long long t = 0;
+  if ((threadIdx.x & 63) == 0) t = atomicAdd(counter, 1ULL);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)t), hi = __builtin_amdgcn_readfirstlane((unsigned)(t >> 32));
+  return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------- walks
+template <int C, int G>
+__global__ __launch_bounds__(256) void batched_helm_walk(int N, SegSrc src, int gl) {
+  const int64_t vb = blockIdx.x;
+  const int s = seg_of(src.bbeg, src.nseg, vb);
+  const GridRef& r = src.r[s];
+  helm_walk_block<C, G>(N, r.nsys, r.c0, r.u, (int64_t)N, gl, vb - src.bbeg[s]);
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(kBihWalkThreads) void batched_bih_walk(int N, SegSrc src, int gl) {
+  extern __shared__ double tab[];
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, kBihWalkThreads);
   __syncthreads();
-  if (threadIdx.x == 0) *s_tile = (long long)atomicAdd(counter, 1ULL);
-  __syncthreads();
-  const long long t = *s_tile;
-  __syncthreads();
-  return t;
+  const int64_t vb = blockIdx.x;
+  const int s = seg_of(src.bbeg, src.nseg, vb);
+  const GridRef& r = src.r[s];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t w = (vb - src.bbeg[s]) * kBihWalkSystems + (wv >> 1) * 64 + lane;
+  if (w >= r.nsys) return;
+  bih_walk_tab<C, G, false>(N, wv & 1, r.c0[w], r.c1[w], r.u + w * (int64_t)N, gl, tab);
 }
 
-__device__ __forceinline__ void tile_range(const shen_problem& d, int64_t t, int64_t& w0, int64_t& wend) {
-  w0 = (t - d.tile_begin) * (int64_t)d.sys_per_tile;
-  wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
-}
-
-__global__ void batched_clear(unsigned long long* __restrict__ counter) {
-  if (blockIdx.x == 0 && threadIdx.x < 32) counter[threadIdx.x] = 0ULL;
-}
-
-// Next item of family FAM (items of the other family are skipped).
-template <int FAM>
-__device__ __forceinline__ int64_t next_own(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                            unsigned long long* __restrict__ counter, long long* s_tile) {
-  for (;;) {
-    const int64_t t = next_item(counter, s_tile);
-    if (t >= tiles_total || desc[find_desc(desc, ndesc, t)].family == FAM) return t;
-  }
-}
-
-template <int FAM>
-__global__ __launch_bounds__(64) void batched_boundary(const shen_problem* __restrict__ desc, int ndesc, int64_t tiles_total,
-                                                       unsigned long long* __restrict__ counter, int gl) {
-  __shared__ long long s_tile;
-  for (int64_t t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile); t < tiles_total;
-       t = next_own<FAM>(desc, ndesc, tiles_total, counter, &s_tile)) {
-    const shen_problem d = desc[find_desc(desc, ndesc, t)];
-    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, d.chunk);
-    if (c.C == 0) continue;
-    int64_t w0, wend;
-    tile_range(d, t, w0, wend);
-    double2* u = reinterpret_cast<double2*>(d.u);
-    for (int64_t ch = w0 * 2 + threadIdx.x; ch < wend * 2; ch += 64) {
-      const int64_t w = ch >> 1;
-      if constexpr (FAM == SHEN_HELMHOLTZ)
-        helm_boundary_chain(d.N, c.C, c.G, (int)(ch & 1), d.c0[w], u + w * (int64_t)d.N, gl);
-      else
-        bih_boundary_chain(d.N, c.C, c.G, (int)(ch & 1), d.c0[w], d.c1[w], u + w * (int64_t)d.N, gl);
-    }
-  }
-}
-
-// Wave solves of one configuration (family FAM, chunk C, G lanes per chain):
-// its work items are the tiles of the descriptors that use this
-// configuration, numbered consecutively in descriptor order; a wavefront maps
-// an item to (descriptor, tile) by one pass over the descriptor table.  Every
-// configuration is a kernel of its own, compiled with that configuration's
-// register budget.
-template <int C, int G, int FAM>
-__global__ __launch_bounds__(64) void batched_wave_cfg(const shen_problem* __restrict__ desc, int ndesc,
-                                                       unsigned long long* __restrict__ counter, int gl) {
-  __shared__ long long s_tile;
+// ------------------------------------------------ per-group wave solves
+// (configurations without the tile layout: one group per wavefront)
+template <int C, int G>
+__global__ __launch_bounds__(64) void batched_helm_solve(int N, SegSrc src, int gl) {
   constexpr int SPW = 64 / (2 * G);
+  const int64_t vg = blockIdx.x;  // items of one group (gpi = 1)
+  const int s = seg_of(src.ibeg, src.nseg, vg);
+  const GridRef& r = src.r[s];
+  helm_wave_body<C, G>(N, r.nsys, (vg - src.ibeg[s]) * SPW, r.c0, r.f, r.u, r.u, (int64_t)N, gl, r.info);
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(256) void batched_bih_solve(int N, SegSrc src, int gl) {
+  extern __shared__ double tab[];
+  constexpr int SPW = 64 / (2 * G);
+  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, 256);
+  __syncthreads();
+  const int64_t vg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (vg >= src.ibeg[src.nseg]) return;
+  const int s = seg_of(src.ibeg, src.nseg, vg);
+  const GridRef& r = src.r[s];
+  bih_wave_body<C, G, true>(N, r.nsys, (vg - src.ibeg[s]) * SPW, r.c0, r.c1, r.f, r.u, r.u, (int64_t)N, gl, r.info, tab);
+}
+
+// --------------------------------------- persistent LDS-streamed solves
+// The bodies of helm_wave_pipe / bih_wave_ptab over a dynamic queue of work
+// items; the next group (of this item, or the first of the next one) streams
+// into the tile while the current one is solved.
+struct GroupCursor {
+  int64_t item, g, gend;  // current item, group within its grid, end of item
+  int s;                  // segment
+};
+__device__ __forceinline__ bool cursor_at(const SegSrc& src, int spw, int64_t item, GroupCursor& c) {
+  if (item >= src.ibeg[src.nseg]) return false;
+  c.item = item;
+  c.s = seg_of(src.ibeg, src.nseg, item);
+  const int64_t groups = (src.r[c.s].nsys + spw - 1) / spw;
+  c.g = (item - src.ibeg[c.s]) * src.gpi;
+  c.gend = c.g + src.gpi < groups ? c.g + src.gpi : groups;
+  return true;
+}
+__device__ __forceinline__ bool cursor_next(const SegSrc& src, int spw, unsigned long long* counter, GroupCursor& c) {
+  if (c.g + 1 < c.gend) {
+    ++c.g;
+    return true;
+  }
+  return cursor_at(src, spw, pull_item(counter), c);
+}
+
+template <int C, int G>
+__global__ __launch_bounds__(64) void batched_helm_pipe(int N, SegSrc src, unsigned long long* __restrict__ counter, int gl) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  __shared__ double2 tile[(C + 1) * 64];
+  const int n = N - 2;
+  GroupCursor cur;
+  if (!cursor_at(src, SPW, pull_item(counter), cur)) return;
+  auto coef = [&](const GroupCursor& c, int l) {
+    const GridRef& r = src.r[c.s];
+    const int64_t w = c.g * SPW + l / (2 * G);
+    return r.c0[w < r.nsys ? w : r.nsys - 1];
+  };
+  double2 x[C], st[1];
+  double al;
+  {
+    const int lane = threadIdx.x & 63;
+    const GridRef& r = src.r[cur.s];
+    prefetch_tile<C, G, 1>(tile, lane, cur.g, N, r.nsys, r.f, r.u, (int64_t)N);
+    al = coef(cur, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    read_tile<C, G, 1>(tile, lane, x, st);
+  }
   for (;;) {
-    const int64_t t = next_item(counter, &s_tile);
-    int64_t base = 0;
-    int di = -1;
-    for (int i = 0; i < ndesc; ++i) {
-      const shen_problem& e = desc[i];
-      if (e.family != FAM || e.nsys <= 0) continue;
-      const WaveCfg c = pick_cfg((e.N + 1) / 2, e.family, e.N, e.chunk);
-      if (!(c.C == C && c.G == G)) continue;
-      const int64_t nt = (e.nsys + e.sys_per_tile - 1) / e.sys_per_tile;
-      if (t < base + nt) {
-        di = i;
-        break;
-      }
-      base += nt;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    lane &= 63;  // opaque, but known to be a lane index
+    GroupCursor nxt = cur;
+    const bool more = cursor_next(src, SPW, counter, nxt);
+    const GridRef& r = src.r[cur.s];
+    const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+    const int k0 = 2 * m * C + p;
+    const int64_t w = cur.g * SPW + sl;
+    const bool wok = w < r.nsys;
+#pragma unroll
+    for (int j = 0; j < C; ++j) x[j] = (wok && k0 + 2 * j < n) ? x[j] : zero2();
+    HelmPrev pv = {0.0, 0.0};
+    if (wok && m > 0 && k0 < n) {
+      pv.rd = st[0].x;
+      pv.g = st[0].y;
     }
-    if (di < 0) return;  // past the last item of this configuration
-    const shen_problem d = desc[di];
-    const int64_t w0 = (t - base) * (int64_t)d.sys_per_tile;
-    const int64_t wend = (w0 + d.sys_per_tile < d.nsys) ? w0 + d.sys_per_tile : d.nsys;
-    for (int64_t wb = w0; wb < wend; wb += SPW) {
-      if constexpr (FAM == SHEN_HELMHOLTZ)
-        helm_wave_body<C, G>(d.N, wend, wb, d.c0, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
-                             reinterpret_cast<const double2*>(d.u), d.N, gl, d.info);
-      else
-        bih_wave_body<C, G>(d.N, wend, wb, d.c0, d.c1, reinterpret_cast<const double2*>(d.f), reinterpret_cast<double2*>(d.u),
-                            reinterpret_cast<const double2*>(d.u), d.N, gl, d.info);
-    }
+    helm_wave_core<C, G, true>(N, lane, w, wok, wok ? al : 0.0, pv, x, r.u, gl, r.info);
+    stage_tile<C, G>(tile, lane, x);
+    store_tile<C, G>(tile, lane, cur.g, N, n, r.nsys, r.u);
+    if (!more) break;
+    cur = nxt;
+    const GridRef& rn = src.r[cur.s];
+    prefetch_tile<C, G, 1>(tile, lane, cur.g, N, rn.nsys, rn.f, rn.u, (int64_t)N);
+    al = coef(cur, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    read_tile<C, G, 1>(tile, lane, x, st);
   }
 }
 
-hipError_t launch_batched(const void* desc, int ndesc, int64_t tiles_total, void* work, int gl, int blocks, void* stream) {
+template <int C, int G>
+__global__ __launch_bounds__(64 * PtabWaves<G>::value) void batched_bih_ptab(int N, SegSrc src,
+                                                                              unsigned long long* __restrict__ counter, int gl) {
+  using TL = Tile<C, G>;
+  constexpr int SPW = TL::SPW;
+  constexpr int RT = 2 * G * C;
+  extern __shared__ double smem[];
+  double* tab = smem;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 6) * 64);
+  double2* coef = tile + (C + 5) * 64;
+  constexpr int WPB = PtabWaves<G>::value;
+  bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 64 * WPB);
+  __syncthreads();
+  const int n = N - 4;
+  GroupCursor cur;
+  if (!cursor_at(src, SPW, pull_item(counter), cur)) return;
+  auto sysc = [&](const GroupCursor& c, int l) {
+    const int64_t w = c.g * SPW + l / (2 * G);
+    const int64_t ns = src.r[c.s].nsys;
+    return w < ns ? w : ns - 1;
+  };
+  {
+    const int lane = threadIdx.x & 63;
+    const GridRef& r = src.r[cur.s];
+    prefetch_tile<C, G, 5>(tile, lane, cur.g, N, r.nsys, r.f, r.u, (int64_t)N);
+    prefetch_coef2(coef, lane, sysc(cur, lane), r.c0, r.c1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  for (;;) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    lane &= 63;  // opaque, but known to be a lane index
+    GroupCursor nxt = cur;
+    const bool more = cursor_next(src, SPW, counter, nxt);
+    const GridRef& r = src.r[cur.s];
+    const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
+    const int k0 = 2 * m * C + p;
+    const int64_t w = cur.g * SPW + sl;
+    const bool wok = w < r.nsys;
+    double2 x[C], st[5];
+    read_states_asm<C, 5>(tile, lane, st);
+    double ca_, cb_;
+    read_coef2(coef, lane, ca_, cb_);
+    BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+    if (wok && m > 0 && k0 < n) {
+      m2 = BihRowState{st[0].x, st[0].y, st[1].x, st[1].y, st[2].x};
+      m4 = BihRowState{st[2].y, st[3].x, st[3].y, st[4].x, st[4].y};
+    }
+    TileFetch4<C, G> fetch;
+    fetch.base = (uint32_t)(uintptr_t)SHEN_LDS(tile);
+    fetch.sl = sl;
+    fetch.k0 = k0;
+    fetch.n = n;
+    fetch.wok = wok;
+    auto prefetch_next = [&]() {
+      if (more) {
+        const GridRef& rn = src.r[nxt.s];
+        prefetch_tile<C, G, 5>(tile, lane, nxt.g, N, rn.nsys, rn.f, rn.u, (int64_t)N);
+        prefetch_coef2(coef, lane, sysc(nxt, lane), rn.c0, rn.c1);
+      }
+    };
+    double2* urow = r.u + (wok ? w : 0) * (int64_t)N;
+    bih_wave_core<C, G, true, true>(N, lane, w, wok, wok ? ca_ : 0.0, wok ? cb_ : 0.0, m2, m4, x, fetch, urow, gl, r.info, tab,
+                                    prefetch_next, std::true_type{}, walk_bad_of(st[0].x, wok && m == 0));
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (wok) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int k = k0 + 2 * j;
+        if (k < N) urow[k] = x[j];
+      }
+    }
+    if (!more) break;
+    cur = nxt;
+  }
+}
+
+// ------------------------------------------------------------- launcher
+namespace {
+// Systems per block of the walk kernels, and whether a configuration has the
+// LDS-streamed persistent solve.
+constexpr int kHelmWalkSystems = 128;
+template <int C, int G>
+constexpr bool has_tile_layout() {
+  return C >= 8 && C % 4 == 0 && G >= 16;
+}
+template <int C, int G>
+constexpr size_t ptab_lds() {
+  return (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)PtabWaves<G>::value * (C + 6) * 64 * sizeof(double2);
+}
+
+// Launches one class (family FAM, configuration C, G, one N) over up to
+// kMaxSeg grids; `counter` is this launch's queue counter.
+template <int C, int G, int FAM>
+hipError_t launch_class(int N, SegSrc& src, unsigned long long* counter, int gl, hipStream_t st) {
+  constexpr int SPW = 64 / (2 * G);
+  const int walk_sys = FAM == SHEN_HELMHOLTZ ? kHelmWalkSystems : kBihWalkSystems;
+  int64_t items = 0, blocks = 0;
+  for (int i = 0; i < src.nseg; ++i) {
+    src.ibeg[i] = items;
+    src.bbeg[i] = blocks;
+    const int64_t groups = (src.r[i].nsys + SPW - 1) / SPW;
+    items += (groups + src.gpi - 1) / src.gpi;
+    blocks += (src.r[i].nsys + walk_sys - 1) / walk_sys;
+  }
+  src.ibeg[src.nseg] = items;
+  src.bbeg[src.nseg] = blocks;
+  if (items == 0) return hipSuccess;
+  if constexpr (FAM == SHEN_HELMHOLTZ) {
+    hipLaunchKernelGGL((batched_helm_walk<C, G>), dim3((unsigned)blocks), dim3(256), 0, st, N, src, gl);
+    if constexpr (has_tile_layout<C, G>()) {
+      const int64_t grid = persistent_blocks((const void*)batched_helm_pipe<C, G>, items);
+      hipLaunchKernelGGL((batched_helm_pipe<C, G>), dim3((unsigned)grid), dim3(64), 0, st, N, src, counter, gl);
+    } else {
+      SegSrc one = src;  // per-group kernel: one group per item
+      one.gpi = 1;
+      int64_t g = 0;
+      for (int i = 0; i < one.nseg; ++i) {
+        one.ibeg[i] = g;
+        g += (one.r[i].nsys + SPW - 1) / SPW;
+      }
+      one.ibeg[one.nseg] = g;
+      hipLaunchKernelGGL((batched_helm_solve<C, G>), dim3((unsigned)g), dim3(64), 0, st, N, one, gl);
+    }
+  } else {
+    const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    static const bool attr = set_dynamic_lds((const void*)batched_bih_walk<C, G>, lds) &&
+                             set_dynamic_lds((const void*)batched_bih_solve<C, G>, lds);
+    (void)attr;
+    hipLaunchKernelGGL((batched_bih_walk<C, G>), dim3((unsigned)blocks), dim3(kBihWalkThreads), lds, st, N, src, gl);
+    if constexpr (has_tile_layout<C, G>() && ptab_lds<C, G>() <= 160 * 1024) {
+      constexpr int kWpb = PtabWaves<G>::value;
+      constexpr size_t plds = ptab_lds<C, G>();
+      static const bool attr2 = set_dynamic_lds((const void*)batched_bih_ptab<C, G>, plds);
+      (void)attr2;
+      const int64_t grid = persistent_blocks((const void*)batched_bih_ptab<C, G>, (items + kWpb - 1) / kWpb, 64 * kWpb, plds);
+      hipLaunchKernelGGL((batched_bih_ptab<C, G>), dim3((unsigned)grid), dim3(64 * kWpb), plds, st, N, src, counter, gl);
+    } else {
+      SegSrc one = src;
+      one.gpi = 1;
+      int64_t g = 0;
+      for (int i = 0; i < one.nseg; ++i) {
+        one.ibeg[i] = g;
+        g += (one.r[i].nsys + SPW - 1) / SPW;
+      }
+      one.ibeg[one.nseg] = g;
+      hipLaunchKernelGGL((batched_bih_solve<C, G>), dim3((unsigned)((g + 3) / 4)), dim3(256), lds, st, N, one, gl);
+    }
+  }
+  return hipGetLastError();
+}
+
+using ClassLaunch = hipError_t (*)(int, SegSrc&, unsigned long long*, int, hipStream_t);
+template <int FAM>
+ClassLaunch class_launcher(WaveCfg c) {
+#define SHEN_CLASS(CC, GG) \
+  if (c.C == CC && c.G == GG) return &launch_class<CC, GG, FAM>;
+  SHEN_CLASS(4, 8)
+  SHEN_CLASS(8, 4)
+  SHEN_CLASS(16, 4)
+  SHEN_CLASS(8, 8)
+  SHEN_CLASS(16, 8)
+  SHEN_CLASS(8, 16)
+  SHEN_CLASS(16, 16)
+  SHEN_CLASS(8, 32)
+  SHEN_CLASS(16, 32)
+#undef SHEN_CLASS
+  return nullptr;
+}
+}  // namespace
+
+int batched_counters(int ndesc) { return ndesc > 0 ? ndesc : 0; }
+
+// Groups the (validated, planned) host descriptors by class in descriptor
+// order and launches every class over its grids, kMaxSeg at a time.
+hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   unsigned long long* counter = reinterpret_cast<unsigned long long*>(work);
-  (void)blocks;
-  hipLaunchKernelGGL(batched_clear, dim3(1), dim3(64), 0, st, counter);
-  if (tiles_total > 0) {
-    const shen_problem* d = (const shen_problem*)desc;
-    hipLaunchKernelGGL(batched_boundary<SHEN_HELMHOLTZ>,
-                       dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_HELMHOLTZ>, tiles_total)), dim3(64),
-                       0, st, d, ndesc, tiles_total, counter + 1, gl);
-    hipLaunchKernelGGL(batched_boundary<SHEN_BIHARMONIC>,
-                       dim3((unsigned)persistent_blocks((const void*)batched_boundary<SHEN_BIHARMONIC>, tiles_total)), dim3(64),
-                       0, st, d, ndesc, tiles_total, counter, gl);
-    int slot = 2;
-#define SHEN_CFG(CC, GG)                                                                                                      \
-  hipLaunchKernelGGL((batched_wave_cfg<CC, GG, SHEN_HELMHOLTZ>),                                                             \
-                     dim3((unsigned)persistent_blocks((const void*)batched_wave_cfg<CC, GG, SHEN_HELMHOLTZ>, tiles_total)),   \
-                     dim3(64), 0, st, d, ndesc, counter + slot, gl);                                                         \
-  ++slot;                                                                                                                   \
-  hipLaunchKernelGGL((batched_wave_cfg<CC, GG, SHEN_BIHARMONIC>),                                                            \
-                     dim3((unsigned)persistent_blocks((const void*)batched_wave_cfg<CC, GG, SHEN_BIHARMONIC>, tiles_total)),  \
-                     dim3(64), 0, st, d, ndesc, counter + slot, gl);                                                         \
-  ++slot;
-    SHEN_CFG(4, 8)
-    SHEN_CFG(8, 4)
-    SHEN_CFG(16, 4)
-    SHEN_CFG(8, 8)
-    SHEN_CFG(8, 16)
-    SHEN_CFG(16, 8)
-    SHEN_CFG(16, 16)
-    SHEN_CFG(8, 32)
-    SHEN_CFG(16, 32)
-#undef SHEN_CFG
+  const int ncounters = batched_counters(ndesc);
+  hipLaunchKernelGGL(batched_clear, dim3(1), dim3(256), 0, st, counter, ncounters);
+  std::vector<char> done((size_t)ndesc, 0);
+  int slot = 0;
+  for (int i = 0; i < ndesc; ++i) {
+    if (done[i] || desc[i].nsys <= 0) continue;
+    const shen_problem& d = desc[i];
+    const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, d.chunk);
+    ClassLaunch fn = d.family == SHEN_HELMHOLTZ ? class_launcher<SHEN_HELMHOLTZ>(c) : class_launcher<SHEN_BIHARMONIC>(c);
+    if (fn == nullptr) return hipErrorInvalidValue;
+    // groups (of 64 / (2G) systems) per work item
+    const int spw = 64 / (2 * c.G);
+    auto gpi_of = [&](const shen_problem& e) {
+      const int g = (e.sys_per_tile + spw - 1) / spw;
+      return g > 0 ? g : 1;
+    };
+    SegSrc src = {};
+    src.gpi = gpi_of(d);
+    for (int j = i; j < ndesc; ++j) {
+      const shen_problem& e = desc[j];
+      if (done[j] || e.nsys <= 0 || e.family != d.family || e.N != d.N) continue;
+      const WaveCfg ce = pick_cfg((e.N + 1) / 2, e.family, e.N, e.chunk);
+      if (ce.C != c.C || ce.G != c.G || gpi_of(e) != src.gpi) continue;
+      done[j] = 1;
+      src.r[src.nseg++] = GridRef{e.nsys, e.c0, e.c1, reinterpret_cast<const double2*>(e.f), reinterpret_cast<double2*>(e.u),
+                                  e.info};
+      if (src.nseg == kMaxSeg) {
+        if (slot >= ncounters) return hipErrorInvalidValue;
+        const hipError_t err = fn(d.N, src, counter + slot++, gl, st);
+        if (err != hipSuccess) return err;
+        src.nseg = 0;
+      }
+    }
+    if (src.nseg > 0) {
+      if (slot >= ncounters) return hipErrorInvalidValue;
+      const hipError_t err = fn(d.N, src, counter + slot++, gl, st);
+      if (err != hipSuccess) return err;
+    }
   }
   return hipGetLastError();
 }

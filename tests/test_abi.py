@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_strings():
     lib = L.lib()
-    assert lib.shen_abi_version() == 2
+    assert lib.shen_abi_version() == 3
     for code in (0, -1, -2, -3, -4, 7):
         assert isinstance(lib.shen_status_string(code), bytes)
     o = L.default_opts()

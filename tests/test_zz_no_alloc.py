@@ -59,8 +59,7 @@ def _run_both(dev, shapes, seed):
         p.info.fill_(-7)
     # the entry point under test, called through the C-ABI directly
     o = solver._opts()
-    rc = L.lib().batched_solve_static(solver.desc.data_ptr(), len(solver.problems), solver.tiles_total, solver.maxN,
-                                      C.byref(o))
+    rc = L.lib().batched_solve_static(solver.desc, len(solver.problems), C.byref(o))
     assert rc == L.SHEN_OK, L.lib().shen_status_string(rc)
     torch.cuda.synchronize()
     rng = np.random.default_rng([1701, seed])
@@ -88,9 +87,14 @@ def test_static_batched_two_calls(dev):
 
 
 def test_static_scratch_limit(dev):
-    """The static buffer covers the work buffer of any descriptor count the ABI accepts here."""
+    """The static buffer covers the work buffer of up to 512 descriptors; a larger batch is refused
+    with SHEN_ESCRATCH before anything is read or launched."""
     from paper_1701_03787_amd import _lib as L
     cap = L.lib().shen_batched_static_bytes()
     assert cap == 4096
-    for nd in (1, 48, 1000, 1 << 20):
+    for nd in (1, 48, 512):
         assert 0 < L.lib().shen_batched_work_bytes(nd) <= cap
+    assert L.lib().shen_batched_work_bytes(513) > cap
+    host = (L.ShenProblem * 600)()
+    o = L.default_opts()
+    assert L.lib().batched_solve_static(host, 600, C.byref(o)) == L.SHEN_ESCRATCH
