@@ -239,6 +239,11 @@ __device__ __forceinline__ double2 rhs_combine(double2 v, double sigma, const do
 __device__ __forceinline__ double c_abs1(double2 a) { return fmax(fabs(a.x), fabs(a.y)); }
 __device__ __forceinline__ double c_absf(float2 a) { return fmax(fabs((double)a.x), fabs((double)a.y)); }
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+// c ? a : b per component (a select of whole double2 values can be lowered
+// to a stack slot addressed by the condition)
+__device__ __forceinline__ double2 c_sel(bool c, double2 a, double2 b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 
 // A pivot is unusable when it is zero, not finite, or numerically zero: no
 // larger than 2^-40 times the magnitude of its row's entries left of and on

@@ -1508,6 +1508,9 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     T00 = n00;
     T01 = n01;
   }
+  // settle the pivot checks here: sunk to their only use at the end, they
+  // would keep every row's pivot and scale live through both sweeps
+  if constexpr (!WALKINFO) asm volatile("" : "+v"(bad));
   // forward scan: (T, b = (y_last, y_last-1)); compose(later, earlier) = (T_l T_e, T_l b_e + b_l)
   const double L00 = T00, L01 = T01, L10 = T10, L11 = T11;  // this chunk's own transfer
   double2 b0 = y1, b1 = y2;
@@ -1550,11 +1553,11 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
         const double2 t0 = chain_lane32<15>(b0, p), t1 = chain_lane32<15>(b1, p);
         const double2 n0 = c_add(c_fma(T00, t0, c_mul(T01, t1)), b0);
         const double2 n1 = c_add(c_fma(T10, t0, c_mul(T11, t1)), b1);
-        b0 = (m >= 16) ? n0 : b0;
-        b1 = (m >= 16) ? n1 : b1;
+        b0 = c_sel(m >= 16, n0, b0);
+        b1 = c_sel(m >= 16, n1, b1);
         const double2 s0 = RowShift<1>::from_lower(b0), s1 = RowShift<1>::from_lower(b1);
-        h1 = (m == 16) ? t0 : s0;
-        h2 = (m == 16) ? t1 : s1;
+        h1 = c_sel(m == 16, t0, s0);
+        h2 = c_sel(m == 16, t1, s1);
       } else {
         h1 = RowShift<1>::from_lower(b0);
         h2 = RowShift<1>::from_lower(b1);
@@ -1600,8 +1603,8 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     } else if constexpr (G == 32) {
       const double2 u1 = RowShift<1>::from_upper(sh1), u2 = RowShift<1>::from_upper(sh2);
       const double2 c1 = chain_lane32<16>(sh1, p), c2 = chain_lane32<16>(sh2, p);
-      nx1 = (m == 15) ? c1 : u1;
-      nx2 = (m == 15) ? c2 : u2;
+      nx1 = c_sel(m == 15, c1, u1);
+      nx2 = c_sel(m == 15, c2, u2);
     } else {
       nx1 = shfl_down2(sh1, 1, G);
       nx2 = shfl_down2(sh2, 1, G);
@@ -1716,14 +1719,14 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
         double2 acc = cv[r];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], t[c], acc);
-        cv[r] = (m < 16) ? acc : cv[r];
+        cv[r] = c_sel(m < 16, acc, cv[r]);
       }
       const double2 s0 = RowShift<1>::from_upper(cv[0]), s1 = RowShift<1>::from_upper(cv[1]);
       const double2 s2 = RowShift<1>::from_upper(cv[2]), s3 = RowShift<1>::from_upper(cv[3]);
-      sa = (m == 15) ? t[0] : s0;
-      sb = (m == 15) ? t[1] : s1;
-      sq = (m == 15) ? t[2] : s2;
-      ss = (m == 15) ? t[3] : s3;
+      sa = c_sel(m == 15, t[0], s0);
+      sb = c_sel(m == 15, t[1], s1);
+      sq = c_sel(m == 15, t[2], s2);
+      ss = c_sel(m == 15, t[3], s3);
     } else {
       sa = RowShift<1>::from_upper(cv[0]);
       sb = RowShift<1>::from_upper(cv[1]);
@@ -2163,8 +2166,13 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
   auto fget = [&](int j) -> double2 {
     if constexpr (kTile) {
       using TL = Tile<C, G>;
-      const int k = k0 + 2 * j;
-      const double2 v = ftile[TL::pos(sl, k)];
+      // tile positions from an opaque lane index at every use: kept from the
+      // first use they were spilled
+      int ln = threadIdx.x;
+      asm volatile("" : "+v"(ln));
+      ln &= 63;
+      const int k = 2 * (ln % G) * C + ((ln / G) & 1) + 2 * j;
+      const double2 v = ftile[TL::pos(ln / (2 * G), k)];
       return (wok && k < n) ? v : zero2();
     } else {
       return fx[kTile ? 0 : j];
@@ -2281,6 +2289,11 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
 // the state (lambda_{j+1}, lambda_{j+2}).  Rows from the LDS table, restart
 // states from the table-driven boundary walk (parked in the lambda row).
 // =========================================================================
+// Whether bih_adjoint_tab keeps its reciprocal pivots in LDS as well as its
+// multipliers (the row table of G = 32 leaves room for the multipliers only).
+template <int G>
+struct AdjR0Lds : std::bool_constant<(G <= 16)> {};
+
 template <int C, int G>
 __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, const double* __restrict__ ca,
                                                        const double* __restrict__ cb, const double2* __restrict__ ufwd,
@@ -2310,14 +2323,29 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
     m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
   }
   const BihRowState in2 = m2, in4 = m4;
-  double2 x[C];
-#pragma unroll
-  for (int j = 0; j < C; ++j) {
+  // gbar of chunk element j.  It is read twice (the local pass and the rerun)
+  // rather than held in registers across the scan; the second read goes
+  // through an opaque copy of the row pointer so that it is not merged with
+  // the first.
+  auto gload = [&](const double2* row, int j) {
     const int k = k0 + 2 * j;
-    x[j] = (wok && k < n) ? grow[k] : zero2();
-  }
-  // factorisation restart (as the table-driven solve); raw U rows kept
-  double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
+    return (wok && k < n) ? row[k] : zero2();
+  };
+  double2 x[C];
+  // factorisation restart (as the table-driven solve); raw U rows kept in
+  // registers, the multipliers (used only by the L^T pass) in LDS after the
+  // row table, element j of thread t at lmul[j * 256 + t]
+  // Where the table leaves room (G <= 16), the reciprocal pivots follow them
+  // (element j of thread t at r0l[j * 256 + t]).
+  double2* lmul = reinterpret_cast<double2*>(tab + 2 * kBihTabPairs * RT);
+  constexpr bool kR0Lds = AdjR0Lds<G>::value;
+  double* r0l = reinterpret_cast<double*>(lmul + C * 256);
+  double r0j[kR0Lds ? 1 : C], u2j[C], u4j[C], pj[C], rj[C];
+  auto R0 = [&](int j) {
+    if constexpr (kR0Lds) return r0l[j * 256 + threadIdx.x];
+    return r0j[kR0Lds ? 0 : j];
+  };
+  double l1_0 = 0.0, l2_0 = 0.0, l2_1 = 0.0;  // elements 0 and 1, for the neighbouring lane
   int bad = INT_MAX;
   {
     BihConst cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
@@ -2334,15 +2362,27 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
       cm2 = c;
       m4 = m2;
       m2 = o;
-      l1j[j] = ok ? l1 : 0.0;
-      l2j[j] = ok ? l2 : 0.0;
-      r0j[j] = ok ? o.rU0 : 0.0;
+      const double l1k = ok ? l1 : 0.0, l2k = ok ? l2 : 0.0;
+      lmul[j * 256 + threadIdx.x] = make_double2(l1k, l2k);
+      if (j == 0) {
+        l1_0 = l1k;
+        l2_0 = l2k;
+      }
+      if (j == 1) l2_1 = l2k;
+      if constexpr (kR0Lds) {
+        r0l[j * 256 + threadIdx.x] = ok ? o.rU0 : 0.0;
+      } else {
+        r0j[kR0Lds ? 0 : j] = ok ? o.rU0 : 0.0;
+      }
       u2j[j] = ok ? o.U2 : 0.0;
       u4j[j] = ok ? o.U4 : 0.0;
       pj[j] = ok ? o.P : 0.0;
       rj[j] = ok ? o.R : 0.0;
     }
   }
+  // the pivot checks are needed only at the end (info); settled here, or the
+  // compiler keeps every row's pivot and scale live until then
+  asm volatile("" : "+v"(bad));
   // coefficients of element j's forward step: U2 of row j-1, U4/P/R of row j-2
   auto U2p = [&](int j) { return j >= 1 ? u2j[j >= 1 ? j - 1 : 0] : in2.U2; };
   auto U4pp = [&](int j) { return j >= 2 ? u4j[j >= 2 ? j - 2 : 0] : (j == 1 ? in2.U4 : in4.U4); };
@@ -2363,7 +2403,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   double2 cv[4] = {zero2(), zero2(), zero2(), zero2()};
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    const double r0 = r0j[j];
+    const double r0 = R0(j);
     const double2 qs = qsj(j);
     const double e1 = -r0 * U2p(j), e2 = -r0 * U4pp(j), e3 = -r0 * qs.x, e4 = -r0 * qs.y;
     const double pp = Ppp(j), rr = Rpp(j);
@@ -2378,7 +2418,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
       A[1][c] = A[0][c];
       A[0][c] = nA0[c];
     }
-    double2 nc0 = c_mul(r0, x[j]);
+    double2 nc0 = c_mul(r0, gload(grow, j));
     nc0 = c_fma(e1, cv[0], nc0);
     nc0 = c_fma(e2, cv[1], nc0);
     nc0 = c_fma(e3, cv[2], nc0);
@@ -2429,11 +2469,13 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   // incoming state from the lane below, then the exact rerun
   double2 z1 = chain_lo<G, 1>(cv[0], m), z2 = chain_lo<G, 1>(cv[1], m), SP = chain_lo<G, 1>(cv[2], m),
           SR = chain_lo<G, 1>(cv[3], m);
+  uintptr_t grow_again = reinterpret_cast<uintptr_t>(grow);
+  asm volatile("" : "+v"(grow_again));
 #pragma unroll
   for (int j = 0; j < C; ++j) {
-    const double r0 = r0j[j];
+    const double r0 = R0(j);
     const double2 qs = qsj(j);
-    double2 z = c_mul(r0, x[j]);
+    double2 z = c_mul(r0, gload(reinterpret_cast<const double2*>(grow_again), j));
     z = c_fma(-r0 * U2p(j), z1, z);
     z = c_fma(-r0 * U4pp(j), z2, z);
     z = c_fma(-r0 * qs.x, SP, z);
@@ -2445,9 +2487,11 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
     x[j] = z;
   }
   // L^T lambda = z: lambda_j = z_j - l1_{j+1} lambda_{j+1} - l2_{j+2} lambda_{j+2}
-  const double nl1_0 = chain_hi<G, 1>(l1j[0], m), nl2_0 = chain_hi<G, 1>(l2j[0], m), nl2_1 = chain_hi<G, 1>(l2j[1], m);
-  auto L1n = [&](int j) { return j + 1 < C ? l1j[j + 1 < C ? j + 1 : 0] : nl1_0; };
-  auto L2nn = [&](int j) { return j + 2 < C ? l2j[j + 2 < C ? j + 2 : 0] : (j + 2 == C ? nl2_0 : nl2_1); };
+  const double nl1_0 = chain_hi<G, 1>(l1_0, m), nl2_0 = chain_hi<G, 1>(l2_0, m), nl2_1 = chain_hi<G, 1>(l2_1, m);
+  auto L1n = [&](int j) { return j + 1 < C ? lmul[(j + 1 < C ? j + 1 : 0) * 256 + threadIdx.x].x : nl1_0; };
+  auto L2nn = [&](int j) {
+    return j + 2 < C ? lmul[(j + 2 < C ? j + 2 : 0) * 256 + threadIdx.x].y : (j + 2 == C ? nl2_0 : nl2_1);
+  };
   double T00 = 1.0, T01 = 0.0, T10 = 0.0, T11 = 1.0;
   double2 a1v = zero2(), a2v = zero2();  // lambda_{j+1}, lambda_{j+2}
 #pragma unroll
@@ -3600,7 +3644,9 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     int32_t* info = a.info ? a.info + s0 : nullptr;
     const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
     if (a.adjoint) {
-      static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, lds) &&
+      // + the multipliers (and the reciprocal pivots)
+      const size_t ldsa = lds + (size_t)C * 256 * (sizeof(double2) + (AdjR0Lds<G>::value ? sizeof(double) : 0));
+      static const bool attra = set_dynamic_lds((const void*)bih_adjoint_tab<C, G>, ldsa) &&
                                 set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds);
       (void)attra;
       // restart states: parked in lambda, or the forward solve's (factor-once mode)
@@ -3610,7 +3656,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       if (a.fac_mode == 0)
         hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
                            dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u, (int64_t)a.N, a.gl);
-      hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), lds, st, a.N, ns,
+      hipLaunchKernelGGL((bih_adjoint_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsa, st, a.N, ns,
                          c0, c1, a.ufwd ? (const double2*)a.ufwd + s0 * a.N : nullptr, f, u, sts, sstride,
                          a.g0 ? a.g0 + s0 : nullptr, a.g1 ? a.g1 + s0 : nullptr, a.gl, info);
       continue;
