@@ -378,6 +378,54 @@ def measure_transforms(dev, args, grid, data, host, rows):
     return out
 
 
+def measure_large_n(dev, args):
+    """Large N (chains spread over the wavefronts of a work group): N=4096 on the 128x65 rfft
+    grid (8,320 systems per family), the paper's largest roundoff-table column; ms, GB/s and
+    sampled errors against the oracle (one row per family: the dense oracle is O(N^3)).  The
+    Helmholtz solve is also timed on the lane-per-chain kernels, which served it before."""
+    import numpy as np
+    import torch
+    from paper_1701_03787_amd import api
+    from paper_1701_03787_amd import workloads as wl
+    kx, kz = wl.rfft_grid(128, 128)
+    g = wl.Grid(4096, kx, kz, 5e-5, 5e-4, 3.0, 6, name="N4096_128x65")
+    out = {"workload": g.name}
+    rows = np.array([int(np.argmax(g.K2))])
+    reps = max(3, min(args.steps, 10))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for fam in ("helmholtz", "biharmonic"):
+        fh = g.rhs(fam)
+        csh = g.coefficients(fam)
+        f = torch.from_numpy(fh).to(dev)
+        cs = [torch.from_numpy(c).to(dev) for c in csh]
+        u = torch.empty_like(f)
+        solve = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
+        ms = timed(lambda: solve(f, *cs, out=u))
+        nbytes = alg_bytes(fam, g.N, g.nsys)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        rec = {"ms": round(ms, 4), "value": round(g.nsys * g.N / (ms * 1e-3), 2), "unit": "system·N/s",
+               "hbm_gbps": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes),
+               "max_rel_err_sampled": _sampled_err(fam, g.N, csh, fh, u, rows)}
+        if fam == "helmholtz":
+            rec["chain_kernels_ms"] = round(timed(lambda: solve(f, *cs, out=u, variant="chain")), 4)
+        out[fam] = rec
+        del f, cs, u
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_mass(dev, args, grid, data, host, rows):
     """Mass-matrix solves u = B^{-1} f (forward Shen transforms, Sec. 2) on the bench
     workload, f standing in for the scalar products S(u): one read of f, one write of u
@@ -571,7 +619,8 @@ def main():
                  "rhs": measure_rhs(dev, args, grid, data, host, rows),
                  "transforms": measure_transforms(dev, args, grid, data, host, rows),
                  "mass": measure_mass(dev, args, grid, data, host, rows),
-                 "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args)}
+                 "batched": measure_batched(dev, args), "adjoint": measure_adjoint(dev, args),
+                 "large_n": measure_large_n(dev, args)}
 
     cpu = None
     if not args.no_cpu:

@@ -136,8 +136,13 @@ int shen_abi_version(void);
 /* Static string describing a SHEN_* return code. */
 const char* shen_status_string(int code);
 
-/* Largest N each entry point accepts on the current device for the given
- * family and precision (depends on the device's LDS size). */
+/* Largest N the solves accept on the current device for the given family
+ * and precision: the larger of the lane-per-chain kernels' limit (set by the
+ * device's LDS size) and, for SHEN_FP64, the large-N wave path's (N <= 4096,
+ * chains spread over up to four wavefronts of one work group; out-of-place
+ * solves only).  In-place calls, SHEN_FP32_REFINE, the adjoints, the
+ * factor-once form and the products are limited by the lane-per-chain
+ * kernels past N = 1024. */
 int32_t shen_max_n(int32_t family, int32_t precision);
 
 /* The wave-kernel configuration the solves of (family, N) use with chunk

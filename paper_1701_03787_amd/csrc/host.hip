@@ -123,6 +123,18 @@ int run_wave(const shen::WaveArgs& w) {
   if (rc != SHEN_OK) return rc;
   return shen::launch_wave(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
 }
+// Large N on the wave path (chains across the wavefronts of a work group):
+// plain FP64 forward solves out of place, past the one-wavefront sizes.
+bool use_multi(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
+  return o.variant != SHEN_VARIANT_CHAIN && !o.transpose && o.precision == SHEN_FP64 && f != u &&
+         shen::multi_waves(family, N) > 0;
+}
+int run_multi(const shen::WaveArgs& w) {
+  DevInfo d;
+  const int rc = device_info(&d);
+  if (rc != SHEN_OK) return rc;
+  return shen::launch_multi(w) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+}
 
 int32_t max_n_for(ChainKind kind, const DevInfo& d) {
   int32_t lo = 5, hi = 1 << 20;
@@ -292,7 +304,14 @@ int32_t shen_max_n(int32_t family, int32_t precision) {
     k = precision == SHEN_FP32_REFINE ? ChainKind::BihMixed : ChainKind::BihSolve;
   else
     return SHEN_EINVAL;
-  return max_n_for(k, d);
+  int32_t nmax = max_n_for(k, d);
+  if (precision == SHEN_FP64) {  // the large-N wave solves (out of place)
+    int32_t top = nmax;
+    for (int32_t N = 1025; N <= 8192; ++N)
+      if (shen::multi_waves(family, N) > 0) top = N;
+    nmax = top > nmax ? top : nmax;
+  }
+  return nmax;
 }
 
 int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c128* f, shen_c128* u, const shen_opts* opts) {
@@ -304,6 +323,19 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_multi(o, 0, N, f, u)) {
+    shen::WaveArgs w;
+    w.family = 0;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = alpha;
+    w.f = f;
+    w.u = u;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    return run_multi(w);
+  }
   if (use_wave(o, 0, N, f, u)) {
     if (!wave_mode_ok(o, 0) || !shen::wave_supported(0, N) || f == (const void*)u) return SHEN_ENOTSUP;
     shen::WaveArgs w;
@@ -349,6 +381,20 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_multi(o, 1, N, f, u)) {
+    shen::WaveArgs w;
+    w.family = 1;
+    w.N = N;
+    w.nsys = nsys;
+    w.c0 = ca;
+    w.c1 = cb;
+    w.f = f;
+    w.u = u;
+    w.info = o.info;
+    w.gl = o.quad == SHEN_QUAD_GL;
+    w.stream = o.stream;
+    return run_multi(w);
+  }
   if (use_wave(o, 1, N, f, u)) {
     if (!wave_mode_ok(o, 1) || !shen::wave_supported(1, N) || f == (const void*)u) return SHEN_ENOTSUP;
     shen::WaveArgs w;

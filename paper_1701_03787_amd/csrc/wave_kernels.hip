@@ -624,12 +624,75 @@ __global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64
 }
 
 // =========================================================================
+// Chains longer than one wavefront (large N).  A work group of W wavefronts
+// holds one system; wavefront v owns chain elements v*G*C .. (v+1)*G*C - 1 of
+// both parity chains (its lanes laid out as in the one-wavefront case).  Each
+// scan of the wave solves runs inside every wavefront as before; the
+// wavefronts then publish their totals in LDS and each folds the totals of
+// the wavefronts before it (forward scans) or after it (backward scan) into
+// the state entering its own segment.  A lane's incoming state is then its
+// neighbour's inclusive map applied to that state.
+// =========================================================================
+struct NoCarry {
+  static constexpr bool on = false;
+  __device__ __forceinline__ int kbase(int, int) const { return 0; }
+};
+static constexpr int kCarryMaxW = 4;     // wavefronts per system
+static constexpr int kCarryWords = 24;   // doubles per (scan, wavefront, parity)
+struct WaveCarry {
+  static constexpr bool on = true;
+  int v, W;     // this wavefront, wavefronts per system
+  double* xch;  // LDS: [3 scans][kCarryMaxW][2 parities][kCarryWords]
+  // first row of this wavefront's chain segments (chunk length C, G lanes)
+  __device__ __forceinline__ int kbase(int C, int G) const { return 2 * v * G * C; }
+  __device__ __forceinline__ double* slot(int scan, int wave, int p) const {
+    return xch + ((scan * kCarryMaxW + wave) * 2 + p) * kCarryWords;
+  }
+  // Publish `cnt` doubles (on the lane that holds the wavefront's total), wait
+  // for every wavefront, then fold: s <- M_u s + c_u over the wavefronts u
+  // before this one (forward) or after it from the top down (backward).
+  template <int D, bool BWD>
+  __device__ __forceinline__ void fold(int scan, int p, bool owner, const double (&M)[D][D], const double2 (&c)[D],
+                                       double2 (&st)[D]) const {
+    if (owner) {
+      double* o = slot(scan, v, p);
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) o[r * D + q] = M[r][q];
+        o[D * D + 2 * r] = c[r].x;
+        o[D * D + 2 * r + 1] = c[r].y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < D; ++r) st[r] = zero2();
+    const int cnt = BWD ? W - 1 - v : v;
+    for (int i = 0; i < cnt; ++i) {
+      const int u = BWD ? W - 1 - i : i;
+      const double* o = slot(scan, u, p);
+      double2 ns[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        double2 acc = make_double2(o[D * D + 2 * r], o[D * D + 2 * r + 1]);
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc = c_fma(o[r * D + q], st[q], acc);
+        ns[r] = acc;
+      }
+#pragma unroll
+      for (int r = 0; r < D; ++r) st[r] = ns[r];
+    }
+  }
+};
+
+// =========================================================================
 // Helmholtz wave solve
 // =========================================================================
 // Solves systems wbase + (lane / 2G) of the wavefront (those below nsys).
-template <int C, int G, bool PIPE = false>
+template <int C, int G, bool PIPE = false, typename Carry = NoCarry>
 __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
-                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info);
+                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info,
+                                              Carry cy = Carry());
 
 template <int C, int G>
 __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ alpha,
@@ -671,13 +734,13 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
 // Everything after the loads: x holds f of this lane's chunk (0 where k >= n),
 // pv the restart state.  Without PIPE the solution is stored to urow; with
 // PIPE it is left in x for the caller.
-template <int C, int G, bool PIPE>
+template <int C, int G, bool PIPE, typename Carry>
 __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
-                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info) {
+                                              double2* __restrict__ urow, int gl, int32_t* __restrict__ info, Carry cy) {
   const int p = (lane / G) & 1;
   const int m = lane % G;
   const int n = N - 2;
-  const int k0 = 2 * m * C + p;
+  const int k0 = cy.kbase(C, G) + 2 * m * C + p;
   const double hm = -0.5 * kPi * al;
   // factorisation restart + local forward elimination (zero incoming state)
   // l of row k is hm times 1/d of row k-2 (helm_step), so it is rebuilt from
@@ -708,7 +771,7 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
   double sT = T;
   double2 sb = yp;
   double2 h;
-  if constexpr (G == 16) {
+  if constexpr (G == 16 && !Carry::on) {
     auto lvl = [&](auto sh) {
       using S = decltype(sh);
       const double oT = S::from_lower(sT);
@@ -731,8 +794,17 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
         sT = sT * oT;
       }
     }
-    h = shfl_up2(sb, 1, G);
-    if (m == 0) h = zero2();
+    if constexpr (Carry::on) {
+      // y entering this wavefront's segment, then entering this lane
+      const double M[1][1] = {{sT}};
+      const double2 c[1] = {sb};
+      double2 sin[1];
+      cy.template fold<1, false>(0, p, m == G - 1, M, c, sin);
+      h = c_sel(m == 0, sin[0], shfl_up2(c_fma(sT, sin[0], sb), 1, G));
+    } else {
+      h = shfl_up2(sb, 1, G);
+      if (m == 0) h = zero2();
+    }
   }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
@@ -778,7 +850,7 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
     c1 = n1;
   };
   double2 sa, sS;
-  if constexpr (G == 16) {
+  if constexpr (G == 16 && !Carry::on) {
     auto lvl = [&](auto sh) {
       using S = decltype(sh);
       compose2(S::from_upper(A00), S::from_upper(A01), S::from_upper(A10), S::from_upper(A11), S::from_upper(c0),
@@ -798,11 +870,21 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
       const double2 oc0 = shfl_down2(c0, d, G), oc1 = shfl_down2(c1, d, G);
       if (m + d < G) compose2(o00, o01, o10, o11, oc0, oc1);
     }
-    sa = shfl_down2(c0, 1, G);
-    sS = shfl_down2(c1, 1, G);
-    if (m == G - 1) {
-      sa = zero2();
-      sS = zero2();
+    if constexpr (Carry::on) {
+      // state entering this wavefront's segment from above, then this lane
+      const double M[2][2] = {{A00, A01}, {A10, A11}};
+      const double2 c[2] = {c0, c1};
+      double2 top[2];
+      cy.template fold<2, true>(1, p, m == 0, M, c, top);
+      sa = c_sel(m == G - 1, top[0], shfl_down2(c_add(c_fma(A00, top[0], c_mul(A01, top[1])), c0), 1, G));
+      sS = c_sel(m == G - 1, top[1], shfl_down2(c_add(c_fma(A10, top[0], c_mul(A11, top[1])), c1), 1, G));
+    } else {
+      sa = shfl_down2(c0, 1, G);
+      sS = shfl_down2(c1, 1, G);
+      if (m == G - 1) {
+        sa = zero2();
+        sS = zero2();
+      }
     }
   }
 #pragma unroll
@@ -1367,11 +1449,12 @@ template <typename F, typename = void>
 struct LazyFetch : std::false_type {};
 template <typename F>
 struct LazyFetch<F, std::void_t<decltype(F::lazy)>> : std::bool_constant<F::lazy> {};
-template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook, bool WALKINFO = false>
+template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook, bool WALKINFO = false,
+          typename Carry = NoCarry>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook(),
-                                              std::bool_constant<WALKINFO> = {}, int walk_bad = INT_MAX);
+                                              std::bool_constant<WALKINFO> = {}, int walk_bad = INT_MAX, Carry cy = Carry());
 
 template <int C, int G, bool TAB = false>
 __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase, const double* __restrict__ ca,
@@ -1424,15 +1507,15 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
 // (it runs the same factorisation) and walk_bad holds, on the lanes of chunk
 // 0, the first unusable row of the lane's chain (INT_MAX: none); the rows of
 // the chunk are then not checked again.
-template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook, bool WALKINFO>
+template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook, bool WALKINFO, typename Carry>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f,
-                                              std::bool_constant<WALKINFO>, int walk_bad) {
+                                              std::bool_constant<WALKINFO>, int walk_bad, Carry cy) {
   const int p = (lane / G) & 1;
   const int m = lane % G;
   const int n = N - 4;
-  const int k0 = 2 * m * C + p;
+  const int k0 = cy.kbase(C, G) + 2 * m * C + p;
   // factorisation restart + local forward elimination; keep normalised U rows
   constexpr int RT = 2 * G * C;
   double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
@@ -1532,7 +1615,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
   // the same within each row, then the upper row completes its prefixes with
   // the lower row's total (lane 15), which is also the state entering lane 16.
   auto fscan = [&]() {
-    if constexpr (G == 16 || G == 32) {
+    if constexpr ((G == 16 || G == 32) && !Carry::on) {
       auto lvl = [&](auto sh) {
         using S = decltype(sh);
         if constexpr (G == 32) {
@@ -1579,6 +1662,19 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     }
   };
   fscan();
+  // with chains across wavefronts: the state entering this wavefront's
+  // segment, hence this lane's, and the state entering the next lane (cn)
+  double2 cn1 = zero2(), cn2 = zero2();
+  if constexpr (Carry::on) {
+    const double M[2][2] = {{T00, T01}, {T10, T11}};
+    const double2 c[2] = {b0, b1};
+    double2 sin[2];
+    cy.template fold<2, false>(0, p, m == G - 1, M, c, sin);
+    cn1 = c_add(c_fma(T00, sin[0], c_mul(T01, sin[1])), b0);
+    cn2 = c_add(c_fma(T10, sin[0], c_mul(T11, sin[1])), b1);
+    h1 = c_sel(m == 0, sin[0], shfl_up2(cn1, 1, G));
+    h2 = c_sel(m == 0, sin[1], shfl_up2(cn2, 1, G));
+  }
   // The chunk-local particular solutions started from a zero state can be far
   // larger than y itself (the forward recurrence has modes of modulus close to
   // one), so the scanned incoming states carry their rounding.  One refinement
@@ -1597,7 +1693,10 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
   after_f();  // f is not read again
   {
     double2 nx1, nx2;  // approximate incoming state of the next chunk
-    if constexpr (G == 16) {
+    if constexpr (Carry::on) {
+      nx1 = cn1;
+      nx2 = cn2;
+    } else if constexpr (G == 16) {
       nx1 = RowShift<1>::from_upper(sh1);
       nx2 = RowShift<1>::from_upper(sh2);
     } else if constexpr (G == 32) {
@@ -1617,6 +1716,16 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     b1 = c_sub(h2, nx2);
   }
   fscan();
+  if constexpr (Carry::on) {  // the correction entering this wavefront's segment, then this lane
+    const double M[2][2] = {{T00, T01}, {T10, T11}};
+    const double2 c[2] = {b0, b1};
+    double2 din[2];
+    cy.template fold<2, false>(1, p, m == G - 1, M, c, din);
+    const double2 e1 = c_add(c_fma(T00, din[0], c_mul(T01, din[1])), b0);
+    const double2 e2 = c_add(c_fma(T10, din[0], c_mul(T11, din[1])), b1);
+    h1 = c_sel(m == 0, din[0], shfl_up2(e1, 1, G));
+    h2 = c_sel(m == 0, din[1], shfl_up2(e2, 1, G));
+  }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     double2 hj = c_mul(-l1j[j], h1);
@@ -1684,7 +1793,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     }
   };
   double2 sa, sb, sq, ss;
-  if constexpr (G == 16 || G == 32) {
+  if constexpr ((G == 16 || G == 32) && !Carry::on) {
     auto lvl = [&](auto sh) {
       using S = decltype(sh);
       double oA[4][4];
@@ -1746,15 +1855,31 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       }
       if (m + d < G) compose4(oA, oc);
     }
-    sa = shfl_down2(cv[0], 1, G);
-    sb = shfl_down2(cv[1], 1, G);
-    sq = shfl_down2(cv[2], 1, G);
-    ss = shfl_down2(cv[3], 1, G);
-    if (m == G - 1) {
-      sa = zero2();
-      sb = zero2();
-      sq = zero2();
-      ss = zero2();
+    if constexpr (Carry::on) {  // the state entering this wavefront's segment from above, then this lane
+      double2 top[4], y[4];
+      cy.template fold<4, true>(2, p, m == 0, A, cv, top);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double2 acc = cv[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = c_fma(A[r][c], top[c], acc);
+        y[r] = acc;
+      }
+      sa = c_sel(m == G - 1, top[0], shfl_down2(y[0], 1, G));
+      sb = c_sel(m == G - 1, top[1], shfl_down2(y[1], 1, G));
+      sq = c_sel(m == G - 1, top[2], shfl_down2(y[2], 1, G));
+      ss = c_sel(m == G - 1, top[3], shfl_down2(y[3], 1, G));
+    } else {
+      sa = shfl_down2(cv[0], 1, G);
+      sb = shfl_down2(cv[1], 1, G);
+      sq = shfl_down2(cv[2], 1, G);
+      ss = shfl_down2(cv[3], 1, G);
+      if (m == G - 1) {
+        sa = zero2();
+        sb = zero2();
+        sq = zero2();
+        ss = zero2();
+      }
     }
   }
 #pragma unroll
@@ -3523,6 +3648,130 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
 }
 
 // =========================================================================
+// Large N: chains longer than one wavefront.  One system per work group of W
+// wavefronts (C = 16, G = 32: 1024 rows per wavefront, N up to 1024 W), the
+// wave cores with the cross-wavefront carries (WaveCarry).  The boundary walk
+// runs one thread per chain over the whole chain and parks the restart state
+// of every chunk (W G per parity) in the output row; both it and the solve
+// compute the row entries (no table, which would not fit in LDS), so the
+// stitched factors are bitwise those of the sequential LU.
+// =========================================================================
+static constexpr int kMultiC = 16, kMultiG = 32;
+
+__global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ alpha,
+                                                       double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  helm_boundary_chain(N, kMultiC, Gt, (int)(t & 1), alpha[w], u + w * (int64_t)N, gl);
+}
+
+__global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ ca,
+                                                      const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nsys) return;
+  const int64_t w = t >> 1;
+  bih_boundary_chain(N, kMultiC, Gt, (int)(t & 1), ca[w], cb[w], u + w * (int64_t)N, gl);
+}
+
+// Lowest bad row over the work group's wavefronts -> info[w].
+__device__ __forceinline__ void multi_info(int bad, int v, int W, int lane, int* __restrict__ badw, int32_t* __restrict__ info,
+                                           int64_t w) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) bad = min(bad, __shfl_xor(bad, d, 64));
+  if (lane == 0) badw[v] = bad;
+  __syncthreads();
+  if (v == 0 && lane == 0) {
+    int b = INT_MAX;
+    for (int i = 0; i < W; ++i) b = min(b, badw[i]);
+    info[w] = (b == INT_MAX) ? 0 : b + 1;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* __restrict__ alpha, const double2* __restrict__ f,
+                                                          double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+  constexpr int C = kMultiC, G = kMultiG;
+  __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
+  __shared__ int badw[kCarryMaxW];
+  const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int64_t w = blockIdx.x;
+  const int p = (lane / G) & 1, mg = v * G + lane % G;
+  const int n = N - 2;
+  const int k0 = 2 * mg * C + p;
+  const double al = alpha[w];
+  const double2* frow = f + w * (int64_t)N;
+  double2* urow = u + w * (int64_t)N;
+  // restart state (every wavefront reads its states before the first
+  // barrier of the scans, and stores only after the last)
+  HelmPrev pv = {0.0, 0.0};
+  if (mg > 0 && k0 < n) {
+    const double2 s = urow[p * W * G + mg];
+    pv.rd = s.x;
+    pv.g = s.y;
+  }
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (k < n) ? frow[k] : zero2();
+  }
+  const WaveCarry cy{v, W, xch};
+  const int bad = helm_wave_core<C, G, true, WaveCarry>(N, lane, w, true, al, pv, x, urow, gl, nullptr, cy);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+  }
+  if (info != nullptr) multi_info(bad, v, W, lane, badw, info, w);
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __restrict__ ca, const double* __restrict__ cb,
+                                                         const double2* __restrict__ f, double2* __restrict__ u, int gl,
+                                                         int32_t* __restrict__ info) {
+  constexpr int C = kMultiC, G = kMultiG;
+  __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
+  __shared__ int badw[kCarryMaxW];
+  const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int64_t w = blockIdx.x;
+  const int p = (lane / G) & 1, mg = v * G + lane % G;
+  const int n = N - 4;
+  const int k0 = 2 * mg * C + p;
+  const double a = ca[w], b = cb[w];
+  const double2* frow = f + w * (int64_t)N;
+  double2* urow = u + w * (int64_t)N;
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  if (mg > 0 && k0 < n) {
+    const double2* sv = urow + (p * W * G + mg) * 5;
+    const double2 s0 = sv[0], s1 = sv[1], s2 = sv[2], s3 = sv[3], s4 = sv[4];
+    m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
+    m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
+  }
+  double2 x[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    x[j] = (k < n) ? frow[k] : zero2();
+  }
+  auto fetch = [&](int j) {
+    const int k = k0 + 2 * j;
+    return (k < n) ? frow[k] : zero2();
+  };
+  const WaveCarry cy{v, W, xch};
+  const int bad = bih_wave_core<C, G, true, false>(N, lane, w, true, a, b, m2, m4, x, fetch, urow, gl, nullptr, nullptr,
+                                                   NoHook(), std::false_type{}, INT_MAX, cy);
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int k = k0 + 2 * j;
+    if (k < N) urow[k] = (k < n) ? x[j] : zero2();
+  }
+  if (info != nullptr) multi_info(bad, v, W, lane, badw, info, w);
+}
+
+// =========================================================================
 // host side
 // =========================================================================
 
@@ -3558,6 +3807,44 @@ bool wave_supported(int family, int N) {
   if (n < 1) return false;
   const WaveCfg c = pick_cfg((N + 1) / 2, family, N, 0);
   return c.C != 0;
+}
+
+// Wavefronts per system of the large-N solves (0: not served there): N past
+// the one-wavefront configurations, up to kCarryMaxW wavefronts.
+int multi_waves(int family, int N) {
+  if (wave_supported(family, N)) return 0;
+  const int per = kMultiC * kMultiG;  // chain elements per wavefront
+  const int W = ((N + 1) / 2 + per - 1) / per;
+  return (W >= 2 && W <= kCarryMaxW) ? W : 0;
+}
+
+hipError_t launch_multi(const WaveArgs& a) {
+  const int W = multi_waves(a.family, a.N);
+  if (W == 0 || a.mixed || a.adjoint || a.fac_mode || a.rhs) return hipErrorInvalidValue;
+  if (a.nsys <= 0) return hipSuccess;
+  if (a.nsys > (int64_t)INT_MAX) return hipErrorInvalidValue;  // one work group per system
+  hipStream_t st = (hipStream_t)a.stream;
+  const int Gt = W * kMultiG;
+  const unsigned walk = (unsigned)((2 * a.nsys + 255) / 256);
+  double2* u = (double2*)a.u;
+  const double2* f = (const double2*)a.f;
+  if (a.family == 0)
+    hipLaunchKernelGGL(helm_walk_multi, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl);
+  else
+    hipLaunchKernelGGL(bih_walk_multi, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl);
+  const dim3 grid((unsigned)a.nsys), block(64 * W);
+#define SHEN_MULTI(WW)                                                                                      \
+  if (W == WW) {                                                                                            \
+    if (a.family == 0)                                                                                      \
+      hipLaunchKernelGGL(helm_wave_multi<WW>, grid, block, 0, st, a.N, a.c0, f, u, a.gl, a.info);           \
+    else                                                                                                    \
+      hipLaunchKernelGGL(bih_wave_multi<WW>, grid, block, 0, st, a.N, a.c0, a.c1, f, u, a.gl, a.info);      \
+  }
+  SHEN_MULTI(2)
+  SHEN_MULTI(3)
+  SHEN_MULTI(4)
+#undef SHEN_MULTI
+  return hipGetLastError();
 }
 
 // Systems per boundary/solve launch pair.  Smaller slices keep the restart
