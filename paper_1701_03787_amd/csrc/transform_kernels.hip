@@ -104,8 +104,14 @@ __device__ __host__ __forceinline__ int pass_radix(int N, int Ns) {
 // tw: this pass's twiddles, w^(jm r) at tw[jm (R-1) + r - 1], jm < Ns.
 // N, Ns and R are powers of two: lgN = log2 N, lgNs = log2 Ns (index
 // arithmetic by shifts and masks).
-template <int R, bool INV>
-__device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lgN, int lgNs, int SB, int tid) {
+// ld(base, k): input point k of the sequence at buf offset base (the first
+// pass of the inverse forms its inputs on the fly from the raw coefficients).
+struct LdsLoad {
+  const double2* buf;
+  __device__ __forceinline__ double2 operator()(int base, int k) const { return buf[lp(base + k)]; }
+};
+template <int R, bool INV, typename Load>
+__device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lgN, int lgNs, int SB, int tid, Load ld) {
   constexpr int PER = 8 / R;  // butterflies per thread (8 points per thread)
   constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int N = 1 << lgN, Ns = 1 << lgNs;
@@ -124,7 +130,7 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lg
       const int jm = j & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double2 a = buf[lp(base + j + r * nb)];
+        double2 a = ld(base, j + r * nb);
         if (r > 0 && jm > 0) {
           const double2 w = tw[jm * (R - 1) + r - 1];
           a = cmul(a, INV ? cconj(w) : w);
@@ -146,21 +152,39 @@ __device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lg
   __syncthreads();
 }
 
-template <bool INV>
-__device__ __forceinline__ void fft_all(double2* buf, const double2* tw, int lgN, int SB, int tid) {
+// All passes; the first reads its inputs through `first`, the others from buf.
+template <bool INV, typename First = LdsLoad>
+__device__ __forceinline__ void fft_all(double2* buf, const double2* tw, int lgN, int SB, int tid, First first) {
+  const LdsLoad plain{buf};
   int lgNs = 0, off = 0;
+  {
+    const int left = lgN;  // first pass (lgN >= 3: N >= 8)
+    if (left >= 3) {
+      fft_pass<8, INV>(buf, tw, lgN, 0, SB, tid, first);
+      off = 7;
+      lgNs = 3;
+    } else if (left == 2) {
+      fft_pass<4, INV>(buf, tw, lgN, 0, SB, tid, first);
+      off = 3;
+      lgNs = 2;
+    } else {
+      fft_pass<2, INV>(buf, tw, lgN, 0, SB, tid, first);
+      off = 1;
+      lgNs = 1;
+    }
+  }
   while (lgNs < lgN) {
     const int left = lgN - lgNs;
     if (left >= 3) {
-      fft_pass<8, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      fft_pass<8, INV>(buf, tw + off, lgN, lgNs, SB, tid, plain);
       off += 7 << lgNs;
       lgNs += 3;
     } else if (left == 2) {
-      fft_pass<4, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      fft_pass<4, INV>(buf, tw + off, lgN, lgNs, SB, tid, plain);
       off += 3 << lgNs;
       lgNs += 2;
     } else {
-      fft_pass<2, INV>(buf, tw + off, lgN, lgNs, SB, tid);
+      fft_pass<2, INV>(buf, tw + off, lgN, lgNs, SB, tid, plain);
       off += 1 << lgNs;
       lgNs += 1;
     }
@@ -295,7 +319,7 @@ __global__ __launch_bounds__(kTfThreads) void cheb_fft(int N, int64_t nsys, int 
     __syncthreads();
     double2 cv[PT];
     if constexpr (dir == 0) {
-      fft_all<false>(buf, tw, lgN, SB, tid);
+      fft_all<false>(buf, tw, lgN, SB, tid, LdsLoad{buf});
       // C_k = (W_k V_k + conj(W_k) V_{N-k}) / 2 times the Gauss weight pi/N,
       // formed where the space's combination needs it (rows k, k+2, k+4)
       auto cheb = [&](int s, int k) {
@@ -352,20 +376,16 @@ __global__ __launch_bounds__(kTfThreads) void cheb_fft(int N, int64_t nsys, int 
         }
         return k == 0 ? z : cscale(0.5, z);
       };
-#pragma unroll
-      for (int t = 0; t < PT; ++t) {
-        const int i = tid + t * kTfThreads;
-        const int s = i >> lgN, k = i & (N - 1);
+      // formed by the first FFT pass as it reads its inputs (buf still holds
+      // the raw coefficients then; the pass writes only after its barrier)
+      auto pre = [&](int base, int k) {
+        const int s = base >> lgN;
         const double2 Zk = zc(s, k);
         const double2 Zm = k == 0 ? zero2() : zc(s, N - k);
         const double2 d = make_double2(Zk.x + Zm.y, Zk.y - Zm.x);  // Z_k - i Z_{N-k}
-        cv[t] = cmul(cconj(wq[k]), d);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int t = 0; t < PT; ++t) buf[lp(tid + t * kTfThreads)] = cv[t];
-      __syncthreads();
-      fft_all<true>(buf, tw, lgN, SB, tid);
+        return cmul(cconj(wq[k]), d);
+      };
+      fft_all<true>(buf, tw, lgN, SB, tid, pre);
       // u_{2q} = v_q, u_{2q+1} = v_{N-1-q}
 #pragma unroll
       for (int t = 0; t < PT; ++t) {
