@@ -354,9 +354,12 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
  * class (family, N, wave configuration), and each class is solved by the
  * kernels of the single-grid path over all of its grids at once (the
  * boundary walk, then the persistent LDS-streamed wave solve, which pulls
- * work items of sys_per_tile systems from a queue).  Every kernel is
- * enqueued on opts->stream; the call may be captured in a hipGraph and
- * replayed (the descriptors are read at capture).
+ * work items of sys_per_tile systems from a queue).  Grids with
+ * 1024 < N <= 4096 take the large-N solves of helmholtz_solve /
+ * biharmonic_solve, one walk and one solve per grid (chunk must be 0 there;
+ * sys_per_tile is ignored).  Every kernel is enqueued on opts->stream; the
+ * call may be captured in a hipGraph and replayed (the descriptors are read
+ * at capture).
  *
  * desc: HOST array of ndesc descriptors, planned by shen_batched_plan and
  *   read by the library at every call.  c0 = alpha (Helmholtz) or a
@@ -368,7 +371,7 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
  *   counters it uses with its first kernel).  Concurrent calls must not
  *   share `work`.
  * Returns SHEN_EINVAL for a descriptor the plan would refuse or that was not
- * planned, SHEN_ENOTSUP for an N without a wave configuration.
+ * planned, SHEN_ENOTSUP for an N beyond 4096.
  */
 typedef struct {
   int32_t family;  /* SHEN_HELMHOLTZ or SHEN_BIHARMONIC */

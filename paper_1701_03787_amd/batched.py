@@ -200,7 +200,8 @@ class BatchedSolver:
             d.u = p.u.data_ptr()
             d.info = p.info.data_ptr() if p.info is not None else None
             tile, chunk = p.tile, p.chunk
-            if tuner is not None and (tile <= 0 or chunk <= 0):
+            # past N = 1024 the large-N solves have no knob to tune
+            if tuner is not None and (tile <= 0 or chunk <= 0) and wave_config(p.family, p.N) is not None:
                 got = tuner.get(self.device, p.family, p.N, quad) or tuner.tune(self.device, p.family, p.N, quad=quad)
                 chunk = chunk if chunk > 0 else got[0]
                 tile = tile if tile > 0 else got[1]

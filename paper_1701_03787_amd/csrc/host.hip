@@ -780,8 +780,12 @@ static int check_desc(const shen_problem& d) {
     if (d.info && !aligned(d.info, 4)) return SHEN_EINVAL;
     if ((const void*)d.f == (const void*)d.u || rows_overlap_partially(d.f, d.u, d.nsys, d.N)) return SHEN_EINVAL;
   }
-  if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
-  if (d.chunk < 0 || d.chunk > 64 || !shen::wave_chunk_ok(d.family, d.N, d.chunk)) return SHEN_EINVAL;
+  if (shen::multi_waves(d.family, d.N) > 0) {  // large N: no chunk knob
+    if (d.chunk != 0) return SHEN_EINVAL;
+  } else {
+    if (!shen::wave_supported(d.family, d.N)) return SHEN_ENOTSUP;
+    if (d.chunk < 0 || d.chunk > 64 || !shen::wave_chunk_ok(d.family, d.N, d.chunk)) return SHEN_EINVAL;
+  }
   if (d.sys_per_tile < 0 || d.sys_per_tile > 1 << 20) return SHEN_EINVAL;
   return SHEN_OK;
 }

@@ -162,23 +162,40 @@ struct BihConst {
 };
 static constexpr int kBihConstN = 11;
 
+// The entries of row k that are polynomials in k (no division): A_{k,k-2},
+// Q_kk, A_{k,k+2} and the tail generators p_k, r_k.
+struct BihPoly {
+  double Am2, Q0, A2, p, r;
+};
+__device__ __forceinline__ BihPoly bih_poly(int k) {
+  const double K = (double)k;
+  BihPoly c;
+  c.A2 = 2.0 * kPi * (K + 1.0) * (K + 2.0);
+  c.Am2 = (k >= 2) ? 2.0 * kPi * (K - 1.0) * (K + 2.0) : 0.0;
+  c.p = 8.0 * kPi * K * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  c.r = 24.0 * kPi * (K + 1.0) * (K + 2.0);
+  c.Q0 = 8.0 * kPi * (K + 1.0) * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  return c;
+}
+
 __device__ __forceinline__ BihConst bih_const(int k, int N, int gl) {
   const double K = (double)k;
   const double p3 = fast_rcp(K + 3.0), p5 = fast_rcp(K + 5.0), p7 = fast_rcp(K + 7.0);
   const double g1 = (K + 2.0) * p3;  // (k+2)/(k+3)
   const double g2 = (K + 1.0) * p3;  // (k+1)/(k+3)
+  const BihPoly q = bih_poly(k);
   BihConst c;
   c.B0 = 0.5 * kPi * (ck(k, N, gl) + 4.0 * g1 * g1 + ck(k + 4, N, gl) * g2 * g2);
   c.B2 = -kPi * (g1 + (K + 4.0) * p5 * g2);
   c.B4 = 0.5 * kPi * g2;
   c.A0 = -4.0 * kPi * (K + 1.0) * (K + 2.0) * g1;
-  c.A2 = 2.0 * kPi * (K + 1.0) * (K + 2.0);
-  c.Am2 = (k >= 2) ? 2.0 * kPi * (K - 1.0) * (K + 2.0) : 0.0;
-  c.p = 8.0 * kPi * K * (K + 1.0) * (K + 2.0) * (K + 4.0);
-  c.r = 24.0 * kPi * (K + 1.0) * (K + 2.0);
+  c.A2 = q.A2;
+  c.Am2 = q.Am2;
+  c.p = q.p;
+  c.r = q.r;
   c.q4 = p7;
   c.s4 = (K + 6.0) * (K + 6.0) * p7;
-  c.Q0 = 8.0 * kPi * (K + 1.0) * (K + 1.0) * (K + 2.0) * (K + 4.0);
+  c.Q0 = q.Q0;
   return c;
 }
 

@@ -287,8 +287,13 @@ __device__ __forceinline__ void bih_step_row32(const BihRow& hd, const BihRowSta
 // that the lanes of one parity read at one step (one per chunk) then fall in
 // distinct 16-byte bank groups, and a row never leaves its chunk's block.
 // Pair 0 holds (q4, s4), which the back substitution reads on its own.
+// Tables of 1024 rows (G = 32, C = 16) are compact: three pairs, (q4, s4),
+// (A0, B0), (B2, B4), the entries that take a division; the polynomial ones
+// (bih_poly) are formed on reading, from the same expressions, so both forms
+// give the same values.  The full table of 1024 rows and the tiles of four
+// wavefronts would exceed the 160 KiB of LDS.
 // ------------------------------------------------------------------------
-static constexpr int kBihTabPairs = 6;
+__host__ __device__ constexpr int bih_tab_pairs(int rt) { return rt >= 1024 ? 3 : 6; }
 __device__ __forceinline__ int bih_tab_row(int k, int C) {
   const int sh = 31 - __builtin_clz(2 * C);  // log2(2C)
   const int mask = (2 * C - 1) < 15 ? (2 * C - 1) : 15;
@@ -301,7 +306,11 @@ __device__ __forceinline__ int bih_tab_row(int k, int C) {
 // k < n are unchanged, and a factorisation run on past n yields l = 0 and
 // unit pivots there: with a zero right-hand side on those rows the solve
 // leaves them exactly zero without any masking.
+// TP: table pairs (3 or 6); 0 = bih_tab_pairs(RT).  A kernel that keeps the
+// full table at 1024 rows passes 6 to every table routine it calls.
+template <int TP = 0>
 __device__ __forceinline__ void bih_tab_fill(double* tab, int RT, int C, int N, int gl, int tid, int nthreads) {
+  const int pairs = TP ? TP : bih_tab_pairs(RT);
   double2* t2 = reinterpret_cast<double2*>(tab);
   const int n = N - 4;
   for (int k = tid; k < RT; k += nthreads) {
@@ -311,6 +320,11 @@ __device__ __forceinline__ void bih_tab_fill(double* tab, int RT, int C, int N, 
     if (k >= n - 4) c.B4 = 0.0;
     const int r = bih_tab_row(k, C);
     t2[0 * RT + r] = make_double2(c.q4, c.s4);
+    if (pairs == 3) {
+      t2[1 * RT + r] = make_double2(c.A0, c.B0);
+      t2[2 * RT + r] = make_double2(c.B2, c.B4);
+      continue;
+    }
     t2[1 * RT + r] = make_double2(c.Am2, c.Q0);
     t2[2 * RT + r] = make_double2(c.A0, c.B0);
     t2[3 * RT + r] = make_double2(c.A2, c.B2);
@@ -318,9 +332,30 @@ __device__ __forceinline__ void bih_tab_fill(double* tab, int RT, int C, int N, 
     t2[5 * RT + r] = make_double2(c.r, 0.0);
   }
 }
+template <int TP = 0>
 __device__ __forceinline__ BihConst bih_tab_get(const double* tab, int RT, int C, int k) {
   const double2* t2 = reinterpret_cast<const double2*>(tab);
   const int r = bih_tab_row(k, C);
+  if ((TP ? TP : bih_tab_pairs(RT)) == 3) {
+    // compact table: A0 is nonzero on every row of the system and zero on the
+    // identity rows past it, which take Q0 = 1 and no other entry
+    const double2 v0 = t2[0 * RT + r], v1 = t2[1 * RT + r], v2 = t2[2 * RT + r];
+    const bool real = v1.x != 0.0;
+    const BihPoly q = bih_poly(k);
+    BihConst c;
+    c.q4 = v0.x;
+    c.s4 = v0.y;
+    c.A0 = v1.x;
+    c.B0 = v1.y;
+    c.B2 = v2.x;
+    c.B4 = v2.y;
+    c.Am2 = real ? q.Am2 : 0.0;
+    c.Q0 = real ? q.Q0 : 1.0;
+    c.A2 = real ? q.A2 : 0.0;
+    c.p = real ? q.p : 0.0;
+    c.r = real ? q.r : 0.0;
+    return c;
+  }
   const double2 v0 = t2[0 * RT + r], v1 = t2[1 * RT + r], v2 = t2[2 * RT + r], v3 = t2[3 * RT + r], v4 = t2[4 * RT + r],
                 v5 = t2[5 * RT + r];
   BihConst c;
@@ -346,9 +381,10 @@ __device__ __forceinline__ double2 bih_tab_qs(const double* tab, int C, int k) {
 // entries below the diagonal of rows 0 .. 3 assemble to +0 unmasked
 // (field-wise selects rather than a branch: a branch between two whole
 // structs is kept in scratch memory)
+template <int TP = 0>
 __device__ __forceinline__ BihConst bih_const_at(const double* tab, int RT, int C, int k, int N, int gl) {
   const bool neg = k < 0;
-  BihConst c = bih_tab_get(tab, RT, C, neg ? 0 : k);
+  BihConst c = bih_tab_get<TP>(tab, RT, C, neg ? 0 : k);
   const double K = (double)k;
   const double p7 = fast_rcp(K + 7.0);
   const double q4n = p7, s4n = (K + 6.0) * (K + 6.0) * p7;  // as bih_const
@@ -536,7 +572,7 @@ __device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, d
 // chunk's included, with the wave solves' rule, and leaves the first unusable
 // row (or -1) in the unused state slot of chunk 0, so that the wave solves
 // need not check their rows again.
-template <int C, int G, bool F32>
+template <int C, int G, bool F32, int TP = 0>
 __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, void* st, int gl, const double* tab) {
   constexpr int RT = 2 * G * C;
   const int n = N - 4;
@@ -544,14 +580,14 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
   const int nchunks = (nc + C - 1) / C;
   if (F32 && nchunks <= 1) return;
   // only the constants of rows k-2 (B2, q4, s4) and k-4 (B4) are carried
-  const BihConst c2 = bih_const_at(tab, RT, C, p - 2, N, gl), c4 = bih_const_at(tab, RT, C, p - 4, N, gl);
+  const BihConst c2 = bih_const_at<TP>(tab, RT, C, p - 2, N, gl), c4 = bih_const_at<TP>(tab, RT, C, p - 4, N, gl);
   double B2m2 = c2.B2, q4m2 = c2.q4, s4m2 = c2.s4, B4m2 = c2.B4, B4m4 = c4.B4;
   using State = typename std::conditional<F32, BihRowState32, BihRowState>::type;
   State m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   int bad = INT_MAX;
   auto row = [&](int i) {
     const int k = 2 * i + p;
-    const BihConst c = bih_tab_get(tab, RT, C, k);
+    const BihConst c = bih_tab_get<TP>(tab, RT, C, k);
     const BihRow h = bih_row_tab(k, a, b, c, B2m2, q4m2, s4m2, B4m4);
     State o;
     if constexpr (F32) {
@@ -615,12 +651,14 @@ __global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64
                                                                     const double* __restrict__ cb, double2* __restrict__ S,
                                                                     int64_t sstride, int gl) {
   extern __shared__ double tab[];
-  bih_tab_fill(tab, 2 * G * C, C, N, gl, threadIdx.x, kBihWalkThreads);
+  // the FP32 walk serves the FP32 + refinement kernel, which keeps the full table
+  constexpr int TP = F32 ? 6 : 0;
+  bih_tab_fill<TP>(tab, 2 * G * C, C, N, gl, threadIdx.x, kBihWalkThreads);
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kBihWalkSystems + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
-  bih_walk_tab<C, G, F32>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
+  bih_walk_tab<C, G, F32, TP>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
 }
 
 // =========================================================================
@@ -1450,7 +1488,7 @@ struct LazyFetch : std::false_type {};
 template <typename F>
 struct LazyFetch<F, std::void_t<decltype(F::lazy)>> : std::bool_constant<F::lazy> {};
 template <int C, int G, bool PIPE = false, bool TAB = false, typename FetchF, typename Hook = NoHook, bool WALKINFO = false,
-          typename Carry = NoCarry>
+          typename Carry = NoCarry, int TP = 0>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f = Hook(),
@@ -1507,7 +1545,7 @@ __device__ __forceinline__ void bih_wave_body(int N, int64_t nsys, int64_t wbase
 // (it runs the same factorisation) and walk_bad holds, on the lanes of chunk
 // 0, the first unusable row of the lane's chain (INT_MAX: none); the rows of
 // the chunk are then not checked again.
-template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook, bool WALKINFO, typename Carry>
+template <int C, int G, bool PIPE, bool TAB, typename FetchF, typename Hook, bool WALKINFO, typename Carry, int TP>
 __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wok, double a, double b, BihRowState m2,
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f,
@@ -1532,8 +1570,8 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
   Recip Rc;
   BihConst cm2, cm4;
   if constexpr (TAB) {
-    cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl);
-    cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+    cm2 = bih_const_at<TP>(tab, RT, C, k0 - 2, N, gl);
+    cm4 = bih_const_at<TP>(tab, RT, C, k0 - 4, N, gl);
   } else {
     Rc.init(k0);
   }
@@ -1544,7 +1582,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     BihRowState o;
     double l1, l2, t0, sc;
     if constexpr (TAB) {
-      const BihConst c = bih_tab_get(tab, RT, C, k);
+      const BihConst c = bih_tab_get<TP>(tab, RT, C, k);
       bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0, sc);
       cm4 = cm2;
       cm2 = c;
@@ -2079,23 +2117,23 @@ __device__ __forceinline__ void bih_solve32(int lane, const BihFac32<C>& F, cons
 // Walking the chunk downwards, each row's constants are read once and carried
 // to the two rows below (which need them as those of rows k-2 and k-4);
 // q_k, s_k are the table's q4, s4 of row k-4.  u must be zero on padding rows.
-template <int C, int G, typename Sink>
+template <int C, int G, int TP = 0, typename Sink>
 __device__ __forceinline__ void bih_apply(int N, int lane, double a, double b, int gl, const double* tab, const double2 (&u)[C],
                                           Sink sink) {
   constexpr int RT = 2 * G * C;
   const int p = (lane / G) & 1, m = lane % G;
   const int k0 = 2 * m * C + p;
   // constants of rows k0 + 2(C-1) and the two below it
-  BihConst c = bih_const_at(tab, RT, C, k0 + 2 * (C - 1), N, gl);
-  BihConst c2 = bih_const_at(tab, RT, C, k0 + 2 * (C - 2), N, gl);
-  BihConst c4 = bih_const_at(tab, RT, C, k0 + 2 * (C - 3), N, gl);
+  BihConst c = bih_const_at<TP>(tab, RT, C, k0 + 2 * (C - 1), N, gl);
+  BihConst c2 = bih_const_at<TP>(tab, RT, C, k0 + 2 * (C - 2), N, gl);
+  BihConst c4 = bih_const_at<TP>(tab, RT, C, k0 + 2 * (C - 3), N, gl);
   double2 TQ = zero2(), TS = zero2();
   {
     // q_k, s_k of every element: rows k-4 of the table
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const double2 qs = (j >= 2) ? bih_tab_qs(tab, C, k0 + 2 * (j - 2)) : make_double2(0.0, 0.0);
-      const BihConst cn = bih_const_at(tab, RT, C, k0 + 2 * j - 4, N, gl);
+      const BihConst cn = bih_const_at<TP>(tab, RT, C, k0 + 2 * j - 4, N, gl);
       const double q = (j >= 2) ? qs.x : cn.q4, sv = (j >= 2) ? qs.y : cn.s4;
       TQ = c_fma(q, u[j], TQ);
       TS = c_fma(sv, u[j], TS);
@@ -2125,7 +2163,7 @@ __device__ __forceinline__ void bih_apply(int N, int lane, double a, double b, i
   for (int j = C - 1; j >= 0; --j) {
     const int k = k0 + 2 * j;
     // constants of row k-6 for the next step down (rows < 0: q4, s4 only)
-    const BihConst c6 = bih_const_at(tab, RT, C, k - 6, N, gl);
+    const BihConst c6 = bih_const_at<TP>(tab, RT, C, k - 6, N, gl);
     const BihRow h = bih_row_tab(k, a, b, c, c2.B2, c2.q4, c2.s4, c4.B4);
     const double2 um4 = (j >= 2) ? u[j >= 2 ? j - 2 : 0] : (j == 1 ? pl1 : pl2);
     const double2 um2 = (j >= 1) ? u[j >= 1 ? j - 1 : 0] : pl1;
@@ -2156,12 +2194,12 @@ __device__ __forceinline__ void bih_apply(int N, int lane, double a, double b, i
 }
 
 // x = f - H u in FP64 (rounded to FP32 on output), 0 on padding rows.
-template <int C, int G, typename FetchF>
+template <int C, int G, int TP = 0, typename FetchF>
 __device__ __forceinline__ void bih_residual(int N, int lane, bool wok, double a, double b, int gl, const double* tab,
                                              FetchF fetch_f, const double2 (&u)[C], float2 (&x)[C]) {
   const int n = N - 4;
   const int k0 = 2 * (lane % G) * C + ((lane / G) & 1);
-  bih_apply<C, G>(N, lane, a, b, gl, tab, u, [&](int j, double2 hu) {
+  bih_apply<C, G, TP>(N, lane, a, b, gl, tab, u, [&](int j, double2 hu) {
     const bool ok = wok && k0 + 2 * j < n;
     x[j] = ok ? to_f2(c_sub(fetch_f(j), hu)) : make_float2(0.0f, 0.0f);
   });
@@ -2238,7 +2276,7 @@ template <int C, int G>
 struct MixedTile {
   static constexpr size_t tile_bytes = (size_t)4 * C * 64 * sizeof(double2);
   static constexpr size_t base_bytes =
-      (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * 64 * 10 * sizeof(double);
+      (size_t)6 * 2 * G * C * sizeof(double2) + (size_t)4 * 64 * 10 * sizeof(double);
   // gfx950: 160 KiB of LDS per work group
   static constexpr bool value = (G >= 16 && C >= 8 && C % 4 == 0) && base_bytes + tile_bytes <= 160 * 1024;
   static constexpr size_t bytes = value ? tile_bytes : 0;
@@ -2254,10 +2292,10 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
   constexpr bool kTile = MixedTile<C, G>::value;
   extern __shared__ double smem[];
   const double* tab = smem;
-  bih_tab_fill(smem, RT, C, N, gl, threadIdx.x, 256);
+  bih_tab_fill<6>(smem, RT, C, N, gl, threadIdx.x, 256);
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double* st64 = smem + 2 * kBihTabPairs * RT + wv * 64 * 10;  // FP64 restart states (fallback)
-  double2* ftile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT + 4 * 64 * 10) + wv * (C * 64);
+  double* st64 = smem + 2 * 6 * RT + wv * 64 * 10;  // FP64 restart states (fallback)
+  double2* ftile = reinterpret_cast<double2*>(smem + 2 * 6 * RT + 4 * 64 * 10) + wv * (C * 64);
   const int lane = threadIdx.x & 63;
   const int sl = lane / (2 * G), p = (lane / G) & 1, m = lane % G;
   const int64_t g = (int64_t)blockIdx.x * 4 + wv;
@@ -2307,12 +2345,12 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
   BihFac32<C> F;
   bool finite32 = true;
   {
-    BihConst cm2 = bih_const_at(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at(tab, RT, C, k0 - 4, N, gl);
+    BihConst cm2 = bih_const_at<6>(tab, RT, C, k0 - 2, N, gl), cm4 = bih_const_at<6>(tab, RT, C, k0 - 4, N, gl);
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const int k = k0 + 2 * j;
       const bool ok = wok && k < n;
-      const BihConst c = bih_tab_get(tab, RT, C, k);
+      const BihConst c = bih_tab_get<6>(tab, RT, C, k);
       BihRowState32 o;
       float l1, l2, t0;
       bih_step_row32(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0);
@@ -2358,7 +2396,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
       refine_decide(it, it_max, dmax, umax, prev, tol, running, conv);
     }
     if (!__any(running)) break;
-    bih_residual<C, G>(N, lane, wok, a, b, gl, tab, fget, ux, x);
+    bih_residual<C, G, 6>(N, lane, wok, a, b, gl, tab, fget, ux, x);
   }
   const bool failed = wok && !conv;
   // the refined solutions leave first, so that the FP64 re-solve below does
@@ -2376,7 +2414,7 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     // sequential walk per chain (lane m = 0) with the table rows, then the
     // FP64 wave solve with the same rows
     double* sts = st64 + sl * 2 * G * 10;
-    if (m == 0 && wok) bih_walk_tab<C, G, false>(N, p, a, b, sts, gl, tab);
+    if (m == 0 && wok) bih_walk_tab<C, G, false, 6>(N, p, a, b, sts, gl, tab);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     BihRowState q2 = {0, 0, 0, 0, 0}, q4 = {0, 0, 0, 0, 0};
@@ -2388,7 +2426,8 @@ __global__ __launch_bounds__(256) void bih_mixed_tab(int N, int64_t nsys, const 
     double2 x64[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) x64[j] = fget(j);
-    bad = bih_wave_core<C, G, true, true>(N, lane, w, wok, a, b, q2, q4, x64, fget, urow, gl, nullptr, tab);
+    bad = bih_wave_core<C, G, true, true, decltype(fget), NoHook, false, NoCarry, 6>(N, lane, w, wok, a, b, q2, q4, x64, fget,
+                                                                                     urow, gl, nullptr, tab);
     if (failed) {
 #pragma unroll
       for (int j = 0; j < C; ++j) {
@@ -2462,7 +2501,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
   // row table, element j of thread t at lmul[j * 256 + t]
   // Where the table leaves room (G <= 16), the reciprocal pivots follow them
   // (element j of thread t at r0l[j * 256 + t]).
-  double2* lmul = reinterpret_cast<double2*>(tab + 2 * kBihTabPairs * RT);
+  double2* lmul = reinterpret_cast<double2*>(tab + 2 * bih_tab_pairs(RT) * RT);
   constexpr bool kR0Lds = AdjR0Lds<G>::value;
   double* r0l = reinterpret_cast<double*>(lmul + C * 256);
   double r0j[kR0Lds ? 1 : C], u2j[C], u4j[C], pj[C], rj[C];
@@ -2986,15 +3025,16 @@ __global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const 
 // refinement sweep has read the current group's f from it.
 // Wavefronts per block of the pipelined biharmonic kernel: four for G = 16
 // (two systems per wavefront, about 500 registers each: one wavefront per
-// SIMD); eight for G = 32 (one system per wavefront, at most 256 registers:
-// two per SIMD), all sharing one row table.
-template <int G>
+// SIMD) and for C = 16, G = 32 (one system per wavefront, 1024 rows, compact
+// row table); eight for C = 8, G = 32 (at most 256 registers: two per SIMD),
+// all sharing one row table.
+template <int C, int G>
 struct PtabWaves {
-  static constexpr int value = (G == 32) ? 8 : 4;
+  static constexpr int value = (G == 32 && C < 16) ? 8 : 4;
 };
 
 template <int C, int G>
-__global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
+__global__ __launch_bounds__((64 * PtabWaves<C, G>::value)) void bih_wave_ptab(int N, int64_t nsys, const double* __restrict__ ca,
                                                      const double* __restrict__ cb, const double2* __restrict__ f,
                                                      double2* __restrict__ u, const double2* __restrict__ sts,
                                                      int64_t sstride, int gl, int32_t* __restrict__ info) {
@@ -3006,9 +3046,9 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void bih_wave_ptab(int N,
   // wavefront index as a scalar: the tile base (and with it the LDS-DMA
   // destinations) and the group loop stay in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 6) * 64);
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * bih_tab_pairs(RT) * RT) + wv * ((C + 6) * 64);
   double2* coef = tile + (C + 5) * 64;  // the group's coefficients (prefetch_coef2)
-  constexpr int WPB = PtabWaves<G>::value;
+  constexpr int WPB = PtabWaves<C, G>::value;
   bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 64 * WPB);
   __syncthreads();
   const int n = N - 4;
@@ -3169,7 +3209,7 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
   extern __shared__ double smem[];
   double* tab = smem;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 1) * 64);
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * bih_tab_pairs(RT) * RT) + wv * ((C + 1) * 64);
   double2* coef = tile + C * 64;
   bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 256);
   __syncthreads();
@@ -3929,7 +3969,7 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     const double2* f = (const double2*)a.f + s0 * a.N;
     double2* u = (double2*)a.u + s0 * a.N;
     int32_t* info = a.info ? a.info + s0 : nullptr;
-    const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    const size_t lds = (size_t)bih_tab_pairs(2 * G * C) * 2 * G * C * sizeof(double2);
     if (a.adjoint) {
       // + the multipliers (and the reciprocal pivots)
       const size_t ldsa = lds + (size_t)C * 256 * (sizeof(double2) + (AdjR0Lds<G>::value ? sizeof(double) : 0));
@@ -3949,12 +3989,14 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
       continue;
     }
     if (a.mixed) {
-      const size_t ldsm = lds + (size_t)4 * 64 * 10 * sizeof(double) + MixedTile<C, G>::bytes;
+      // the FP32 + refinement kernel and its walk keep the full row table
+      const size_t ldsf = (size_t)6 * 2 * G * C * sizeof(double2);
+      const size_t ldsm = ldsf + (size_t)4 * 64 * 10 * sizeof(double) + MixedTile<C, G>::bytes;
       static const bool attrm = set_dynamic_lds((const void*)bih_mixed_tab<C, G>, ldsm) &&
-                                set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
+                                set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, ldsf);
       (void)attrm;
       hipLaunchKernelGGL((bih_boundary_tab<C, G, true>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
-                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, u,
+                         dim3(kBihWalkThreads), ldsf, st, a.N, ns, c0, c1, u,
                          (int64_t)a.N, a.gl);
       hipLaunchKernelGGL((bih_mixed_tab<C, G>), dim3((unsigned)((ns + 4 * SPW - 1) / (4 * SPW))), dim3(256), ldsm, st, a.N, ns, c0,
                          c1, f, u, a.gl, info, a.iters ? a.iters + s0 : nullptr, a.it_max, a.tol);
@@ -3974,9 +4016,9 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
                          sts, sstride, a.gl);
     if (a.fac_mode == 1) continue;
     // gfx950: 160 KiB of LDS per work group
-    constexpr int kWpb = PtabWaves<G>::value;
+    constexpr int kWpb = PtabWaves<C, G>::value;
     constexpr size_t kPtabLds =
-        (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)kWpb * (C + 6) * 64 * sizeof(double2);
+        (size_t)bih_tab_pairs(2 * G * C) * 2 * G * C * sizeof(double2) + (size_t)kWpb * (C + 6) * 64 * sizeof(double2);
     if constexpr (C >= 8 && C % 4 == 0 && G >= 16 && kPtabLds <= 160 * 1024) {
       const size_t lds2 = kPtabLds;
       static const bool attr2 = set_dynamic_lds((const void*)bih_wave_ptab<C, G>, lds2);
@@ -4016,7 +4058,7 @@ static hipError_t launch_matvec_t(const WaveArgs& a) {
                            0.0, 0.0, nullptr);
       }
     } else {
-      constexpr size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 1) * 64 * sizeof(double2);
+      constexpr size_t lds = (size_t)bih_tab_pairs(2 * G * C) * 2 * G * C * sizeof(double2) + (size_t)4 * (C + 1) * 64 * sizeof(double2);
       if constexpr (lds > 160 * 1024) {
         return hipErrorInvalidValue;
       } else if (a.rhs) {
@@ -4050,7 +4092,7 @@ static WaveCfg matvec_cfg(int family, int N) {
 bool matvec_wave_supported(int family, int N) {
   const WaveCfg c = matvec_cfg(family, N);
   if (!(c.C >= 8 && c.C % 4 == 0 && c.G >= 16)) return false;
-  const size_t lds = (size_t)kBihTabPairs * 2 * c.G * c.C * sizeof(double2) + (size_t)4 * (c.C + 1) * 64 * sizeof(double2);
+  const size_t lds = (size_t)bih_tab_pairs(2 * c.G * c.C) * 2 * c.G * c.C * sizeof(double2) + (size_t)4 * (c.C + 1) * 64 * sizeof(double2);
   return family == 0 || lds <= 160 * 1024;
 }
 
@@ -4317,7 +4359,7 @@ __global__ __launch_bounds__(64) void batched_helm_pipe(int N, SegSrc src, unsig
 }
 
 template <int C, int G>
-__global__ __launch_bounds__(64 * PtabWaves<G>::value) void batched_bih_ptab(int N, SegSrc src,
+__global__ __launch_bounds__((64 * PtabWaves<C, G>::value)) void batched_bih_ptab(int N, SegSrc src,
                                                                               unsigned long long* __restrict__ counter, int gl) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
@@ -4325,9 +4367,9 @@ __global__ __launch_bounds__(64 * PtabWaves<G>::value) void batched_bih_ptab(int
   extern __shared__ double smem[];
   double* tab = smem;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double2* tile = reinterpret_cast<double2*>(smem + 2 * kBihTabPairs * RT) + wv * ((C + 6) * 64);
+  double2* tile = reinterpret_cast<double2*>(smem + 2 * bih_tab_pairs(RT) * RT) + wv * ((C + 6) * 64);
   double2* coef = tile + (C + 5) * 64;
-  constexpr int WPB = PtabWaves<G>::value;
+  constexpr int WPB = PtabWaves<C, G>::value;
   bih_tab_fill(tab, RT, C, N, gl, threadIdx.x, 64 * WPB);
   __syncthreads();
   const int n = N - 4;
@@ -4405,7 +4447,7 @@ constexpr bool has_tile_layout() {
 }
 template <int C, int G>
 constexpr size_t ptab_lds() {
-  return (size_t)kBihTabPairs * 2 * G * C * sizeof(double2) + (size_t)PtabWaves<G>::value * (C + 6) * 64 * sizeof(double2);
+  return (size_t)bih_tab_pairs(2 * G * C) * 2 * G * C * sizeof(double2) + (size_t)PtabWaves<C, G>::value * (C + 6) * 64 * sizeof(double2);
 }
 
 // Launches one class (family FAM, configuration C, G, one N) over up to
@@ -4442,13 +4484,13 @@ hipError_t launch_class(int N, SegSrc& src, unsigned long long* counter, int gl,
       hipLaunchKernelGGL((batched_helm_solve<C, G>), dim3((unsigned)g), dim3(64), 0, st, N, one, gl);
     }
   } else {
-    const size_t lds = (size_t)kBihTabPairs * 2 * G * C * sizeof(double2);
+    const size_t lds = (size_t)bih_tab_pairs(2 * G * C) * 2 * G * C * sizeof(double2);
     static const bool attr = set_dynamic_lds((const void*)batched_bih_walk<C, G>, lds) &&
                              set_dynamic_lds((const void*)batched_bih_solve<C, G>, lds);
     (void)attr;
     hipLaunchKernelGGL((batched_bih_walk<C, G>), dim3((unsigned)blocks), dim3(kBihWalkThreads), lds, st, N, src, gl);
     if constexpr (has_tile_layout<C, G>() && ptab_lds<C, G>() <= 160 * 1024) {
-      constexpr int kWpb = PtabWaves<G>::value;
+      constexpr int kWpb = PtabWaves<C, G>::value;
       constexpr size_t plds = ptab_lds<C, G>();
       static const bool attr2 = set_dynamic_lds((const void*)batched_bih_ptab<C, G>, plds);
       (void)attr2;
@@ -4502,6 +4544,23 @@ hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int g
   for (int i = 0; i < ndesc; ++i) {
     if (done[i] || desc[i].nsys <= 0) continue;
     const shen_problem& d = desc[i];
+    if (multi_waves(d.family, d.N) > 0) {  // large N: its own walk and solve
+      WaveArgs a;
+      a.family = d.family;
+      a.N = d.N;
+      a.nsys = d.nsys;
+      a.c0 = d.c0;
+      a.c1 = d.c1;
+      a.f = d.f;
+      a.u = d.u;
+      a.info = d.info;
+      a.gl = gl;
+      a.stream = stream;
+      const hipError_t err = launch_multi(a);
+      if (err != hipSuccess) return err;
+      done[i] = 1;
+      continue;
+    }
     const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, d.chunk);
     ClassLaunch fn = d.family == SHEN_HELMHOLTZ ? class_launcher<SHEN_HELMHOLTZ>(c) : class_launcher<SHEN_BIHARMONIC>(c);
     if (fn == nullptr) return hipErrorInvalidValue;

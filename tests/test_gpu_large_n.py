@@ -136,3 +136,39 @@ def test_large_n_refusals(dev):
     g = wl.small_grid(2048, 1, index=4)
     with pytest.raises(_lib.ShenError):
         api.helmholtz_solve(T(g.rhs("helmholtz"), dev), T(g.coefficients("helmholtz")[0], dev), chunk=16)
+
+
+def test_batched_with_large_n_grids(dev):
+    """The batched form with grids past N = 1024 next to one-wavefront grids: the large-N grids
+    take their own walk and solve; eager result against the oracle on sampled rows, and three
+    graph replays equal to it bit for bit."""
+    from paper_1701_03787_amd.batched import BatchedProblem, BatchedSolver
+    grids = [wl.small_grid(N, ns, index=20 + i, kmax=200) for i, (N, ns) in enumerate([(4096, 3), (512, 40), (2050, 5)])]
+    case(test="batched_large_n")
+    probs, host = [], []
+    for g in grids:
+        for fam in ("helmholtz", "biharmonic"):
+            f = g.rhs(fam)
+            cs = g.coefficients(fam)
+            probs.append(BatchedProblem(fam, T(f, dev), [T(c, dev) for c in cs]))
+            rows = np.array([0, g.nsys - 1])
+            host.append((g, fam, f[rows], tuple(c[rows] for c in cs), rows))
+    s = BatchedSolver(probs)
+    cfg = s.configurations()
+    assert cfg["biharmonic|4096"]["C"] is None  # no wave configuration to tune there
+    s.run()
+    torch.cuda.synchronize()
+    for p, (g, fam, f, cs, rows) in zip(probs, host):
+        ref = so.solve(fam, g.N, cs, f)
+        assert so.rel_err_per_system(p.u.cpu().numpy()[rows], ref).max() <= TOL, (g.name, fam)
+        assert np.all(p.u.cpu().numpy()[:, wl.n_unknowns(fam, g.N):] == 0)
+    eager = [p.u.clone() for p in probs]
+    s.capture()
+    for r in range(3):
+        for p in probs:
+            p.u.zero_()
+        torch.cuda.synchronize()
+        s.replay()
+        torch.cuda.synchronize()
+        for p, e in zip(probs, eager):
+            assert torch.equal(p.u, e), r
