@@ -24,7 +24,7 @@ METRIC = "wall-normal solves·N/s + HBM GB/s, FP32+refine vs FP64 at 1e-12 rel e
 HBM_PEAK_GBS = 8000.0
 
 
-KERNEL_SOURCES = ("wave_kernels.hip", "shen_rows.hpp", "shen_launch.hpp", "host.hip")
+KERNEL_SOURCES = ("wave_kernels.hip", "shen_rows.hpp", "shen_launch.hpp")  # the solve kernels and their launchers
 
 
 def kernel_source_hash() -> str:
