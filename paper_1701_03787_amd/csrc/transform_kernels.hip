@@ -258,8 +258,10 @@ __device__ __forceinline__ double2 forward_out(const double2* c, int k, int N, i
 // solve); dir 1: Shen coefficients -> point values.  Gauss points, N = 2^m.
 // Each thread moves 8 points of a batch; the next batch's rows are loaded
 // into registers while the current one is transformed.
+// Three work groups per CU (LDS allows three at N = 512): the inverse is held
+// to the forward's register budget for that.
 template <int DIR>
-__global__ __launch_bounds__(kTfThreads) void cheb_fft(int N, int64_t nsys, int space, int solve,
+__global__ __launch_bounds__(kTfThreads, 3) void cheb_fft(int N, int64_t nsys, int space, int solve,
                                                        const double2* __restrict__ in, double2* __restrict__ out) {
   constexpr int dir = DIR;
   extern __shared__ double2 lds[];
