@@ -21,6 +21,8 @@
 // c_0 = 2, c_k = 1 otherwise, c_{N-1} = 2 for Gauss-Lobatto quadrature.
 #pragma once
 
+#include <limits.h>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -269,6 +271,9 @@ __device__ __forceinline__ double2 c_sel(bool c, double2 a, double2 b) {
 // the subdiagonal entries of row k.
 constexpr double kPivTiny = 0x1p-40;
 __device__ __forceinline__ bool bad_pivot(double d, double scale) { return !(fabs(d) > kPivTiny * scale) || !isfinite(d); }
+// The first unusable row: rows come in increasing k, so the lowest k flagged
+// so far (INT_MAX: none).  Branch-free, unlike a conditional assignment.
+__device__ __forceinline__ int first_bad(int bad, bool isbad, int k) { return min(bad, isbad ? k : INT_MAX); }
 __device__ __forceinline__ double row_scale(const HelmRow& h) { return fabs(h.h0) + fabs(h.hm); }
 __device__ __forceinline__ double row_scale(const BihRow& h) { return fabs(h.h0) + fabs(h.hm2) + fabs(h.hm4); }
 

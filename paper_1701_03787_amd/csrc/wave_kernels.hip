@@ -596,7 +596,7 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
     } else {
       double l1, l2, t0, sc;
       bih_step_row(h, m2, m4, o, l1, l2, t0, sc);
-      if (i < nc && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+      bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
     }
     m4 = m2;
     m2 = o;
@@ -794,7 +794,7 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
     const bool ok = wok && k < n;
     double l, g, rd, d, sc;
     helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
-    if (ok && bad_pivot(d, sc) && bad == INT_MAX) bad = k;
+    bad = first_bad(bad, ok && bad_pivot(d, sc), k);
     pv.rd = rd;
     pv.g = g;
     l = ok ? l : 0.0;
@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, con
     const bool ok = wok && k < n;
     double l, g, r, d, sc;
     helm_step(k, al, N, gl, pv, l, g, r, d, sc);
-    if (ok && bad_pivot(d, sc) && bad == INT_MAX) bad = k;
+    bad = first_bad(bad, ok && bad_pivot(d, sc), k);
     pv.rd = r;
     pv.g = g;
     rdj[j] = ok ? r : 0.0;
@@ -1592,7 +1592,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       q4j[TAB ? 0 : j] = Rc.p7;  // q_{k+4} = 1/(k+7)
     }
     if constexpr (!WALKINFO) {
-      if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+      bad = first_bad(bad, ok && bad_pivot(t0, sc), k);
     }
     m4 = m2;
     m2 = o;
@@ -2521,7 +2521,7 @@ __global__ __launch_bounds__(256) void bih_adjoint_tab(int N, int64_t nsys, cons
       BihRowState o;
       double l1, l2, t0, sc;
       bih_step_row(bih_row_tab(k, a, b, c, cm2.B2, cm2.q4, cm2.s4, cm4.B4), m2, m4, o, l1, l2, t0, sc);
-      if (ok && bad_pivot(t0, sc) && bad == INT_MAX) bad = k;
+      bad = first_bad(bad, ok && bad_pivot(t0, sc), k);
       cm4 = cm2;
       cm2 = c;
       m4 = m2;
