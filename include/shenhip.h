@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define SHENHIP_ABI_VERSION 3
+#define SHENHIP_ABI_VERSION 4
 
 typedef struct {
   double re, im;
@@ -120,6 +120,17 @@ typedef struct {
   int32_t* iters;     /* optional DEVICE int32[nsys]: FP32_REFINE solves
                          write the number of corrections applied per system
                          (0 .. refine_max); not written otherwise            */
+  void* work;         /* optional DEVICE scratch for in-place FP64 solves
+                         (u == f) of N with a wave configuration: with
+                         work_bytes >= nsys * shen_factor_bytes(family, N,
+                         opts) they run as a factor call into `work`
+                         followed by the factored solve in place (the
+                         wave kernels) instead of on the lane-per-chain
+                         kernels.  Owned by the caller; must not overlap
+                         f / u; its contents on entry do not matter.
+                         NULL: in-place calls take the lane-per-chain
+                         kernels.  Ignored by out-of-place calls.       */
+  int64_t work_bytes; /* size of `work` in bytes                           */
 } shen_opts;
 
 /* kernel variants (opts.variant); 0 picks per N and mode */

@@ -39,6 +39,8 @@ class ShenOpts(C.Structure):
         ("variant", C.c_int32),
         ("chunk", C.c_int32),
         ("iters", C.c_void_p),
+        ("work", C.c_void_p),
+        ("work_bytes", C.c_int64),
     ]
 
 

@@ -22,8 +22,17 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+def _work_tensor(work, device):
+    """(pointer, bytes) of an in-place workspace: a contiguous device tensor, or None."""
+    if work is None:
+        return None, 0
+    if not isinstance(work, torch.Tensor) or not work.is_contiguous() or work.device != device:
+        raise ValueError(f"work must be a contiguous tensor on {device}")
+    return work.data_ptr(), work.numel() * work.element_size()
+
+
 def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8, refine_tol=1e-14,
-          variant="auto", chunk=0, iters=None) -> L.ShenOpts:
+          variant="auto", chunk=0, iters=None, work=None) -> L.ShenOpts:
     o = L.default_opts()
     o.stream = _stream_handle(device)
     o.precision = _PREC[precision]
@@ -35,6 +44,7 @@ def _opts(device, precision="fp64", quad="gc", transpose=False, info=None, refin
     o.variant = _VARIANT[variant] if isinstance(variant, str) else int(variant)
     o.chunk = int(chunk)
     o.iters = iters.data_ptr() if iters is not None else None
+    o.work, o.work_bytes = _work_tensor(work, device)
     return o
 
 
@@ -112,11 +122,13 @@ def _result(u, inf, its):
 
 
 def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                    refine_tol=1e-14, variant="auto", chunk=0, iters=None):
+                    refine_tol=1e-14, variant="auto", chunk=0, iters=None, work=None):
     """u = (S + alpha B)^{-1} f per system (or the transposed system).
 
     Returns u, then info and iters when requested (True or an int32 tensor of the batch
-    shape): info per system, and for precision="fp32_refine" the corrections applied."""
+    shape): info per system, and for precision="fp32_refine" the corrections applied.
+    work: a device tensor of at least nsys * factor_bytes(family, N) bytes, for in-place
+    solves (out=f) on the wave kernels."""
     f = _rows(f, "f")
     N = f.shape[-1]
     lead = f.shape[:-1]
@@ -124,14 +136,14 @@ def helmholtz_solve(f, alpha, *, out=None, precision="fp64", quad="gc", transpos
     u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
     its = _info_tensor(iters, lead, f.device, "iters")
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its, work)
     L.check(L.lib().helmholtz_solve(N, _nsys(lead), alpha.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "helmholtz_solve")
     return _result(u, inf, its)
 
 
 def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpose=False, info=None, refine_max=8,
-                     refine_tol=1e-14, variant="auto", chunk=0, iters=None):
+                     refine_tol=1e-14, variant="auto", chunk=0, iters=None, work=None):
     """u = (Q + a A + b B)^{-1} f per system (or the transposed system); returns as helmholtz_solve."""
     f = _rows(f, "f")
     N = f.shape[-1]
@@ -141,7 +153,7 @@ def biharmonic_solve(f, a, b, *, out=None, precision="fp64", quad="gc", transpos
     u = _out(out, f)
     inf = _info_tensor(info, lead, f.device)
     its = _info_tensor(iters, lead, f.device, "iters")
-    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its)
+    o = _opts(f.device, precision, quad, transpose, inf, refine_max, refine_tol, variant, chunk, its, work)
     L.check(L.lib().biharmonic_solve(N, _nsys(lead), a.data_ptr(), b.data_ptr(), f.data_ptr(), u.data_ptr(), C.byref(o)),
             "biharmonic_solve")
     return _result(u, inf, its)

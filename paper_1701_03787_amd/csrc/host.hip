@@ -61,6 +61,7 @@ int check_opts(const shen_opts& o) {
   if (o.iters && !aligned(o.iters, 4)) return SHEN_EINVAL;
   if (o.refine_max > 64) return SHEN_EINVAL;
   if (o.chunk < 0 || o.chunk > 64) return SHEN_EINVAL;
+  if (o.work_bytes < 0 || (o.work && !aligned(o.work, 16))) return SHEN_EINVAL;
   return SHEN_OK;
 }
 
@@ -183,6 +184,33 @@ int factored(int family, int32_t N, int64_t nsys, const double* c0, const double
   w.fac = fac;
   w.fac_mode = mode;
   return run_wave(w);
+}
+
+// In-place FP64 solves on the wave kernels through the caller's workspace
+// (opts.work): the boundary walk parks its restart states there instead of in
+// u (a factor call), then the factored solve runs in place.
+bool use_inplace_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
+  return f == u && o.work && o.variant != SHEN_VARIANT_CHAIN && !o.transpose && o.precision == SHEN_FP64 &&
+         shen::wave_supported(family, N);
+}
+int inplace_wave(int family, int32_t N, int64_t nsys, const double* c0, const double* c1, const shen_c128* f, shen_c128* u,
+                 const shen_opts& o) {
+  const int64_t slot = shen::wave_state_slot(family, N, o.chunk);
+  if (slot <= 0) return SHEN_ENOTSUP;
+  const int64_t need = nsys * slot * 16;
+  if (o.work_bytes < need) return SHEN_EINVAL;
+  const uintptr_t pw = (uintptr_t)o.work, pu = (uintptr_t)u, lu = (uintptr_t)nsys * (uintptr_t)N * 16u;
+  if (pw < pu + lu && pu < pw + (uintptr_t)need) return SHEN_EINVAL;  // workspace inside the rows
+  shen_opts of = o;
+  of.info = nullptr;
+  of.work = nullptr;
+  of.work_bytes = 0;
+  int rc = factored(family, N, nsys, c0, c1, o.work, nullptr, nullptr, &of, 1);
+  if (rc != SHEN_OK) return rc;
+  shen_opts os = o;
+  os.work = nullptr;
+  os.work_bytes = 0;
+  return factored(family, N, nsys, c0, c1, o.work, f, u, &os, 2);
 }
 
 // Adjoint with the restart states of a factor call (no walk; lambda may alias gbar).
@@ -323,6 +351,7 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_inplace_wave(o, 0, N, f, u)) return inplace_wave(SHEN_HELMHOLTZ, N, nsys, alpha, nullptr, f, u, o);
   if (use_multi(o, 0, N, f, u)) {
     shen::WaveArgs w;
     w.family = 0;
@@ -381,6 +410,7 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_inplace_wave(o, 1, N, f, u)) return inplace_wave(SHEN_BIHARMONIC, N, nsys, ca, cb, f, u, o);
   if (use_multi(o, 1, N, f, u)) {
     shen::WaveArgs w;
     w.family = 1;

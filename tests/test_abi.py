@@ -29,13 +29,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_strings():
     lib = L.lib()
-    assert lib.shen_abi_version() == 3
+    assert lib.shen_abi_version() == 4
     for code in (0, -1, -2, -3, -4, 7):
         assert isinstance(lib.shen_status_string(code), bytes)
     o = L.default_opts()
     assert o.precision == 0 and o.quad == 0 and o.transpose == 0 and o.refine_max == 8
     assert o.refine_tol == pytest.approx(1e-14)
-    assert C.sizeof(L.ShenOpts) == 56
+    assert C.sizeof(L.ShenOpts) == 72
     assert C.sizeof(L.ShenProblem) == 72
 
 
@@ -66,6 +66,11 @@ def test_bad_enums_and_sizes():
         setattr(o, field, val)
         assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL, field
         assert lib.biharmonic_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL, field
+    o = L.default_opts()
+    o.work, o.work_bytes = ALIGNED + 8, 1 << 20  # misaligned workspace
+    assert lib.helmholtz_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
+    o.work, o.work_bytes = ALIGNED, -1           # negative size
+    assert lib.biharmonic_solve(16, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
     o = L.default_opts()
     assert lib.biharmonic_solve(4, 4, ALIGNED, ALIGNED, ALIGNED, ALIGNED, C.byref(o)) == L.SHEN_EINVAL
     o.info = ALIGNED + 2

@@ -95,6 +95,37 @@ def test_factored_in_place_and_chunk(dev, family):
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_one_call_in_place_with_workspace(dev, family):
+    """An in-place one-call solve given a workspace (opts.work) runs on the wave kernels (a factor
+    call into the workspace, then the factored solve in place): bitwise the out-of-place result,
+    at ragged and tiled N, GC and GL.  A workspace too small is refused before any launch; without
+    one the in-place call takes the lane-per-chain kernels and meets the same bar."""
+    from paper_1701_03787_amd import api, _lib
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    for N, quad in ((130, "gc"), (512, "gc"), (512, "gl"), (1024, "gc")):
+        g = wl.small_grid(N, 37, kmax=362, index=N + 12, nu=5e-5, dt=5e-4)
+        csn = g.coefficients(family)
+        cs = [T(c, dev) for c in csn]
+        fh = g.rhs(family)
+        case(test="inplace_work", family=family, N=N, quad=quad)
+        ref = fn(T(fh, dev), *cs, quad=quad)
+        work = torch.empty(g.nsys * api.factor_bytes(family, N) // 8, dtype=torch.float64, device=dev)
+        f = T(fh, dev)
+        u = fn(f, *cs, out=f, quad=quad, work=work)
+        torch.cuda.synchronize()
+        assert u.data_ptr() == f.data_ptr()
+        assert torch.equal(f, ref)
+        qo = so.GL if quad == "gl" else so.GC
+        assert so.rel_err_per_system(f.cpu().numpy(), so.solve(family, N, csn, fh, quad=qo)).max() <= TOL
+        with pytest.raises(_lib.ShenError):
+            fn(f, *cs, out=f, quad=quad, work=work[: work.numel() // 2])
+        f2 = T(fh, dev)
+        fn(f2, *cs, out=f2, quad=quad)  # no workspace: lane-per-chain kernels
+        torch.cuda.synchronize()
+        assert so.rel_err_per_system(f2.cpu().numpy(), so.solve(family, N, csn, fh, quad=qo)).max() <= TOL
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
 def test_factored_full_size_sampled(dev, family):
     """The bench workload (N=512, 512x257 wavenumbers): bitwise equal to the one-call solve on
     every system, and sampled systems against the oracle."""
