@@ -135,8 +135,8 @@ struct BihRow {
   double q2, s2, q4, s4;
 };
 
-__device__ __forceinline__ BihRow bih_row(int k, double a, double b, int N, int gl, const Recip& R) {
-  const BihMats m = bih_mats(k, N, gl, R);
+// Row k of the system from its coefficient-free entries m = bih_mats(k, ...).
+__device__ __forceinline__ BihRow bih_row_from(const BihMats& m, double a, double b) {
   BihRow h;
   h.hm4 = b * m.Bm4;
   h.hm2 = a * m.Am2 + b * m.Bm2;
@@ -150,6 +150,9 @@ __device__ __forceinline__ BihRow bih_row(int k, double a, double b, int N, int 
   h.q4 = m.q4;
   h.s4 = m.s4;
   return h;
+}
+__device__ __forceinline__ BihRow bih_row(int k, double a, double b, int N, int gl, const Recip& R) {
+  return bih_row_from(bih_mats(k, N, gl, R), a, b);
 }
 
 // Coefficient-free constants of biharmonic row k, from which BihRow is

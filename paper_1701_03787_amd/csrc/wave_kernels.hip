@@ -3706,12 +3706,67 @@ __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int 
   helm_boundary_chain(N, kMultiC, Gt, (int)(t & 1), alpha[w], u + w * (int64_t)N, gl);
 }
 
+// The biharmonic walk over whole chains: every thread of a block walks the
+// same rows (its parity's), so the coefficient-free entries of the next
+// 2 kWalkWin rows (bih_mats, the values the solve computes for the same rows)
+// are formed once per block into an LDS window, and each thread only combines
+// them with its coefficients (bih_row_from) before the factorisation step.
+static constexpr int kWalkWin = 64;      // chain elements per window
+static constexpr int kWalkWords = 18;    // doubles per window row (17 used)
+__device__ __forceinline__ void mats_put(double* d, const BihMats& m) {
+  d[0] = m.Bm4, d[1] = m.Am2, d[2] = m.Bm2, d[3] = m.Q0, d[4] = m.A0, d[5] = m.B0, d[6] = m.Q2, d[7] = m.A2, d[8] = m.B2;
+  d[9] = m.Q4, d[10] = m.B4, d[11] = m.p, d[12] = m.r, d[13] = m.q2, d[14] = m.s2, d[15] = m.q4, d[16] = m.s4;
+}
+__device__ __forceinline__ BihMats mats_get(const double* d) {
+  BihMats m;
+  m.Bm4 = d[0], m.Am2 = d[1], m.Bm2 = d[2], m.Q0 = d[3], m.A0 = d[4], m.B0 = d[5], m.Q2 = d[6], m.A2 = d[7], m.B2 = d[8];
+  m.Q4 = d[9], m.B4 = d[10], m.p = d[11], m.r = d[12], m.q2 = d[13], m.s2 = d[14], m.q4 = d[15], m.s4 = d[16];
+  return m;
+}
 __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ ca,
                                                       const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+  constexpr int C = kMultiC;
+  __shared__ double win[2 * kWalkWin * kWalkWords];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
-  const int64_t w = t >> 1;
-  bih_boundary_chain(N, kMultiC, Gt, (int)(t & 1), ca[w], cb[w], u + w * (int64_t)N, gl);
+  const bool act = t < 2 * nsys;  // inactive threads still take part in the barriers
+  const int64_t w = act ? t >> 1 : 0;
+  const int p = (int)(t & 1);
+  const int n = N - 4;
+  const int nc = (n - p + 1) / 2;
+  const int ilast = ((nc + C - 1) / C - 1) * C;            // this chain's last chunk start
+  const int ilast0 = (((n + 1) / 2 + C - 1) / C - 1) * C;  // the longest chain's (p = 0)
+  const double a = act ? ca[w] : 0.0, b = act ? cb[w] : 0.0;
+  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  for (int i0 = 0; i0 < ilast0; i0 += kWalkWin) {
+    __syncthreads();  // the previous window is no longer read
+    for (int r = threadIdx.x; r < 2 * kWalkWin; r += blockDim.x) {
+      const int k = 2 * i0 + r;
+      if (k < N) {
+        Recip R;
+        R.init(k);
+        mats_put(win + r * kWalkWords, bih_mats(k, N, gl, R));
+      }
+    }
+    __syncthreads();
+    const int iend = (i0 + kWalkWin < ilast) ? i0 + kWalkWin : ilast;
+    for (int i = i0; i < iend; ++i) {
+      const int k = 2 * i + p;
+      BihRowState o;
+      double l1, l2, t0;
+      bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0);
+      m4 = m2;
+      m2 = o;
+      if (act && (i + 1) % C == 0) {
+        double2* sv = reinterpret_cast<double2*>(st + (p * Gt + (i + 1) / C) * 10);
+        sv[0] = make_double2(m2.rU0, m2.U2);
+        sv[1] = make_double2(m2.U4, m2.P);
+        sv[2] = make_double2(m2.R, m4.rU0);
+        sv[3] = make_double2(m4.U2, m4.U4);
+        sv[4] = make_double2(m4.P, m4.R);
+      }
+    }
+  }
 }
 
 // Lowest bad row over the work group's wavefronts -> info[w].
