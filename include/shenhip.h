@@ -167,6 +167,11 @@ int shen_wave_config(int32_t family, int32_t N, int32_t chunk, int32_t* C, int32
  * Helmholtz solve (Sec. 4, the odd/even upper-Hessenberg LU with the
  * constant tail of U):  (S + alpha_w B) u_w = f_w  for w < nsys,
  * or the transposed system when opts->transpose.  N >= 3.
+ * Transposed solves (FP64 only, else SHEN_ENOTSUP) are the adjoint solve
+ * without gradients: out of place at N with a wave configuration they run
+ * on the adjoint wave kernels, otherwise on the lane-per-chain kernels
+ * (variant SHEN_VARIANT_WAVE in place: SHEN_ENOTSUP).  The same holds for
+ * biharmonic_solve.
  */
 int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c128* f, shen_c128* u,
                     const shen_opts* opts);

@@ -107,10 +107,18 @@ int run(ChainArgs& a) {
 // restart states in u); everything else, and sizes it does not cover, goes to
 // the chain kernels.
 // The wave kernels cover the plain FP64 and the FP32 + refinement solves of
-// both families, not the transposed solve.
+// both families here; the transposed solve reaches them through the adjoint
+// (use_adjoint_wave).
 bool wave_mode_ok(const shen_opts& o, int family) {
   (void)family;
   return !o.transpose;
+}
+// The transposed FP64 solve H^T u = f is the adjoint solve without gradients:
+// out of place, at N with a wave configuration, it runs on the adjoint wave
+// kernels.
+bool use_adjoint_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
+  return o.transpose && o.precision == SHEN_FP64 && o.variant != SHEN_VARIANT_CHAIN && f != u &&
+         shen::wave_supported(family, N);
 }
 bool use_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
   if (o.variant == SHEN_VARIANT_CHAIN) return false;
@@ -351,6 +359,7 @@ int helmholtz_solve(int32_t N, int64_t nsys, const double* alpha, const shen_c12
   if (check_rows(f) || check_rows(u) || check_coef(alpha)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_adjoint_wave(o, 0, N, f, u)) return helmholtz_adjoint(N, nsys, alpha, nullptr, f, u, nullptr, opts);
   if (use_inplace_wave(o, 0, N, f, u)) return inplace_wave(SHEN_HELMHOLTZ, N, nsys, alpha, nullptr, f, u, o);
   if (use_multi(o, 0, N, f, u)) {
     shen::WaveArgs w;
@@ -410,6 +419,7 @@ int biharmonic_solve(int32_t N, int64_t nsys, const double* ca, const double* cb
   if (check_rows(f) || check_rows(u) || check_coef(ca) || check_coef(cb)) return SHEN_EINVAL;
   if (rows_overlap_partially(f, u, nsys, N)) return SHEN_EINVAL;
   if (o.transpose && o.precision != SHEN_FP64) return SHEN_ENOTSUP;
+  if (use_adjoint_wave(o, 1, N, f, u)) return biharmonic_adjoint(N, nsys, ca, cb, nullptr, f, u, nullptr, nullptr, opts);
   if (use_inplace_wave(o, 1, N, f, u)) return inplace_wave(SHEN_BIHARMONIC, N, nsys, ca, cb, f, u, o);
   if (use_multi(o, 1, N, f, u)) {
     shen::WaveArgs w;

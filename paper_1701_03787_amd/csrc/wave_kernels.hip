@@ -243,11 +243,6 @@ __device__ __forceinline__ void bih_step(int k, double a, double b, int N, int g
                                          double& sc) {
   bih_step_row(bih_row(k, a, b, N, gl, Rc), m2, m4, o, l1, l2, t0out, sc);
 }
-__device__ __forceinline__ void bih_step(int k, double a, double b, int N, int gl, const Recip& Rc, const BihRowState& m2,
-                                         const BihRowState& m4, BihRowState& o, double& l1, double& l2, double& t0out) {
-  double sc;
-  bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0out, sc);
-}
 
 // The same step in FP32 (mixed-precision form): row entries formed in FP64
 // and rounded once, factorisation arithmetic in FP32.
@@ -529,37 +524,6 @@ template <int C, int G>
 __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, const double* __restrict__ alpha,
                                                        double2* __restrict__ S, int64_t sstride, int gl) {
   helm_walk_block<C, G>(N, nsys, alpha, S, sstride, gl, blockIdx.x);
-}
-
-__device__ __forceinline__ void bih_boundary_chain(int N, int C, int G, int p, double a, double b, double2* __restrict__ urow,
-                                                   int gl) {
-  const int n = N - 4;
-  const int nc = (n - p + 1) / 2;
-  const int nchunks = (nc + C - 1) / C;
-  if (nchunks <= 1) return;
-  double* st = reinterpret_cast<double*>(urow);
-  BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-  Recip Rc;
-  Rc.init(p);
-  const int ilast = (nchunks - 1) * C;
-  for (int i = 0; i < ilast; ++i) {
-    const int k = 2 * i + p;
-    if (i > 0) Rc.advance(k);
-    BihRowState o;
-    double l1, l2, t0;
-    bih_step(k, a, b, N, gl, Rc, m2, m4, o, l1, l2, t0);
-    m4 = m2;
-    m2 = o;
-    if ((i + 1) % C == 0) {
-      const int m = (i + 1) / C;
-      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 10);
-      s[0] = make_double2(m2.rU0, m2.U2);
-      s[1] = make_double2(m2.U4, m2.P);
-      s[2] = make_double2(m2.R, m4.rU0);
-      s[3] = make_double2(m4.U2, m4.U4);
-      s[4] = make_double2(m4.P, m4.R);
-    }
-  }
 }
 
 // Table-driven form of the biharmonic boundary walk: the rows are assembled

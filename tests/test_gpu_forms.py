@@ -393,13 +393,54 @@ def test_mixed_precision_wave_sizes(dev, family, N):
     assert np.all(u.cpu().numpy()[:, wl.n_unknowns(family, N):] == 0)
 
 
-def test_wave_variant_refuses_transpose(dev):
+def test_wave_variant_refuses_transpose_in_place(dev):
+    """The transposed solve runs on the wave kernels out of place only (through the adjoint);
+    in place, a caller that insists on them is refused."""
     from paper_1701_03787_amd import api, _lib
     g = wl.small_grid(64, 3)
     f = T(g.rhs("helmholtz"), dev)
     a = T(g.coefficients("helmholtz")[0], dev)
     with pytest.raises(_lib.ShenError):
-        api.helmholtz_solve(f, a, transpose=True, variant="wave")
+        api.helmholtz_solve(f, a, transpose=True, variant="wave", out=f)
+    u = api.helmholtz_solve(f, a, transpose=True, variant="wave")
+    torch.cuda.synchronize()
+    ref = so.solve("helmholtz", 64, g.coefficients("helmholtz"), g.rhs("helmholtz"), transpose=True)
+    assert so.rel_err_per_system(u.cpu().numpy(), ref).max() <= TOL
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_transposed_solve_wave_vs_oracle(dev, family):
+    """H^T u = f on the adjoint wave kernels (out of place, the automatic choice at these N)
+    against the oracle, and against the lane-per-chain kernels at twice the bar; ragged system
+    counts, both quadratures, zero tail, info bit-exact with one failing system."""
+    from paper_1701_03787_amd import api
+    fn = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+    for N, nsys in ((13, 5), (97, 37), (512, 70), (1024, 9)):
+        for quad in ("gc", "gl"):
+            case(test="transposed", family=family, N=N, nsys=nsys, quad=quad)
+            g = wl.small_grid(N, nsys, kmax=362, index=N + 3, nu=5e-5, dt=5e-4)
+            cs = [c.copy() for c in g.coefficients(family)]
+            f = g.rhs(family)
+            qo = so.GL if quad == "gl" else so.GC
+            ref = so.solve(family, N, cs, f, quad=qo, transpose=True)
+            u, info = fn(T(f, dev), *[T(c, dev) for c in cs], transpose=True, quad=quad, info=True)
+            uc = fn(T(f, dev), *[T(c, dev) for c in cs], transpose=True, quad=quad, variant="chain")
+            torch.cuda.synchronize()
+            u, uc = u.cpu().numpy(), uc.cpu().numpy()
+            assert np.all(info.cpu().numpy() == 0)
+            assert np.all(u[:, wl.n_unknowns(family, N):] == 0)
+            assert so.rel_err_per_system(u, ref).max() <= TOL, (N, quad)
+            assert so.rel_err_per_system(u, uc).max() <= 2 * TOL, (N, quad)
+    N = 97
+    g = wl.small_grid(N, 4, index=8)
+    cs = [c.copy() for c in g.coefficients(family)]
+    cs[0][1] = np.inf
+    case(test="transposed_info", family=family, N=N)
+    u, info = fn(T(g.rhs(family), dev), *[T(c, dev) for c in cs], transpose=True, info=True)
+    assert list(info.cpu().numpy()) == [0, 1, 0, 0]
+    ok = np.array([0, 2, 3])
+    ref = so.solve(family, N, tuple(c[ok] for c in cs), g.rhs(family)[ok], transpose=True)
+    assert so.rel_err_per_system(u.cpu().numpy()[ok], ref).max() <= TOL
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
