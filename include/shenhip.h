@@ -149,9 +149,10 @@ const char* shen_status_string(int code);
 
 /* Largest N the solves accept on the current device for the given family
  * and precision: the larger of the lane-per-chain kernels' limit (set by the
- * device's LDS size) and, for SHEN_FP64, the large-N wave path's (N <= 4096,
- * chains spread over up to four wavefronts of one work group; out-of-place
- * solves only).  In-place calls, SHEN_FP32_REFINE, the adjoints, the
+ * device's LDS size) and, for SHEN_FP64, the large-N wave path's (N <= 8192,
+ * chains spread over up to four wavefronts of one work group: both parity
+ * chains of a system per work group up to N = 4096, one per work group past
+ * it; out-of-place solves only).  In-place calls, SHEN_FP32_REFINE, the adjoints, the
  * factor-once form and the products are limited by the lane-per-chain
  * kernels past N = 1024. */
 int32_t shen_max_n(int32_t family, int32_t precision);
@@ -371,7 +372,7 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
  * kernels of the single-grid path over all of its grids at once (the
  * boundary walk, then the persistent LDS-streamed wave solve, which pulls
  * work items of sys_per_tile systems from a queue).  Grids with
- * 1024 < N <= 4096 take the large-N solves of helmholtz_solve /
+ * 1024 < N <= 8192 take the large-N solves of helmholtz_solve /
  * biharmonic_solve, one walk and one solve per grid (chunk must be 0 there;
  * sys_per_tile is ignored).  Every kernel is enqueued on opts->stream; the
  * call may be captured in a hipGraph and replayed (the descriptors are read
@@ -387,7 +388,7 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
  *   counters it uses with its first kernel).  Concurrent calls must not
  *   share `work`.
  * Returns SHEN_EINVAL for a descriptor the plan would refuse or that was not
- * planned, SHEN_ENOTSUP for an N beyond 4096.
+ * planned, SHEN_ENOTSUP for an N beyond 8192.
  */
 typedef struct {
   int32_t family;  /* SHEN_HELMHOLTZ or SHEN_BIHARMONIC */

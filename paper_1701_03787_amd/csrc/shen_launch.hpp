@@ -80,9 +80,10 @@ struct WaveCfg {
 };
 __host__ __device__ WaveCfg pick_cfg(int nc, int family, int N, int prefC);
 bool wave_supported(int family, int N);
-// Large N (chains across wavefronts): wavefronts per system, 0 if (family, N)
-// is not served there; plain FP64 forward solves out of place only.
-int multi_waves(int family, int N);
+// Large N (chains across wavefronts): wavefronts per work group, 0 if
+// (family, N) is not served there; *one (if given): one parity chain per work
+// group (N past 4096).  Plain FP64 forward solves out of place only.
+int multi_waves(int family, int N, bool* one = nullptr);
 hipError_t launch_multi(const WaveArgs& a);
 bool wave_chunk_ok(int family, int N, int chunk);
 // Batched form: the host descriptors (validated, planned), one launch pair

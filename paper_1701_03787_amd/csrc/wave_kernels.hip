@@ -637,53 +637,75 @@ __global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64
 // =========================================================================
 struct NoCarry {
   static constexpr bool on = false;
-  __device__ __forceinline__ int kbase(int, int) const { return 0; }
+  __device__ __forceinline__ int parity(int h) const { return h; }
+  __device__ __forceinline__ int kbase(int, int, int) const { return 0; }
 };
-static constexpr int kCarryMaxW = 4;     // wavefronts per system
-static constexpr int kCarryWords = 24;   // doubles per (scan, wavefront, parity)
+static constexpr int kCarryMaxW = 4;     // wavefronts per work group
+static constexpr int kCarryWords = 24;   // doubles per (scan, segment)
+// Publish this segment's map (`owner` lane: the one holding the segment's
+// total), wait for the work group, then fold the maps of the segments before
+// this one (forward) or after it, from the top down (backward):
+// s <- M_u s + c_u, from s = 0.  Segment u's slot is base + u * stride.
+template <int D, bool BWD>
+__device__ __forceinline__ void fold_segments(double* base, int stride, int seg, int nseg, bool owner,
+                                              const double (&M)[D][D], const double2 (&c)[D], double2 (&st)[D]) {
+  if (owner) {
+    double* o = base + seg * stride;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+#pragma unroll
+      for (int q = 0; q < D; ++q) o[r * D + q] = M[r][q];
+      o[D * D + 2 * r] = c[r].x;
+      o[D * D + 2 * r + 1] = c[r].y;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < D; ++r) st[r] = zero2();
+  const int cnt = BWD ? nseg - 1 - seg : seg;
+  for (int i = 0; i < cnt; ++i) {
+    const int u = BWD ? nseg - 1 - i : i;
+    const double* o = base + u * stride;
+    double2 ns[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      double2 acc = make_double2(o[D * D + 2 * r], o[D * D + 2 * r + 1]);
+#pragma unroll
+      for (int q = 0; q < D; ++q) acc = c_fma(o[r * D + q], st[q], acc);
+      ns[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r) st[r] = ns[r];
+  }
+}
+// Both parity chains of one system per work group: wavefront v holds segment
+// v of each (its lower G lanes parity 0, its upper G lanes parity 1).
 struct WaveCarry {
   static constexpr bool on = true;
   int v, W;     // this wavefront, wavefronts per system
   double* xch;  // LDS: [3 scans][kCarryMaxW][2 parities][kCarryWords]
+  __device__ __forceinline__ int parity(int h) const { return h; }
   // first row of this wavefront's chain segments (chunk length C, G lanes)
-  __device__ __forceinline__ int kbase(int C, int G) const { return 2 * v * G * C; }
-  __device__ __forceinline__ double* slot(int scan, int wave, int p) const {
-    return xch + ((scan * kCarryMaxW + wave) * 2 + p) * kCarryWords;
-  }
-  // Publish `cnt` doubles (on the lane that holds the wavefront's total), wait
-  // for every wavefront, then fold: s <- M_u s + c_u over the wavefronts u
-  // before this one (forward) or after it from the top down (backward).
+  __device__ __forceinline__ int kbase(int C, int G, int) const { return 2 * v * G * C; }
   template <int D, bool BWD>
-  __device__ __forceinline__ void fold(int scan, int p, bool owner, const double (&M)[D][D], const double2 (&c)[D],
+  __device__ __forceinline__ void fold(int scan, int h, bool owner, const double (&M)[D][D], const double2 (&c)[D],
                                        double2 (&st)[D]) const {
-    if (owner) {
-      double* o = slot(scan, v, p);
-#pragma unroll
-      for (int r = 0; r < D; ++r) {
-#pragma unroll
-        for (int q = 0; q < D; ++q) o[r * D + q] = M[r][q];
-        o[D * D + 2 * r] = c[r].x;
-        o[D * D + 2 * r + 1] = c[r].y;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < D; ++r) st[r] = zero2();
-    const int cnt = BWD ? W - 1 - v : v;
-    for (int i = 0; i < cnt; ++i) {
-      const int u = BWD ? W - 1 - i : i;
-      const double* o = slot(scan, u, p);
-      double2 ns[D];
-#pragma unroll
-      for (int r = 0; r < D; ++r) {
-        double2 acc = make_double2(o[D * D + 2 * r], o[D * D + 2 * r + 1]);
-#pragma unroll
-        for (int q = 0; q < D; ++q) acc = c_fma(o[r * D + q], st[q], acc);
-        ns[r] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < D; ++r) st[r] = ns[r];
-    }
+    fold_segments<D, BWD>(xch + ((scan * kCarryMaxW) * 2 + h) * kCarryWords, 2 * kCarryWords, v, W, owner, M, c, st);
+  }
+};
+// One parity chain per work group (N past what two-parity work groups hold):
+// the 2W half-wavefronts of G lanes are consecutive segments of that chain,
+// half h of wavefront v being segment 2v + h.
+struct ChainCarry {
+  static constexpr bool on = true;
+  int v, W, pp;  // this wavefront, wavefronts per chain, the chain's parity
+  double* xch;   // LDS: [3 scans][2 kCarryMaxW segments][kCarryWords]
+  __device__ __forceinline__ int parity(int) const { return pp; }
+  __device__ __forceinline__ int kbase(int C, int G, int h) const { return 2 * (2 * v + h) * G * C; }
+  template <int D, bool BWD>
+  __device__ __forceinline__ void fold(int scan, int h, bool owner, const double (&M)[D][D], const double2 (&c)[D],
+                                       double2 (&st)[D]) const {
+    fold_segments<D, BWD>(xch + scan * 2 * kCarryMaxW * kCarryWords, kCarryWords, 2 * v + h, 2 * W, owner, M, c, st);
   }
 };
 
@@ -739,10 +761,11 @@ __device__ __forceinline__ void helm_wave_body(int N, int64_t nsys, int64_t wbas
 template <int C, int G, bool PIPE, typename Carry>
 __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool wok, double al, HelmPrev pv, double2 (&x)[C],
                                               double2* __restrict__ urow, int gl, int32_t* __restrict__ info, Carry cy) {
-  const int p = (lane / G) & 1;
+  const int hf = (lane / G) & 1;  // which G-lane half of the 2G lanes
+  const int p = cy.parity(hf);    // the parity of this lane's chain
   const int m = lane % G;
   const int n = N - 2;
-  const int k0 = cy.kbase(C, G) + 2 * m * C + p;
+  const int k0 = cy.kbase(C, G, hf) + 2 * m * C + p;
   const double hm = -0.5 * kPi * al;
   // factorisation restart + local forward elimination (zero incoming state)
   // l of row k is hm times 1/d of row k-2 (helm_step), so it is rebuilt from
@@ -801,7 +824,7 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
       const double M[1][1] = {{sT}};
       const double2 c[1] = {sb};
       double2 sin[1];
-      cy.template fold<1, false>(0, p, m == G - 1, M, c, sin);
+      cy.template fold<1, false>(0, hf, m == G - 1, M, c, sin);
       h = c_sel(m == 0, sin[0], shfl_up2(c_fma(sT, sin[0], sb), 1, G));
     } else {
       h = shfl_up2(sb, 1, G);
@@ -877,7 +900,7 @@ __device__ __forceinline__ int helm_wave_core(int N, int lane, int64_t w, bool w
       const double M[2][2] = {{A00, A01}, {A10, A11}};
       const double2 c[2] = {c0, c1};
       double2 top[2];
-      cy.template fold<2, true>(1, p, m == 0, M, c, top);
+      cy.template fold<2, true>(1, hf, m == 0, M, c, top);
       sa = c_sel(m == G - 1, top[0], shfl_down2(c_add(c_fma(A00, top[0], c_mul(A01, top[1])), c0), 1, G));
       sS = c_sel(m == G - 1, top[1], shfl_down2(c_add(c_fma(A10, top[0], c_mul(A11, top[1])), c1), 1, G));
     } else {
@@ -1514,10 +1537,11 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
                                               BihRowState m4, double2 (&x)[C], FetchF fetch_f, double2* __restrict__ urow,
                                               int gl, int32_t* __restrict__ info, const double* tab, Hook after_f,
                                               std::bool_constant<WALKINFO>, int walk_bad, Carry cy) {
-  const int p = (lane / G) & 1;
+  const int hf = (lane / G) & 1;  // which G-lane half of the 2G lanes
+  const int p = cy.parity(hf);    // the parity of this lane's chain
   const int m = lane % G;
   const int n = N - 4;
-  const int k0 = cy.kbase(C, G) + 2 * m * C + p;
+  const int k0 = cy.kbase(C, G, hf) + 2 * m * C + p;
   // factorisation restart + local forward elimination; keep normalised U rows
   constexpr int RT = 2 * G * C;
   double l1j[C], l2j[C], r0j[C], u2j[C], u4j[C], pj[C], rj[C];
@@ -1635,7 +1659,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       if constexpr (G == 32) {
         // (T is now this lane's prefix within its row: missing partners
         // composed as the identity)
-        const double2 t0 = chain_lane32<15>(b0, p), t1 = chain_lane32<15>(b1, p);
+        const double2 t0 = chain_lane32<15>(b0, hf), t1 = chain_lane32<15>(b1, hf);
         const double2 n0 = c_add(c_fma(T00, t0, c_mul(T01, t1)), b0);
         const double2 n1 = c_add(c_fma(T10, t0, c_mul(T11, t1)), b1);
         b0 = c_sel(m >= 16, n0, b0);
@@ -1671,7 +1695,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     const double M[2][2] = {{T00, T01}, {T10, T11}};
     const double2 c[2] = {b0, b1};
     double2 sin[2];
-    cy.template fold<2, false>(0, p, m == G - 1, M, c, sin);
+    cy.template fold<2, false>(0, hf, m == G - 1, M, c, sin);
     cn1 = c_add(c_fma(T00, sin[0], c_mul(T01, sin[1])), b0);
     cn2 = c_add(c_fma(T10, sin[0], c_mul(T11, sin[1])), b1);
     h1 = c_sel(m == 0, sin[0], shfl_up2(cn1, 1, G));
@@ -1703,7 +1727,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       nx2 = RowShift<1>::from_upper(sh2);
     } else if constexpr (G == 32) {
       const double2 u1 = RowShift<1>::from_upper(sh1), u2 = RowShift<1>::from_upper(sh2);
-      const double2 c1 = chain_lane32<16>(sh1, p), c2 = chain_lane32<16>(sh2, p);
+      const double2 c1 = chain_lane32<16>(sh1, hf), c2 = chain_lane32<16>(sh2, hf);
       nx1 = c_sel(m == 15, c1, u1);
       nx2 = c_sel(m == 15, c2, u2);
     } else {
@@ -1722,7 +1746,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     const double M[2][2] = {{T00, T01}, {T10, T11}};
     const double2 c[2] = {b0, b1};
     double2 din[2];
-    cy.template fold<2, false>(1, p, m == G - 1, M, c, din);
+    cy.template fold<2, false>(1, hf, m == G - 1, M, c, din);
     const double2 e1 = c_add(c_fma(T00, din[0], c_mul(T01, din[1])), b0);
     const double2 e2 = c_add(c_fma(T10, din[0], c_mul(T11, din[1])), b1);
     h1 = c_sel(m == 0, din[0], shfl_up2(e1, 1, G));
@@ -1824,7 +1848,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
       // also the state entering lane 15
       double2 t[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) t[r] = chain_lane32<16>(cv[r], p);
+      for (int r = 0; r < 4; ++r) t[r] = chain_lane32<16>(cv[r], hf);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         double2 acc = cv[r];
@@ -1859,7 +1883,7 @@ __device__ __forceinline__ int bih_wave_core(int N, int lane, int64_t w, bool wo
     }
     if constexpr (Carry::on) {  // the state entering this wavefront's segment from above, then this lane
       double2 top[4], y[4];
-      cy.template fold<4, true>(2, p, m == 0, A, cv, top);
+      cy.template fold<4, true>(2, hf, m == 0, A, cv, top);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         double2 acc = cv[r];
@@ -3652,22 +3676,67 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
 }
 
 // =========================================================================
-// Large N: chains longer than one wavefront.  One system per work group of W
-// wavefronts (C = 16, G = 32: 1024 rows per wavefront, N up to 1024 W), the
-// wave cores with the cross-wavefront carries (WaveCarry).  The boundary walk
-// runs one thread per chain over the whole chain and parks the restart state
-// of every chunk (W G per parity) in the output row; both it and the solve
-// compute the row entries (no table, which would not fit in LDS), so the
-// stitched factors are bitwise those of the sequential LU.
+// Large N: chains longer than one wavefront, C = 16, G = 32 (512 chain
+// elements per G-lane group), the wave cores with cross-wavefront carries.
+// Two layouts:
+//  * up to 2048 elements per chain (N <= 4096): one system per work group of
+//    W wavefronts, both parity chains in every wavefront (WaveCarry);
+//  * up to 4096 (N <= 8192): one parity chain per work group of W
+//    wavefronts, whose 2W half-wavefronts are consecutive segments of it
+//    (ChainCarry); the two chains of a system solve in different work groups.
+// The boundary walk runs one thread per chain over the whole chain and parks
+// the restart state of every chunk in the output row: with two parities per
+// work group at [(p Gt + c) s + i] (s = 1 or 5 double2 per state, Gt chunks
+// per chain); with one parity per work group interleaved by parity, at
+// [2 (c s + i) + p], so that neither chain's solve writes (rows of its own
+// parity) where the other still reads its states.  In that layout the walk
+// also makes the pivot checks of every row (it runs the same factorisation)
+// and writes info.  Both walk and solve compute the row entries (no table,
+// which would not fit in LDS), so the stitched factors are bitwise those of
+// the sequential LU.
 // =========================================================================
 static constexpr int kMultiC = 16, kMultiG = 32;
 
+// Helmholtz walk over one whole chain, states interleaved by parity; returns
+// the chain's first unusable row (INT_MAX: none).
+__device__ __forceinline__ int helm_walk_chain_il(int N, int C, int p, double al, double2* __restrict__ urow, int gl) {
+  const int n = N - 2;
+  const int nc = (n - p + 1) / 2;
+  const int ilast = ((nc + C - 1) / C - 1) * C;  // last chunk start
+  HelmPrev pv = {0.0, 0.0};
+  int bad = INT_MAX;
+  for (int i = 0; i < nc; ++i) {
+    const int k = 2 * i + p;
+    double l, g, rd, d, sc;
+    helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
+    bad = first_bad(bad, bad_pivot(d, sc), k);
+    pv.rd = rd;
+    pv.g = g;
+    if ((i + 1) % C == 0 && i + 1 <= ilast) urow[2 * ((i + 1) / C) + p] = make_double2(rd, g);
+  }
+  return bad;
+}
+
+// Lowest bad row of the two chains of system w (threads t and t ^ 1) -> info[w].
+__device__ __forceinline__ void walk_info(int bad, bool act, int p, int64_t w, int32_t* __restrict__ info) {
+  bad = min(bad, __shfl_xor(bad, 1));
+  if (act && p == 0) info[w] = (bad == INT_MAX) ? 0 : bad + 1;
+}
+
+template <bool ONE>
 __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ alpha,
-                                                       double2* __restrict__ u, int gl) {
+                                                       double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nsys) return;
+  const bool act = t < 2 * nsys;  // both threads of a system share this (2 nsys is even)
+  if (!act) return;
   const int64_t w = t >> 1;
-  helm_boundary_chain(N, kMultiC, Gt, (int)(t & 1), alpha[w], u + w * (int64_t)N, gl);
+  const int p = (int)(t & 1);
+  if constexpr (ONE) {
+    const int bad = helm_walk_chain_il(N, kMultiC, p, alpha[w], u + w * (int64_t)N, gl);
+    if (info != nullptr) walk_info(bad, act, p, w, info);
+  } else {
+    helm_boundary_chain(N, kMultiC, Gt, p, alpha[w], u + w * (int64_t)N, gl);
+  }
 }
 
 // The biharmonic walk over whole chains: every thread of a block walks the
@@ -3687,8 +3756,10 @@ __device__ __forceinline__ BihMats mats_get(const double* d) {
   m.Q4 = d[9], m.B4 = d[10], m.p = d[11], m.r = d[12], m.q2 = d[13], m.s2 = d[14], m.q4 = d[15], m.s4 = d[16];
   return m;
 }
+template <bool ONE>
 __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ ca,
-                                                      const double* __restrict__ cb, double2* __restrict__ u, int gl) {
+                                                      const double* __restrict__ cb, double2* __restrict__ u, int gl,
+                                                      int32_t* __restrict__ info) {
   constexpr int C = kMultiC;
   __shared__ double win[2 * kWalkWin * kWalkWords];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -3698,11 +3769,16 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
   const int ilast = ((nc + C - 1) / C - 1) * C;            // this chain's last chunk start
-  const int ilast0 = (((n + 1) / 2 + C - 1) / C - 1) * C;  // the longest chain's (p = 0)
+  const int nc0 = (n + 1) / 2;                             // the longest chain (p = 0)
+  const int ilast0 = ((nc0 + C - 1) / C - 1) * C;          // and its last chunk start
+  // rows stepped through: up to the last chunk start, or (checking every
+  // pivot) the whole chain
+  const int iend_all = ONE ? nc0 : ilast0, iend_mine = ONE ? nc : ilast;
   const double a = act ? ca[w] : 0.0, b = act ? cb[w] : 0.0;
   double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-  for (int i0 = 0; i0 < ilast0; i0 += kWalkWin) {
+  int bad = INT_MAX;
+  for (int i0 = 0; i0 < iend_all; i0 += kWalkWin) {
     __syncthreads();  // the previous window is no longer read
     for (int r = threadIdx.x; r < 2 * kWalkWin; r += blockDim.x) {
       const int k = 2 * i0 + r;
@@ -3713,23 +3789,32 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
       }
     }
     __syncthreads();
-    const int iend = (i0 + kWalkWin < ilast) ? i0 + kWalkWin : ilast;
+    const int iend = (i0 + kWalkWin < iend_mine) ? i0 + kWalkWin : iend_mine;
     for (int i = i0; i < iend; ++i) {
       const int k = 2 * i + p;
       BihRowState o;
-      double l1, l2, t0;
-      bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0);
+      double l1, l2, t0, sc;
+      bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0, sc);
+      if constexpr (ONE) bad = first_bad(bad, bad_pivot(t0, sc), k);
       m4 = m2;
       m2 = o;
-      if (act && (i + 1) % C == 0) {
-        double2* sv = reinterpret_cast<double2*>(st + (p * Gt + (i + 1) / C) * 10);
-        sv[0] = make_double2(m2.rU0, m2.U2);
-        sv[1] = make_double2(m2.U4, m2.P);
-        sv[2] = make_double2(m2.R, m4.rU0);
-        sv[3] = make_double2(m4.U2, m4.U4);
-        sv[4] = make_double2(m4.P, m4.R);
+      if (act && (i + 1) % C == 0 && i + 1 <= ilast) {
+        const int c = (i + 1) / C;
+        const double v[10] = {m2.rU0, m2.U2, m2.U4, m2.P, m2.R, m4.rU0, m4.U2, m4.U4, m4.P, m4.R};
+        if constexpr (ONE) {
+          double2* sv = reinterpret_cast<double2*>(st);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sv[2 * (5 * c + q) + p] = make_double2(v[2 * q], v[2 * q + 1]);
+        } else {
+          double2* sv = reinterpret_cast<double2*>(st + (p * Gt + c) * 10);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) sv[q] = make_double2(v[2 * q], v[2 * q + 1]);
+        }
       }
     }
+  }
+  if constexpr (ONE) {
+    if (info != nullptr) walk_info(bad, act, p, w, info);
   }
 }
 
@@ -3747,26 +3832,39 @@ __device__ __forceinline__ void multi_info(int bad, int v, int W, int lane, int*
   }
 }
 
-template <int W>
+// Work group -> (system, lane's chain parity, lane's chunk in its chain).
+template <int W, bool ONE>
+struct MultiLane {
+  int64_t w;
+  int v, lane, h, p, mg;
+  __device__ __forceinline__ MultiLane() {
+    v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    lane = threadIdx.x & 63;
+    w = ONE ? (int64_t)(blockIdx.x >> 1) : (int64_t)blockIdx.x;
+    h = (lane / kMultiG) & 1;
+    p = ONE ? (int)(blockIdx.x & 1) : h;
+    mg = (ONE ? 2 * v + h : v) * kMultiG + lane % kMultiG;
+  }
+};
+
+template <int W, bool ONE>
 __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* __restrict__ alpha, const double2* __restrict__ f,
                                                           double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
   constexpr int C = kMultiC, G = kMultiG;
   __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
   __shared__ int badw[kCarryMaxW];
-  const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const int64_t w = blockIdx.x;
-  const int p = (lane / G) & 1, mg = v * G + lane % G;
+  const MultiLane<W, ONE> L;
+  const int64_t w = L.w;
   const int n = N - 2;
-  const int k0 = 2 * mg * C + p;
+  const int k0 = 2 * L.mg * C + L.p;
   const double al = alpha[w];
   const double2* frow = f + w * (int64_t)N;
   double2* urow = u + w * (int64_t)N;
   // restart state (every wavefront reads its states before the first
   // barrier of the scans, and stores only after the last)
   HelmPrev pv = {0.0, 0.0};
-  if (mg > 0 && k0 < n) {
-    const double2 s = urow[p * W * G + mg];
+  if (L.mg > 0 && k0 < n) {
+    const double2 s = ONE ? urow[2 * L.mg + L.p] : urow[L.p * W * G + L.mg];
     pv.rd = s.x;
     pv.g = s.y;
   }
@@ -3776,38 +3874,43 @@ __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* _
     const int k = k0 + 2 * j;
     x[j] = (k < n) ? frow[k] : zero2();
   }
-  const WaveCarry cy{v, W, xch};
-  const int bad = helm_wave_core<C, G, true, WaveCarry>(N, lane, w, true, al, pv, x, urow, gl, nullptr, cy);
+  int bad;
+  if constexpr (ONE) {
+    const ChainCarry cy{L.v, W, L.p, xch};
+    bad = helm_wave_core<C, G, true, ChainCarry>(N, L.lane, w, true, al, pv, x, urow, gl, nullptr, cy);
+  } else {
+    const WaveCarry cy{L.v, W, xch};
+    bad = helm_wave_core<C, G, true, WaveCarry>(N, L.lane, w, true, al, pv, x, urow, gl, nullptr, cy);
+  }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int k = k0 + 2 * j;
     if (k < N) urow[k] = (k < n) ? x[j] : zero2();
   }
-  if (info != nullptr) multi_info(bad, v, W, lane, badw, info, w);
+  if (!ONE && info != nullptr) multi_info(bad, L.v, W, L.lane, badw, info, w);
 }
 
-template <int W>
+template <int W, bool ONE>
 __global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __restrict__ ca, const double* __restrict__ cb,
                                                          const double2* __restrict__ f, double2* __restrict__ u, int gl,
                                                          int32_t* __restrict__ info) {
   constexpr int C = kMultiC, G = kMultiG;
   __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
   __shared__ int badw[kCarryMaxW];
-  const int v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const int64_t w = blockIdx.x;
-  const int p = (lane / G) & 1, mg = v * G + lane % G;
+  const MultiLane<W, ONE> L;
+  const int64_t w = L.w;
   const int n = N - 4;
-  const int k0 = 2 * mg * C + p;
+  const int k0 = 2 * L.mg * C + L.p;
   const double a = ca[w], b = cb[w];
   const double2* frow = f + w * (int64_t)N;
   double2* urow = u + w * (int64_t)N;
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
-  if (mg > 0 && k0 < n) {
-    const double2* sv = urow + (p * W * G + mg) * 5;
-    const double2 s0 = sv[0], s1 = sv[1], s2 = sv[2], s3 = sv[3], s4 = sv[4];
-    m2 = BihRowState{s0.x, s0.y, s1.x, s1.y, s2.x};
-    m4 = BihRowState{s2.y, s3.x, s3.y, s4.x, s4.y};
+  if (L.mg > 0 && k0 < n) {
+    double2 s[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q] = ONE ? urow[2 * (5 * L.mg + q) + L.p] : urow[(L.p * W * G + L.mg) * 5 + q];
+    m2 = BihRowState{s[0].x, s[0].y, s[1].x, s[1].y, s[2].x};
+    m4 = BihRowState{s[2].y, s[3].x, s[3].y, s[4].x, s[4].y};
   }
   double2 x[C];
 #pragma unroll
@@ -3819,15 +3922,22 @@ __global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __
     const int k = k0 + 2 * j;
     return (k < n) ? frow[k] : zero2();
   };
-  const WaveCarry cy{v, W, xch};
-  const int bad = bih_wave_core<C, G, true, false>(N, lane, w, true, a, b, m2, m4, x, fetch, urow, gl, nullptr, nullptr,
-                                                   NoHook(), std::false_type{}, INT_MAX, cy);
+  int bad;
+  if constexpr (ONE) {  // the walk has checked every pivot and writes info
+    const ChainCarry cy{L.v, W, L.p, xch};
+    bad = bih_wave_core<C, G, true, false>(N, L.lane, w, true, a, b, m2, m4, x, fetch, urow, gl, nullptr, nullptr, NoHook(),
+                                           std::true_type{}, INT_MAX, cy);
+  } else {
+    const WaveCarry cy{L.v, W, xch};
+    bad = bih_wave_core<C, G, true, false>(N, L.lane, w, true, a, b, m2, m4, x, fetch, urow, gl, nullptr, nullptr, NoHook(),
+                                           std::false_type{}, INT_MAX, cy);
+  }
 #pragma unroll
   for (int j = 0; j < C; ++j) {
     const int k = k0 + 2 * j;
     if (k < N) urow[k] = (k < n) ? x[j] : zero2();
   }
-  if (info != nullptr) multi_info(bad, v, W, lane, badw, info, w);
+  if (!ONE && info != nullptr) multi_info(bad, L.v, W, L.lane, badw, info, w);
 }
 
 // =========================================================================
@@ -3868,40 +3978,59 @@ bool wave_supported(int family, int N) {
   return c.C != 0;
 }
 
-// Wavefronts per system of the large-N solves (0: not served there): N past
-// the one-wavefront configurations, up to kCarryMaxW wavefronts.
-int multi_waves(int family, int N) {
+// Wavefronts per work group of the large-N solves (0: not served there): N
+// past the one-wavefront configurations; two parity chains per work group
+// while they fit in kCarryMaxW wavefronts (2048 chain elements), else one
+// chain per work group (4096 elements), *one set.
+int multi_waves(int family, int N, bool* one) {
+  if (one) *one = false;
   if (wave_supported(family, N)) return 0;
-  const int per = kMultiC * kMultiG;  // chain elements per wavefront
-  const int W = ((N + 1) / 2 + per - 1) / per;
-  return (W >= 2 && W <= kCarryMaxW) ? W : 0;
+  const int per = kMultiC * kMultiG;  // chain elements per G-lane group
+  const int nc = (N + 1) / 2;         // the longer chain's bound
+  const int W2 = (nc + per - 1) / per;
+  if (W2 >= 2 && W2 <= kCarryMaxW) return W2;
+  const int W1 = (nc + 2 * per - 1) / (2 * per);
+  if (W1 < 2 || W1 > kCarryMaxW) return 0;
+  if (one) *one = true;
+  return W1;
 }
 
 hipError_t launch_multi(const WaveArgs& a) {
-  const int W = multi_waves(a.family, a.N);
+  bool one = false;
+  const int W = multi_waves(a.family, a.N, &one);
   if (W == 0 || a.mixed || a.adjoint || a.fac_mode || a.rhs) return hipErrorInvalidValue;
   if (a.nsys <= 0) return hipSuccess;
-  if (a.nsys > (int64_t)INT_MAX) return hipErrorInvalidValue;  // one work group per system
+  // one work group per system (per chain with one parity per work group)
+  if (a.nsys > (int64_t)(one ? INT_MAX / 2 : INT_MAX)) return hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)a.stream;
   const int Gt = W * kMultiG;
   const unsigned walk = (unsigned)((2 * a.nsys + 255) / 256);
   double2* u = (double2*)a.u;
   const double2* f = (const double2*)a.f;
-  if (a.family == 0)
-    hipLaunchKernelGGL(helm_walk_multi, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl);
-  else
-    hipLaunchKernelGGL(bih_walk_multi, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl);
-  const dim3 grid((unsigned)a.nsys), block(64 * W);
-#define SHEN_MULTI(WW)                                                                                      \
-  if (W == WW) {                                                                                            \
-    if (a.family == 0)                                                                                      \
-      hipLaunchKernelGGL(helm_wave_multi<WW>, grid, block, 0, st, a.N, a.c0, f, u, a.gl, a.info);           \
-    else                                                                                                    \
-      hipLaunchKernelGGL(bih_wave_multi<WW>, grid, block, 0, st, a.N, a.c0, a.c1, f, u, a.gl, a.info);      \
+  if (one) {
+    if (a.family == 0)
+      hipLaunchKernelGGL(helm_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl, a.info);
+    else
+      hipLaunchKernelGGL(bih_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl, a.info);
+  } else {
+    if (a.family == 0)
+      hipLaunchKernelGGL(helm_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl, nullptr);
+    else
+      hipLaunchKernelGGL(bih_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl, nullptr);
   }
-  SHEN_MULTI(2)
-  SHEN_MULTI(3)
-  SHEN_MULTI(4)
+  const dim3 grid((unsigned)(one ? 2 * a.nsys : a.nsys)), block(64 * W);
+#define SHEN_MULTI(WW, ONE)                                                                                        \
+  if (W == WW && one == ONE) {                                                                                     \
+    if (a.family == 0)                                                                                             \
+      hipLaunchKernelGGL((helm_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, f, u, a.gl, a.info);           \
+    else                                                                                                           \
+      hipLaunchKernelGGL((bih_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, a.c1, f, u, a.gl, a.info);      \
+  }
+  SHEN_MULTI(2, false)
+  SHEN_MULTI(3, false)
+  SHEN_MULTI(4, false)
+  SHEN_MULTI(3, true)
+  SHEN_MULTI(4, true)
 #undef SHEN_MULTI
   return hipGetLastError();
 }

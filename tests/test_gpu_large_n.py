@@ -1,6 +1,7 @@
-"""GPU parity of the large-N wave solves (1024 < N <= 4096: each parity chain spread over the
-wavefronts of one work group, the scans carried across them through LDS) against the oracle,
-and against the lane-per-chain kernels where those serve the same N.
+"""GPU parity of the large-N wave solves (1024 < N <= 8192: chains spread over the wavefronts of
+one work group, the scans carried across them through LDS; both parity chains of a system per work
+group up to N = 4096, one chain per work group past it) against the oracle, and against the
+lane-per-chain kernels where those serve the same N.
 
 Bars: per-system relative max-norm error <= 1e-12 against the oracle (the solves' bar), zero
 tail and info bit-exact; the Sec. 5 roundoff protocol within 4x of the paper's table at its
@@ -45,15 +46,16 @@ def solve(family, coeffs, f, dev, **kw):
     return out.cpu().numpy()
 
 
-# 2, 3 and 4 wavefronts per system, ragged and exact fills of the last one
-SIZES = (1025, 1537, 2048, 2049, 3001, 4096)
+# two parities per work group: 2, 3 and 4 wavefronts, ragged and exact fills of the last one;
+# one parity per work group: 3 and 4 wavefronts (6 and 8 segments), ragged and exact
+SIZES = (1025, 1537, 2048, 2049, 3001, 4096, 4097, 6143, 8192)
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
 def test_large_n_vs_oracle(dev, family):
     for N in SIZES:
         nsys = 3 if N <= 2049 else 2
-        for quad in ("gc", "gl") if N in (1537, 4096) else ("gc",):
+        for quad in ("gc", "gl") if N in (1537, 4096, 8192) else ("gc",):
             case(test="large_n", family=family, N=N, nsys=nsys, quad=quad)
             g = wl.small_grid(N, nsys, kmax=362, index=N, nu=5e-5, dt=5e-4)
             cs = g.coefficients(family)
@@ -74,7 +76,7 @@ def test_large_n_vs_chain_kernels(dev, family):
     lane-per-chain kernels also serve N, the two agree to twice the bar (each is within the bar
     of the exact solution), and sampled rows match the oracle."""
     from paper_1701_03787_amd import _lib
-    for N in (1100, 2000, 2900):
+    for N in (1100, 2000, 2900, 4500):
         g = wl.small_grid(N, 97, kmax=362, index=N + 1, nu=5e-5, dt=5e-4)
         cs = g.coefficients(family)
         f = g.rhs(family)
@@ -92,17 +94,26 @@ def test_large_n_vs_chain_kernels(dev, family):
 
 
 @pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-def test_large_n_info(dev, family):
-    """A non-finite coefficient fails row 0 of that system only (info 1); the others solve."""
-    N = 2049
+@pytest.mark.parametrize("N", [2049, 4500])
+def test_large_n_info(dev, family, N):
+    """info in both large-N layouts (N = 4500: written by the walk, which checks every pivot).
+    System 1 is singular in the leading block of row 11's chain, an odd row (oracle: minus a
+    generalised eigenvalue, polished), so its pivot at row 11 is unusable: info 12, the lower of
+    the two chains' first bad rows.  System 2 has a non-finite coefficient: row 0, info 1.  The
+    others solve to the bar."""
     g = wl.small_grid(N, 4, kmax=200, index=9)
     cs = [c.copy() for c in g.coefficients(family)]
+    if family == "helmholtz":
+        cs[0][1] = so.singular_coefficient(family, N, 11)
+    else:
+        cs[0][1] = -1000.0
+        cs[1][1] = so.singular_coefficient(family, N, 11, a=-1000.0)
     cs[0][2] = np.nan
     f = g.rhs(family)
     case(test="large_n_info", family=family, N=N)
     u, info = solve(family, cs, f, dev, info=True)
-    assert list(info) == [0, 0, 1, 0]
-    ok = np.array([0, 1, 3])
+    assert list(info) == [0, 12, 1, 0]
+    ok = np.array([0, 3])
     ref = so.solve(family, N, tuple(c[ok] for c in cs), f[ok])
     assert so.rel_err_per_system(u[ok], ref).max() <= TOL
 
@@ -127,12 +138,17 @@ def test_roundoff_protocol_large_n(dev, family):
 
 
 def test_large_n_refusals(dev):
-    """Past 4096 the biharmonic has no kernel here (the lane-per-chain kernels stop earlier);
-    a chunk length is not a knob of the large-N path."""
+    """Past 8192 the biharmonic has no kernel here (the lane-per-chain kernels stop earlier);
+    a chunk length is not a knob of the large-N path; the other forms stay on the lane-per-chain
+    kernels there (no FP32 + refinement biharmonic at 4500)."""
     from paper_1701_03787_amd import _lib, api
-    g = wl.small_grid(4097, 1, index=3)
+    g = wl.small_grid(8193, 1, index=3)
     with pytest.raises(_lib.ShenError):
         api.biharmonic_solve(T(g.rhs("biharmonic"), dev), *[T(c, dev) for c in g.coefficients("biharmonic")])
+    g = wl.small_grid(4500, 1, index=3)
+    with pytest.raises(_lib.ShenError):
+        api.biharmonic_solve(T(g.rhs("biharmonic"), dev), *[T(c, dev) for c in g.coefficients("biharmonic")],
+                             precision="fp32_refine")
     g = wl.small_grid(2048, 1, index=4)
     with pytest.raises(_lib.ShenError):
         api.helmholtz_solve(T(g.rhs("helmholtz"), dev), T(g.coefficients("helmholtz")[0], dev), chunk=16)
@@ -143,7 +159,8 @@ def test_batched_with_large_n_grids(dev):
     take their own walk and solve; eager result against the oracle on sampled rows, and three
     graph replays equal to it bit for bit."""
     from paper_1701_03787_amd.batched import BatchedProblem, BatchedSolver
-    grids = [wl.small_grid(N, ns, index=20 + i, kmax=200) for i, (N, ns) in enumerate([(4096, 3), (512, 40), (2050, 5)])]
+    grids = [wl.small_grid(N, ns, index=20 + i, kmax=200)
+             for i, (N, ns) in enumerate([(4096, 3), (512, 40), (2050, 5), (5000, 2)])]
     case(test="batched_large_n")
     probs, host = [], []
     for g in grids:
