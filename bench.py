@@ -380,17 +380,15 @@ def measure_transforms(dev, args, grid, data, host, rows):
 
 def measure_large_n(dev, args):
     """Large N (chains spread over the wavefronts of a work group): N=4096 on the 128x65 rfft
-    grid (8,320 systems per family), the paper's largest roundoff-table column; ms, GB/s and
-    sampled errors against the oracle (one row per family: the dense oracle is O(N^3)).  The
-    Helmholtz solve is also timed on the lane-per-chain kernels, which served it before."""
+    grid (8,320 systems per family), the paper's largest roundoff-table column, and N=8192 on
+    the 64x33 grid of the paper's 64x64 timing mesh (its largest timing-table column; one parity
+    chain per work group there); ms, GB/s and sampled errors against the oracle (one row per
+    family: the dense oracle is O(N^3)).  At N=4096 the Helmholtz solve is also timed on the
+    lane-per-chain kernels, which served it before."""
     import numpy as np
     import torch
     from paper_1701_03787_amd import api
     from paper_1701_03787_amd import workloads as wl
-    kx, kz = wl.rfft_grid(128, 128)
-    g = wl.Grid(4096, kx, kz, 5e-5, 5e-4, 3.0, 6, name="N4096_128x65")
-    out = {"workload": g.name}
-    rows = np.array([int(np.argmax(g.K2))])
     reps = max(3, min(args.steps, 10))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -405,24 +403,33 @@ def measure_large_n(dev, args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    for fam in ("helmholtz", "biharmonic"):
-        fh = g.rhs(fam)
-        csh = g.coefficients(fam)
-        f = torch.from_numpy(fh).to(dev)
-        cs = [torch.from_numpy(c).to(dev) for c in csh]
-        u = torch.empty_like(f)
-        solve = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
-        ms = timed(lambda: solve(f, *cs, out=u))
-        nbytes = alg_bytes(fam, g.N, g.nsys)
-        gbs = nbytes / (ms * 1e-3) / 1e9
-        rec = {"ms": round(ms, 4), "value": round(g.nsys * g.N / (ms * 1e-3), 2), "unit": "system·N/s",
-               "hbm_gbps": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes),
-               "max_rel_err_sampled": _sampled_err(fam, g.N, csh, fh, u, rows)}
-        if fam == "helmholtz":
-            rec["chain_kernels_ms"] = round(timed(lambda: solve(f, *cs, out=u, variant="chain")), 4)
-        out[fam] = rec
-        del f, cs, u
-    torch.cuda.empty_cache()
+    def one_grid(N, nk, chain):
+        kx, kz = wl.rfft_grid(nk, nk)
+        g = wl.Grid(N, kx, kz, 5e-5, 5e-4, 3.0, 6, name=f"N{N}_{nk}x{nk // 2 + 1}")
+        out = {"workload": g.name}
+        rows = np.array([int(np.argmax(g.K2))])
+        for fam in ("helmholtz", "biharmonic"):
+            fh = g.rhs(fam)
+            csh = g.coefficients(fam)
+            f = torch.from_numpy(fh).to(dev)
+            cs = [torch.from_numpy(c).to(dev) for c in csh]
+            u = torch.empty_like(f)
+            solve = api.helmholtz_solve if fam == "helmholtz" else api.biharmonic_solve
+            ms = timed(lambda: solve(f, *cs, out=u))
+            nbytes = alg_bytes(fam, g.N, g.nsys)
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            rec = {"ms": round(ms, 4), "value": round(g.nsys * g.N / (ms * 1e-3), 2), "unit": "system·N/s",
+                   "hbm_gbps": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes),
+                   "max_rel_err_sampled": _sampled_err(fam, g.N, csh, fh, u, rows)}
+            if chain and fam == "helmholtz":
+                rec["chain_kernels_ms"] = round(timed(lambda: solve(f, *cs, out=u, variant="chain")), 4)
+            out[fam] = rec
+            del f, cs, u
+        torch.cuda.empty_cache()
+        return out
+
+    out = one_grid(4096, 128, True)
+    out["paper_max_n"] = one_grid(8192, 64, False)
     return out
 
 
