@@ -405,28 +405,6 @@ __device__ __forceinline__ BihConst bih_const_at(const double* tab, int RT, int 
 
 // States parked in u[w] (as doubles): Helmholtz [(p*G + m)*2 + {0,1}] = (1/d, g)
 // of row 2(mC)-2+p; biharmonic [(p*G + m)*10 + ...] = rows k-2 then k-4.
-__device__ __forceinline__ void helm_boundary_chain(int N, int C, int G, int p, double al, double2* __restrict__ urow, int gl) {
-  const int n = N - 2;
-  const int nc = (n - p + 1) / 2;  // elements in this chain
-  const int nchunks = (nc + C - 1) / C;
-  if (nchunks <= 1) return;
-  double* st = reinterpret_cast<double*>(urow);
-  HelmPrev pv = {0.0, 0.0};
-  const int ilast = (nchunks - 1) * C;  // last chunk start
-  for (int i = 0; i < ilast; ++i) {
-    const int k = 2 * i + p;
-    double l, g, rd, d;
-    helm_step(k, al, N, gl, pv, l, g, rd, d);
-    pv.rd = rd;
-    pv.g = g;
-    if ((i + 1) % C == 0) {
-      const int m = (i + 1) / C;
-      double2* s = reinterpret_cast<double2*>(st + (p * G + m) * 2);
-      *s = make_double2(pv.rd, pv.g);
-    }
-  }
-}
-
 // FP32 restart states (float2 (1/d, g) at float2 slot p*G + m of u[w]).
 __global__ __launch_bounds__(256) void helm_boundary32(int N, int64_t nsys, int C, int G, const double* __restrict__ alpha,
                                                        double2* __restrict__ u, int gl) {
@@ -3697,22 +3675,33 @@ __global__ __launch_bounds__((64 * MassLds<C, G, FAM, OP>::WPB)) void mass_wave_
 // =========================================================================
 static constexpr int kMultiC = 16, kMultiG = 32;
 
-// Helmholtz walk over one whole chain, states interleaved by parity; returns
-// the chain's first unusable row (INT_MAX: none).
-__device__ __forceinline__ int helm_walk_chain_il(int N, int C, int p, double al, double2* __restrict__ urow, int gl) {
+// Helmholtz walk over one chain, a chunk of C rows at a time (unrolled, so
+// that the entries of later rows are formed while the recurrence of earlier
+// ones runs; one wavefront per SIMD leaves that latency exposed otherwise),
+// parking the state entering every later chunk: interleaved by parity (IL,
+// double2 slot 2c + p) or at slot p Gt + c.  CHECK: step through the whole
+// chain and return its first unusable row (INT_MAX: none); else stop at the
+// last chunk start.
+template <int C, bool IL, bool CHECK>
+__device__ __forceinline__ int helm_walk_chain(int N, int Gt, int p, double al, double2* __restrict__ urow, int gl) {
   const int n = N - 2;
   const int nc = (n - p + 1) / 2;
-  const int ilast = ((nc + C - 1) / C - 1) * C;  // last chunk start
+  const int nchunks = (nc + C - 1) / C;
+  const int cend = CHECK ? nchunks : nchunks - 1;
   HelmPrev pv = {0.0, 0.0};
   int bad = INT_MAX;
-  for (int i = 0; i < nc; ++i) {
-    const int k = 2 * i + p;
-    double l, g, rd, d, sc;
-    helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
-    bad = first_bad(bad, bad_pivot(d, sc), k);
-    pv.rd = rd;
-    pv.g = g;
-    if ((i + 1) % C == 0 && i + 1 <= ilast) urow[2 * ((i + 1) / C) + p] = make_double2(rd, g);
+  for (int c = 0; c < cend; ++c) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = c * C + j;
+      const int k = 2 * i + p;
+      double l, g, rd, d, sc;
+      helm_step(k, al, N, gl, pv, l, g, rd, d, sc);
+      if constexpr (CHECK) bad = first_bad(bad, i < nc && bad_pivot(d, sc), k);
+      pv.rd = rd;
+      pv.g = g;
+    }
+    if (c + 1 < nchunks) urow[IL ? 2 * (c + 1) + p : p * Gt + c + 1] = make_double2(pv.rd, pv.g);
   }
   return bad;
 }
@@ -3732,10 +3721,10 @@ __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int 
   const int64_t w = t >> 1;
   const int p = (int)(t & 1);
   if constexpr (ONE) {
-    const int bad = helm_walk_chain_il(N, kMultiC, p, alpha[w], u + w * (int64_t)N, gl);
+    const int bad = helm_walk_chain<kMultiC, true, true>(N, Gt, p, alpha[w], u + w * (int64_t)N, gl);
     if (info != nullptr) walk_info(bad, act, p, w, info);
   } else {
-    helm_boundary_chain(N, kMultiC, Gt, p, alpha[w], u + w * (int64_t)N, gl);
+    helm_walk_chain<kMultiC, false, false>(N, Gt, p, alpha[w], u + w * (int64_t)N, gl);
   }
 }
 
@@ -3768,17 +3757,18 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
   const int p = (int)(t & 1);
   const int n = N - 4;
   const int nc = (n - p + 1) / 2;
-  const int ilast = ((nc + C - 1) / C - 1) * C;            // this chain's last chunk start
-  const int nc0 = (n + 1) / 2;                             // the longest chain (p = 0)
-  const int ilast0 = ((nc0 + C - 1) / C - 1) * C;          // and its last chunk start
-  // rows stepped through: up to the last chunk start, or (checking every
-  // pivot) the whole chain
-  const int iend_all = ONE ? nc0 : ilast0, iend_mine = ONE ? nc : ilast;
+  const int nch = (nc + C - 1) / C;              // chunks of this chain
+  const int nch0 = ((n + 1) / 2 + C - 1) / C;    // of the longest chain (p = 0)
+  // chunks stepped through by the block: up to the last chunk start, or
+  // (checking every pivot) the whole chain
+  const int cend = ONE ? nch0 : nch0 - 1;
+  constexpr int WC = kWalkWin / C;               // chunks per window
   const double a = act ? ca[w] : 0.0, b = act ? cb[w] : 0.0;
-  double* st = reinterpret_cast<double*>(u + w * (int64_t)N);
+  double2* sv = u + w * (int64_t)N;
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   int bad = INT_MAX;
-  for (int i0 = 0; i0 < iend_all; i0 += kWalkWin) {
+  for (int c0 = 0; c0 < cend; c0 += WC) {
+    const int i0 = c0 * C;
     __syncthreads();  // the previous window is no longer read
     for (int r = threadIdx.x; r < 2 * kWalkWin; r += blockDim.x) {
       const int k = 2 * i0 + r;
@@ -3789,27 +3779,26 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
       }
     }
     __syncthreads();
-    const int iend = (i0 + kWalkWin < iend_mine) ? i0 + kWalkWin : iend_mine;
-    for (int i = i0; i < iend; ++i) {
-      const int k = 2 * i + p;
-      BihRowState o;
-      double l1, l2, t0, sc;
-      bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0, sc);
-      if constexpr (ONE) bad = first_bad(bad, bad_pivot(t0, sc), k);
-      m4 = m2;
-      m2 = o;
-      if (act && (i + 1) % C == 0 && i + 1 <= ilast) {
-        const int c = (i + 1) / C;
+    for (int cc = 0; cc < WC && c0 + cc < cend; ++cc) {
+      const int c = c0 + cc;
+      // C rows unrolled (rows past the chain, whose window rows may be
+      // unset, only feed a recurrence that is not used again)
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const int i = c * C + j;
+        const int k = 2 * i + p;
+        BihRowState o;
+        double l1, l2, t0, sc;
+        bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0, sc);
+        if constexpr (ONE) bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
+        m4 = m2;
+        m2 = o;
+      }
+      if (act && c + 1 < nch) {  // the state entering chunk c + 1
         const double v[10] = {m2.rU0, m2.U2, m2.U4, m2.P, m2.R, m4.rU0, m4.U2, m4.U4, m4.P, m4.R};
-        if constexpr (ONE) {
-          double2* sv = reinterpret_cast<double2*>(st);
 #pragma unroll
-          for (int q = 0; q < 5; ++q) sv[2 * (5 * c + q) + p] = make_double2(v[2 * q], v[2 * q + 1]);
-        } else {
-          double2* sv = reinterpret_cast<double2*>(st + (p * Gt + c) * 10);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) sv[q] = make_double2(v[2 * q], v[2 * q + 1]);
-        }
+        for (int q = 0; q < 5; ++q)
+          sv[ONE ? 2 * (5 * (c + 1) + q) + p : (p * Gt + c + 1) * 5 + q] = make_double2(v[2 * q], v[2 * q + 1]);
       }
     }
   }
