@@ -2900,25 +2900,33 @@ __device__ __forceinline__ void store_tile(const double2* T, int lane, int64_t g
   }
 }
 
+// Rows of sh (the scalar products S(h) of a Crank-Nicolson right-hand side)
+// in store_tile's layout, 0 where there is no such row; issued before the
+// tile's arithmetic, so that their latency is hidden behind it.
+template <int C, int G>
+__device__ __forceinline__ void load_tile_sh(int lane, int64_t g, int N, int n, int64_t nsys, const double2* __restrict__ sh,
+                                             double2 (&v)[C]) {
+  using TL = Tile<C, G>;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int s = i / TL::NB;
+    const int64_t w = g * TL::SPW + s;
+    const int k = TL::row(i, lane);
+    v[i] = (sh != nullptr && w < nsys && k < n) ? sh[w * (int64_t)N + k] : zero2();
+  }
+}
+
 // As store_tile, for the Crank-Nicolson right-hand side: the staged rows hold
-// -H'u, and sigma S(h) (rows of sh, when given) is added on the way out.
+// -H'u, and sigma S(h) (shv from load_tile_sh) is added on the way out.
 template <int C, int G>
 __device__ __forceinline__ void store_tile_rhs(const double2* T, int lane, int64_t g, int N, int n, int64_t nsys,
-                                               double2* __restrict__ u, double sigma, const double2* __restrict__ sh) {
+                                               double2* __restrict__ u, double sigma, const double2 (&shv)[C]) {
   using TL = Tile<C, G>;
   double2 v[C];
 #pragma unroll
-  for (int i = 0; i < C; ++i) v[i] = T[64 * i + lane];
+  for (int i = 0; i < C; ++i) v[i] = c_fma(sigma, shv[i], T[64 * i + lane]);
+  // keep the LDS reads together (not sunk into the masked stores one by one)
   asm volatile("" ::: "memory");
-  if (sh != nullptr) {
-#pragma unroll
-    for (int i = 0; i < C; ++i) {
-      const int s = i / TL::NB;
-      const int64_t w = g * TL::SPW + s;
-      const int k = TL::row(i, lane);
-      if (w < nsys && k < n) v[i] = c_fma(sigma, sh[w * (int64_t)N + k], v[i]);
-    }
-  }
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     const int s = i / TL::NB;
@@ -3144,11 +3152,15 @@ __global__ __launch_bounds__(64) void helm_matvec_pipe(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double al, unused;
     read_coef2(coef, lane, al, unused);
-    if constexpr (RHS) al = rhs_alpha(al, inv);
+    double2 shv[RHS ? C : 1];
+    if constexpr (RHS) {
+      al = rhs_alpha(al, inv);
+      load_tile_sh<C, G>(lane, g, N, n, nsys, sh, shv);
+    }
     helm_apply<C, G>(N, lane, al, gl, x, [&](int j, double2 v) { y[j] = RHS ? make_double2(-v.x, -v.y) : v; });
     stage_tile<C, G>(tile, lane, y);
     if constexpr (RHS) {
-      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, sh);
+      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, shv);
     } else {
       store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
     }
@@ -3204,15 +3216,17 @@ __global__ __launch_bounds__(256) void bih_matvec_ptab(int N, int64_t nsys, cons
     read_tile_rows<C, G>(tile, lane, n, wok, x);
     double a, b;
     read_coef2(coef, lane, a, b);
+    double2 shv[RHS ? C : 1];
     if constexpr (RHS) {
       const double K2 = a;
       a = rhs_a(K2, inv);
       b = rhs_b(K2, inv);
+      load_tile_sh<C, G>(lane, g, N, n, nsys, sh, shv);
     }
     bih_apply<C, G>(N, lane, a, b, gl, tab, x, [&](int j, double2 v) { y[j] = RHS ? make_double2(-v.x, -v.y) : v; });
     stage_tile<C, G>(tile, lane, y);
     if constexpr (RHS) {
-      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, sh);
+      store_tile_rhs<C, G>(tile, lane, g, N, n, nsys, hu, sigma, shv);
     } else {
       store_tile<C, G>(tile, lane, g, N, n, nsys, hu);
     }
