@@ -2937,7 +2937,7 @@ __device__ __forceinline__ void store_tile_rhs(const double2* T, int lane, int64
 }
 
 template <int C, int G>
-__global__ __launch_bounds__(64) void helm_wave_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
+__global__ __launch_bounds__(64, 2) void helm_wave_pipe(int N, int64_t nsys, const double* __restrict__ alpha,
                                                      const double2* __restrict__ f, double2* __restrict__ u,
                                                      const double2* __restrict__ sts, int64_t sstride, int gl,
                                                      int32_t* __restrict__ info) {
@@ -4456,7 +4456,7 @@ __device__ __forceinline__ bool cursor_next(const SegSrc& src, int spw, unsigned
 }
 
 template <int C, int G>
-__global__ __launch_bounds__(64) void batched_helm_pipe(int N, SegSrc src, unsigned long long* __restrict__ counter, int gl) {
+__global__ __launch_bounds__(64, 2) void batched_helm_pipe(int N, SegSrc src, unsigned long long* __restrict__ counter, int gl) {
   using TL = Tile<C, G>;
   constexpr int SPW = TL::SPW;
   __shared__ double2 tile[(C + 1) * 64];
