@@ -260,13 +260,10 @@ CHUNK_CASES = {
 }
 
 
-@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
-@pytest.mark.parametrize("ci", [0, 1, 2])
+@pytest.mark.parametrize("family,ci", [(fam, i) for fam, cases in CHUNK_CASES.items() for i in range(len(cases))])
 def test_wave_chunk_knob(dev, family, ci):
     """Every chunk length the wave kernels offer gives the oracle's answer, over ragged N and at the
     channel size (the knob only changes the lane/chunk split)."""
-    if ci >= len(CHUNK_CASES[family]):
-        pytest.skip("the biharmonic wave kernels offer two chunk lengths")
     chunk, Ns = CHUNK_CASES[family][ci]
     for N in Ns:
         nsys = 37
