@@ -383,7 +383,8 @@ def measure_large_n(dev, args):
     grid (8,320 systems per family), the paper's largest roundoff-table column, and N=8192 on
     the 64x33 grid of the paper's 64x64 timing mesh (its largest timing-table column; one parity
     chain per work group there); ms, GB/s and sampled errors against the oracle (one row per
-    family: the dense oracle is O(N^3)).  At N=4096 the Helmholtz solve is also timed on the
+    family: the dense oracle is O(N^3)), and the factored solve (restart states computed once
+    beforehand, as the paper times its solves).  At N=4096 the Helmholtz solve is also timed on the
     lane-per-chain kernels, which served it before."""
     import numpy as np
     import torch
@@ -423,6 +424,16 @@ def measure_large_n(dev, args):
                    "max_rel_err_sampled": _sampled_err(fam, g.N, csh, fh, u, rows)}
             if chain and fam == "helmholtz":
                 rec["chain_kernels_ms"] = round(timed(lambda: solve(f, *cs, out=u, variant="chain")), 4)
+            # the solve with the factorisation done once beforehand (the paper's timed configuration)
+            if fam == "helmholtz":
+                fac = api.helmholtz_factor(cs[0], g.N)
+                fms = timed(lambda: api.helmholtz_solve_factored(f, cs[0], fac, out=u))
+            else:
+                fac = api.biharmonic_factor(cs[0], cs[1], g.N)
+                fms = timed(lambda: api.biharmonic_solve_factored(f, cs[0], cs[1], fac, out=u))
+            rec["factored_ms"] = round(fms, 4)
+            rec["factored_hbm_gbps"] = round(nbytes / (fms * 1e-3) / 1e9, 2)
+            del fac
             out[fam] = rec
             del f, cs, u
         torch.cuda.empty_cache()

@@ -121,7 +121,8 @@ typedef struct {
                          write the number of corrections applied per system
                          (0 .. refine_max); not written otherwise            */
   void* work;         /* optional DEVICE scratch for in-place FP64 solves
-                         (u == f) of N with a wave configuration: with
+                         (u == f) of N the wave solves serve (N <= 8192,
+                         the large-N solves included): with
                          work_bytes >= nsys * shen_factor_bytes(family, N,
                          opts) they run as a factor call into `work`
                          followed by the factored solve in place (the
@@ -221,8 +222,9 @@ int biharmonic_adjoint(int32_t N, int64_t nsys, const double* a, const double* b
  * as helmholtz_solve does.  u == f (in place) is allowed; fac must not
  * overlap u.  FP64 only, no transpose, wave kernels only: SHEN_ENOTSUP for
  * opts->precision != SHEN_FP64, opts->transpose, opts->variant ==
- * SHEN_VARIANT_CHAIN, or an N without a wave configuration.  Results are
- * bitwise those of helmholtz_solve / biharmonic_solve with the same opts.
+ * SHEN_VARIANT_CHAIN, or an N neither the one-wavefront nor the large-N
+ * wave solves serve (N <= 8192; past 1024 opts->chunk must be 0).  Results
+ * are bitwise those of helmholtz_solve / biharmonic_solve with the same opts.
  */
 int64_t shen_factor_bytes(int32_t family, int32_t N, const shen_opts* opts); /* per system, or < 0 */
 int helmholtz_factor(int32_t N, int64_t nsys, const double* alpha, void* fac, const shen_opts* opts);
@@ -238,8 +240,8 @@ int biharmonic_solve_factored(int32_t N, int64_t nsys, const double* a, const do
  * bitwise, without their boundary walk; a differentiable time step can thus
  * factor once for its forward solve and its backward pass.  lambda may alias
  * gbar here; fac must not overlap lambda.  Wave kernels only: SHEN_ENOTSUP
- * for opts->variant == SHEN_VARIANT_CHAIN or an N without a wave
- * configuration.
+ * for opts->variant == SHEN_VARIANT_CHAIN or an N without a one-wavefront
+ * configuration (N > 1024: the factor calls serve the solves only).
  */
 int helmholtz_adjoint_factored(int32_t N, int64_t nsys, const double* alpha, const void* fac, const shen_c128* u,
                                const shen_c128* gbar, shen_c128* lambda, double* grad_alpha, const shen_opts* opts);

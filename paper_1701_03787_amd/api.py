@@ -451,10 +451,11 @@ def biharmonic_adjoint(u, gbar, a, b, *, quad="gc", coef_grad=True, info=None, v
 # --------------------------------------------------------------------------
 
 def _factor_if_wave(family, N, make):
-    """The factor-once states when the wave kernels cover N, else None (the solve then walks itself)."""
-    o = L.default_opts()
+    """The factor-once states when the one-wavefront kernels cover N (their adjoint reuses them),
+    else None (the solves then walk themselves)."""
     fam = L.SHEN_HELMHOLTZ if family == "helmholtz" else L.SHEN_BIHARMONIC
-    if L.lib().shen_factor_bytes(fam, int(N), C.byref(o)) <= 0:
+    c, g = C.c_int32(0), C.c_int32(0)
+    if L.lib().shen_wave_config(fam, int(N), 0, C.byref(c), C.byref(g)) != L.SHEN_OK:
         return None
     return make()
 

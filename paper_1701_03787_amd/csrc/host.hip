@@ -191,7 +191,7 @@ int factored(int family, int32_t N, int64_t nsys, const double* c0, const double
   w.stream = o.stream;
   w.fac = fac;
   w.fac_mode = mode;
-  return run_wave(w);
+  return shen::multi_waves(family, N) > 0 ? run_multi(w) : run_wave(w);
 }
 
 // In-place FP64 solves on the wave kernels through the caller's workspace
@@ -199,7 +199,7 @@ int factored(int family, int32_t N, int64_t nsys, const double* c0, const double
 // u (a factor call), then the factored solve runs in place.
 bool use_inplace_wave(const shen_opts& o, int family, int32_t N, const void* f, const void* u) {
   return f == u && o.work && o.variant != SHEN_VARIANT_CHAIN && !o.transpose && o.precision == SHEN_FP64 &&
-         shen::wave_supported(family, N);
+         (shen::wave_supported(family, N) || shen::multi_waves(family, N) > 0);
 }
 int inplace_wave(int family, int32_t N, int64_t nsys, const double* c0, const double* c1, const shen_c128* f, shen_c128* u,
                  const shen_opts& o) {
@@ -244,7 +244,8 @@ int adjoint_factored(int family, int32_t N, int64_t nsys, const double* c0, cons
     const uintptr_t la = (uintptr_t)nsys * (uintptr_t)(slot > 0 ? slot : 1) * 16u, lb = (uintptr_t)nsys * (uintptr_t)N * 16u;
     if (pa < pb + lb && pb < pa + la) return SHEN_EINVAL;
   }
-  if (o.variant == SHEN_VARIANT_CHAIN || slot == 0) return SHEN_ENOTSUP;
+  // (no adjoint past the one-wavefront sizes on the wave kernels)
+  if (o.variant == SHEN_VARIANT_CHAIN || slot == 0 || shen::multi_waves(family, N) > 0) return SHEN_ENOTSUP;
   shen::WaveArgs w;
   w.family = family;
   w.N = N;

@@ -3726,19 +3726,35 @@ __device__ __forceinline__ void walk_info(int bad, bool act, int p, int64_t w, i
   if (act && p == 0) info[w] = (bad == INT_MAX) ? 0 : bad + 1;
 }
 
+// The first unusable row of a chain (-1: none), parked by a factor call of the
+// one-parity layout in the slot its chain leaves unused (chunk 0), where the
+// factored solve reads it back for info.
+__device__ __forceinline__ void park_bad(double2* __restrict__ srow, int p, int bad) {
+  srow[p] = make_double2(bad == INT_MAX ? -1.0 : (double)bad, 0.0);
+}
+__device__ __forceinline__ int parked_bad(const double2* __restrict__ srow, int p) {
+  const double v = srow[p].x;
+  return v >= 0.0 ? (int)v : INT_MAX;
+}
+
+// States of system w go to S + w sstride (the output row, or a factor buffer).
+// ONE: info (one-call solves) or the parked first bad rows (factor calls).
 template <bool ONE>
 __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ alpha,
-                                                       double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+                                                       double2* __restrict__ S, int64_t sstride, int gl,
+                                                       int32_t* __restrict__ info, int park) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = t < 2 * nsys;  // both threads of a system share this (2 nsys is even)
   if (!act) return;
   const int64_t w = t >> 1;
   const int p = (int)(t & 1);
+  double2* srow = S + w * sstride;
   if constexpr (ONE) {
-    const int bad = helm_walk_chain<kMultiC, true, true>(N, Gt, p, alpha[w], u + w * (int64_t)N, gl);
+    const int bad = helm_walk_chain<kMultiC, true, true>(N, Gt, p, alpha[w], srow, gl);
     if (info != nullptr) walk_info(bad, act, p, w, info);
+    if (park) park_bad(srow, p, bad);
   } else {
-    helm_walk_chain<kMultiC, false, false>(N, Gt, p, alpha[w], u + w * (int64_t)N, gl);
+    helm_walk_chain<kMultiC, false, false>(N, Gt, p, alpha[w], srow, gl);
   }
 }
 
@@ -3761,8 +3777,8 @@ __device__ __forceinline__ BihMats mats_get(const double* d) {
 }
 template <bool ONE>
 __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ ca,
-                                                      const double* __restrict__ cb, double2* __restrict__ u, int gl,
-                                                      int32_t* __restrict__ info) {
+                                                      const double* __restrict__ cb, double2* __restrict__ S,
+                                                      int64_t sstride, int gl, int32_t* __restrict__ info, int park) {
   constexpr int C = kMultiC;
   __shared__ double win[2 * kWalkWin * kWalkWords];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -3778,7 +3794,7 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
   const int cend = ONE ? nch0 : nch0 - 1;
   constexpr int WC = kWalkWin / C;               // chunks per window
   const double a = act ? ca[w] : 0.0, b = act ? cb[w] : 0.0;
-  double2* sv = u + w * (int64_t)N;
+  double2* sv = S + w * sstride;
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
   int bad = INT_MAX;
   for (int c0 = 0; c0 < cend; c0 += WC) {
@@ -3818,6 +3834,7 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
   }
   if constexpr (ONE) {
     if (info != nullptr) walk_info(bad, act, p, w, info);
+    if (park && act) park_bad(sv, p, bad);
   }
 }
 
@@ -3850,9 +3867,13 @@ struct MultiLane {
   }
 };
 
+// States of system w from sts + w sstride.  ONE: info only from the parked
+// first bad rows of a factor call (parked_info), else the walk wrote it.
 template <int W, bool ONE>
 __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* __restrict__ alpha, const double2* __restrict__ f,
-                                                          double2* __restrict__ u, int gl, int32_t* __restrict__ info) {
+                                                          double2* __restrict__ u, const double2* __restrict__ sts,
+                                                          int64_t sstride, int gl, int32_t* __restrict__ info,
+                                                          int parked_info) {
   constexpr int C = kMultiC, G = kMultiG;
   __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
   __shared__ int badw[kCarryMaxW];
@@ -3865,11 +3886,16 @@ __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* _
   double2* urow = u + w * (int64_t)N;
   // restart state (every wavefront reads its states before the first
   // barrier of the scans, and stores only after the last)
+  const double2* srow = sts + w * sstride;
   HelmPrev pv = {0.0, 0.0};
   if (L.mg > 0 && k0 < n) {
-    const double2 s = ONE ? urow[2 * L.mg + L.p] : urow[L.p * W * G + L.mg];
+    const double2 s = ONE ? srow[2 * L.mg + L.p] : srow[L.p * W * G + L.mg];
     pv.rd = s.x;
     pv.g = s.y;
+  }
+  if (ONE && parked_info && info != nullptr && L.p == 0 && threadIdx.x == 0) {
+    const int b = min(parked_bad(srow, 0), parked_bad(srow, 1));
+    info[w] = (b == INT_MAX) ? 0 : b + 1;
   }
   double2 x[C];
 #pragma unroll
@@ -3895,8 +3921,9 @@ __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* _
 
 template <int W, bool ONE>
 __global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __restrict__ ca, const double* __restrict__ cb,
-                                                         const double2* __restrict__ f, double2* __restrict__ u, int gl,
-                                                         int32_t* __restrict__ info) {
+                                                         const double2* __restrict__ f, double2* __restrict__ u,
+                                                         const double2* __restrict__ sts, int64_t sstride, int gl,
+                                                         int32_t* __restrict__ info, int parked_info) {
   constexpr int C = kMultiC, G = kMultiG;
   __shared__ double xch[3 * kCarryMaxW * 2 * kCarryWords];
   __shared__ int badw[kCarryMaxW];
@@ -3907,11 +3934,16 @@ __global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __
   const double a = ca[w], b = cb[w];
   const double2* frow = f + w * (int64_t)N;
   double2* urow = u + w * (int64_t)N;
+  const double2* srow = sts + w * sstride;
   BihRowState m2 = {0, 0, 0, 0, 0}, m4 = {0, 0, 0, 0, 0};
+  if (ONE && parked_info && info != nullptr && L.p == 0 && threadIdx.x == 0) {
+    const int bq = min(parked_bad(srow, 0), parked_bad(srow, 1));
+    info[w] = (bq == INT_MAX) ? 0 : bq + 1;
+  }
   if (L.mg > 0 && k0 < n) {
     double2 s[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) s[q] = ONE ? urow[2 * (5 * L.mg + q) + L.p] : urow[(L.p * W * G + L.mg) * 5 + q];
+    for (int q = 0; q < 5; ++q) s[q] = ONE ? srow[2 * (5 * L.mg + q) + L.p] : srow[(L.p * W * G + L.mg) * 5 + q];
     m2 = BihRowState{s[0].x, s[0].y, s[1].x, s[1].y, s[2].x};
     m4 = BihRowState{s[2].y, s[3].x, s[3].y, s[4].x, s[4].y};
   }
@@ -4001,33 +4033,46 @@ int multi_waves(int family, int N, bool* one) {
 hipError_t launch_multi(const WaveArgs& a) {
   bool one = false;
   const int W = multi_waves(a.family, a.N, &one);
-  if (W == 0 || a.mixed || a.adjoint || a.fac_mode || a.rhs) return hipErrorInvalidValue;
+  if (W == 0 || a.mixed || a.adjoint || a.rhs) return hipErrorInvalidValue;
   if (a.nsys <= 0) return hipSuccess;
   // one work group per system (per chain with one parity per work group)
   if (a.nsys > (int64_t)(one ? INT_MAX / 2 : INT_MAX)) return hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)a.stream;
   const int Gt = W * kMultiG;
-  const unsigned walk = (unsigned)((2 * a.nsys + 255) / 256);
+  // restart states in the output row, or in the factor buffer (fac_mode 1:
+  // the walk alone, 2: the solve alone)
+  double2* S = a.fac_mode ? (double2*)a.fac : (double2*)a.u;
+  const int64_t ss = a.fac_mode ? wave_state_slot(a.family, a.N, 0) : (int64_t)a.N;
+  if (a.fac_mode != 2) {
+    const unsigned walk = (unsigned)((2 * a.nsys + 255) / 256);
+    int32_t* winfo = (one && a.fac_mode == 0) ? a.info : nullptr;
+    const int park = one && a.fac_mode == 1;
+    if (one) {
+      if (a.family == 0)
+        hipLaunchKernelGGL(helm_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, S, ss, a.gl, winfo, park);
+      else
+        hipLaunchKernelGGL(bih_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, S, ss, a.gl, winfo,
+                           park);
+    } else {
+      if (a.family == 0)
+        hipLaunchKernelGGL(helm_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, S, ss, a.gl, nullptr, 0);
+      else
+        hipLaunchKernelGGL(bih_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, S, ss, a.gl, nullptr,
+                           0);
+    }
+  }
+  if (a.fac_mode == 1) return hipGetLastError();
   double2* u = (double2*)a.u;
   const double2* f = (const double2*)a.f;
-  if (one) {
-    if (a.family == 0)
-      hipLaunchKernelGGL(helm_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl, a.info);
-    else
-      hipLaunchKernelGGL(bih_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl, a.info);
-  } else {
-    if (a.family == 0)
-      hipLaunchKernelGGL(helm_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, u, a.gl, nullptr);
-    else
-      hipLaunchKernelGGL(bih_walk_multi<false>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, u, a.gl, nullptr);
-  }
+  const int parked = one && a.fac_mode == 2;
   const dim3 grid((unsigned)(one ? 2 * a.nsys : a.nsys)), block(64 * W);
-#define SHEN_MULTI(WW, ONE)                                                                                        \
-  if (W == WW && one == ONE) {                                                                                     \
-    if (a.family == 0)                                                                                             \
-      hipLaunchKernelGGL((helm_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, f, u, a.gl, a.info);           \
-    else                                                                                                           \
-      hipLaunchKernelGGL((bih_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, a.c1, f, u, a.gl, a.info);      \
+#define SHEN_MULTI(WW, ONE)                                                                                          \
+  if (W == WW && one == ONE) {                                                                                       \
+    if (a.family == 0)                                                                                               \
+      hipLaunchKernelGGL((helm_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, f, u, S, ss, a.gl, a.info, parked); \
+    else                                                                                                             \
+      hipLaunchKernelGGL((bih_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, a.c1, f, u, S, ss, a.gl, a.info,     \
+                         parked);                                                                                    \
   }
   SHEN_MULTI(2, false)
   SHEN_MULTI(3, false)
@@ -4303,8 +4348,13 @@ hipError_t launch_mass_wave(const WaveArgs& a) {
 // double2 per system of the factor-once state slots (0: no wave kernel for N)
 int64_t wave_state_slot(int family, int N, int chunk) {
   const WaveCfg c = pick_cfg((N + 1) / 2, family, N, chunk);
-  if (c.C == 0) return 0;
-  return (int64_t)2 * c.G * (family == 0 ? 1 : 5);
+  if (c.C != 0) return (int64_t)2 * c.G * (family == 0 ? 1 : 5);
+  // large N: W G chunks per chain and wavefront group; with one parity per
+  // work group the 2 W G chunks of a chain are interleaved by parity
+  bool one = false;
+  const int W = chunk == 0 ? multi_waves(family, N, &one) : 0;
+  if (W == 0) return 0;
+  return (int64_t)(one ? 4 : 2) * W * kMultiG * (family == 0 ? 1 : 5);
 }
 
 hipError_t launch_wave(const WaveArgs& a) {

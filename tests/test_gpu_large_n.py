@@ -189,3 +189,50 @@ def test_batched_with_large_n_grids(dev):
         torch.cuda.synchronize()
         for p, e in zip(probs, eager):
             assert torch.equal(p.u, e), r
+
+
+@pytest.mark.parametrize("family", ["helmholtz", "biharmonic"])
+def test_large_n_factored_and_in_place(dev, family):
+    """Factor once / solve many past N = 1024 in both layouts (N = 2049: two parity chains per work
+    group; N = 4500 and 8192: one per work group, info parked by the factor call): the factored solve,
+    out of place and in place, and the one-call in-place solve through a workspace are bitwise the
+    one-call out-of-place solve, info included (a singular system at odd row 11, a non-finite one).
+    The adjoint has no factored form there and says so."""
+    from paper_1701_03787_amd import _lib, api
+    for N in (2049, 4500, 8192):
+        g = wl.small_grid(N, 4, kmax=200, index=N + 7)
+        cs = [c.copy() for c in g.coefficients(family)]
+        if family == "helmholtz":
+            cs[0][1] = so.singular_coefficient(family, N, 11)
+        else:
+            cs[0][1] = -1000.0
+            cs[1][1] = so.singular_coefficient(family, N, 11, a=-1000.0)
+        cs[0][2] = np.inf
+        case(test="large_n_factored", family=family, N=N)
+        f = T(g.rhs(family), dev)
+        ct = [T(c, dev) for c in cs]
+        solve = api.helmholtz_solve if family == "helmholtz" else api.biharmonic_solve
+        ref, rinfo = solve(f, *ct, info=True)
+        if family == "helmholtz":
+            fac = api.helmholtz_factor(ct[0], N)
+            u, info = api.helmholtz_solve_factored(f, ct[0], fac, info=True)
+            x = f.clone()
+            _, info2 = api.helmholtz_solve_factored(x, ct[0], fac, out=x, info=True)
+        else:
+            fac = api.biharmonic_factor(*ct, N)
+            u, info = api.biharmonic_solve_factored(f, *ct, fac, info=True)
+            x = f.clone()
+            _, info2 = api.biharmonic_solve_factored(x, *ct, fac, out=x, info=True)
+        y = f.clone()
+        work = torch.empty(g.nsys * api.factor_bytes(family, N) // 8, dtype=torch.float64, device=dev)
+        _, info3 = solve(y, *ct, out=y, work=work, info=True)
+        torch.cuda.synchronize()
+        assert list(rinfo.cpu().numpy()) == [0, 12, 1, 0]
+        for got, gi in ((u, info), (x, info2), (y, info3)):
+            assert torch.equal(gi, rinfo)
+            ok = torch.tensor([0, 3], device=dev)
+            assert torch.equal(got[ok], ref[ok])
+        adj = api.helmholtz_adjoint if family == "helmholtz" else api.biharmonic_adjoint
+        with pytest.raises(_lib.ShenError) as ei:
+            adj(ref, f, *ct, fac=fac)
+        assert ei.value.code == _lib.SHEN_ENOTSUP
