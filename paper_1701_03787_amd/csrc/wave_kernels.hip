@@ -3853,6 +3853,10 @@ __device__ __forceinline__ void multi_info(int bad, int v, int W, int lane, int*
 }
 
 // Work group -> (system, lane's chain parity, lane's chunk in its chain).
+// With one parity per work group, the two chains of a system go to blocks 8
+// apart (blocks 16q .. 16q + 15 hold systems 8q .. 8q + 7, parity 0 then 1):
+// blocks are dealt to the 8 XCDs in turn, so both land on the same XCD and
+// share its L2, where the rows of the two parities share cache lines.
 template <int W, bool ONE>
 struct MultiLane {
   int64_t w;
@@ -3860,17 +3864,20 @@ struct MultiLane {
   __device__ __forceinline__ MultiLane() {
     v = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     lane = threadIdx.x & 63;
-    w = ONE ? (int64_t)(blockIdx.x >> 1) : (int64_t)blockIdx.x;
+    const int64_t b = blockIdx.x;
+    w = ONE ? (b >> 4) * 8 + (b & 7) : b;
     h = (lane / kMultiG) & 1;
-    p = ONE ? (int)(blockIdx.x & 1) : h;
+    p = ONE ? (int)((b >> 3) & 1) : h;
     mg = (ONE ? 2 * v + h : v) * kMultiG + lane % kMultiG;
   }
 };
+// Blocks of the one-parity grid: 16 per 8 systems (those past nsys exit).
+inline int64_t multi_one_blocks(int64_t nsys) { return (nsys + 7) / 8 * 16; }
 
 // States of system w from sts + w sstride.  ONE: info only from the parked
 // first bad rows of a factor call (parked_info), else the walk wrote it.
 template <int W, bool ONE>
-__global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* __restrict__ alpha, const double2* __restrict__ f,
+__global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, int64_t nsys, const double* __restrict__ alpha, const double2* __restrict__ f,
                                                           double2* __restrict__ u, const double2* __restrict__ sts,
                                                           int64_t sstride, int gl, int32_t* __restrict__ info,
                                                           int parked_info) {
@@ -3879,6 +3886,7 @@ __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* _
   __shared__ int badw[kCarryMaxW];
   const MultiLane<W, ONE> L;
   const int64_t w = L.w;
+  if (w >= nsys) return;  // the whole work group (padding blocks of the one-parity grid)
   const int n = N - 2;
   const int k0 = 2 * L.mg * C + L.p;
   const double al = alpha[w];
@@ -3920,7 +3928,7 @@ __global__ __launch_bounds__(64 * W) void helm_wave_multi(int N, const double* _
 }
 
 template <int W, bool ONE>
-__global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __restrict__ ca, const double* __restrict__ cb,
+__global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, int64_t nsys, const double* __restrict__ ca, const double* __restrict__ cb,
                                                          const double2* __restrict__ f, double2* __restrict__ u,
                                                          const double2* __restrict__ sts, int64_t sstride, int gl,
                                                          int32_t* __restrict__ info, int parked_info) {
@@ -3929,6 +3937,7 @@ __global__ __launch_bounds__(64 * W) void bih_wave_multi(int N, const double* __
   __shared__ int badw[kCarryMaxW];
   const MultiLane<W, ONE> L;
   const int64_t w = L.w;
+  if (w >= nsys) return;  // the whole work group (padding blocks of the one-parity grid)
   const int n = N - 4;
   const int k0 = 2 * L.mg * C + L.p;
   const double a = ca[w], b = cb[w];
@@ -4036,7 +4045,7 @@ hipError_t launch_multi(const WaveArgs& a) {
   if (W == 0 || a.mixed || a.adjoint || a.rhs) return hipErrorInvalidValue;
   if (a.nsys <= 0) return hipSuccess;
   // one work group per system (per chain with one parity per work group)
-  if (a.nsys > (int64_t)(one ? INT_MAX / 2 : INT_MAX)) return hipErrorInvalidValue;
+  if ((one ? multi_one_blocks(a.nsys) : a.nsys) > (int64_t)INT_MAX) return hipErrorInvalidValue;
   hipStream_t st = (hipStream_t)a.stream;
   const int Gt = W * kMultiG;
   // restart states in the output row, or in the factor buffer (fac_mode 1:
@@ -4065,13 +4074,14 @@ hipError_t launch_multi(const WaveArgs& a) {
   double2* u = (double2*)a.u;
   const double2* f = (const double2*)a.f;
   const int parked = one && a.fac_mode == 2;
-  const dim3 grid((unsigned)(one ? 2 * a.nsys : a.nsys)), block(64 * W);
+  const dim3 grid((unsigned)(one ? multi_one_blocks(a.nsys) : a.nsys)), block(64 * W);
 #define SHEN_MULTI(WW, ONE)                                                                                          \
   if (W == WW && one == ONE) {                                                                                       \
     if (a.family == 0)                                                                                               \
-      hipLaunchKernelGGL((helm_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, f, u, S, ss, a.gl, a.info, parked); \
+      hipLaunchKernelGGL((helm_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.nsys, a.c0, f, u, S, ss, a.gl, a.info,     \
+                         parked);                                                                                    \
     else                                                                                                             \
-      hipLaunchKernelGGL((bih_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.c0, a.c1, f, u, S, ss, a.gl, a.info,     \
+      hipLaunchKernelGGL((bih_wave_multi<WW, ONE>), grid, block, 0, st, a.N, a.nsys, a.c0, a.c1, f, u, S, ss, a.gl, a.info, \
                          parked);                                                                                    \
   }
   SHEN_MULTI(2, false)
