@@ -236,3 +236,27 @@ def test_large_n_factored_and_in_place(dev, family):
         with pytest.raises(_lib.ShenError) as ei:
             adj(ref, f, *ct, fac=fac)
         assert ei.value.code == _lib.SHEN_ENOTSUP
+
+
+@pytest.mark.parametrize("family,N", [("helmholtz", 2049), ("helmholtz", 4500), ("biharmonic", 2049)])
+def test_large_n_autograd(dev, family, N):
+    """The differentiable solves past N = 1024: the forward solve on the large-N wave kernels (no
+    factor there), the backward pass on the lane-per-chain adjoint, against the oracle's gradients
+    (lambda = H^-T gu to the solves' bar, the coefficient gradients to 1e-10 relative)."""
+    from paper_1701_03787_amd import api
+    g = wl.small_grid(N, 2, kmax=200, index=N + 11)
+    cs = g.coefficients(family)
+    f = g.rhs(family)
+    gu = wl.random_vector((g.nsys, N), (N, 3))
+    gu[:, wl.n_unknowns(family, N):] = 0
+    case(test="large_n_autograd", family=family, N=N)
+    u_ref, lam_ref, grads_ref = so.solve_grads(family, N, cs, f, gu)
+    ft = T(f, dev).requires_grad_(True)
+    ct = [T(c, dev).requires_grad_(True) for c in cs]
+    u = api.helmholtz(ft, *ct) if family == "helmholtz" else api.biharmonic(ft, *ct)
+    torch.autograd.backward([torch.view_as_real(u)], [torch.view_as_real(T(gu, dev))])
+    torch.cuda.synchronize()
+    assert so.rel_err_per_system(u.detach().cpu().numpy(), u_ref).max() <= TOL
+    assert so.rel_err_per_system(ft.grad.cpu().numpy(), lam_ref).max() <= TOL
+    for c, gr in zip(ct, grads_ref):
+        np.testing.assert_allclose(c.grad.cpu().numpy(), gr, rtol=1e-10, atol=1e-300)
