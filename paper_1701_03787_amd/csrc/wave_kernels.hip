@@ -513,8 +513,9 @@ __global__ __launch_bounds__(256) void helm_boundary_t(int N, int64_t nsys, cons
 // The FP64 walk (F32 false) also checks every pivot of the chain, the last
 // chunk's included, with the wave solves' rule, and leaves the first unusable
 // row (or -1) in the unused state slot of chunk 0, so that the wave solves
-// need not check their rows again.
-template <int C, int G, bool F32, int TP = 0>
+// need not check their rows again.  CHECK false (a one-call solve without
+// info): no checks, and no steps past the last chunk start.
+template <int C, int G, bool F32, int TP = 0, bool CHECK = !F32>
 __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, void* st, int gl, const double* tab) {
   constexpr int RT = 2 * G * C;
   const int n = N - 4;
@@ -538,7 +539,7 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
     } else {
       double l1, l2, t0, sc;
       bih_step_row(h, m2, m4, o, l1, l2, t0, sc);
-      bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
+      if constexpr (CHECK) bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
     }
     m4 = m2;
     m2 = o;
@@ -569,7 +570,7 @@ __device__ __forceinline__ void bih_walk_tab(int N, int p, double a, double b, v
       sv[4] = make_double2(m4.P, m4.R);
     }
   }
-  if constexpr (!F32) {
+  if constexpr (!F32 && CHECK) {
     const int i0 = (nchunks > 1 ? nchunks - 1 : 0) * C;
     for (int i = i0; i < nc; ++i) row(i);
     double2* sv = reinterpret_cast<double2*>(reinterpret_cast<double*>(st) + (p * G) * 10);
@@ -588,7 +589,7 @@ __device__ __forceinline__ int walk_bad_of(double v, bool chunk0) { return (chun
 // blocks leave six on the CUs that take a third block).
 static constexpr int kBihWalkThreads = 384;
 static constexpr int kBihWalkSystems = kBihWalkThreads / 2;
-template <int C, int G, bool F32>
+template <int C, int G, bool F32, bool CHECK = !F32>
 __global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64_t nsys, const double* __restrict__ ca,
                                                                     const double* __restrict__ cb, double2* __restrict__ S,
                                                                     int64_t sstride, int gl) {
@@ -600,7 +601,7 @@ __global__ __launch_bounds__(kBihWalkThreads) void bih_boundary_tab(int N, int64
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * kBihWalkSystems + (wv >> 1) * 64 + lane;
   if (w >= nsys) return;
-  bih_walk_tab<C, G, F32, TP>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
+  bih_walk_tab<C, G, F32, TP, CHECK>(N, wv & 1, ca[w], cb[w], S + w * sstride, gl, tab);
 }
 
 // =========================================================================
@@ -4210,16 +4211,21 @@ static hipError_t launch_bih_t(const WaveArgs& a) {
     }
     static const bool attr = set_dynamic_lds((const void*)bih_wave_tab<C, G>, lds) &&
                              set_dynamic_lds((const void*)bih_boundary_tab<C, G, false>, lds) &&
+                             set_dynamic_lds((const void*)bih_boundary_tab<C, G, false, false>, lds) &&
                              set_dynamic_lds((const void*)bih_boundary_tab<C, G, true>, lds);
     (void)attr;
     // restart states: parked in u (one call), or in the caller's slots (factor-once mode)
     constexpr int64_t kSlot = 2 * G * 5;  // double2 per system
     double2* sts = a.fac_mode ? (double2*)a.fac + s0 * kSlot : u;
     const int64_t sstride = a.fac_mode ? kSlot : (int64_t)a.N;
-    if (a.fac_mode != 2)
-      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), dim3((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems)),
-                         dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1,
-                         sts, sstride, a.gl);
+    const dim3 wgrid((unsigned)((ns + kBihWalkSystems - 1) / kBihWalkSystems));
+    // the pivot checks serve info only: a one-call solve without info skips them
+    if (a.fac_mode == 0 && info == nullptr)
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false, false>), wgrid, dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, sts,
+                         sstride, a.gl);
+    else if (a.fac_mode != 2)
+      hipLaunchKernelGGL((bih_boundary_tab<C, G, false>), wgrid, dim3(kBihWalkThreads), lds, st, a.N, ns, c0, c1, sts, sstride,
+                         a.gl);
     if (a.fac_mode == 1) continue;
     // gfx950: 160 KiB of LDS per work group
     constexpr int kWpb = PtabWaves<C, G>::value;
