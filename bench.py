@@ -510,8 +510,8 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the systems are independent and would shard by wavenumber range, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); the systems are "
+              "independent and would shard by wavenumber range, with no exchange", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
