@@ -3739,8 +3739,9 @@ __device__ __forceinline__ int parked_bad(const double2* __restrict__ srow, int 
 }
 
 // States of system w go to S + w sstride (the output row, or a factor buffer).
-// ONE: info (one-call solves) or the parked first bad rows (factor calls).
-template <bool ONE>
+// ONE: the interleaved layout; CHECK: the pivot checks of every row, for info
+// (one-call solves) or the parked first bad rows (factor calls).
+template <bool ONE, bool CHECK = ONE>
 __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ alpha,
                                                        double2* __restrict__ S, int64_t sstride, int gl,
                                                        int32_t* __restrict__ info, int park) {
@@ -3750,12 +3751,10 @@ __global__ __launch_bounds__(256) void helm_walk_multi(int N, int64_t nsys, int 
   const int64_t w = t >> 1;
   const int p = (int)(t & 1);
   double2* srow = S + w * sstride;
-  if constexpr (ONE) {
-    const int bad = helm_walk_chain<kMultiC, true, true>(N, Gt, p, alpha[w], srow, gl);
+  const int bad = helm_walk_chain<kMultiC, ONE, CHECK>(N, Gt, p, alpha[w], srow, gl);
+  if constexpr (CHECK) {
     if (info != nullptr) walk_info(bad, act, p, w, info);
     if (park) park_bad(srow, p, bad);
-  } else {
-    helm_walk_chain<kMultiC, false, false>(N, Gt, p, alpha[w], srow, gl);
   }
 }
 
@@ -3776,7 +3775,7 @@ __device__ __forceinline__ BihMats mats_get(const double* d) {
   m.Q4 = d[9], m.B4 = d[10], m.p = d[11], m.r = d[12], m.q2 = d[13], m.s2 = d[14], m.q4 = d[15], m.s4 = d[16];
   return m;
 }
-template <bool ONE>
+template <bool ONE, bool CHECK = ONE>
 __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int Gt, const double* __restrict__ ca,
                                                       const double* __restrict__ cb, double2* __restrict__ S,
                                                       int64_t sstride, int gl, int32_t* __restrict__ info, int park) {
@@ -3792,7 +3791,7 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
   const int nch0 = ((n + 1) / 2 + C - 1) / C;    // of the longest chain (p = 0)
   // chunks stepped through by the block: up to the last chunk start, or
   // (checking every pivot) the whole chain
-  const int cend = ONE ? nch0 : nch0 - 1;
+  const int cend = CHECK ? nch0 : nch0 - 1;
   constexpr int WC = kWalkWin / C;               // chunks per window
   const double a = act ? ca[w] : 0.0, b = act ? cb[w] : 0.0;
   double2* sv = S + w * sstride;
@@ -3821,7 +3820,7 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
         BihRowState o;
         double l1, l2, t0, sc;
         bih_step_row(bih_row_from(mats_get(win + (k - 2 * i0) * kWalkWords), a, b), m2, m4, o, l1, l2, t0, sc);
-        if constexpr (ONE) bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
+        if constexpr (CHECK) bad = first_bad(bad, i < nc && bad_pivot(t0, sc), k);
         m4 = m2;
         m2 = o;
       }
@@ -3833,7 +3832,7 @@ __global__ __launch_bounds__(256) void bih_walk_multi(int N, int64_t nsys, int G
       }
     }
   }
-  if constexpr (ONE) {
+  if constexpr (CHECK) {
     if (info != nullptr) walk_info(bad, act, p, w, info);
     if (park && act) park_bad(sv, p, bad);
   }
@@ -4057,7 +4056,14 @@ hipError_t launch_multi(const WaveArgs& a) {
     const unsigned walk = (unsigned)((2 * a.nsys + 255) / 256);
     int32_t* winfo = (one && a.fac_mode == 0) ? a.info : nullptr;
     const int park = one && a.fac_mode == 1;
-    if (one) {
+    if (one && a.fac_mode == 0 && a.info == nullptr) {  // the checks only serve info
+      if (a.family == 0)
+        hipLaunchKernelGGL((helm_walk_multi<true, false>), dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, S, ss, a.gl,
+                           nullptr, 0);
+      else
+        hipLaunchKernelGGL((bih_walk_multi<true, false>), dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, a.c1, S, ss,
+                           a.gl, nullptr, 0);
+    } else if (one) {
       if (a.family == 0)
         hipLaunchKernelGGL(helm_walk_multi<true>, dim3(walk), dim3(256), 0, st, a.N, a.nsys, Gt, a.c0, S, ss, a.gl, winfo, park);
       else
