@@ -376,9 +376,12 @@ int biharmonic_rhs(int32_t N, int64_t nsys, const double* K2, double nu, double 
  * work items of sys_per_tile systems from a queue).  Grids with
  * 1024 < N <= 8192 take the large-N solves of helmholtz_solve /
  * biharmonic_solve, one walk and one solve per grid (chunk must be 0 there;
- * sys_per_tile is ignored).  Every kernel is enqueued on opts->stream; the
- * call may be captured in a hipGraph and replayed (the descriptors are read
- * at capture).
+ * sys_per_tile is ignored).  The classes are dealt to four side streams
+ * forked from opts->stream and joined back to it before the call returns
+ * (the library creates them, with their events, once per device, at default
+ * priority, in shen_batched_plan or else at the first call), so the whole
+ * call is ordered on opts->stream; it may be captured in a hipGraph and
+ * replayed (the descriptors are read at capture).
  *
  * desc: HOST array of ndesc descriptors, planned by shen_batched_plan and
  *   read by the library at every call.  c0 = alpha (Helmholtz) or a
@@ -425,8 +428,9 @@ int batched_solve(const shen_problem* desc, int32_t ndesc, void* work, const she
  * harnesses that forbid hipMalloc): the work counters live in a static
  * device array of shen_batched_static_bytes() bytes (4 KiB) that the library
  * holds on each device it runs on until the process ends.  The call itself
- * allocates nothing.  Same descriptors, planning, arguments, results and
- * errors as batched_solve, plus SHEN_ESCRATCH when
+ * allocates nothing, and creates no streams: its classes run one after
+ * another on opts->stream.  Same descriptors, planning, arguments, results
+ * and errors as batched_solve, plus SHEN_ESCRATCH when
  * shen_batched_work_bytes(ndesc) exceeds the static buffer.  Every call on
  * one device shares that device's buffer: calls that overlap on a device
  * (other streams, other threads, or two replays of graphs that captured

@@ -844,6 +844,8 @@ int64_t shen_batched_plan(shen_problem* desc, int32_t ndesc, const shen_opts* op
     d.tile_begin = total;
     total += (d.nsys + d.sys_per_tile - 1) / d.sys_per_tile;
   }
+  // best effort: where this fails (no device here), batched_solve tries again
+  (void)shen::batched_fork_prepare();
   return total;
 }
 
@@ -871,7 +873,8 @@ int batched_solve(const shen_problem* desc, int32_t ndesc, void* work, const she
   if (!work || !aligned(work, 8)) return SHEN_EINVAL;
   const int rc = batched_common(desc, ndesc, o);
   if (rc) return rc;
-  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream, true) == hipSuccess ? SHEN_OK
+                                                                                                        : SHEN_ELAUNCH;
 }
 
 int64_t shen_batched_static_bytes(void) { return (int64_t)shen::kBatchedStaticWords * 8; }
@@ -887,7 +890,9 @@ int batched_solve_static(const shen_problem* desc, int32_t ndesc, const shen_opt
   if (rc) return rc;
   void* work = nullptr;
   if (shen::batched_static_scratch(&work) != hipSuccess || work == nullptr) return SHEN_EDEVICE;
-  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream) == hipSuccess ? SHEN_OK : SHEN_ELAUNCH;
+  // in order on the caller's stream: no side streams or events to create
+  return shen::launch_batched(desc, ndesc, work, o.quad == SHEN_QUAD_GL, o.stream, false) == hipSuccess ? SHEN_OK
+                                                                                                         : SHEN_ELAUNCH;
 }
 
 }  // extern "C"

@@ -88,7 +88,12 @@ hipError_t launch_multi(const WaveArgs& a);
 bool wave_chunk_ok(int family, int N, int chunk);
 // Batched form: the host descriptors (validated, planned), one launch pair
 // per class; `work` holds batched_counters(ndesc) queue counters.
-hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream);
+// fork: deal the classes to side streams forked from and joined to `stream`
+// (false: everything in order on `stream`, creating nothing).
+hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream, bool fork);
+// Creates the current device's side streams of launch_batched now (a planning
+// call), so that a solve under graph capture creates nothing.
+hipError_t batched_fork_prepare();
 int batched_counters(int ndesc);
 // Library-owned counter array of the batched launch (one per device, 8-byte
 // words): device address for the current device, looked up on first use.

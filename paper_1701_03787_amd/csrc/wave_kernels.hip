@@ -4757,11 +4757,79 @@ int batched_counters(int ndesc) { return ndesc > 0 ? ndesc : 0; }
 
 // Groups the (validated, planned) host descriptors by class in descriptor
 // order and launches every class over its grids, kMaxSeg at a time.
-hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream) {
+// Side streams of the batched launch, per device: the classes (each a walk
+// and a solve, or several such pairs) are dealt to kForkStreams streams forked
+// from the caller's stream and joined back to it before the call returns, so
+// that the latency-bound walks and the small classes overlap other classes'
+// solves.  Created once per device (default priority, non-blocking), with
+// one fork and one join event per stream; the enqueue of a forked call holds
+// the lock, so calls from several host threads do not mix their events.  The
+// fork/join is graph-capturable (the side streams join the capture and are
+// joined back before the call returns).
+static constexpr int kForkStreams = 4;
+static constexpr int kForkDevices = 64;
+struct ForkSet {
+  bool ok = false;
+  hipStream_t s[kForkStreams];
+  hipEvent_t fork;
+  hipEvent_t join[kForkStreams];
+};
+static std::mutex g_fork_mu;
+static ForkSet g_fork[kForkDevices];
+
+// The current device's set, created on first use; called with g_fork_mu held.
+static hipError_t fork_set_locked(ForkSet** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kForkDevices) return hipErrorInvalidDevice;
+  ForkSet& f = g_fork[dev];
+  if (!f.ok) {
+    for (int i = 0; i < kForkStreams; ++i) {
+      if ((e = hipStreamCreateWithFlags(&f.s[i], hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&f.join[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if ((e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    f.ok = true;
+  }
+  *out = &f;
+  return hipSuccess;
+}
+
+hipError_t batched_fork_prepare() {
+  std::lock_guard<std::mutex> lk(g_fork_mu);
+  ForkSet* fs = nullptr;
+  return fork_set_locked(&fs);
+}
+
+hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int gl, void* stream, bool fork) {
   hipStream_t st = (hipStream_t)stream;
   unsigned long long* counter = reinterpret_cast<unsigned long long*>(work);
   const int ncounters = batched_counters(ndesc);
   hipLaunchKernelGGL(batched_clear, dim3(1), dim3(256), 0, st, counter, ncounters);
+  std::unique_lock<std::mutex> lk(g_fork_mu, std::defer_lock);
+  ForkSet* fs = nullptr;
+  if (fork) {
+    lk.lock();
+    hipError_t e = fork_set_locked(&fs);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(fs->fork, st)) != hipSuccess) return e;
+    for (int k = 0; k < kForkStreams; ++k)
+      if ((e = hipStreamWaitEvent(fs->s[k], fs->fork, 0)) != hipSuccess) return e;
+  }
+  int ncls = 0;
+  auto class_stream = [&]() { return fork ? fs->s[ncls++ % kForkStreams] : st; };
+  // every side stream joins the caller's stream again, also after an error
+  auto finish = [&](hipError_t err) {
+    if (fork) {
+      for (int k = 0; k < kForkStreams; ++k) {
+        const hipError_t e1 = hipEventRecord(fs->join[k], fs->s[k]);
+        const hipError_t e2 = hipStreamWaitEvent(st, fs->join[k], 0);
+        if (err == hipSuccess) err = e1 != hipSuccess ? e1 : e2;
+      }
+    }
+    return err != hipSuccess ? err : hipGetLastError();
+  };
   std::vector<char> done((size_t)ndesc, 0);
   int slot = 0;
   for (int i = 0; i < ndesc; ++i) {
@@ -4778,15 +4846,16 @@ hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int g
       a.u = d.u;
       a.info = d.info;
       a.gl = gl;
-      a.stream = stream;
+      a.stream = (void*)class_stream();
       const hipError_t err = launch_multi(a);
-      if (err != hipSuccess) return err;
+      if (err != hipSuccess) return finish(err);
       done[i] = 1;
       continue;
     }
     const WaveCfg c = pick_cfg((d.N + 1) / 2, d.family, d.N, d.chunk);
     ClassLaunch fn = d.family == SHEN_HELMHOLTZ ? class_launcher<SHEN_HELMHOLTZ>(c) : class_launcher<SHEN_BIHARMONIC>(c);
-    if (fn == nullptr) return hipErrorInvalidValue;
+    if (fn == nullptr) return finish(hipErrorInvalidValue);
+    const hipStream_t sc = class_stream();
     // groups (of 64 / (2G) systems) per work item
     const int spw = 64 / (2 * c.G);
     auto gpi_of = [&](const shen_problem& e) {
@@ -4804,19 +4873,19 @@ hipError_t launch_batched(const shen_problem* desc, int ndesc, void* work, int g
       src.r[src.nseg++] = GridRef{e.nsys, e.c0, e.c1, reinterpret_cast<const double2*>(e.f), reinterpret_cast<double2*>(e.u),
                                   e.info};
       if (src.nseg == kMaxSeg) {
-        if (slot >= ncounters) return hipErrorInvalidValue;
-        const hipError_t err = fn(d.N, src, counter + slot++, gl, st);
-        if (err != hipSuccess) return err;
+        if (slot >= ncounters) return finish(hipErrorInvalidValue);
+        const hipError_t err = fn(d.N, src, counter + slot++, gl, sc);
+        if (err != hipSuccess) return finish(err);
         src.nseg = 0;
       }
     }
     if (src.nseg > 0) {
-      if (slot >= ncounters) return hipErrorInvalidValue;
-      const hipError_t err = fn(d.N, src, counter + slot++, gl, st);
-      if (err != hipSuccess) return err;
+      if (slot >= ncounters) return finish(hipErrorInvalidValue);
+      const hipError_t err = fn(d.N, src, counter + slot++, gl, sc);
+      if (err != hipSuccess) return finish(err);
     }
   }
-  return hipGetLastError();
+  return finish(hipSuccess);
 }
 
 // ------------------------------------------------------------------------
