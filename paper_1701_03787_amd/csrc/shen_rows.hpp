@@ -208,6 +208,7 @@ __device__ __forceinline__ BihConst bih_const(int k, int N, int gl) {
 // s4) and k-4 (B4).
 __device__ __forceinline__ BihRow bih_row_tab(int k, double a, double b, const BihConst& c, double B2m2, double q4m2,
                                               double s4m2, double B4m4) {
+  (void)k;  // the row index is carried by the table entries
   // explicit fused multiply-adds: the same rounding wherever a row is built
   BihRow h;
   // rows 0 .. 3: B4m4 (k < 4), B2m2 and Am2 (k < 2) are +0 (no such rows

@@ -114,7 +114,7 @@ template <int R, bool INV, typename Load>
 __device__ __forceinline__ void fft_pass(double2* buf, const double2* tw, int lgN, int lgNs, int SB, int tid, Load ld) {
   constexpr int PER = 8 / R;  // butterflies per thread (8 points per thread)
   constexpr int lgR = R == 8 ? 3 : (R == 4 ? 2 : 1);
-  const int N = 1 << lgN, Ns = 1 << lgNs;
+  const int Ns = 1 << lgNs;
   const int lgnb = lgN - lgR;
   const int nb = 1 << lgnb;  // butterflies per sequence
   const int total = SB * nb;

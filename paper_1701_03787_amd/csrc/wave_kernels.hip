@@ -957,7 +957,7 @@ __global__ __launch_bounds__(64) void helm_adjoint_wave(int N, int64_t nsys, con
   }
   // factorisation restart (as the solve)
   const bool has_prev = k0 >= 2;
-  const double rd_in = has_prev ? pv.rd : 0.0, g_in = has_prev ? pv.g : 0.0;
+  const double g_in = has_prev ? pv.g : 0.0;
   double rdj[C], gj[C];
   int bad = INT_MAX;
 #pragma unroll
@@ -4330,6 +4330,7 @@ hipError_t launch_matvec_wave(const WaveArgs& a) {
 // Mass-matrix solves: the configuration by N (the tile layout needs G >= 16
 // lanes per chain and C >= 8 rows per chunk); C = 0 beyond N = 1024.
 static WaveCfg mass_cfg(int family, int N) {
+  (void)family;  // both bases take the same configurations
   const int nc = (N + 1) / 2;
   if (nc <= 128) return WaveCfg{8, 16};
   if (nc <= 256) return WaveCfg{16, 16};
