@@ -216,7 +216,8 @@ __device__ __forceinline__ void fill_twiddles(double2* tw, int N) {
 __device__ __forceinline__ double2 shen_combine(const double2* c, int k, int space) {
   if (space == SHEN_SPACE_DIRICHLET) return csub(c[k], c[k + 2]);
   const double K = (double)k;
-  const double g1 = 2.0 * (K + 2.0) / (K + 3.0), g2 = (K + 1.0) / (K + 3.0);
+  const double r = 1.0 / (K + 3.0);  // one division for both weights
+  const double g1 = 2.0 * (K + 2.0) * r, g2 = (K + 1.0) * r;
   return c_fma(g2, c[k + 4], c_fma(-g1, c[k + 2], c[k]));
 }
 // Chebyshev coefficient z_k of sum_j f_j phi_j (the transposed combination),
@@ -225,14 +226,12 @@ __device__ __forceinline__ double2 shen_to_cheb(const double2* f, int k, int n, 
   if (space == SHEN_SPACE_CHEBYSHEV) return f[k];
   double2 z = k < n ? f[k] : zero2();
   if (space == SHEN_SPACE_DIRICHLET) return (k >= 2 && k - 2 < n) ? csub(z, f[k - 2]) : z;
-  if (k >= 2 && k - 2 < n) {
-    const double K = (double)(k - 2);
-    z = c_fma(-2.0 * (K + 2.0) / (K + 3.0), f[k - 2], z);
-  }
-  if (k >= 4 && k - 4 < n) {
-    const double K = (double)(k - 4);
-    z = c_fma((K + 1.0) / (K + 3.0), f[k - 4], z);
-  }
+  // weights -2k/(k+1) of f_{k-2} and (k-3)/(k-1) of f_{k-4}, from one
+  // division: 1/(k+1) = (k-1) R and 1/(k-1) = (k+1) R with R = 1/((k+1)(k-1))
+  const double K = (double)k;
+  const double R = 1.0 / ((K + 1.0) * (K - 1.0));
+  if (k >= 2 && k - 2 < n) z = c_fma(-2.0 * K * ((K - 1.0) * R), f[k - 2], z);
+  if (k >= 4 && k - 4 < n) z = c_fma((K - 3.0) * ((K + 1.0) * R), f[k - 4], z);
   return z;
 }
 __device__ __forceinline__ int space_n(int space, int N) {
@@ -366,14 +365,11 @@ __global__ __launch_bounds__(kTfThreads, 3) void cheb_fft(int N, int64_t nsys, i
           if (space == SHEN_SPACE_DIRICHLET) {
             if (k >= 2 && k - 2 < n) z = csub(z, buf[lp(i - 2)]);
           } else {
-            if (k >= 2 && k - 2 < n) {
-              const double K = (double)(k - 2);
-              z = c_fma(-2.0 * (K + 2.0) * fast_rcp(K + 3.0), buf[lp(i - 2)], z);
-            }
-            if (k >= 4 && k - 4 < n) {
-              const double K = (double)(k - 4);
-              z = c_fma((K + 1.0) * fast_rcp(K + 3.0), buf[lp(i - 4)], z);
-            }
+            // weights -2k/(k+1) and (k-3)/(k-1) from one reciprocal (as shen_to_cheb)
+            const double K = (double)k;
+            const double R = fast_rcp((K + 1.0) * (K - 1.0));
+            if (k >= 2 && k - 2 < n) z = c_fma(-2.0 * K * ((K - 1.0) * R), buf[lp(i - 2)], z);
+            if (k >= 4 && k - 4 < n) z = c_fma((K - 3.0) * ((K + 1.0) * R), buf[lp(i - 4)], z);
           }
         }
         return k == 0 ? z : cscale(0.5, z);
