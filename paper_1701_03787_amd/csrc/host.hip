@@ -779,9 +779,11 @@ int shen_forward_transform(int32_t N, int64_t nsys, int32_t space, const shen_c1
   const int rc2 = device_info(&d);
   if (rc2 != SHEN_OK) return rc2;
   const int chebyshev = space == SHEN_SPACE_CHEBYSHEV;
-  if (shen::launch_transform(N, nsys, space, 0, chebyshev, o.quad == SHEN_QUAD_GL, u, uhat, o.stream) != hipSuccess)
+  // the FFT kernel solves the Dirichlet mass matrix itself (one pass)
+  const int fused = space == SHEN_SPACE_DIRICHLET && shen::transform_fused_mass_ok(N, o.quad == SHEN_QUAD_GL);
+  if (shen::launch_transform(N, nsys, space, 0, chebyshev || fused, o.quad == SHEN_QUAD_GL, u, uhat, o.stream) != hipSuccess)
     return SHEN_ELAUNCH;
-  if (chebyshev) return SHEN_OK;
+  if (chebyshev || fused) return SHEN_OK;
   shen_opts om = o;
   om.variant = 0;
   return mass_solve(space == SHEN_SPACE_DIRICHLET ? SHEN_HELMHOLTZ : SHEN_BIHARMONIC, N, nsys, uhat, uhat, &om);

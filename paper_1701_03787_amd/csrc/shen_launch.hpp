@@ -110,6 +110,7 @@ hipError_t launch_mass_wave(const WaveArgs& a);  // family, N, nsys, f, u (may a
 // Shen transforms: dir 0 point values -> scalar products (solve: Chebyshev
 // coefficients), dir 1 Shen coefficients -> point values
 bool transform_fft_ok(int N, int gl);
+bool transform_fused_mass_ok(int N, int gl);
 size_t transform_direct_lds(int N, int gl, int* sb_out);
 hipError_t launch_transform(int N, int64_t nsys, int space, int dir, int solve, int gl, const void* in, void* out,
                             void* stream);

@@ -252,9 +252,110 @@ __device__ __forceinline__ double2 forward_out(const double2* c, int k, int N, i
   return shen_combine(c, k, space);
 }
 
+// Dirichlet mass solve B u = s of every parity chain of a batch, in place in
+// LDS.  At Gauss points B is, per chain, tridiagonal with off-diagonals -pi/2
+// and diagonal pi, except 3 pi / 2 in row 0 (c_0 = 2), so its LU pivots have
+// a closed form: d_m = (pi/2) r_m with r_m = (2m+3)/(2m+1) (even chain) or
+// (m+2)/(m+1) (odd chain) at chain row m (r_{m+1} = 2 - 1/r_m).  Forward
+// y_m = s_m + a_m y_{m-1} with a_m = (pi/2) / d_{m-1}, then backward
+// u_m = b_m + e_m u_{m+1} with b_m = y_m / d_m, e_m = (pi/2) / d_m.
+// T = N/16 lanes per chain, 8 chain rows each (a chain has at most N/2 rows);
+// every first-order recurrence is solved per lane from a zero carry, the
+// lanes' affine maps (product of the coefficients, local result) are
+// scanned across the chain's lanes with shuffles, and the carry is added
+// back.  T divides 64, so a chain's lanes sit in one wavefront.
+__device__ __forceinline__ double dirichlet_rpivot(int p, int m) {  // 1 / d_m
+  const double M = (double)m;
+  return p == 0 ? (2.0 / kPi) * (2.0 * M + 1.0) * fast_rcp(2.0 * M + 3.0)
+                : (2.0 / kPi) * (M + 1.0) * fast_rcp(M + 2.0);
+}
+__device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int lgN, int n, int sb) {
+  const int T = 1 << (lgN - 4);              // lanes per chain
+  const int ch = tid >> (lgN - 4), q = tid & (T - 1);
+  const int s = ch >> 1, p = ch & 1;
+  const bool act = s < sb;
+  const int nm = (n - p + 1) / 2;            // rows of this chain
+  const int base = s << lgN;
+  const double c = 0.5 * kPi;
+  double2 v[8];
+  double rd[9];                               // 1/d of rows 8q - 1 .. 8q + 7
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int m = 8 * q + j - 1;
+    rd[j] = m >= 0 ? dirichlet_rpivot(p, m) : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = 8 * q + j;
+    v[j] = (act && m < nm) ? buf[lp(base + 2 * m + p)] : zero2();
+  }
+  // forward: local sweep from a zero carry; P = product of the a's
+  double P = 1.0;
+  double2 y = zero2();
+  double pj[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = 8 * q + j;
+    const double am = m < nm ? c * rd[j] : 0.0;  // a_m (0 at row 0 and past the chain)
+    y = c_fma(am, y, m < nm ? v[j] : zero2());
+    v[j] = y;
+    P *= am;
+    pj[j] = P;
+  }
+  // exclusive scan over the lanes of the chain: carry into lane q
+  double cP = P;
+  double2 cy = y;
+  for (int d = 1; d < T; d <<= 1) {
+    const double oP = __shfl_up(cP, d, T);
+    const double2 oy = make_double2(__shfl_up(cy.x, d, T), __shfl_up(cy.y, d, T));
+    if (q >= d) {
+      cy = c_fma(cP, oy, cy);
+      cP *= oP;
+    }
+  }
+  double2 yin = make_double2(__shfl_up(cy.x, 1, T), __shfl_up(cy.y, 1, T));
+  if (q == 0) yin = zero2();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = c_fma(pj[j], yin, v[j]);
+  // backward: u_m = rd_m y_m + (c rd_m) u_{m+1}, local from a zero carry
+  double E = 1.0;
+  double2 x = zero2();
+  double ej[8];
+#pragma unroll
+  for (int j = 7; j >= 0; --j) {
+    const int m = 8 * q + j;
+    const bool ok = m < nm;
+    const double em = ok ? c * rd[j + 1] : 0.0;
+    x = ok ? c_fma(em, x, cscale(rd[j + 1], v[j])) : zero2();
+    v[j] = x;
+    E *= em;
+    ej[j] = E;
+  }
+  // inclusive suffix scan: carry into lane q from the lanes above it
+  double cE = E;
+  double2 cx = x;
+  for (int d = 1; d < T; d <<= 1) {
+    const double oE = __shfl_down(cE, d, T);
+    const double2 ox = make_double2(__shfl_down(cx.x, d, T), __shfl_down(cx.y, d, T));
+    if (q + d < T) {
+      cx = c_fma(cE, ox, cx);
+      cE *= oE;
+    }
+  }
+  double2 xin = make_double2(__shfl_down(cx.x, 1, T), __shfl_down(cx.y, 1, T));
+  if (q == T - 1) xin = zero2();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = 8 * q + j;
+    if (act && m < nm) buf[lp(base + 2 * m + p)] = c_fma(ej[j], xin, v[j]);
+  }
+}
+
 // ---------------------------------------------------------------- FFT path
-// dir 0: point values -> scalar products (or Chebyshev coefficients with
-// solve); dir 1: Shen coefficients -> point values.  Gauss points, N = 2^m.
+// dir 0: point values -> scalar products (with solve: the coefficients, i.e.
+// for the Chebyshev space the scaled products, for the Dirichlet space the
+// mass solve of dirichlet_mass_lanes in LDS: the whole forward transform in one
+// pass); dir 1: Shen coefficients -> point values.  Gauss points, N = 2^m.
 // Each thread moves 8 points of a batch; the next batch's rows are loaded
 // into registers while the current one is transformed.
 // Three work groups per CU (LDS allows three at N = 512): the inverse is held
@@ -345,6 +446,18 @@ __global__ __launch_bounds__(kTfThreads, 3) void cheb_fft(int N, int64_t nsys, i
           }
         }
         cv[t] = r;
+      }
+      if (solve && space == SHEN_SPACE_DIRICHLET && N >= 16 && N <= 1024) {
+        // the forward transform: the mass solve of every chain of the batch
+        // in LDS (one thread per chain), before the batch goes out
+        __syncthreads();  // every read of the FFT output is done
+#pragma unroll
+        for (int t = 0; t < PT; ++t) buf[lp(tid + t * kTfThreads)] = cv[t];
+        __syncthreads();
+        dirichlet_mass_lanes(buf, tid, lgN, n, sb);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < PT; ++t) cv[t] = buf[lp(tid + t * kTfThreads)];
       }
 #pragma unroll
       for (int t = 0; t < PT; ++t) {
@@ -479,6 +592,9 @@ int grid_for(const void* kernel, int64_t batches, size_t lds) {
 }  // namespace
 
 bool transform_fft_ok(int N, int gl) { return !gl && N >= 8 && N <= kTfPoints && (N & (N - 1)) == 0; }
+// The Dirichlet forward transform in one pass (FFT kernel with the mass solve
+// of dirichlet_mass_lanes): a chain's N/16 lanes within one wavefront.
+bool transform_fused_mass_ok(int N, int gl) { return transform_fft_ok(N, gl) && N >= 16 && N <= 1024; }
 
 size_t transform_direct_lds(int N, int gl, int* sb_out) {
   const int M = gl ? (N > 1 ? N - 1 : 1) : 2 * N;
