@@ -277,13 +277,10 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   const int nm = (n - p + 1) / 2;            // rows of this chain
   const int base = s << lgN;
   const double c = 0.5 * kPi;
+  // a_m = c / d_{m-1} (0 at row 0 and past the chain), e_m = c / d_m (0 past it)
+  auto a_of = [&](int m) { return (m >= 1 && m < nm) ? c * dirichlet_rpivot(p, m - 1) : 0.0; };
+  auto e_of = [&](int m) { return m < nm ? c * dirichlet_rpivot(p, m) : 0.0; };
   double2 v[8];
-  double rd[9];                               // 1/d of rows 8q - 1 .. 8q + 7
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    const int m = 8 * q + j - 1;
-    rd[j] = m >= 0 ? dirichlet_rpivot(p, m) : 0.0;
-  }
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int m = 8 * q + j;
@@ -292,15 +289,12 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   // forward: local sweep from a zero carry; P = product of the a's
   double P = 1.0;
   double2 y = zero2();
-  double pj[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int m = 8 * q + j;
-    const double am = m < nm ? c * rd[j] : 0.0;  // a_m (0 at row 0 and past the chain)
-    y = c_fma(am, y, m < nm ? v[j] : zero2());
+    const double am = a_of(8 * q + j);
+    y = c_fma(am, y, v[j]);
     v[j] = y;
     P *= am;
-    pj[j] = P;
   }
   // exclusive scan over the lanes of the chain: carry into lane q
   double cP = P;
@@ -315,21 +309,22 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   }
   double2 yin = make_double2(__shfl_up(cy.x, 1, T), __shfl_up(cy.y, 1, T));
   if (q == 0) yin = zero2();
+  double pj = 1.0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = c_fma(pj[j], yin, v[j]);
-  // backward: u_m = rd_m y_m + (c rd_m) u_{m+1}, local from a zero carry
+  for (int j = 0; j < 8; ++j) {
+    pj *= a_of(8 * q + j);
+    v[j] = c_fma(pj, yin, v[j]);
+  }
+  // backward: u_m = (y_m + c u_{m+1}) / d_m, local from a zero carry
   double E = 1.0;
   double2 x = zero2();
-  double ej[8];
 #pragma unroll
   for (int j = 7; j >= 0; --j) {
     const int m = 8 * q + j;
-    const bool ok = m < nm;
-    const double em = ok ? c * rd[j + 1] : 0.0;
-    x = ok ? c_fma(em, x, cscale(rd[j + 1], v[j])) : zero2();
+    const double rdm = m < nm ? dirichlet_rpivot(p, m) : 0.0;
+    x = cscale(rdm, c_fma(c, x, v[j]));  // (0 past the chain)
     v[j] = x;
-    E *= em;
-    ej[j] = E;
+    E *= c * rdm;
   }
   // inclusive suffix scan: carry into lane q from the lanes above it
   double cE = E;
@@ -344,10 +339,12 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   }
   double2 xin = make_double2(__shfl_down(cx.x, 1, T), __shfl_down(cx.y, 1, T));
   if (q == T - 1) xin = zero2();
+  double ej = 1.0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 7; j >= 0; --j) {
     const int m = 8 * q + j;
-    if (act && m < nm) buf[lp(base + 2 * m + p)] = c_fma(ej[j], xin, v[j]);
+    ej *= e_of(m);
+    if (act && m < nm) buf[lp(base + 2 * m + p)] = c_fma(ej, xin, v[j]);
   }
 }
 
@@ -360,8 +357,10 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
 // into registers while the current one is transformed.
 // Three work groups per CU (LDS allows three at N = 512): the inverse is held
 // to the forward's register budget for that.
-template <int DIR>
-__global__ __launch_bounds__(kTfThreads, 3) void cheb_fft(int N, int64_t nsys, int space, int solve,
+// MASS (a separate instance, so that the others keep their registers): the
+// Dirichlet forward transform, with the mass solve after the scalar products.
+template <int DIR, bool MASS = false>
+__global__ __launch_bounds__(kTfThreads, (MASS ? 2 : 3)) void cheb_fft(int N, int64_t nsys, int space, int solve,
                                                        const double2* __restrict__ in, double2* __restrict__ out) {
   constexpr int dir = DIR;
   extern __shared__ double2 lds[];
@@ -447,7 +446,7 @@ __global__ __launch_bounds__(kTfThreads, 3) void cheb_fft(int N, int64_t nsys, i
         }
         cv[t] = r;
       }
-      if (solve && space == SHEN_SPACE_DIRICHLET && N >= 16 && N <= 1024) {
+      if constexpr (MASS) {
         // the forward transform: the mass solve of every chain of the batch
         // in LDS (one thread per chain), before the batch goes out
         __syncthreads();  // every read of the FFT output is done
@@ -613,13 +612,19 @@ hipError_t launch_transform(int N, int64_t nsys, int space, int dir, int solve, 
     const size_t lds = (size_t)(kTfSlots + 2 * N) * sizeof(double2);
     static const bool attr =
         hipFuncSetAttribute((const void*)cheb_fft<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess &&
+        hipFuncSetAttribute((const void*)cheb_fft<0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) ==
+            hipSuccess &&
         hipFuncSetAttribute((const void*)cheb_fft<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
     (void)attr;
     const int SB = kTfPoints / N;
     const int64_t batches = (nsys + SB - 1) / SB;
-    const void* k = dir == 0 ? (const void*)cheb_fft<0> : (const void*)cheb_fft<1>;
+    const bool mass = dir == 0 && solve && space == SHEN_SPACE_DIRICHLET && transform_fused_mass_ok(N, gl);
+    const void* k = mass ? (const void*)cheb_fft<0, true> : dir == 0 ? (const void*)cheb_fft<0> : (const void*)cheb_fft<1>;
     const int grid = grid_for(k, batches, lds);
-    if (dir == 0)
+    if (mass)
+      hipLaunchKernelGGL((cheb_fft<0, true>), dim3((unsigned)grid), dim3(kTfThreads), lds, st, N, nsys, space, solve,
+                         (const double2*)in, (double2*)out);
+    else if (dir == 0)
       hipLaunchKernelGGL(cheb_fft<0>, dim3((unsigned)grid), dim3(kTfThreads), lds, st, N, nsys, space, solve,
                          (const double2*)in, (double2*)out);
     else
