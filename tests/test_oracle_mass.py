@@ -185,3 +185,30 @@ def test_derivative_of_a_dirichlet_function_is_reproduced():
     uhat[0, :nb] = uh
     got = so.derivative_solve(N, uhat)
     np.testing.assert_allclose(got[0, :nd].real, fd, atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [16, 64, 512, 1024])
+def test_dirichlet_mass_pivots_closed_form(N):
+    """At Gauss points the Dirichlet mass matrix restricted to a parity chain is tridiagonal with
+    off-diagonals -pi/2 and diagonal pi (3 pi/2 in row 0 of the even chain), so the unpivoted LU
+    pivots are d_m = (pi/2)(2m+3)/(2m+1) (even chain) and (pi/2)(m+2)/(m+1) (odd chain): the
+    closed form the one-pass Dirichlet forward transform uses.  Checked against the pivot
+    recurrence of the oracle's matrix, and their product against its determinant."""
+    B = so.mass_matrix("helmholtz", N, so.GC)
+    n = N - 2
+    for p in (0, 1):
+        idx = np.arange(p, n, 2)
+        Bc = B[np.ix_(idx, idx)]
+        assert np.allclose(np.diag(Bc, 1), -np.pi / 2) and np.allclose(np.diag(Bc, -1), -np.pi / 2)
+        assert np.count_nonzero(np.triu(Bc, 2)) == 0
+        d = np.empty(len(idx))
+        prev = None
+        for m in range(len(idx)):  # the pivot recurrence of the unpivoted LU
+            d[m] = Bc[m, m] if m == 0 else Bc[m, m] - Bc[m, m - 1] * Bc[m - 1, m] / prev
+            prev = d[m]
+        M = np.arange(len(idx), dtype=np.float64)
+        closed = (np.pi / 2) * ((2 * M + 3) / (2 * M + 1) if p == 0 else (M + 2) / (M + 1))
+        np.testing.assert_allclose(d, closed, rtol=1e-13)
+        # and the product of the pivots is the determinant of the chain's matrix
+        sign, logdet = np.linalg.slogdet(Bc)
+        assert sign > 0 and abs(logdet - np.sum(np.log(closed))) <= 1e-10 * max(1.0, abs(logdet))
