@@ -277,9 +277,16 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   const int nm = (n - p + 1) / 2;            // rows of this chain
   const int base = s << lgN;
   const double c = 0.5 * kPi;
-  // a_m = c / d_{m-1} (0 at row 0 and past the chain), e_m = c / d_m (0 past it)
-  auto a_of = [&](int m) { return (m >= 1 && m < nm) ? c * dirichlet_rpivot(p, m - 1) : 0.0; };
-  auto e_of = [&](int m) { return m < nm ? c * dirichlet_rpivot(p, m) : 0.0; };
+  // 1/d of rows 8q - 1 .. 8q + 7 (0 outside the chain); a_m = c rd_{m-1},
+  // e_m = c rd_m (so a is 0 at row 0 and past the chain, e past it)
+  double rd[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const int m = 8 * q + j - 1;
+    rd[j] = (m >= 0 && m < nm) ? dirichlet_rpivot(p, m) : 0.0;
+  }
+  auto a_of = [&](int j) { return 8 * q + j < nm ? c * rd[j] : 0.0; };
+  auto e_of = [&](int j) { return c * rd[j + 1]; };
   double2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -291,7 +298,7 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   double2 y = zero2();
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double am = a_of(8 * q + j);
+    const double am = a_of(j);
     y = c_fma(am, y, v[j]);
     v[j] = y;
     P *= am;
@@ -312,7 +319,7 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   double pj = 1.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    pj *= a_of(8 * q + j);
+    pj *= a_of(j);
     v[j] = c_fma(pj, yin, v[j]);
   }
   // backward: u_m = (y_m + c u_{m+1}) / d_m, local from a zero carry
@@ -320,9 +327,8 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
   double2 x = zero2();
 #pragma unroll
   for (int j = 7; j >= 0; --j) {
-    const int m = 8 * q + j;
-    const double rdm = m < nm ? dirichlet_rpivot(p, m) : 0.0;
-    x = cscale(rdm, c_fma(c, x, v[j]));  // (0 past the chain)
+    const double rdm = rd[j + 1];  // (0 past the chain)
+    x = cscale(rdm, c_fma(c, x, v[j]));
     v[j] = x;
     E *= c * rdm;
   }
@@ -343,7 +349,7 @@ __device__ __forceinline__ void dirichlet_mass_lanes(double2* buf, int tid, int 
 #pragma unroll
   for (int j = 7; j >= 0; --j) {
     const int m = 8 * q + j;
-    ej *= e_of(m);
+    ej *= e_of(j);
     if (act && m < nm) buf[lp(base + 2 * m + p)] = c_fma(ej, xin, v[j]);
   }
 }
