@@ -250,3 +250,33 @@ def test_rhs_argument_errors():
         assert fn(16, 0, None, 5e-5, 5e-4, None, None, None, C.byref(o)) == L.SHEN_OK
         o.transpose = 1
         assert fn(16, 4, A, 5e-5, 5e-4, B, None, S, C.byref(o)) == L.SHEN_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_1701_03787_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libshenhip.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.lib()
+
+
+def test_product_path_never_reaches_the_oracle():
+    # the package (binding, kernels, launchers) imports and includes nothing of the oracle
+    import ast
+    pkg = os.path.join(ROOT, "paper_1701_03787_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            path = os.path.join(dirpath, name)
+            if name.endswith(".py"):
+                tree = ast.parse(open(path).read(), path)
+                for node in ast.walk(tree):
+                    if isinstance(node, ast.Import):
+                        mods = [a.name for a in node.names]
+                    elif isinstance(node, ast.ImportFrom):
+                        mods = [node.module or ""]
+                    else:
+                        continue
+                    assert not any(m.split(".")[0] == "oracle" for m in mods), (path, mods)
+            elif name.endswith((".hip", ".hpp", ".h", ".cpp")):
+                src = open(path).read()
+                assert "oracle/" not in src and "shen_oracle" not in src, path
