@@ -280,3 +280,21 @@ def test_product_path_never_reaches_the_oracle():
             elif name.endswith((".hip", ".hpp", ".h", ".cpp")):
                 src = open(path).read()
                 assert "oracle/" not in src and "shen_oracle" not in src, path
+
+
+def test_oracle_is_independent_of_the_package():
+    # the oracle imports nothing of the GPU package, not even the shared input generators
+    import ast
+    odir = os.path.join(ROOT, "oracle")
+    for name in os.listdir(odir):
+        if not name.endswith(".py"):
+            continue
+        path = os.path.join(odir, name)
+        for node in ast.walk(ast.parse(open(path).read(), path)):
+            if isinstance(node, ast.Import):
+                mods = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                mods = [node.module or ""] if node.level == 0 else []
+            else:
+                continue
+            assert not any(m.split(".")[0] in ("paper_1701_03787_amd", "torch", "ctypes") for m in mods), (path, mods)
